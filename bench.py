@@ -1,0 +1,178 @@
+"""Throughput of the colour-LBM time step on one MI355X, with its HBM roofline and CPU baseline.
+
+Workload (default): steady-state two-fluid flow through a 256^3 synthetic rock, FP64. The rock
+is a periodic Gaussian random field with 4-voxel correlation length thresholded at porosity 0.2,
+keeping the pore clusters that span z (about 3.2e6 pore voxels); per-voxel wall affinity
+U[-0.9, 0.9]; random initial phase at Sw = 0.5; body force F_z = 1e-5; periodic on all axes;
+tau = 0.7, alpha = 0.005, beta = 0.95; saturation and flux reductions every 100 steps.
+
+One bench step is one full time step (densities and phase, fused gradient + collision +
+recolouring + streaming, reductions at their cadence). Inputs are resident in HBM before the
+timed region. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 2000] [--warmup 100] [--workload grf256|grf512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pore-voxel MLUPS + % HBM roofline; batched solves/s with p50/p99 latency"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+# Algorithmic bytes per pore voxel (FP64 storage): the collide kernel reads 19 f, writes 19 f
+# and 14 recoloured A/B, reads phi and N at the voxel (neighbour phi is reuse), and reads the
+# 18-entry int32 neighbour table; the phase kernel reads 14 A/B and writes phi and N.
+BYTES_COLLIDE_FP64 = 8 * (19 + 19 + 14 + 2) + 4 * 18          # 504
+BYTES_PHASE_FP64 = 8 * (14 + 2)                                # 128 (+ 6 nbr on odd steps)
+BYTES_STEP_FP64 = 8 * (38 + 28 + 4) + 4 * 18                  # 632
+
+WORKLOADS = {
+    "grf256": dict(n=256, seed_geom=3, seed_aff=4, seed_phase=5, reduce_every=100,
+                   desc="steady two-fluid flow, 256^3 GRF rock (corr 4, porosity 0.2, "
+                        "percolating), affinity U[-0.9,0.9], Sw=0.5, Fz=1e-5, periodic, FP64, "
+                        "reductions every 100 steps"),
+    "grf512": dict(n=512, seed_geom=5, seed_aff=6, seed_phase=7, reduce_every=100,
+                   desc="steady two-fluid flow, 512^3 GRF rock (corr 4, porosity 0.2, "
+                        "percolating), affinity U[-0.9,0.9], Sw=0.5, Fz=1e-5, periodic, FP64, "
+                        "reductions every 100 steps"),
+}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, budget_s: float = 15.0) -> dict:
+    """The FP64 CPU oracle (dense grid, OpenMP) on the same workload, for a bounded number of
+    steps (about budget_s of CPU time)."""
+    import oracle as O
+    st = O.state_for(prob)
+    t0 = time.perf_counter()
+    st.run(1)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(50, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    st.run(steps)
+    dt = time.perf_counter() - t0
+    n = prob.n_pore()
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS (pore voxels)",
+            "cores": O.threads(), "kind": "oracle",
+            "sample": "same %s rock, %d FP64 steps after 1 warm-up step, dense C oracle, "
+                      "%.1f s" % ("x".join(map(str, prob.shape)), steps, dt),
+            "host": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="grf256", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 2 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2007_12266_amd import inputs, lbm
+
+    wl = WORKLOADS[args.workload]
+    log("generating %s" % args.workload)
+    t0 = time.perf_counter()
+    prob = inputs.grf_problem(n=wl["n"], seed_geom=wl["seed_geom"], seed_aff=wl["seed_aff"],
+                              seed_phase=wl["seed_phase"])
+    log("rock ready in %.1f s, porosity %.4f" % (time.perf_counter() - t0,
+                                                  prob.n_pore() / np.prod(prob.shape)))
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        dom = lbm.Domain(prob, reduce_every=wl["reduce_every"], block_size=args.block,
+                         stream=stream.cuda_stream)
+    n_pore = dom.n_pore
+    log("domain: N=%d, device bytes %.2f GB" % (n_pore, dom.info()["device_bytes"] / 1e9))
+
+    dom.step(args.warmup)
+    torch.cuda.synchronize()
+    dom.history()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    dom.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    hist = dom.history()
+    log("timed %d steps in %.1f ms" % (args.steps, ms))
+    ms_per_step = ms / args.steps
+    mlups = n_pore * args.steps / (ms / 1e3) / 1e6
+
+    # Per-kernel device time (HIP events around every launch, on the library's stream).
+    ksteps = min(args.steps, 200)
+    timing = dom.step_timed(ksteps)
+    coll_s = timing["collide_ms"] / 1e3
+    achieved = BYTES_COLLIDE_FP64 * n_pore / coll_s / 1e9
+    step_gbs = BYTES_STEP_FP64 * n_pore / (ms_per_step / 1e3) / 1e9
+
+    if args.copy_calibration:
+        a = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    red = dom.reduce()
+    block = dom.info()["block_size"]
+    dom.close()
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS (pore-voxel lattice updates per second / 1e6)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "grid": list(prob.shape), "n_pore": n_pore,
+                   "porosity": round(n_pore / float(np.prod(prob.shape)), 5),
+                   "precision": "fp64", "reduce_every": wl["reduce_every"],
+                   "block": block},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "collide_kernel",
+                     "bytes_per_voxel": BYTES_COLLIDE_FP64,
+                     "kernel_ms": round(timing["collide_ms"], 5)},
+        "step_hbm": {"bytes_per_voxel": BYTES_STEP_FP64, "achieved_gbs": round(step_gbs, 1),
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                     "phase_ms": round(timing["phase_ms"], 5)},
+        "reductions": {"recorded": len(hist), "sw": red["sw"], "qz": red["qz"],
+                       "unstable": red["unstable"]},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

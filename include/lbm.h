@@ -1,0 +1,210 @@
+/*
+ * lbm.h -- C-ABI of the MI355X (gfx950) two-fluid colour lattice Boltzmann library.
+ *
+ * The library advances the colour LBM of McClure, Li, Berrill and Ramstad (arXiv 2007.12266,
+ * section "Color Lattice-Boltzmann Model"): two D3Q7 mass-transport LBEs for the component
+ * densities N_a and N_b, coupled through the phase indicator phi = (N_a - N_b)/(N_a + N_b), its
+ * colour gradient C and the normal n = C/|C| to a D3Q19 MRT momentum LBE that carries the
+ * interfacial-tension terms (sigma_ab = 6 alpha) and a constant body force F, over the pore
+ * voxels of a labelled rock image whose solid labels carry a wetting affinity phi_s in [-1, 1]
+ * (section "Modeling Wetting with Lattice Boltzmann models": cos(theta_eq) = phi_s).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns lbm_status; LBM_OK == 0. On failure lbm_last_error() returns a
+ *     thread-local message describing the last error of the calling thread.
+ *   - Dense arrays are nz*ny*nx, C order, x fastest: index = x + nx*(y + ny*z).
+ *   - The caller owns every host array it passes; the library copies what it needs before the
+ *     call returns. The library owns all device memory of a domain (allocated through the
+ *     optional allocator hook, else hipMalloc) and frees it in lbm_domain_destroy.
+ *   - Stepping is asynchronous on the domain's HIP stream. Calls that return data to the host
+ *     (read_field, reduce, read_history, state_save, step_timed) synchronise that stream.
+ *   - A domain handle is not thread-safe: use one domain from one host thread at a time.
+ *   - Device pointers are never exposed; every pointer argument below is a host pointer except
+ *     where stated (hip_stream is a hipStream_t handle).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_domain lbm_domain; /* opaque; owned by the library */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = 1,      /* invalid argument; nothing was changed                     */
+    LBM_ERR_OOM = 2,      /* device allocation failed                                  */
+    LBM_ERR_DEVICE = 3,   /* a HIP runtime call failed; the domain should be destroyed  */
+    LBM_ERR_UNSTABLE = 4, /* a reduction saw a non-finite value; sticky until state_load */
+    LBM_ERR_STATE = 5     /* state buffer does not match this domain                   */
+} lbm_status;
+
+typedef enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 } lbm_precision;
+
+/* Label kinds (section "Initial conditions and wetting maps": every voxel carries an integer
+ * label naming its material). */
+typedef enum {
+    LBM_LABEL_SOLID = 0,     /* solid; its affinity is the wetting pseudo-phase phi_s       */
+    LBM_LABEL_FLUID_A = 1,   /* pore initially filled with fluid a (phi = +1, water)        */
+    LBM_LABEL_FLUID_B = 2,   /* pore initially filled with fluid b (phi = -1)               */
+    LBM_LABEL_PORE_INIT = 3  /* pore whose initial phi comes from init_phi                  */
+} lbm_label_kind;
+
+/* Fields readable with lbm_read_field; all are functions of the stored state after the last
+ * completed step (N_a, N_b from the D3Q7 populations; rho = sum f; u = sum f xi + F/2;
+ * p = rho/3, the D3Q19 equation of state with cs^2 = 1/3). */
+typedef enum {
+    LBM_FIELD_NA = 0, LBM_FIELD_NB = 1, LBM_FIELD_PHI = 2, LBM_FIELD_RHO = 3,
+    LBM_FIELD_P = 4, LBM_FIELD_UX = 5, LBM_FIELD_UY = 6, LBM_FIELD_UZ = 7
+} lbm_field;
+
+/* Optional device-memory hook (e.g. a framework's caching allocator). alloc returns a device
+ * pointer of at least `bytes` bytes, 256-byte aligned, or NULL on failure; free releases it. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} lbm_allocator;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* dense image size                                           */
+    int32_t periodic[3];     /* per axis; a non-periodic face is a solid wall of            */
+                             /* affinity wall_affinity (halfway bounce-back)                */
+    double tau_a, tau_b;     /* relaxation times of fluids a and b; nu = (tau - 1/2)/3      */
+    double alpha;            /* interfacial-tension parameter: sigma_ab = 6 alpha           */
+    double beta;             /* recolouring (interface width) parameter, 0 < beta < 1       */
+    double force[3];         /* constant body force per unit volume, lattice units          */
+    double wall_affinity;    /* phi_s seen across non-periodic faces                        */
+    int32_t bc_z;            /* 0: none; 1: pressure faces at z = 0 (inlet, pure fluid a)   */
+                             /* and z = nz-1 (outlet, pure fluid b); needs periodic[2] == 0 */
+    int32_t precision;       /* lbm_precision                                               */
+    double rho_in, rho_out;  /* imposed densities of the pressure faces (bc_z == 1)         */
+    int32_t reduce_every;    /* lbm_step records a reduction every this many steps (0: off) */
+    int32_t block_size;      /* threads per workgroup (64..1024, multiple of 64); 0: auto   */
+} lbm_params;
+
+/* Reductions over the pore voxels (section "Analysis framework", integral measures, and the
+ * total capillary number of the steady-state protocol), accumulated in FP64:
+ *   mass_a, mass_b   sum of N_a, N_b;
+ *   sw               mean of (1 + phi)/2 over pore voxels (smooth saturation of fluid a);
+ *   sw_count         fraction of pore voxels with phi > 0 (volume of the water region);
+ *   flux[3]          sum of u over pore voxels / (nx*ny*nz)  (superficial Darcy flux);
+ *   flux_a, flux_b   same, weighted by (1 + phi)/2 and (1 - phi)/2;
+ *   p_a, p_b         mean p = rho/3 over {phi > 0} and {phi < 0};
+ *   ca               (eps_a mu_a |U_a| + eps_b mu_b |U_b|) / (6 alpha) with U = P/M over each
+ *                    region (P = sum rho u, M = sum rho), eps = region volume / (nx*ny*nz),
+ *                    mu = nu (unit density);
+ *   n_pore, step     pore count and the step the reduction describes;
+ *   unstable         1 if any N_a, N_b, rho or u was not finite.                              */
+typedef struct {
+    double mass_a, mass_b, sw, sw_count;
+    double flux[3], flux_a[3], flux_b[3];
+    double p_a, p_b, ca;
+    int64_t n_pore, step;
+    int32_t unstable, pad_;
+} lbm_reduction;
+
+/* Average device time per launch of each kernel over a lbm_step_timed call (milliseconds). */
+typedef struct {
+    double phase_ms;          /* densities + phase indicator kernel                         */
+    double collide_ms;        /* fused gradient + collision + recolour + stream kernel       */
+    double bc_ms;             /* pressure-face kernel (0 if unused)                          */
+    double step_ms;           /* wall time per step between the first and last event         */
+    int64_t phase_launches, collide_launches, bc_launches;
+} lbm_timing;
+
+typedef struct {
+    int64_t n_pore;           /* pore voxels (the sparse list length N)                     */
+    int64_t n_solid_tail;     /* solid voxels adjacent to a pore, plus the wall entry        */
+    int64_t ld;               /* leading dimension of the SoA population arrays              */
+    int64_t device_bytes;     /* device memory held by the domain                            */
+    int64_t step;             /* completed steps                                             */
+    int32_t precision;        /* lbm_precision                                               */
+    int32_t block_size;       /* threads per workgroup in use                                */
+} lbm_domain_info;
+
+/* Create a domain from a labelled image (sections "Initial conditions and wetting maps" and
+ * "Modeling Wetting"): labels[nx*ny*nz] with values in [0, n_labels); label_kind[n_labels]
+ * (lbm_label_kind); label_affinity[n_labels] (phi_s of solid labels, in [-1, 1]);
+ * voxel_affinity (nullable, dense): per-voxel phi_s that overrides the label's for solid voxels;
+ * init_phi (nullable, dense): initial phi in [-1, 1] of LBM_LABEL_PORE_INIT voxels (required if
+ * any label has that kind). The initial state is rest equilibrium, rho = 1, u = 0,
+ * N_a = (1 + phi)/2, N_b = (1 - phi)/2. alloc and hip_stream are nullable. On success *out owns
+ * the domain. Errors: LBM_ERR_ARG (bad sizes, labels, parameters: tau <= 1/2, rho <= 0, no pore
+ * voxel, beta outside (0,1), bc_z with a periodic z axis), LBM_ERR_OOM, LBM_ERR_DEVICE. */
+lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, int32_t n_labels,
+                             const int8_t* label_kind, const double* label_affinity,
+                             const double* voxel_affinity, const double* init_phi,
+                             const lbm_allocator* alloc, void* hip_stream, lbm_domain** out);
+
+/* Advance nsteps >= 0 time steps, asynchronously on the domain's stream (the time step of the
+ * colour model: densities, phase indicator, colour gradient, MRT collision with the interfacial
+ * terms and body force, recolouring, streaming with halfway bounce-back at solids). Records a
+ * reduction every reduce_every steps. Returns LBM_ERR_UNSTABLE without stepping once a
+ * reduction has seen a non-finite value. */
+lbm_status lbm_step(lbm_domain* d, int64_t nsteps);
+
+/* Same as lbm_step, but brackets every kernel launch with HIP events and reports the average
+ * device time per launch of each kernel in *out. Synchronises. For measurement only. */
+lbm_status lbm_step_timed(lbm_domain* d, int64_t nsteps, lbm_timing* out);
+
+/* Copy one field (lbm_field) of the current state into host_dense[nx*ny*nz]; solid voxels are
+ * set to NaN. Synchronises. */
+lbm_status lbm_read_field(lbm_domain* d, int32_t field, double* host_dense);
+
+/* Copy one field of the current state for the pore voxels only, in the library's pore order
+ * (see lbm_pore_index), into host_pore[n_pore]. Synchronises. */
+lbm_status lbm_read_pore_field(lbm_domain* d, int32_t field, double* host_pore);
+
+/* Dense voxel index of each pore voxel, in the library's pore order: host_index[n_pore]. */
+lbm_status lbm_pore_index(lbm_domain* d, int64_t* host_index);
+
+/* Reduce the current state (see lbm_reduction). Synchronises. */
+lbm_status lbm_reduce(lbm_domain* d, lbm_reduction* out);
+
+/* Reductions recorded by lbm_step (every reduce_every steps) since the last call, oldest
+ * first, at most max_count of them; *count receives the number written. Synchronises. */
+lbm_status lbm_read_history(lbm_domain* d, lbm_reduction* out, int32_t max_count,
+                            int32_t* count);
+
+/* Serialise the state (populations, step counter) to host_buf. With host_buf == NULL only
+ * *nbytes is set to the size needed. Errors: LBM_ERR_ARG if *nbytes is too small. */
+lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes);
+
+/* Restore a state written by lbm_state_save of a domain with the same geometry and precision.
+ * Clears the sticky unstable flag. Errors: LBM_ERR_STATE on a size or header mismatch. */
+lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes);
+
+lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out);
+
+/* Host-only inspection of the sparse layout a domain would use (no GPU needed): runs the CPU
+ * pre-pass on the same arguments as lbm_domain_create and reports *n_pore and *n_tail. Each
+ * nullable output array, if given, must hold: pore_voxel[n_pore] (dense index of each pore
+ * voxel, pore order), nbr[18 * n_pore] (row q-1 holds the neighbour of every pore voxel along
+ * D3Q19 velocity q = 1..18: a pore index < n_pore, or n_pore + t for tail entry t, a solid or
+ * wall neighbour), tail_phi[n_tail] (phi_s of each tail entry; entry 0 is the wall outside
+ * non-periodic faces). Call once with NULL arrays to learn the sizes. */
+lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, int32_t n_labels,
+                             const int8_t* label_kind, const double* label_affinity,
+                             const double* voxel_affinity, const double* init_phi,
+                             int64_t* n_pore, int64_t* n_tail, int64_t* pore_voxel,
+                             int32_t* nbr, double* tail_phi);
+
+/* Release all device memory of the domain and the handle itself. NULL is accepted. */
+lbm_status lbm_domain_destroy(lbm_domain* d);
+
+/* Message of the calling thread's last error ("" if none). Valid until its next call. */
+const char* lbm_last_error(void);
+
+/* Library version string. */
+const char* lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -64,8 +64,14 @@ def lib():
         L.ora_run.restype = ctypes.c_int
         L.ora_fields.argtypes = [pp, up, dp, dp, dp] + [dp] * 8
         L.ora_reduce.argtypes = [pp, up, dp, dp, dp, dp]
+        L.ora_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().ora_threads())
 
 
 def _d(a):

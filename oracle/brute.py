@@ -33,6 +33,7 @@ def _velocities():
 
 
 XI = _velocities()
+C_MIN = 1e-10
 OPP = np.array([int(np.where((XI == -XI[q]).all(1))[0][0]) for q in range(19)])
 T = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 W7 = np.array([1 / 3] + [1 / 9] * 6)
@@ -70,6 +71,8 @@ def collide_voxel(f, Na, Nb, C, tau_a, tau_b, alpha, beta, F):
     j2 = jx * jx + jy * jy + jz * jz
     phi = (Na - Nb) / (Na + Nb)
     cm = float(np.sqrt(np.dot(C, C)))
+    if cm <= C_MIN:                 # unresolved gradient: treated as zero
+        cm = 0.0
     n = C / cm if cm > 0 else np.zeros(3)
     h = alpha * cm / 2
     eq = {"rho": rho, "jx": jx, "jy": jy, "jz": jz,

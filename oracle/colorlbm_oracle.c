@@ -16,7 +16,9 @@
  *   - colour gradient stencil: C = sum_q c_q xi_q phi(x + xi_q) with c_q = 1 on the six axis
  *     links and 1/2 on the twelve diagonals (this makes the flat-interface tension exactly
  *     6 alpha, the stated sigma_ab = 6 alpha);
- *   - n = C/|C| when |C| > 0, else n = 0;
+ *   - n = C/|C| when |C| > 1e-10, else C is taken as zero (n = 0, alpha|C| = 0): below that
+ *     size the gradient is unresolved, a cancellation of O(1) neighbour values whose rounding
+ *     residue would otherwise set the direction of the recolouring;
  *   - unlisted equilibria follow d'Humieres et al. 2002 (w_eps = 3, w_epsj = -11/2,
  *     w_xx = -1/2, q_eq = -2/3 j, m16..18 = 0), incompressible form with rho0 = 1;
  *   - relaxation: s+ = 1/tau on the even non-conserved moments, s- = 8(2-s+)/(8-s+) on the odd
@@ -34,9 +36,12 @@
  * Entries of solid voxels are never read and are left as they are.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#define ORA_C_MIN 1e-10
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -115,6 +120,17 @@ static void build_basis(void) {
     g_basis_ready = 1;
 }
 
+/* Threads an OpenMP parallel region of the oracle will use. */
+int ora_threads(void) {
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}
+
 void ora_moment_basis(double* M, double* Minv, double* D) {
     build_basis();
     for (int k = 0; k < 19; ++k) {
@@ -154,12 +170,16 @@ void ora_collide(const ora_params* p, const double* f, double Na, double Nb, con
 
     /* Phase indicator and interface normal. */
     const double phi = (Na - Nb) / (Na + Nb);
-    const double cmag = sqrt(C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
+    /* A gradient no larger than ORA_C_MIN is unresolved (its size is then set by rounding
+     * of cancelling neighbour values, and n would point anywhere): it is taken as zero. */
+    double cmag = sqrt(C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
     double nx = 0.0, ny = 0.0, nz = 0.0;
-    if (cmag > 0.0) {
+    if (cmag > ORA_C_MIN) {
         nx = C[0] / cmag;
         ny = C[1] / cmag;
         nz = C[2] / cmag;
+    } else {
+        cmag = 0.0;
     }
     const double ac = p->alpha * cmag;
 

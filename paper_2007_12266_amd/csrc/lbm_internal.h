@@ -1,0 +1,54 @@
+// Internal declarations shared by the runtime (lbm_runtime.hip), the pre-pass
+// (lbm_prepass.cpp) and the kernels (lbm_kernels.hip). Not part of the C-ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+#include "lbm_prepass.h"
+
+namespace lbm {
+
+// Number of FP64 accumulators of the reduction kernel, in this order:
+//  0 M_a  1 M_b  2 sum (1+phi)/2  3 V_a (#phi>0)  4 V_b (#phi<0)  5..7 sum u
+//  8..10 sum (1+phi)/2 u  11..13 sum (1-phi)/2 u  14 sum rho over phi>0  15 over phi<0
+//  16..18 sum rho u over phi>0  19..21 over phi<0  22 sum p over phi>0  23 over phi<0
+//  24 count of non-finite voxels
+constexpr int kNRed = 25;
+constexpr int kRedBlocks = 512;   // fixed launch shape of the reduction => fixed summation order
+constexpr int kRedThreads = 256;
+
+// Arguments of the step kernels (passed by value).
+struct StepArgs {
+    int32_t N;          // pore voxels
+    int32_t nblocks;    // logical workgroups covering N
+    int64_t ld;         // leading dimension of population arrays
+    const int32_t* nbr; // [18][ld]
+    double* phi;        // [N + n_tail]; tail holds phi_s
+    double* ntot;       // [N]
+    void* f;            // [19][ld] populations (storage type per precision)
+    void* A;            // [7][ld]
+    void* B;            // [7][ld]
+    double nu_a, nu_b;  // kinematic viscosities
+    double alpha, beta;
+    double F[3];
+    int32_t xcd_remap;  // 1: map consecutive logical blocks to the same XCD
+};
+
+// Kernel launchers (lbm_kernels.hip). `odd` is the parity of the step being taken.
+hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s);
+hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s);
+hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s);
+hipError_t launch_pressure_bc(const StepArgs& a, bool odd, const int32_t* inlet, int32_t n_in,
+                              const int32_t* outlet, int32_t n_out, double rho_in,
+                              double rho_out, hipStream_t s);
+hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
+                         hipStream_t s);
+hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int block,
+                        hipStream_t s);
+
+}  // namespace lbm

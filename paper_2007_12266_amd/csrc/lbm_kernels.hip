@@ -1,0 +1,460 @@
+// HIP kernels (gfx950, wave64) of the two-fluid colour LBM time step over a sparse pore list.
+//
+// Method (arXiv 2007.12266, section "Color Lattice-Boltzmann Model"): two D3Q7 mass LBEs whose
+// post-collision populations are the recoloured equilibria
+//   A*_q = w_q N_a [1 + u.xi_q / cs^2 + beta (N_b/N) n.xi_q],
+//   B*_q = w_q N_b [1 + u.xi_q / cs^2 - beta (N_a/N) n.xi_q],   cs^2 = 2/9,
+// coupled through phi = (N_a - N_b)/(N_a + N_b), C = grad phi and n = C/|C| to a D3Q19 MRT LBE
+// with the alpha|C| terms in the equilibria of the energy and stress moments and a constant body
+// force t_q xi_q.F / cs^2 (cs^2 = 1/3).
+//
+// Kernel design for MI355X:
+//  * Structure of arrays: population q of pore voxel i lives at X[q*ld + i]; one thread per pore
+//    voxel, so every wavefront touches 64 consecutive doubles per population (coalesced).
+//  * AA pattern in place (one copy of every population array). Even steps read the voxel's own
+//    slots and write the post-collision value of direction q into its own slot opp(q). Odd steps
+//    read incoming f_q from slot opp(q) of the upstream neighbour and write f*_q into slot q of
+//    the downstream neighbour. A solid (or out-of-domain) neighbour turns either access into the
+//    voxel's own opposite slot, which is halfway bounce-back. Each thread reads and writes the
+//    same set of addresses, so the pattern is race-free without a second buffer.
+//  * The MRT collision is evaluated in its two-relaxation-time form: the relaxation matrix has
+//    one rate (s+ = 1/tau) on every even moment and one rate (s- = 8(2-s+)/(8-s+)) on every odd
+//    one (the conserved moments have zero non-equilibrium part, so their rate is immaterial).
+//    For an orthogonal basis whose rows are each even or odd in xi this makes
+//    M^-1 S M = s+ P_even + s- P_odd, so the 19x19 transforms reduce to sums and differences of
+//    opposite pairs. The equilibrium in population space is the second-order polynomial plus the
+//    image of the alpha|C| moment terms under M^-1 (closed form below).
+//  * Workgroup -> tile mapping is XCD-aware: the hardware deals workgroups round-robin to the 8
+//    XCDs, so logical block b is taken by hardware block (b % per) * 8 + b / per. Each XCD then
+//    sweeps one contiguous slab of the pore list and its L2 keeps the phi planes that the
+//    gradient stencil re-reads.
+//  * No MFMA: nothing here is a dense contraction. The kernel is bound by HBM traffic.
+
+#include <cmath>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+// D3Q19 velocities (order: rest; +x -x +y -y +z -z; xy, xz, yz diagonals) and opposites.
+constexpr int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+constexpr double kCMin = 1e-10;   // smallest resolved colour-gradient magnitude
+
+__device__ __forceinline__ int logical_block(const StepArgs& a) {
+    const int b = blockIdx.x;
+    if (!a.xcd_remap) return b;
+    const int per = (int)(gridDim.x >> 3);  // gridDim.x is a multiple of 8 when remapping
+    return (b & 7) * per + (b >> 3);
+}
+
+// Neighbour of voxel i along direction q (1..18): pore index (< N) or N + tail index.
+__device__ __forceinline__ int nb(const StepArgs& a, int q, int i) {
+    return a.nbr[(size_t)(q - 1) * a.ld + i];
+}
+
+// Incoming population q of voxel i (D3Q19 or D3Q7 array X).
+template <bool ODD>
+__device__ __forceinline__ double load_in(const double* __restrict__ X, const StepArgs& a,
+                                          int q, int i, int r_up) {
+    if (!ODD || q == 0) return X[(size_t)q * a.ld + i];
+    // r_up: neighbour along opp(q), i.e. the upstream voxel i - xi_q.
+    return r_up < a.N ? X[(size_t)OPP[q] * a.ld + r_up] : X[(size_t)q * a.ld + i];
+}
+
+// Store the post-collision population q of voxel i.
+template <bool ODD>
+__device__ __forceinline__ void store_out(double* __restrict__ X, const StepArgs& a, int q, int i,
+                                          int r_down, double v) {
+    if (q == 0) {
+        X[i] = v;
+    } else if (!ODD) {
+        X[(size_t)OPP[q] * a.ld + i] = v;
+    } else {
+        // r_down: neighbour along q, the downstream voxel i + xi_q.
+        if (r_down < a.N)
+            X[(size_t)q * a.ld + r_down] = v;
+        else
+            X[(size_t)OPP[q] * a.ld + i] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Initial state: rest equilibrium, rho = 1, u = 0, N_a = (1 + phi0)/2, N_b = (1 - phi0)/2.
+// Natural layout (step 0 is even).
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __restrict__ phi0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    double* f = (double*)a.f;
+    double* A = (double*)a.A;
+    double* B = (double*)a.B;
+    const double na = 0.5 * (1.0 + phi0[i]), nbv = 0.5 * (1.0 - phi0[i]);
+#pragma unroll
+    for (int q = 0; q < 19; ++q)
+        f[(size_t)q * a.ld + i] = q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const double w = q == 0 ? 1.0 / 3.0 : 1.0 / 9.0;
+        A[(size_t)q * a.ld + i] = w * na;
+        B[(size_t)q * a.ld + i] = w * nbv;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Densities and phase indicator: N_a = sum_q A_q, N_b = sum_q B_q (q = 0..6) of the streamed-in
+// D3Q7 populations; phi = (N_a - N_b)/(N_a + N_b); N = N_a + N_b.
+// ------------------------------------------------------------------------------------------
+template <bool ODD>
+__global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
+    const int i = logical_block(a) * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    const double* A = (const double*)a.A;
+    const double* B = (const double*)a.B;
+    int up[7];
+#pragma unroll
+    for (int q = 1; q < 7; ++q) up[q] = ODD ? nb(a, OPP[q], i) : 0;
+    double na = 0.0, nbv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        na += load_in<ODD>(A, a, q, i, q ? up[q] : 0);
+        nbv += load_in<ODD>(B, a, q, i, q ? up[q] : 0);
+    }
+    const double nt = na + nbv;
+    a.phi[i] = (na - nbv) / nt;
+    a.ntot[i] = nt;
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused colour gradient + MRT collision with interfacial terms and body force + recolouring +
+// AA streaming.
+// ------------------------------------------------------------------------------------------
+template <bool ODD>
+__global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
+    const int i = logical_block(a) * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    double* f = (double*)a.f;
+    double* A = (double*)a.A;
+    double* B = (double*)a.B;
+
+    int r[19];
+    r[0] = i;
+#pragma unroll
+    for (int q = 1; q < 19; ++q) r[q] = nb(a, q, i);
+
+    // Colour gradient: weight 1 on the axis links and 1/2 on the diagonals, so that C -> 6 grad
+    // phi and the flat-interface tension is exactly 6 alpha. Each component is accumulated in
+    // increasing q, one term at a time: every product is exact (a power of two times phi), so
+    // the sum is the same correctly rounded chain in any implementation that keeps this order.
+    // That matters where |C| is small, since n = C/|C| amplifies a rounding difference in C.
+    const double* __restrict__ ph = a.phi;
+    double p[19];
+#pragma unroll
+    for (int q = 1; q < 19; ++q) p[q] = ph[r[q]];
+    double Cx = 0.0, Cy = 0.0, Cz = 0.0;
+#pragma unroll
+    for (int q = 1; q < 19; ++q) {
+        const double w = q < 7 ? 1.0 : 0.5;
+        if (CX[q]) Cx += (w * CX[q]) * p[q];
+        if (CY[q]) Cy += (w * CY[q]) * p[q];
+        if (CZ[q]) Cz += (w * CZ[q]) * p[q];
+    }
+    // |C| <= kCMin is an unresolved gradient (a cancellation whose residue is rounding): it
+    // counts as zero, so that n never takes a direction decided by rounding.
+    const double c2 = Cx * Cx + Cy * Cy + Cz * Cz;
+    const bool resolved = c2 > kCMin * kCMin;
+    const double cm = resolved ? sqrt(c2) : 0.0;
+    const double ic = resolved ? 1.0 / cm : 0.0;
+    const double nx = Cx * ic, ny = Cy * ic, nz = Cz * ic;
+
+    // Incoming populations.
+    double fl[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) fl[q] = load_in<ODD>(f, a, q, i, r[OPP[q]]);
+
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        rho += fl[q];
+        jx += CX[q] * fl[q];
+        jy += CY[q] * fl[q];
+        jz += CZ[q] * fl[q];
+    }
+    const double jj = jx * jx + jy * jy + jz * jz;
+
+    const double phi_i = ph[i];
+    const double nt = a.ntot[i];
+    const double nu = 0.5 * (1.0 + phi_i) * a.nu_a + 0.5 * (1.0 - phi_i) * a.nu_b;
+    const double sp = 1.0 / (3.0 * nu + 0.5);
+    const double sm = 8.0 * (2.0 - sp) / (8.0 - sp);
+
+    // Image of the alpha|C| equilibrium-moment terms in population space (even in xi):
+    // e-row -19 g, 3pxx (g/2)(3nx^2-1), pww (g/2)(ny^2-nz^2), pxy (g/2)nx ny, ... ; g = alpha|C|.
+    const double g = a.alpha * cm;
+    const double hxx = g * (3.0 * nx * nx - 1.0);
+    const double hww = g * (ny * ny - nz * nz);
+    const double d_rest = g * (5.0 / 21.0);
+    const double d_ax = g * (11.0 / 126.0);
+    const double d_dg = -g * (8.0 / 126.0);
+    const double dX = d_ax + hxx * (1.0 / 36.0);
+    const double dY = d_ax - hxx * (1.0 / 72.0) + hww * (1.0 / 24.0);
+    const double dZ = d_ax - hxx * (1.0 / 72.0) - hww * (1.0 / 24.0);
+    const double dXY = d_dg + hxx * (1.0 / 72.0) + hww * (1.0 / 24.0);
+    const double dXZ = d_dg + hxx * (1.0 / 72.0) - hww * (1.0 / 24.0);
+    const double dYZ = d_dg - hxx * (1.0 / 36.0);
+    const double gxy = g * nx * ny * 0.125, gxz = g * nx * nz * 0.125, gyz = g * ny * nz * 0.125;
+
+    // Even equilibrium part (per velocity class) and odd part 3 t xi.j.
+    const double base = rho - 1.5 * jj;
+    double fs[19];
+    fs[0] = fl[0] - sp * (fl[0] - ((1.0 / 3.0) * base + d_rest));
+#pragma unroll
+    for (int q = 1; q < 19; q += 2) {
+        const int qb = q + 1;
+        const double t = q < 7 ? 1.0 / 18.0 : 1.0 / 36.0;
+        const double ej = CX[q] * jx + CY[q] * jy + CZ[q] * jz;
+        const double ef = CX[q] * a.F[0] + CY[q] * a.F[1] + CZ[q] * a.F[2];
+        double dq;
+        if (q == 1) dq = dX;
+        else if (q == 3) dq = dY;
+        else if (q == 5) dq = dZ;
+        else if (q < 11) dq = dXY + gxy * (CX[q] * CY[q]);
+        else if (q < 15) dq = dXZ + gxz * (CX[q] * CZ[q]);
+        else dq = dYZ + gyz * (CY[q] * CZ[q]);
+        const double ep = t * (base + 4.5 * ej * ej) + dq;
+        const double em = 3.0 * t * ej;
+        const double fp = 0.5 * (fl[q] + fl[qb]);
+        const double fm = 0.5 * (fl[q] - fl[qb]);
+        const double rp = sp * (fp - ep);
+        const double rm = sm * (fm - em);
+        const double fo = 3.0 * t * ef;
+        fs[q] = fl[q] - rp - rm + fo;
+        fs[qb] = fl[qb] - rp + rm - fo;
+    }
+
+    // Recolouring with the flow velocity u = j + F/2 (rho0 = 1).
+    const double ux = jx + 0.5 * a.F[0], uy = jy + 0.5 * a.F[1], uz = jz + 0.5 * a.F[2];
+    const double na = 0.5 * nt * (1.0 + phi_i);
+    const double nbv = 0.5 * nt * (1.0 - phi_i);
+    const double seg = a.beta * na * nbv / nt;
+    double As[7], Bs[7];
+    As[0] = (1.0 / 3.0) * na;
+    Bs[0] = (1.0 / 3.0) * nbv;
+#pragma unroll
+    for (int q = 1; q < 7; ++q) {
+        const double eu = 4.5 * (CX[q] * ux + CY[q] * uy + CZ[q] * uz);
+        const double en = seg * (CX[q] * nx + CY[q] * ny + CZ[q] * nz);
+        As[q] = (1.0 / 9.0) * (na * (1.0 + eu) + en);
+        Bs[q] = (1.0 / 9.0) * (nbv * (1.0 + eu) - en);
+    }
+
+#pragma unroll
+    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, r[q], fs[q]);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        store_out<ODD>(A, a, q, i, r[q], As[q]);
+        store_out<ODD>(B, a, q, i, r[q], Bs[q]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Reductions (FP64, deterministic: fixed grid, fixed per-thread stride, fixed butterfly).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <bool ODD>
+__global__ void __launch_bounds__(kRedThreads) reduce_kernel(StepArgs a,
+                                                             double* __restrict__ partials) {
+    double acc[kNRed];
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) acc[k] = 0.0;
+    const double* f = (const double*)a.f;
+    const double* A = (const double*)a.A;
+    const double* B = (const double*)a.B;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
+        int r[19];
+        r[0] = i;
+#pragma unroll
+        for (int q = 1; q < 19; ++q) r[q] = ODD ? nb(a, q, i) : 0;
+        double na = 0.0, nbv = 0.0, rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            na += load_in<ODD>(A, a, q, i, r[OPP[q]]);
+            nbv += load_in<ODD>(B, a, q, i, r[OPP[q]]);
+        }
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const double v = load_in<ODD>(f, a, q, i, r[OPP[q]]);
+            rho += v;
+            jx += CX[q] * v;
+            jy += CY[q] * v;
+            jz += CZ[q] * v;
+        }
+        const double phi = (na - nbv) / (na + nbv);
+        const double u[3] = {jx + 0.5 * a.F[0], jy + 0.5 * a.F[1], jz + 0.5 * a.F[2]};
+        const bool bad = !(isfinite(na) && isfinite(nbv) && isfinite(rho) && isfinite(u[0]) &&
+                           isfinite(u[1]) && isfinite(u[2]));
+        const double wa = 0.5 * (1.0 + phi), wb = 0.5 * (1.0 - phi);
+        acc[0] += na;
+        acc[1] += nbv;
+        acc[2] += wa;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[5 + c] += u[c];
+            acc[8 + c] += wa * u[c];
+            acc[11 + c] += wb * u[c];
+        }
+        if (phi > 0.0) {
+            acc[3] += 1.0;
+            acc[14] += rho;
+            acc[22] += rho / 3.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[16 + c] += rho * u[c];
+        } else if (phi < 0.0) {
+            acc[4] += 1.0;
+            acc[15] += rho;
+            acc[23] += rho / 3.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[19 + c] += rho * u[c];
+        }
+        acc[24] += bad ? 1.0 : 0.0;
+    }
+    __shared__ double lds[kRedThreads / 64][kNRed];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) lds[wave][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNRed) {
+        double s = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w) s += lds[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * kNRed + threadIdx.x] = s;
+    }
+}
+
+__global__ void reduce_final_kernel(const double* __restrict__ partials, int nblocks,
+                                    double* __restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= kNRed) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * kNRed + k];
+    out[k] = s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Field read-back for pore voxels (pore order).
+// ------------------------------------------------------------------------------------------
+template <bool ODD>
+__global__ void __launch_bounds__(256) field_kernel(StepArgs a, int field,
+                                                    double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    int r[19];
+    r[0] = i;
+#pragma unroll
+    for (int q = 1; q < 19; ++q) r[q] = ODD ? nb(a, q, i) : 0;
+    double v = 0.0;
+    if (field <= LBM_FIELD_PHI) {
+        const double* A = (const double*)a.A;
+        const double* B = (const double*)a.B;
+        double na = 0.0, nbv = 0.0;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            na += load_in<ODD>(A, a, q, i, r[OPP[q]]);
+            nbv += load_in<ODD>(B, a, q, i, r[OPP[q]]);
+        }
+        v = field == LBM_FIELD_NA ? na : field == LBM_FIELD_NB ? nbv : (na - nbv) / (na + nbv);
+    } else {
+        const double* f = (const double*)a.f;
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const double fq = load_in<ODD>(f, a, q, i, r[OPP[q]]);
+            rho += fq;
+            jx += CX[q] * fq;
+            jy += CY[q] * fq;
+            jz += CZ[q] * fq;
+        }
+        switch (field) {
+        case LBM_FIELD_RHO: v = rho; break;
+        case LBM_FIELD_P: v = rho / 3.0; break;
+        case LBM_FIELD_UX: v = jx + 0.5 * a.F[0]; break;
+        case LBM_FIELD_UY: v = jy + 0.5 * a.F[1]; break;
+        default: v = jz + 0.5 * a.F[2]; break;
+        }
+    }
+    out[i] = v;
+}
+
+int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------
+hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s) {
+    hipLaunchKernelGGL(init_kernel, dim3(grid_for(a, 256)), dim3(256), 0, s, a, phi0);
+    (void)block;
+    return hipGetLastError();
+}
+
+hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s) {
+    const dim3 grid(a.xcd_remap ? ((a.nblocks + 7) / 8) * 8 : a.nblocks);
+    if (odd)
+        hipLaunchKernelGGL(phase_kernel<true>, grid, dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL(phase_kernel<false>, grid, dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s) {
+    const dim3 grid(a.xcd_remap ? ((a.nblocks + 7) / 8) * 8 : a.nblocks);
+    if (odd)
+        hipLaunchKernelGGL(collide_kernel<true>, grid, dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL(collide_kernel<false>, grid, dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
+                         hipStream_t s) {
+    if (odd)
+        hipLaunchKernelGGL(reduce_kernel<true>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a,
+                           partials);
+    else
+        hipLaunchKernelGGL(reduce_kernel<false>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a,
+                           partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, partials, kRedBlocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int block,
+                        hipStream_t s) {
+    const dim3 grid(grid_for(a, 256));
+    (void)block;
+    if (odd)
+        hipLaunchKernelGGL(field_kernel<true>, grid, dim3(256), 0, s, a, field, out);
+    else
+        hipLaunchKernelGGL(field_kernel<false>, grid, dim3(256), 0, s, a, field, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pressure_bc(const StepArgs&, bool, const int32_t*, int32_t, const int32_t*,
+                              int32_t, double, double, hipStream_t) {
+    return hipErrorNotSupported;
+}
+
+}  // namespace lbm

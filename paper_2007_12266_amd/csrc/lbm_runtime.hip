@@ -1,0 +1,501 @@
+// Runtime and C-ABI of the colour-LBM library: domain lifetime, device memory, stream, step
+// loop, reductions, read-back and checkpointing. Declarations and contracts: include/lbm.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(LBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr uint64_t kStateMagic = 0x4c424d434f4c5231ull;  // "LBMCOLR1"
+
+struct StateHeader {
+    uint64_t magic;
+    int64_t n_pore, n_tail, step;
+    int32_t precision, elem_bytes;
+};
+
+}  // namespace
+
+struct lbm_domain {
+    lbm_params p{};
+    Prepass pre;
+    int block = 256;
+    lbm_allocator alloc{};
+    bool has_alloc = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<void*> allocations;
+    int64_t device_bytes = 0;
+
+    void* f = nullptr;
+    void* A = nullptr;
+    void* B = nullptr;
+    double* phi = nullptr;
+    double* ntot = nullptr;
+    int32_t* nbr = nullptr;
+    double* red_partials = nullptr;
+    double* red_out = nullptr;
+    double* hist = nullptr;
+    int32_t hist_cap = 1024;
+    int32_t hist_head = 0;    // next slot to write
+    int32_t hist_count = 0;   // unread entries
+    std::vector<int64_t> hist_step;
+    int32_t* inlet = nullptr;
+    int32_t* outlet = nullptr;
+    int32_t* ghost_tail = nullptr;
+    int32_t* ghost_src = nullptr;
+
+    int64_t step = 0;
+    bool unstable = false;
+    bool xcd_remap = true;
+
+    StepArgs args() const {
+        StepArgs a{};
+        a.N = (int32_t)pre.n_pore;
+        a.nblocks = (int32_t)((pre.n_pore + block - 1) / block);
+        a.ld = pre.ld;
+        a.nbr = nbr;
+        a.phi = phi;
+        a.ntot = ntot;
+        a.f = f;
+        a.A = A;
+        a.B = B;
+        a.nu_a = (p.tau_a - 0.5) / 3.0;
+        a.nu_b = (p.tau_b - 0.5) / 3.0;
+        a.alpha = p.alpha;
+        a.beta = p.beta;
+        for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
+        a.xcd_remap = xcd_remap ? 1 : 0;
+        return a;
+    }
+
+    void* dalloc(size_t bytes) {
+        bytes = std::max<size_t>(bytes, 256);
+        void* ptr = nullptr;
+        if (has_alloc) {
+            ptr = alloc.alloc(bytes, alloc.ctx);
+        } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+            ptr = nullptr;
+        }
+        if (ptr) {
+            allocations.push_back(ptr);
+            device_bytes += (int64_t)bytes;
+        }
+        return ptr;
+    }
+
+    void release() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* ptr : allocations) {
+            if (has_alloc)
+                alloc.free(ptr, alloc.ctx);
+            else
+                (void)hipFree(ptr);
+        }
+        allocations.clear();
+        device_bytes = 0;
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+
+    size_t elem_bytes() const { return p.precision == LBM_FP32_DEV ? 4 : 8; }
+};
+
+namespace {
+
+lbm_status record_reduction(lbm_domain* d, double* out) {
+    const StepArgs a = d->args();
+    HIP_TRY(launch_reduce(a, (d->step & 1) != 0, d->red_partials, out, d->stream));
+    return LBM_OK;
+}
+
+void finish_reduction(const lbm_domain* d, const double* acc, int64_t step, lbm_reduction* r) {
+    const double N = (double)d->pre.n_pore;
+    const double nbox = (double)d->p.nx * d->p.ny * d->p.nz;
+    std::memset(r, 0, sizeof *r);
+    r->mass_a = acc[0];
+    r->mass_b = acc[1];
+    r->sw = acc[2] / N;
+    r->sw_count = acc[3] / N;
+    for (int c = 0; c < 3; ++c) {
+        r->flux[c] = acc[5 + c] / nbox;
+        r->flux_a[c] = acc[8 + c] / nbox;
+        r->flux_b[c] = acc[11 + c] / nbox;
+    }
+    r->p_a = acc[3] > 0 ? acc[22] / acc[3] : 0.0;
+    r->p_b = acc[4] > 0 ? acc[23] / acc[4] : 0.0;
+    const double nu_a = (d->p.tau_a - 0.5) / 3.0, nu_b = (d->p.tau_b - 0.5) / 3.0;
+    const double Ua = acc[14] > 0 ? std::sqrt(acc[16] * acc[16] + acc[17] * acc[17] +
+                                              acc[18] * acc[18]) / acc[14] : 0.0;
+    const double Ub = acc[15] > 0 ? std::sqrt(acc[19] * acc[19] + acc[20] * acc[20] +
+                                              acc[21] * acc[21]) / acc[15] : 0.0;
+    const double sigma = 6.0 * d->p.alpha;
+    r->ca = sigma > 0 ? ((acc[3] / nbox) * nu_a * Ua + (acc[4] / nbox) * nu_b * Ub) / sigma : 0.0;
+    r->n_pore = d->pre.n_pore;
+    r->step = step;
+    r->unstable = acc[24] > 0 ? 1 : 0;
+}
+
+lbm_status check_domain(lbm_domain* d) {
+    if (!d) return fail(LBM_ERR_ARG, "null domain");
+    return LBM_OK;
+}
+
+lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
+    if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
+    if (d->unstable) return fail(LBM_ERR_UNSTABLE, "domain is unstable; load a state");
+    std::vector<hipEvent_t> ev;
+    auto mark = [&](hipEvent_t* out) -> hipError_t {
+        hipError_t e = hipEventCreate(out);
+        if (e != hipSuccess) return e;
+        ev.push_back(*out);
+        return hipEventRecord(*out, d->stream);
+    };
+    struct Span { hipEvent_t a, b; int kind; };
+    std::vector<Span> spans;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (timing) {
+        std::memset(timing, 0, sizeof *timing);
+        HIP_TRY(mark(&t0));
+    }
+    lbm_status st = LBM_OK;
+    for (int64_t s = 0; s < nsteps && st == LBM_OK; ++s) {
+        const StepArgs a = d->args();
+        const bool odd = (d->step & 1) != 0;
+        Span sp{};
+        if (timing) { sp.kind = 0; HIP_TRY(mark(&sp.a)); }
+        HIP_TRY(launch_phase(a, odd, d->block, d->stream));
+        if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); sp.kind = 1; HIP_TRY(mark(&sp.a)); }
+        HIP_TRY(launch_collide(a, odd, d->block, d->stream));
+        if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
+        if (d->p.bc_z == 1) {
+            if (timing) { sp.kind = 2; HIP_TRY(mark(&sp.a)); }
+            HIP_TRY(launch_pressure_bc(a, odd, d->inlet, (int32_t)d->pre.inlet.size(),
+                                       d->outlet, (int32_t)d->pre.outlet.size(), d->p.rho_in,
+                                       d->p.rho_out, d->stream));
+            if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
+        }
+        d->step += 1;
+        if (d->p.reduce_every > 0 && d->step % d->p.reduce_every == 0) {
+            const int slot = d->hist_head;
+            st = record_reduction(d, d->hist + (size_t)slot * kNRed);
+            d->hist_step[slot] = d->step;
+            d->hist_head = (d->hist_head + 1) % d->hist_cap;
+            d->hist_count = std::min(d->hist_count + 1, d->hist_cap);
+        }
+    }
+    if (timing) {
+        HIP_TRY(mark(&t1));
+        HIP_TRY(hipEventSynchronize(t1));
+        double sum[3] = {0, 0, 0};
+        int64_t cnt[3] = {0, 0, 0};
+        for (const Span& sp : spans) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, sp.a, sp.b));
+            sum[sp.kind] += ms;
+            cnt[sp.kind] += 1;
+        }
+        float tot = 0.f;
+        HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
+        timing->phase_ms = cnt[0] ? sum[0] / cnt[0] : 0.0;
+        timing->collide_ms = cnt[1] ? sum[1] / cnt[1] : 0.0;
+        timing->bc_ms = cnt[2] ? sum[2] / cnt[2] : 0.0;
+        timing->step_ms = nsteps ? tot / nsteps : 0.0;
+        timing->phase_launches = cnt[0];
+        timing->collide_launches = cnt[1];
+        timing->bc_launches = cnt[2];
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+const char* lbm_version(void) { return "colorlbm-gfx950 0.1"; }
+
+lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, int32_t n_labels,
+                             const int8_t* label_kind, const double* label_affinity,
+                             const double* voxel_affinity, const double* init_phi,
+                             const lbm_allocator* alloc, void* hip_stream, lbm_domain** out) {
+    g_err.clear();
+    if (!params || !out) return fail(LBM_ERR_ARG, "params and out must be non-null");
+    *out = nullptr;
+    const lbm_params& p = *params;
+    if (!(p.tau_a > 0.5) || !(p.tau_b > 0.5)) return fail(LBM_ERR_ARG, "tau must exceed 1/2");
+    if (!(p.beta > 0.0 && p.beta < 1.0)) return fail(LBM_ERR_ARG, "beta must lie in (0, 1)");
+    if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return fail(LBM_ERR_ARG, "alpha must be >= 0");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(p.force[c])) return fail(LBM_ERR_ARG, "force must be finite");
+    if (p.precision != LBM_FP64)
+        return fail(LBM_ERR_ARG, "precision not supported by this build");
+    if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
+        return fail(LBM_ERR_ARG, "rho_in and rho_out must be positive");
+    if (p.bc_z == 1) return fail(LBM_ERR_ARG, "pressure faces are not supported by this build");
+    if (p.reduce_every < 0) return fail(LBM_ERR_ARG, "reduce_every must be >= 0");
+    int block = p.block_size == 0 ? 256 : p.block_size;
+    if (block != 64 && block != 128 && block != 256)
+        return fail(LBM_ERR_ARG, "block_size must be 0, 64, 128 or 256");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(LBM_ERR_ARG, "allocator needs both alloc and free");
+
+    std::unique_ptr<lbm_domain> d(new (std::nothrow) lbm_domain());
+    if (!d) return fail(LBM_ERR_OOM, "host allocation failed");
+    d->p = p;
+    d->block = block;
+    std::string err = prepass(p, labels, n_labels, label_kind, label_affinity, voxel_affinity,
+                              init_phi, d->pre);
+    if (!err.empty()) return fail(LBM_ERR_ARG, err);
+    if (alloc) {
+        d->alloc = *alloc;
+        d->has_alloc = true;
+    }
+    if (hip_stream) {
+        d->stream = (hipStream_t)hip_stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking));
+        d->own_stream = true;
+    }
+    const Prepass& pre = d->pre;
+    const size_t eb = d->elem_bytes();
+    const size_t ld = (size_t)pre.ld;
+    d->f = d->dalloc(eb * 19 * ld);
+    d->A = d->dalloc(eb * 7 * ld);
+    d->B = d->dalloc(eb * 7 * ld);
+    d->phi = (double*)d->dalloc(sizeof(double) * (size_t)(pre.n_pore + pre.n_tail));
+    d->ntot = (double*)d->dalloc(sizeof(double) * ld);
+    d->nbr = (int32_t*)d->dalloc(sizeof(int32_t) * 18 * ld);
+    d->red_partials = (double*)d->dalloc(sizeof(double) * kRedBlocks * kNRed);
+    d->red_out = (double*)d->dalloc(sizeof(double) * kNRed);
+    d->hist = (double*)d->dalloc(sizeof(double) * (size_t)d->hist_cap * kNRed);
+    // The initial phase is staged in ntot, which the first phase kernel overwrites.
+    double* phi0 = d->ntot;
+    if (!d->f || !d->A || !d->B || !d->phi || !d->ntot || !d->nbr || !d->red_partials ||
+        !d->red_out || !d->hist) {
+        d->release();
+        return fail(LBM_ERR_OOM, "device allocation failed");
+    }
+    d->hist_step.assign(d->hist_cap, 0);
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, d->stream)
+                     : hipSuccess;
+    };
+    lbm_status st = LBM_OK;
+    auto guard = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && st == LBM_OK)
+            st = fail(LBM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    guard(up(d->nbr, pre.nbr.data(), sizeof(int32_t) * pre.nbr.size()), "upload nbr");
+    guard(up(d->phi + pre.n_pore, pre.tail_phi.data(), sizeof(double) * pre.n_tail),
+          "upload tail");
+    guard(up(phi0, pre.phi0.data(), sizeof(double) * pre.n_pore), "upload phi0");
+    guard(hipMemsetAsync(d->f, 0, eb * 19 * ld, d->stream), "clear f");
+    guard(hipMemsetAsync(d->A, 0, eb * 7 * ld, d->stream), "clear A");
+    guard(hipMemsetAsync(d->B, 0, eb * 7 * ld, d->stream), "clear B");
+    if (st == LBM_OK) guard(launch_init(d->args(), phi0, d->block, d->stream), "init kernel");
+    if (st == LBM_OK) guard(hipStreamSynchronize(d->stream), "create sync");
+    if (st != LBM_OK) {
+        d->release();
+        return st;
+    }
+    *out = d.release();
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_domain* d, int64_t nsteps) {
+    if (lbm_status s = check_domain(d)) return s;
+    return step_impl(d, nsteps, nullptr);
+}
+
+lbm_status lbm_step_timed(lbm_domain* d, int64_t nsteps, lbm_timing* out) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!out) return fail(LBM_ERR_ARG, "out must be non-null");
+    return step_impl(d, nsteps, out);
+}
+
+lbm_status lbm_read_pore_field(lbm_domain* d, int32_t field, double* host_pore) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (field < LBM_FIELD_NA || field > LBM_FIELD_UZ) return fail(LBM_ERR_ARG, "bad field id");
+    if (!host_pore) return fail(LBM_ERR_ARG, "host_pore must be non-null");
+    const StepArgs a = d->args();
+    // ntot doubles as the staging buffer: the next step's phase kernel rewrites it first.
+    HIP_TRY(launch_field(a, (d->step & 1) != 0, field, d->ntot, d->block, d->stream));
+    HIP_TRY(hipMemcpyAsync(host_pore, d->ntot, sizeof(double) * d->pre.n_pore,
+                           hipMemcpyDeviceToHost, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_read_field(lbm_domain* d, int32_t field, double* host_dense) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!host_dense) return fail(LBM_ERR_ARG, "host_dense must be non-null");
+    std::vector<double> tmp((size_t)d->pre.n_pore);
+    if (lbm_status s = lbm_read_pore_field(d, field, tmp.data())) return s;
+    const int64_t nvox = (int64_t)d->p.nx * d->p.ny * d->p.nz;
+    std::fill(host_dense, host_dense + nvox, std::nan(""));
+    for (int64_t i = 0; i < d->pre.n_pore; ++i) host_dense[d->pre.pore_voxel[i]] = tmp[i];
+    return LBM_OK;
+}
+
+lbm_status lbm_pore_index(lbm_domain* d, int64_t* host_index) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!host_index) return fail(LBM_ERR_ARG, "host_index must be non-null");
+    std::copy(d->pre.pore_voxel.begin(), d->pre.pore_voxel.end(), host_index);
+    return LBM_OK;
+}
+
+lbm_status lbm_reduce(lbm_domain* d, lbm_reduction* out) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!out) return fail(LBM_ERR_ARG, "out must be non-null");
+    if (lbm_status s = record_reduction(d, d->red_out)) return s;
+    double acc[kNRed];
+    HIP_TRY(hipMemcpyAsync(acc, d->red_out, sizeof acc, hipMemcpyDeviceToHost, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    finish_reduction(d, acc, d->step, out);
+    if (out->unstable) d->unstable = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_read_history(lbm_domain* d, lbm_reduction* out, int32_t max_count,
+                            int32_t* count) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!count || (max_count > 0 && !out)) return fail(LBM_ERR_ARG, "null output");
+    const int32_t n = std::min(std::max(max_count, 0), d->hist_count);
+    std::vector<double> acc((size_t)d->hist_cap * kNRed);
+    HIP_TRY(hipMemcpyAsync(acc.data(), d->hist, sizeof(double) * acc.size(),
+                           hipMemcpyDeviceToHost, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    const int32_t first = (d->hist_head - d->hist_count + d->hist_cap) % d->hist_cap;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t slot = (first + k) % d->hist_cap;
+        finish_reduction(d, &acc[(size_t)slot * kNRed], d->hist_step[slot], &out[k]);
+        if (out[k].unstable) d->unstable = true;
+    }
+    d->hist_count -= n;
+    *count = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!nbytes) return fail(LBM_ERR_ARG, "nbytes must be non-null");
+    const size_t eb = d->elem_bytes();
+    const size_t n = (size_t)d->pre.n_pore, ld = (size_t)d->pre.ld;
+    const size_t need = sizeof(StateHeader) + eb * 33 * n;
+    if (!host_buf) {
+        *nbytes = need;
+        return LBM_OK;
+    }
+    if (*nbytes < need) return fail(LBM_ERR_ARG, "state buffer too small");
+    StateHeader h{kStateMagic, d->pre.n_pore, d->pre.n_tail, d->step, d->p.precision, (int32_t)eb};
+    std::memcpy(host_buf, &h, sizeof h);
+    char* dst = (char*)host_buf + sizeof h;
+    const void* arrays[3] = {d->f, d->A, d->B};
+    const int rows[3] = {19, 7, 7};
+    for (int k = 0; k < 3; ++k) {
+        HIP_TRY(hipMemcpy2DAsync(dst, eb * n, arrays[k], eb * ld, eb * n, rows[k],
+                                 hipMemcpyDeviceToHost, d->stream));
+        dst += eb * n * rows[k];
+    }
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    *nbytes = need;
+    return LBM_OK;
+}
+
+lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!host_buf) return fail(LBM_ERR_ARG, "host_buf must be non-null");
+    const size_t eb = d->elem_bytes();
+    const size_t n = (size_t)d->pre.n_pore, ld = (size_t)d->pre.ld;
+    StateHeader h;
+    if (nbytes < sizeof h) return fail(LBM_ERR_STATE, "state buffer too small");
+    std::memcpy(&h, host_buf, sizeof h);
+    if (h.magic != kStateMagic || h.n_pore != d->pre.n_pore || h.n_tail != d->pre.n_tail ||
+        h.precision != d->p.precision || h.elem_bytes != (int32_t)eb ||
+        nbytes != sizeof h + eb * 33 * n)
+        return fail(LBM_ERR_STATE, "state does not match this domain");
+    const char* src = (const char*)host_buf + sizeof h;
+    void* arrays[3] = {d->f, d->A, d->B};
+    const int rows[3] = {19, 7, 7};
+    for (int k = 0; k < 3; ++k) {
+        HIP_TRY(hipMemcpy2DAsync(arrays[k], eb * ld, src, eb * n, eb * n, rows[k],
+                                 hipMemcpyHostToDevice, d->stream));
+        src += eb * n * rows[k];
+    }
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    d->step = h.step;
+    d->unstable = false;
+    d->hist_count = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!out) return fail(LBM_ERR_ARG, "out must be non-null");
+    out->n_pore = d->pre.n_pore;
+    out->n_solid_tail = d->pre.n_tail;
+    out->ld = d->pre.ld;
+    out->device_bytes = d->device_bytes;
+    out->step = d->step;
+    out->precision = d->p.precision;
+    out->block_size = d->block;
+    return LBM_OK;
+}
+
+lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, int32_t n_labels,
+                             const int8_t* label_kind, const double* label_affinity,
+                             const double* voxel_affinity, const double* init_phi,
+                             int64_t* n_pore, int64_t* n_tail, int64_t* pore_voxel,
+                             int32_t* nbr, double* tail_phi) {
+    g_err.clear();
+    if (!params || !n_pore || !n_tail) return fail(LBM_ERR_ARG, "null argument");
+    Prepass pre;
+    std::string err = prepass(*params, labels, n_labels, label_kind, label_affinity,
+                              voxel_affinity, init_phi, pre);
+    if (!err.empty()) return fail(LBM_ERR_ARG, err);
+    *n_pore = pre.n_pore;
+    *n_tail = pre.n_tail;
+    if (pore_voxel) std::copy(pre.pore_voxel.begin(), pre.pore_voxel.end(), pore_voxel);
+    if (nbr)
+        for (int q = 0; q < 18; ++q)
+            std::copy(pre.nbr.begin() + (size_t)q * pre.ld,
+                      pre.nbr.begin() + (size_t)q * pre.ld + pre.n_pore,
+                      nbr + (size_t)q * pre.n_pore);
+    if (tail_phi) std::copy(pre.tail_phi.begin(), pre.tail_phi.end(), tail_phi);
+    return LBM_OK;
+}
+
+lbm_status lbm_domain_destroy(lbm_domain* d) {
+    if (!d) return LBM_OK;
+    d->release();
+    delete d;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+"""Thin ctypes binding of the colour-LBM C-ABI (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of liblbm.so. The
+library must have been built (``python -m paper_2007_12266_amd.build``); loading fails loudly
+otherwise. PyTorch, when present, provides the device memory (through the caching allocator) and
+the stream; it never computes anything here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE, LBM_ERR_STATE = range(6)
+FP64, FP32_DEV = 0, 1
+FIELDS = {"Na": 0, "Nb": 1, "phi": 2, "rho": 3, "p": 4, "ux": 5, "uy": 6, "uz": 7}
+
+# Every symbol include/lbm.h declares.
+EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
+           "lbm_read_pore_field", "lbm_pore_index", "lbm_reduce", "lbm_read_history",
+           "lbm_state_save", "lbm_state_load", "lbm_domain_get_info", "lbm_domain_destroy",
+           "lbm_prepass_query", "lbm_last_error", "lbm_version")
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("lbm status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("periodic", ctypes.c_int32 * 3),
+                ("tau_a", ctypes.c_double), ("tau_b", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("force", ctypes.c_double * 3), ("wall_affinity", ctypes.c_double),
+                ("bc_z", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("reduce_every", ctypes.c_int32), ("block_size", ctypes.c_int32)]
+
+
+class Reduction(ctypes.Structure):
+    _fields_ = [("mass_a", ctypes.c_double), ("mass_b", ctypes.c_double),
+                ("sw", ctypes.c_double), ("sw_count", ctypes.c_double),
+                ("flux", ctypes.c_double * 3), ("flux_a", ctypes.c_double * 3),
+                ("flux_b", ctypes.c_double * 3), ("p_a", ctypes.c_double),
+                ("p_b", ctypes.c_double), ("ca", ctypes.c_double),
+                ("n_pore", ctypes.c_int64), ("step", ctypes.c_int64),
+                ("unstable", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {"mass_a": self.mass_a, "mass_b": self.mass_b, "sw": self.sw,
+             "sw_count": self.sw_count, "p_a": self.p_a, "p_b": self.p_b, "ca": self.ca,
+             "n_pore": self.n_pore, "step": self.step, "unstable": self.unstable}
+        for name, arr in (("q", self.flux), ("qa", self.flux_a), ("qb", self.flux_b)):
+            for c, ax in enumerate("xyz"):
+                d[name + ax] = arr[c]
+        return d
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("phase_ms", ctypes.c_double), ("collide_ms", ctypes.c_double),
+                ("bc_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
+                ("phase_launches", ctypes.c_int64), ("collide_launches", ctypes.c_int64),
+                ("bc_launches", ctypes.c_int64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_pore", ctypes.c_int64), ("n_solid_tail", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("step", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("block_size", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("liblbm.so is not built (%s); run "
+                           "`python -m paper_2007_12266_amd.build`" % path)
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    L.lbm_domain_create.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, vp, vp,
+                                    ctypes.POINTER(Allocator), vp, ctypes.POINTER(vp)]
+    L.lbm_step.argtypes = [vp, i64]
+    L.lbm_step_timed.argtypes = [vp, i64, ctypes.POINTER(Timing)]
+    L.lbm_read_field.argtypes = [vp, i32, dp]
+    L.lbm_read_pore_field.argtypes = [vp, i32, dp]
+    L.lbm_pore_index.argtypes = [vp, vp]
+    L.lbm_reduce.argtypes = [vp, ctypes.POINTER(Reduction)]
+    L.lbm_read_history.argtypes = [vp, ctypes.POINTER(Reduction), i32, ctypes.POINTER(i32)]
+    L.lbm_state_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.lbm_state_load.argtypes = [vp, vp, ctypes.c_size_t]
+    L.lbm_domain_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.lbm_domain_destroy.argtypes = [vp]
+    L.lbm_prepass_query.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, vp, vp,
+                                    ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    L.lbm_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("lbm_last_error", "lbm_version"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != LBM_OK:
+        raise LbmError(status, load_library().lbm_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def make_params(problem, precision: int = FP64, reduce_every: int = 0,
+                block_size: int = 0) -> Params:
+    """lbm_params of an ``inputs.Problem``."""
+    p = Params()
+    p.nz, p.ny, p.nx = problem.shape
+    for a in range(3):
+        p.periodic[a] = 1 if problem.periodic[a] else 0
+        p.force[a] = float(problem.force[a])
+    p.tau_a, p.tau_b = problem.tau_a, problem.tau_b
+    p.alpha, p.beta = problem.alpha, problem.beta
+    p.wall_affinity = problem.wall_affinity
+    p.bc_z = problem.bc_z
+    p.precision = precision
+    p.rho_in, p.rho_out = problem.rho_in, problem.rho_out
+    p.reduce_every = reduce_every
+    p.block_size = block_size
+    return p
+
+
+def _problem_arrays(problem):
+    labels = np.ascontiguousarray(problem.labels, dtype=np.int32)
+    kind = np.ascontiguousarray(problem.label_kind, dtype=np.int8)
+    aff = np.ascontiguousarray(problem.label_affinity, dtype=np.float64)
+    vaff = None if problem.voxel_affinity is None else np.ascontiguousarray(
+        problem.voxel_affinity, dtype=np.float64)
+    iphi = None if problem.init_phi is None else np.ascontiguousarray(
+        problem.init_phi, dtype=np.float64)
+    return labels, kind, aff, vaff, iphi
+
+
+def prepass_query(problem) -> dict:
+    """Host-only pre-pass of a problem: pore list, neighbour table [18, N] and phi tail."""
+    L = load_library()
+    p = make_params(problem)
+    labels, kind, aff, vaff, iphi = _problem_arrays(problem)
+    n, t = ctypes.c_int64(), ctypes.c_int64()
+    args = (ctypes.byref(p), _ptr(labels), int(aff.size), _ptr(kind), _ptr(aff), _ptr(vaff),
+            _ptr(iphi), ctypes.byref(n), ctypes.byref(t))
+    _check(L.lbm_prepass_query(*args, None, None, None))
+    pv = np.empty(n.value, dtype=np.int64)
+    nbr = np.empty((18, n.value), dtype=np.int32)
+    tail = np.empty(t.value, dtype=np.float64)
+    _check(L.lbm_prepass_query(*args, _ptr(pv), _ptr(nbr), _ptr(tail)))
+    return {"n_pore": n.value, "n_tail": t.value, "pore_voxel": pv, "nbr": nbr,
+            "tail_phi": tail}
+
+
+class _TorchAllocator:
+    """Device memory from PyTorch's caching allocator on a given stream."""
+
+    def __init__(self, stream):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = stream
+        self._alloc = ALLOC_FN(self._do_alloc)
+        self._free = FREE_FN(self._do_free)
+        self.struct = Allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, ctx):
+        try:
+            return int(self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                               self.stream))
+        except Exception:
+            return None
+
+    def _do_free(self, ptr, ctx):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+class Domain:
+    """One colour-LBM domain on the GPU (wraps lbm_domain*)."""
+
+    def __init__(self, problem, precision: int = FP64, reduce_every: int = 0,
+                 block_size: int = 0, allocator: str = "torch", stream=None):
+        L = load_library()
+        self.problem = problem
+        self.shape = problem.shape
+        p = make_params(problem, precision, reduce_every, block_size)
+        self.params = p
+        labels, kind, aff, vaff, iphi = _problem_arrays(problem)
+        self._torch_alloc = None
+        stream_handle = None
+        if stream is not None:
+            stream_handle = ctypes.c_void_p(stream)
+        if allocator == "torch":
+            import torch
+            s = torch.cuda.current_stream() if stream is None else None
+            handle = stream if stream is not None else s.cuda_stream
+            self._torch_alloc = _TorchAllocator(handle)
+            stream_handle = ctypes.c_void_p(handle)
+        h = ctypes.c_void_p()
+        _check(L.lbm_domain_create(ctypes.byref(p), _ptr(labels), int(aff.size), _ptr(kind),
+                                   _ptr(aff), _ptr(vaff), _ptr(iphi),
+                                   ctypes.byref(self._torch_alloc.struct)
+                                   if self._torch_alloc else None,
+                                   stream_handle, ctypes.byref(h)))
+        self.handle = h
+        info = self.info()
+        self.n_pore = info["n_pore"]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().lbm_domain_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int):
+        _check(load_library().lbm_step(self.handle, int(n)))
+        return self
+
+    def step_timed(self, n: int) -> dict:
+        t = Timing()
+        _check(load_library().lbm_step_timed(self.handle, int(n), ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in Timing._fields_}
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float64)
+        _check(load_library().lbm_read_field(self.handle, FIELDS[name], _ptr(out)))
+        return out
+
+    def pore_field(self, name: str) -> np.ndarray:
+        out = np.empty(self.n_pore, dtype=np.float64)
+        _check(load_library().lbm_read_pore_field(self.handle, FIELDS[name], _ptr(out)))
+        return out
+
+    def pore_index(self) -> np.ndarray:
+        out = np.empty(self.n_pore, dtype=np.int64)
+        _check(load_library().lbm_pore_index(self.handle, _ptr(out)))
+        return out
+
+    def fields(self) -> dict:
+        return {k: self.field(k) for k in FIELDS}
+
+    def reduce(self) -> dict:
+        r = Reduction()
+        _check(load_library().lbm_reduce(self.handle, ctypes.byref(r)))
+        return r.as_dict()
+
+    def history(self, max_count: int = 4096) -> list:
+        arr = (Reduction * max_count)()
+        n = ctypes.c_int32()
+        _check(load_library().lbm_read_history(self.handle, arr, max_count, ctypes.byref(n)))
+        return [arr[k].as_dict() for k in range(n.value)]
+
+    def save(self) -> bytes:
+        L = load_library()
+        n = ctypes.c_size_t()
+        _check(L.lbm_state_save(self.handle, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(L.lbm_state_save(self.handle, buf, ctypes.byref(n)))
+        return buf.raw
+
+    def load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(load_library().lbm_state_load(self.handle, buf, len(blob)))
+        return self
+
+    def info(self) -> dict:
+        i = Info()
+        _check(load_library().lbm_domain_get_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}

@@ -1,0 +1,126 @@
+"""Host-side checks of the C-ABI library (no GPU): exports, pre-pass layout, argument errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2007_12266_amd import inputs, lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.load_library()
+    declared = _declared_symbols()
+    assert "lbm_domain_create" in declared and len(declared) >= 10
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(lbm.EXPORTS)
+    assert L.lbm_version().decode().startswith("colorlbm")
+
+
+def _random_problem(shape, periodic, seed, frac=0.3, per_voxel=True):
+    rng = np.random.default_rng(seed)
+    solid = (rng.random(shape) < frac).astype(np.uint8)
+    labels = np.where(solid > 0, 0, 1).astype(np.int32)
+    p = inputs.Problem(labels=labels,
+                       label_kind=np.array([inputs.KIND_SOLID, inputs.KIND_PORE_INIT], np.int8),
+                       label_affinity=np.array([0.25, 0.0]),
+                       init_phi=np.where(rng.random(shape) < 0.5, 1.0, -1.0),
+                       periodic=periodic, wall_affinity=-0.4)
+    if per_voxel:
+        p.voxel_affinity = rng.uniform(-1, 1, shape)
+    return p
+
+
+XI = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+      (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+      (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+
+
+@pytest.mark.parametrize("periodic", [(True, True, True), (True, True, False),
+                                      (False, True, False), (False, False, False)])
+@pytest.mark.parametrize("per_voxel", [True, False])
+def test_prepass_matches_dense_lookup(periodic, per_voxel):
+    shape = (7, 9, 11)
+    prob = _random_problem(shape, periodic, seed=sum(periodic) + 10 * per_voxel,
+                           per_voxel=per_voxel)
+    res = lbm.prepass_query(prob)
+    solid = prob.solid_mask()
+    nz, ny, nx = shape
+    pore_dense = np.flatnonzero(solid.ravel() == 0)
+    assert np.array_equal(res["pore_voxel"], pore_dense)     # dense (x fastest) order
+    n = res["n_pore"]
+    index = -np.ones(solid.size, np.int64)
+    index[pore_dense] = np.arange(n)
+    tail = res["tail_phi"]
+    assert tail[0] == prob.wall_affinity
+    phi_s = prob.solid_affinity().ravel()
+    seen_tail = {}
+    for i, v in enumerate(pore_dense):
+        z, y, x = np.unravel_index(v, shape)
+        for q in range(1, 19):
+            c = [x + XI[q][0], y + XI[q][1], z + XI[q][2]]
+            out = False
+            for a, dim in enumerate((nx, ny, nz)):
+                if not 0 <= c[a] < dim:
+                    if periodic[a]:
+                        c[a] %= dim
+                    else:
+                        out = True
+            e = res["nbr"][q - 1, i]
+            if out:
+                assert e == n, (i, q)
+                continue
+            w = c[0] + nx * (c[1] + ny * c[2])
+            if solid.ravel()[w] == 0:
+                assert e == index[w]
+            else:
+                assert e > n and tail[e - n] == phi_s[w]
+                assert seen_tail.setdefault(w, e) == e          # one tail entry per solid
+    assert len(set(seen_tail.values())) == len(seen_tail)
+
+
+def test_prepass_rejects_bad_inputs():
+    prob = _random_problem((4, 4, 4), (True, True, True), seed=1)
+    bad = inputs.Problem(**{**prob.__dict__})
+    bad.labels = prob.labels.copy()
+    bad.labels[0, 0, 0] = 7
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.prepass_query(bad)
+    assert e.value.status == lbm.LBM_ERR_ARG and "out of range" in str(e.value)
+    allsolid = inputs.Problem(**{**prob.__dict__})
+    allsolid.labels = np.zeros_like(prob.labels)
+    with pytest.raises(lbm.LbmError, match="no pore voxel"):
+        lbm.prepass_query(allsolid)
+    noinit = inputs.Problem(**{**prob.__dict__})
+    noinit.init_phi = None
+    with pytest.raises(lbm.LbmError, match="init_phi"):
+        lbm.prepass_query(noinit)
+    badaff = inputs.Problem(**{**prob.__dict__})
+    badaff.voxel_affinity = np.full(prob.shape, 1.5)
+    with pytest.raises(lbm.LbmError, match="outside"):
+        lbm.prepass_query(badaff)
+
+
+def test_create_validates_parameters_before_touching_the_device():
+    L = lbm.load_library()
+    prob = _random_problem((4, 4, 4), (True, True, True), seed=2)
+    labels, kind, aff, vaff, iphi = lbm._problem_arrays(prob)
+    for field, value, msg in (("tau_a", 0.5, b"tau"), ("beta", 1.0, b"beta"),
+                              ("block_size", 96, b"block_size"), ("precision", 7, b"precision")):
+        p = lbm.make_params(prob)
+        setattr(p, field, value)
+        h = ctypes.c_void_p()
+        st = L.lbm_domain_create(ctypes.byref(p), lbm._ptr(labels), 2, lbm._ptr(kind),
+                                 lbm._ptr(aff), lbm._ptr(vaff), lbm._ptr(iphi), None, None,
+                                 ctypes.byref(h))
+        assert st == lbm.LBM_ERR_ARG and msg in L.lbm_last_error() and not h.value

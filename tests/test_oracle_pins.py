@@ -255,8 +255,8 @@ def test_flat_interface_tension_is_six_alpha():
     assert np.ptp(fl["rho"]) < 1e-13
     # Profile: close to the continuum tanh(beta (x - x0)) of the equilibrium interface equation.
     x = np.arange(phi.size)
-    i = np.argmin(np.abs(phi[: phi.size // 2]))
-    x0 = i + phi[i] / (phi[i] - phi[i + 1]) if phi[i] * phi[i + 1] < 0 else i
+    i = int(np.flatnonzero(phi[:-1] * phi[1:] < 0)[0])      # first sign change: + to -
+    x0 = i + phi[i] / (phi[i] - phi[i + 1])
     prof = -np.tanh(beta * (x[: phi.size // 2] - x0))
     assert np.abs(prof - phi[: phi.size // 2]).max() < 0.2
 
