@@ -55,22 +55,56 @@ def log(msg):
 
 def cpu_baseline(prob, budget_s: float = 15.0) -> dict:
     """The FP64 CPU oracle (dense grid, OpenMP) on the same workload, for a bounded number of
-    steps (about budget_s of CPU time)."""
+    steps sized to take about budget_s."""
     import oracle as O
     st = O.state_for(prob)
+    st.run(1)                                    # first touch of the oracle's buffers
     t0 = time.perf_counter()
-    st.run(1)
-    t1 = time.perf_counter() - t0
-    steps = max(1, min(50, int(budget_s / max(t1, 1e-3))))
+    st.run(2)
+    per_step = (time.perf_counter() - t0) / 2
+    steps = max(2, min(200, int(budget_s / max(per_step, 1e-3))))
     t0 = time.perf_counter()
     st.run(steps)
     dt = time.perf_counter() - t0
     n = prob.n_pore()
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS (pore voxels)",
+    return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS (pore voxels)",
             "cores": O.threads(), "kind": "oracle",
-            "sample": "same %s rock, %d FP64 steps after 1 warm-up step, dense C oracle, "
-                      "%.1f s" % ("x".join(map(str, prob.shape)), steps, dt),
-            "host": platform.processor() or platform.machine()}
+            "sample": "the same %s rock and parameters, %d FP64 steps in one call after 3 "
+                      "warm-up steps, dense C oracle with OpenMP, %.1f s"
+                      % ("x".join(map(str, prob.shape)), steps, dt),
+            "host_cpu": _cpu_model()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.machine()
+
+
+def _profiled_traffic():
+    """Calibrated collide-kernel HBM bytes per pore voxel from the committed rocprofv3 summary,
+    if it was measured on the current kernel source; else None."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "collide_phase_grf256_fp64.md")
+    src = os.path.join(ROOT, "paper_2007_12266_amd", "csrc", "lbm_kernels.hip")
+    try:
+        vals = {}
+        for line in open(prof):
+            if ":" in line and line.strip().split(":")[0] in (
+                    "traffic_collide_bytes_per_voxel", "kernel_source_sha256_prefix"):
+                k, v = line.strip().split(":", 1)
+                vals[k] = v.strip()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if digest.startswith(vals["kernel_source_sha256_prefix"]):
+            return float(vals["traffic_collide_bytes_per_voxel"])
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
 
 
 def main():
@@ -128,6 +162,8 @@ def main():
     timing = dom.step_timed(ksteps)
     coll_s = timing["collide_ms"] / 1e3
     achieved = BYTES_COLLIDE_FP64 * n_pore / coll_s / 1e9
+    tb = _profiled_traffic() if args.workload == "grf256" else None
+    traffic = None if tb is None else round(tb * n_pore / coll_s / 1e9, 1)
     step_gbs = BYTES_STEP_FP64 * n_pore / (ms_per_step / 1e3) / 1e9
 
     if args.copy_calibration:
@@ -159,7 +195,9 @@ def main():
                    "block": block},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "collide_kernel",
+                     "traffic": traffic, "traffic_unit": "GB/s (rocprofv3 FETCH_SIZE x2.0 + "
+                     "WRITE_SIZE x1.0 per voxel, over this run's kernel time)",
+                     "kernel": "collide_kernel",
                      "bytes_per_voxel": BYTES_COLLIDE_FP64,
                      "kernel_ms": round(timing["collide_ms"], 5)},
         "step_hbm": {"bytes_per_voxel": BYTES_STEP_FP64, "achieved_gbs": round(step_gbs, 1),
