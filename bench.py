@@ -30,21 +30,27 @@ if ROOT not in sys.path:
 METRIC = "pore-voxel MLUPS + % HBM roofline; batched solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 
-# Algorithmic bytes per pore voxel (FP64 storage): the collide kernel reads 19 f, writes 19 f
-# and 14 recoloured A/B, reads phi and N at the voxel (neighbour phi is reuse), and reads the
-# 18-entry int32 neighbour table; the phase kernel reads 14 A/B and writes phi and N.
-BYTES_COLLIDE_FP64 = 8 * (19 + 19 + 14 + 2) + 4 * 18          # 504
-BYTES_PHASE_FP64 = 8 * (14 + 2)                                # 128 (+ 6 nbr on odd steps)
-BYTES_STEP_FP64 = 8 * (38 + 28 + 4) + 4 * 18                  # 632
+# Algorithmic bytes per pore voxel and step, by storage precision (E = bytes per stored value):
+# the collide kernel reads 19 f, writes 19 f and 14 recoloured A/B, reads phi and N at the voxel
+# (neighbour phi is reuse) and reads the 18-entry int32 neighbour table; the phase kernel reads
+# 14 A/B and writes phi and N. Whole step: E*(38 f + 28 A/B + 4 phi/N) + 4*18.
+def _bytes(E):
+    return {"collide": E * (19 + 19 + 14 + 2) + 4 * 18,
+            "phase": E * (14 + 2),
+            "step": E * (38 + 28 + 4) + 4 * 18}
+
+
+BYTES = {"fp64": _bytes(8), "fp32dev": _bytes(4)}   # fp64: 504 / 128 / 632; fp32dev: 288 / 64 / 352
+
 
 WORKLOADS = {
     "grf256": dict(n=256, seed_geom=3, seed_aff=4, seed_phase=5, reduce_every=100,
                    desc="steady two-fluid flow, 256^3 GRF rock (corr 4, porosity 0.2, "
-                        "percolating), affinity U[-0.9,0.9], Sw=0.5, Fz=1e-5, periodic, FP64, "
+                        "percolating), affinity U[-0.9,0.9], Sw=0.5, Fz=1e-5, periodic, "
                         "reductions every 100 steps"),
     "grf512": dict(n=512, seed_geom=5, seed_aff=6, seed_phase=7, reduce_every=100,
                    desc="steady two-fluid flow, 512^3 GRF rock (corr 4, porosity 0.2, "
-                        "percolating), affinity U[-0.9,0.9], Sw=0.5, Fz=1e-5, periodic, FP64, "
+                        "percolating), affinity U[-0.9,0.9], Sw=0.5, Fz=1e-5, periodic, "
                         "reductions every 100 steps"),
 }
 
@@ -86,11 +92,11 @@ def _cpu_model() -> str:
     return platform.machine()
 
 
-def _profiled_traffic():
+def _profiled_traffic(precision: str):
     """Calibrated collide-kernel HBM bytes per pore voxel from the committed rocprofv3 summary,
     if it was measured on the current kernel source; else None."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "collide_phase_grf256_fp64.md")
+    prof = os.path.join(ROOT, "profiles", "collide_phase_grf256_%s.md" % precision)
     src = os.path.join(ROOT, "paper_2007_12266_amd", "csrc", "lbm_kernels.hip")
     try:
         vals = {}
@@ -115,6 +121,7 @@ def main():
     ap.add_argument("--workload", default="grf256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32dev"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -137,7 +144,8 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         dom = lbm.Domain(prob, reduce_every=wl["reduce_every"], block_size=args.block,
-                         stream=stream.cuda_stream)
+                         stream=stream.cuda_stream,
+                         precision=lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV)
     n_pore = dom.n_pore
     log("domain: N=%d, device bytes %.2f GB" % (n_pore, dom.info()["device_bytes"] / 1e9))
 
@@ -161,10 +169,11 @@ def main():
     ksteps = min(args.steps, 200)
     timing = dom.step_timed(ksteps)
     coll_s = timing["collide_ms"] / 1e3
-    achieved = BYTES_COLLIDE_FP64 * n_pore / coll_s / 1e9
-    tb = _profiled_traffic() if args.workload == "grf256" else None
+    nbytes = BYTES[args.precision]
+    achieved = nbytes["collide"] * n_pore / coll_s / 1e9
+    tb = _profiled_traffic(args.precision) if args.workload == "grf256" else None
     traffic = None if tb is None else round(tb * n_pore / coll_s / 1e9, 1)
-    step_gbs = BYTES_STEP_FP64 * n_pore / (ms_per_step / 1e3) / 1e9
+    step_gbs = nbytes["step"] * n_pore / (ms_per_step / 1e3) / 1e9
 
     if args.copy_calibration:
         a = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
@@ -187,20 +196,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "grid": list(prob.shape), "n_pore": n_pore,
                    "porosity": round(n_pore / float(np.prod(prob.shape)), 5),
-                   "precision": "fp64", "reduce_every": wl["reduce_every"],
+                   "precision": args.precision, "reduce_every": wl["reduce_every"],
                    "block": block},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "GB/s (rocprofv3 FETCH_SIZE x2.0 + "
                      "WRITE_SIZE x1.0 per voxel, over this run's kernel time)",
                      "kernel": "collide_kernel",
-                     "bytes_per_voxel": BYTES_COLLIDE_FP64,
+                     "bytes_per_voxel": nbytes["collide"],
                      "kernel_ms": round(timing["collide_ms"], 5)},
-        "step_hbm": {"bytes_per_voxel": BYTES_STEP_FP64, "achieved_gbs": round(step_gbs, 1),
+        "step_hbm": {"bytes_per_voxel": nbytes["step"], "achieved_gbs": round(step_gbs, 1),
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                      "phase_ms": round(timing["phase_ms"], 5)},
         "reductions": {"recorded": len(hist), "sw": red["sw"], "qz": red["qz"],

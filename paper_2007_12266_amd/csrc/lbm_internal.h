@@ -28,8 +28,8 @@ struct StepArgs {
     int32_t nblocks;    // logical workgroups covering N
     int64_t ld;         // leading dimension of population arrays
     const int32_t* nbr; // [18][ld]
-    double* phi;        // [N + n_tail]; tail holds phi_s
-    double* ntot;       // [N]
+    void* phi;          // [N + n_tail] in the storage type; the tail holds phi_s
+    void* ntot;         // [N] in the storage type
     void* f;            // [19][ld] populations (storage type per precision)
     void* A;            // [7][ld]
     void* B;            // [7][ld]
@@ -37,6 +37,7 @@ struct StepArgs {
     double alpha, beta;
     double F[3];
     int32_t xcd_remap;  // 1: map consecutive logical blocks to the same XCD
+    int32_t prec;       // lbm_precision
 };
 
 // Kernel launchers (lbm_kernels.hip). `odd` is the parity of the step being taken.

@@ -28,6 +28,11 @@
 //    XCDs, so logical block b is taken by hardware block (b % per) * 8 + b / per. Each XCD then
 //    sweeps one contiguous slab of the pore list and its L2 keeps the phi planes that the
 //    gradient stencil re-reads.
+//  * Two storage precisions share every kernel body through a precision policy: FP64 stores f, A,
+//    B, phi and N in double and computes in double; FP32-deviation stores f as the deviation
+//    f_q - t_q from the rest equilibrium (rho0 = 1), A, B, phi and N as float, and computes in
+//    float on those deviations. The two-rate collision is invariant under that shift (t_q is
+//    the same for q and opp(q)), so the same formulas serve both.
 //  * No MFMA: nothing here is a dense contraction. The kernel is bound by HBM traffic.
 
 #include <cmath>
@@ -42,7 +47,30 @@ constexpr int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 
 constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-constexpr double kCMin = 1e-10;   // smallest resolved colour-gradient magnitude
+
+__host__ __device__ constexpr double tw(int q) {   // D3Q19 weights t_q
+    return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+__host__ __device__ constexpr double ww(int q) {   // D3Q7 weights w_q
+    return q == 0 ? 1.0 / 3.0 : 1.0 / 9.0;
+}
+
+// Precision policies. S: storage type of f, A, B, phi, N. R: arithmetic type. kDev: f is stored
+// as f_q - t_q. kCMin: smallest resolved colour-gradient magnitude (a few orders above the
+// rounding noise of C in that precision); a smaller |C| counts as zero.
+template <int PREC> struct Prec;
+template <> struct Prec<LBM_FP64> {
+    using S = double;
+    using R = double;
+    static constexpr bool kDev = false;
+    static constexpr double kCMin = 1e-10;
+};
+template <> struct Prec<LBM_FP32_DEV> {
+    using S = float;
+    using R = float;
+    static constexpr bool kDev = true;
+    static constexpr double kCMin = 1e-5;
+};
 
 __device__ __forceinline__ int logical_block(const StepArgs& a) {
     const int b = blockIdx.x;
@@ -57,18 +85,18 @@ __device__ __forceinline__ int nb(const StepArgs& a, int q, int i) {
 }
 
 // Incoming population q of voxel i (D3Q19 or D3Q7 array X).
-template <bool ODD>
-__device__ __forceinline__ double load_in(const double* __restrict__ X, const StepArgs& a,
-                                          int q, int i, int r_up) {
+template <bool ODD, typename S>
+__device__ __forceinline__ S load_in(const S* __restrict__ X, const StepArgs& a, int q, int i,
+                                     int r_up) {
     if (!ODD || q == 0) return X[(size_t)q * a.ld + i];
     // r_up: neighbour along opp(q), i.e. the upstream voxel i - xi_q.
     return r_up < a.N ? X[(size_t)OPP[q] * a.ld + r_up] : X[(size_t)q * a.ld + i];
 }
 
 // Store the post-collision population q of voxel i.
-template <bool ODD>
-__device__ __forceinline__ void store_out(double* __restrict__ X, const StepArgs& a, int q, int i,
-                                          int r_down, double v) {
+template <bool ODD, typename S>
+__device__ __forceinline__ void store_out(S* __restrict__ X, const StepArgs& a, int q, int i,
+                                          int r_down, S v) {
     if (q == 0) {
         X[i] = v;
     } else if (!ODD) {
@@ -86,21 +114,22 @@ __device__ __forceinline__ void store_out(double* __restrict__ X, const StepArgs
 // Initial state: rest equilibrium, rho = 1, u = 0, N_a = (1 + phi0)/2, N_b = (1 - phi0)/2.
 // Natural layout (step 0 is even).
 // ------------------------------------------------------------------------------------------
+template <int PREC>
 __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __restrict__ phi0) {
+    using P = Prec<PREC>;
+    using S = typename P::S;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    double* f = (double*)a.f;
-    double* A = (double*)a.A;
-    double* B = (double*)a.B;
+    S* f = (S*)a.f;
+    S* A = (S*)a.A;
+    S* B = (S*)a.B;
     const double na = 0.5 * (1.0 + phi0[i]), nbv = 0.5 * (1.0 - phi0[i]);
 #pragma unroll
-    for (int q = 0; q < 19; ++q)
-        f[(size_t)q * a.ld + i] = q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    for (int q = 0; q < 19; ++q) f[(size_t)q * a.ld + i] = (S)(P::kDev ? 0.0 : tw(q));
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-        const double w = q == 0 ? 1.0 / 3.0 : 1.0 / 9.0;
-        A[(size_t)q * a.ld + i] = w * na;
-        B[(size_t)q * a.ld + i] = w * nbv;
+        A[(size_t)q * a.ld + i] = (S)(ww(q) * na);
+        B[(size_t)q * a.ld + i] = (S)(ww(q) * nbv);
     }
 }
 
@@ -108,37 +137,45 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __r
 // Densities and phase indicator: N_a = sum_q A_q, N_b = sum_q B_q (q = 0..6) of the streamed-in
 // D3Q7 populations; phi = (N_a - N_b)/(N_a + N_b); N = N_a + N_b.
 // ------------------------------------------------------------------------------------------
-template <bool ODD>
+template <int PREC, bool ODD>
 __global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
-    const int i = logical_block(a) * blockDim.x + threadIdx.x;
+    using P = Prec<PREC>;
+    using S = typename P::S;
+        const int i = logical_block(a) * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    const double* A = (const double*)a.A;
-    const double* B = (const double*)a.B;
+    const S* A = (const S*)a.A;
+    const S* B = (const S*)a.B;
     int up[7];
 #pragma unroll
     for (int q = 1; q < 7; ++q) up[q] = ODD ? nb(a, OPP[q], i) : 0;
-    double na = 0.0, nbv = 0.0;
+    // The sums are accumulated in double in both precisions: a float running sum of seven
+    // populations carries a mean rounding bias of a few 1e-9, which would create that much
+    // mass per step.
+    double na = 0, nbv = 0;
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-        na += load_in<ODD>(A, a, q, i, q ? up[q] : 0);
-        nbv += load_in<ODD>(B, a, q, i, q ? up[q] : 0);
+        na += (double)load_in<ODD>(A, a, q, i, q ? up[q] : 0);
+        nbv += (double)load_in<ODD>(B, a, q, i, q ? up[q] : 0);
     }
     const double nt = na + nbv;
-    a.phi[i] = (na - nbv) / nt;
-    a.ntot[i] = nt;
+    ((S*)a.phi)[i] = (S)((na - nbv) / nt);
+    ((S*)a.ntot)[i] = (S)nt;
 }
 
 // ------------------------------------------------------------------------------------------
 // Fused colour gradient + MRT collision with interfacial terms and body force + recolouring +
 // AA streaming.
 // ------------------------------------------------------------------------------------------
-template <bool ODD>
+template <int PREC, bool ODD>
 __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
+    using P = Prec<PREC>;
+    using S = typename P::S;
+    using R = typename P::R;
     const int i = logical_block(a) * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    double* f = (double*)a.f;
-    double* A = (double*)a.A;
-    double* B = (double*)a.B;
+    S* f = (S*)a.f;
+    S* A = (S*)a.A;
+    S* B = (S*)a.B;
 
     int r[19];
     r[0] = i;
@@ -150,32 +187,33 @@ __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
     // increasing q, one term at a time: every product is exact (a power of two times phi), so
     // the sum is the same correctly rounded chain in any implementation that keeps this order.
     // That matters where |C| is small, since n = C/|C| amplifies a rounding difference in C.
-    const double* __restrict__ ph = a.phi;
-    double p[19];
+    const S* __restrict__ ph = (const S*)a.phi;
+    R p[19];
 #pragma unroll
-    for (int q = 1; q < 19; ++q) p[q] = ph[r[q]];
-    double Cx = 0.0, Cy = 0.0, Cz = 0.0;
+    for (int q = 1; q < 19; ++q) p[q] = (R)ph[r[q]];
+    R Cx = 0, Cy = 0, Cz = 0;
 #pragma unroll
     for (int q = 1; q < 19; ++q) {
-        const double w = q < 7 ? 1.0 : 0.5;
+        const R w = q < 7 ? (R)1 : (R)0.5;
         if (CX[q]) Cx += (w * CX[q]) * p[q];
         if (CY[q]) Cy += (w * CY[q]) * p[q];
         if (CZ[q]) Cz += (w * CZ[q]) * p[q];
     }
     // |C| <= kCMin is an unresolved gradient (a cancellation whose residue is rounding): it
     // counts as zero, so that n never takes a direction decided by rounding.
-    const double c2 = Cx * Cx + Cy * Cy + Cz * Cz;
-    const bool resolved = c2 > kCMin * kCMin;
-    const double cm = resolved ? sqrt(c2) : 0.0;
-    const double ic = resolved ? 1.0 / cm : 0.0;
-    const double nx = Cx * ic, ny = Cy * ic, nz = Cz * ic;
+    const R c2 = Cx * Cx + Cy * Cy + Cz * Cz;
+    const bool resolved = c2 > (R)(P::kCMin * P::kCMin);
+    const R cm = resolved ? sqrt(c2) : (R)0;
+    const R ic = resolved ? (R)1 / cm : (R)0;
+    const R nx = Cx * ic, ny = Cy * ic, nz = Cz * ic;
 
-    // Incoming populations.
-    double fl[19];
+    // Incoming populations (f, or f - t in deviation storage).
+    R fl[19];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) fl[q] = load_in<ODD>(f, a, q, i, r[OPP[q]]);
+    for (int q = 0; q < 19; ++q) fl[q] = (R)load_in<ODD>(f, a, q, i, r[OPP[q]]);
 
-    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    // rho (or rho - 1 in deviation storage) and j.
+    R rho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
         rho += fl[q];
@@ -183,81 +221,133 @@ __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
         jy += CY[q] * fl[q];
         jz += CZ[q] * fl[q];
     }
-    const double jj = jx * jx + jy * jy + jz * jz;
+    const R jj = jx * jx + jy * jy + jz * jz;
 
-    const double phi_i = ph[i];
-    const double nt = a.ntot[i];
-    const double nu = 0.5 * (1.0 + phi_i) * a.nu_a + 0.5 * (1.0 - phi_i) * a.nu_b;
-    const double sp = 1.0 / (3.0 * nu + 0.5);
-    const double sm = 8.0 * (2.0 - sp) / (8.0 - sp);
+    const R phi_i = (R)ph[i];
+    const R nt = (R)((const S*)a.ntot)[i];
+    const R nu = (R)0.5 * ((R)1 + phi_i) * (R)a.nu_a + (R)0.5 * ((R)1 - phi_i) * (R)a.nu_b;
+    const R sp = (R)1 / ((R)3 * nu + (R)0.5);
+    const R sm = (R)8 * ((R)2 - sp) / ((R)8 - sp);
 
     // Image of the alpha|C| equilibrium-moment terms in population space (even in xi):
     // e-row -19 g, 3pxx (g/2)(3nx^2-1), pww (g/2)(ny^2-nz^2), pxy (g/2)nx ny, ... ; g = alpha|C|.
-    const double g = a.alpha * cm;
-    const double hxx = g * (3.0 * nx * nx - 1.0);
-    const double hww = g * (ny * ny - nz * nz);
-    const double d_rest = g * (5.0 / 21.0);
-    const double d_ax = g * (11.0 / 126.0);
-    const double d_dg = -g * (8.0 / 126.0);
-    const double dX = d_ax + hxx * (1.0 / 36.0);
-    const double dY = d_ax - hxx * (1.0 / 72.0) + hww * (1.0 / 24.0);
-    const double dZ = d_ax - hxx * (1.0 / 72.0) - hww * (1.0 / 24.0);
-    const double dXY = d_dg + hxx * (1.0 / 72.0) + hww * (1.0 / 24.0);
-    const double dXZ = d_dg + hxx * (1.0 / 72.0) - hww * (1.0 / 24.0);
-    const double dYZ = d_dg - hxx * (1.0 / 36.0);
-    const double gxy = g * nx * ny * 0.125, gxz = g * nx * nz * 0.125, gyz = g * ny * nz * 0.125;
+    const R g = (R)a.alpha * cm;
+    const R hxx = g * ((R)3 * nx * nx - (R)1);
+    const R hww = g * (ny * ny - nz * nz);
+    const R d_rest = g * (R)(5.0 / 21.0);
+    const R d_ax = g * (R)(11.0 / 126.0);
+    const R d_dg = -g * (R)(8.0 / 126.0);
+    const R dX = d_ax + hxx * (R)(1.0 / 36.0);
+    const R dY = d_ax - hxx * (R)(1.0 / 72.0) + hww * (R)(1.0 / 24.0);
+    const R dZ = d_ax - hxx * (R)(1.0 / 72.0) - hww * (R)(1.0 / 24.0);
+    const R dXY = d_dg + hxx * (R)(1.0 / 72.0) + hww * (R)(1.0 / 24.0);
+    const R dXZ = d_dg + hxx * (R)(1.0 / 72.0) - hww * (R)(1.0 / 24.0);
+    const R dYZ = d_dg - hxx * (R)(1.0 / 36.0);
+    const R gxy = g * nx * ny * (R)0.125, gxz = g * nx * nz * (R)0.125;
+    const R gyz = g * ny * nz * (R)0.125;
 
-    // Even equilibrium part (per velocity class) and odd part 3 t xi.j.
-    const double base = rho - 1.5 * jj;
-    double fs[19];
-    fs[0] = fl[0] - sp * (fl[0] - ((1.0 / 3.0) * base + d_rest));
+    // Even equilibrium part (per velocity class) and odd part 3 t xi.j. The rest weight t_q
+    // multiplies rho in the even part; with deviation storage both sides carry -t_q.
+    const R base = rho - (R)1.5 * jj;
+    R fs[19];
+    fs[0] = fl[0] - sp * (fl[0] - ((R)(1.0 / 3.0) * base + d_rest));
 #pragma unroll
     for (int q = 1; q < 19; q += 2) {
         const int qb = q + 1;
-        const double t = q < 7 ? 1.0 / 18.0 : 1.0 / 36.0;
-        const double ej = CX[q] * jx + CY[q] * jy + CZ[q] * jz;
-        const double ef = CX[q] * a.F[0] + CY[q] * a.F[1] + CZ[q] * a.F[2];
-        double dq;
+        const R t = (R)tw(q);
+        const R ej = CX[q] * jx + CY[q] * jy + CZ[q] * jz;
+        const R ef = (R)(CX[q] * a.F[0] + CY[q] * a.F[1] + CZ[q] * a.F[2]);
+        R dq;
         if (q == 1) dq = dX;
         else if (q == 3) dq = dY;
         else if (q == 5) dq = dZ;
-        else if (q < 11) dq = dXY + gxy * (CX[q] * CY[q]);
-        else if (q < 15) dq = dXZ + gxz * (CX[q] * CZ[q]);
-        else dq = dYZ + gyz * (CY[q] * CZ[q]);
-        const double ep = t * (base + 4.5 * ej * ej) + dq;
-        const double em = 3.0 * t * ej;
-        const double fp = 0.5 * (fl[q] + fl[qb]);
-        const double fm = 0.5 * (fl[q] - fl[qb]);
-        const double rp = sp * (fp - ep);
-        const double rm = sm * (fm - em);
-        const double fo = 3.0 * t * ef;
+        else if (q < 11) dq = dXY + gxy * (R)(CX[q] * CY[q]);
+        else if (q < 15) dq = dXZ + gxz * (R)(CX[q] * CZ[q]);
+        else dq = dYZ + gyz * (R)(CY[q] * CZ[q]);
+        const R ep = t * (base + (R)4.5 * ej * ej) + dq;
+        const R em = (R)3 * t * ej;
+        const R fp = (R)0.5 * (fl[q] + fl[qb]);
+        const R fm = (R)0.5 * (fl[q] - fl[qb]);
+        const R rp = sp * (fp - ep);
+        const R rm = sm * (fm - em);
+        const R fo = (R)3 * t * ef;
         fs[q] = fl[q] - rp - rm + fo;
         fs[qb] = fl[qb] - rp + rm - fo;
     }
 
     // Recolouring with the flow velocity u = j + F/2 (rho0 = 1).
-    const double ux = jx + 0.5 * a.F[0], uy = jy + 0.5 * a.F[1], uz = jz + 0.5 * a.F[2];
-    const double na = 0.5 * nt * (1.0 + phi_i);
-    const double nbv = 0.5 * nt * (1.0 - phi_i);
-    const double seg = a.beta * na * nbv / nt;
-    double As[7], Bs[7];
-    As[0] = (1.0 / 3.0) * na;
-    Bs[0] = (1.0 / 3.0) * nbv;
+    const R ux = jx + (R)(0.5 * a.F[0]), uy = jy + (R)(0.5 * a.F[1]);
+    const R uz = jz + (R)(0.5 * a.F[2]);
+    const R na = (R)0.5 * nt * ((R)1 + phi_i);
+    const R nbv = (R)0.5 * nt * ((R)1 - phi_i);
+    const R seg = (R)a.beta * na * nbv / nt;
+    R As[7], Bs[7];
 #pragma unroll
     for (int q = 1; q < 7; ++q) {
-        const double eu = 4.5 * (CX[q] * ux + CY[q] * uy + CZ[q] * uz);
-        const double en = seg * (CX[q] * nx + CY[q] * ny + CZ[q] * nz);
-        As[q] = (1.0 / 9.0) * (na * (1.0 + eu) + en);
-        Bs[q] = (1.0 / 9.0) * (nbv * (1.0 + eu) - en);
+        const R eu = (R)4.5 * (CX[q] * ux + CY[q] * uy + CZ[q] * uz);
+        const R en = seg * (CX[q] * nx + CY[q] * ny + CZ[q] * nz);
+        As[q] = (R)(1.0 / 9.0) * (na * ((R)1 + eu) + en);
+        Bs[q] = (R)(1.0 / 9.0) * (nbv * ((R)1 + eu) - en);
+    }
+    if (P::kDev) {
+        // In float the rounded weights sum to 1 + 1.5e-8, which would create that much mass
+        // every step. The rest population takes what the moving ones leave (w_0 N exactly in
+        // exact arithmetic, since the velocity and normal terms cancel between opposite pairs).
+        double sa = 0, sb = 0;
+#pragma unroll
+        for (int q = 1; q < 7; ++q) {
+            sa += (double)(S)As[q];
+            sb += (double)(S)Bs[q];
+        }
+        As[0] = (R)((double)na - sa);
+        Bs[0] = (R)((double)nbv - sb);
+    } else {
+        As[0] = (R)(1.0 / 3.0) * na;
+        Bs[0] = (R)(1.0 / 3.0) * nbv;
     }
 
 #pragma unroll
-    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, r[q], fs[q]);
+    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, r[q], (S)fs[q]);
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-        store_out<ODD>(A, a, q, i, r[q], As[q]);
-        store_out<ODD>(B, a, q, i, r[q], Bs[q]);
+        store_out<ODD>(A, a, q, i, r[q], (S)As[q]);
+        store_out<ODD>(B, a, q, i, r[q], (S)Bs[q]);
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-voxel read-out in FP64 from either storage: N_a, N_b, rho, j.
+// ------------------------------------------------------------------------------------------
+template <int PREC, bool ODD>
+__device__ __forceinline__ void voxel_state(const StepArgs& a, int i, double& na, double& nbv,
+                                            double& rho, double& jx, double& jy, double& jz) {
+    using P = Prec<PREC>;
+    using S = typename P::S;
+    const S* f = (const S*)a.f;
+    const S* A = (const S*)a.A;
+    const S* B = (const S*)a.B;
+    int r[19];
+    r[0] = i;
+#pragma unroll
+    for (int q = 1; q < 19; ++q) r[q] = ODD ? nb(a, q, i) : 0;
+    na = 0.0;
+    nbv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        na += (double)load_in<ODD>(A, a, q, i, r[OPP[q]]);
+        nbv += (double)load_in<ODD>(B, a, q, i, r[OPP[q]]);
+    }
+    rho = 0.0;
+    jx = jy = jz = 0.0;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        const double v = (double)load_in<ODD>(f, a, q, i, r[OPP[q]]);
+        rho += v;
+        jx += CX[q] * v;
+        jy += CY[q] * v;
+        jz += CZ[q] * v;
+    }
+    if (P::kDev) rho += 1.0;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -269,35 +359,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <bool ODD>
+template <int PREC, bool ODD>
 __global__ void __launch_bounds__(kRedThreads) reduce_kernel(StepArgs a,
                                                              double* __restrict__ partials) {
     double acc[kNRed];
 #pragma unroll
     for (int k = 0; k < kNRed; ++k) acc[k] = 0.0;
-    const double* f = (const double*)a.f;
-    const double* A = (const double*)a.A;
-    const double* B = (const double*)a.B;
     const int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
-        int r[19];
-        r[0] = i;
-#pragma unroll
-        for (int q = 1; q < 19; ++q) r[q] = ODD ? nb(a, q, i) : 0;
-        double na = 0.0, nbv = 0.0, rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            na += load_in<ODD>(A, a, q, i, r[OPP[q]]);
-            nbv += load_in<ODD>(B, a, q, i, r[OPP[q]]);
-        }
-#pragma unroll
-        for (int q = 0; q < 19; ++q) {
-            const double v = load_in<ODD>(f, a, q, i, r[OPP[q]]);
-            rho += v;
-            jx += CX[q] * v;
-            jy += CY[q] * v;
-            jz += CZ[q] * v;
-        }
+        double na, nbv, rho, jx, jy, jz;
+        voxel_state<PREC, ODD>(a, i, na, nbv, rho, jx, jy, jz);
         const double phi = (na - nbv) / (na + nbv);
         const double u[3] = {jx + 0.5 * a.F[0], jy + 0.5 * a.F[1], jz + 0.5 * a.F[2]};
         const bool bad = !(isfinite(na) && isfinite(nbv) && isfinite(rho) && isfinite(u[0]) &&
@@ -352,89 +423,79 @@ __global__ void reduce_final_kernel(const double* __restrict__ partials, int nbl
 }
 
 // ------------------------------------------------------------------------------------------
-// Field read-back for pore voxels (pore order).
+// Field read-back for pore voxels (pore order), in FP64.
 // ------------------------------------------------------------------------------------------
-template <bool ODD>
+template <int PREC, bool ODD>
 __global__ void __launch_bounds__(256) field_kernel(StepArgs a, int field,
                                                     double* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    int r[19];
-    r[0] = i;
-#pragma unroll
-    for (int q = 1; q < 19; ++q) r[q] = ODD ? nb(a, q, i) : 0;
-    double v = 0.0;
-    if (field <= LBM_FIELD_PHI) {
-        const double* A = (const double*)a.A;
-        const double* B = (const double*)a.B;
-        double na = 0.0, nbv = 0.0;
-#pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            na += load_in<ODD>(A, a, q, i, r[OPP[q]]);
-            nbv += load_in<ODD>(B, a, q, i, r[OPP[q]]);
-        }
-        v = field == LBM_FIELD_NA ? na : field == LBM_FIELD_NB ? nbv : (na - nbv) / (na + nbv);
-    } else {
-        const double* f = (const double*)a.f;
-        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-        for (int q = 0; q < 19; ++q) {
-            const double fq = load_in<ODD>(f, a, q, i, r[OPP[q]]);
-            rho += fq;
-            jx += CX[q] * fq;
-            jy += CY[q] * fq;
-            jz += CZ[q] * fq;
-        }
-        switch (field) {
-        case LBM_FIELD_RHO: v = rho; break;
-        case LBM_FIELD_P: v = rho / 3.0; break;
-        case LBM_FIELD_UX: v = jx + 0.5 * a.F[0]; break;
-        case LBM_FIELD_UY: v = jy + 0.5 * a.F[1]; break;
-        default: v = jz + 0.5 * a.F[2]; break;
-        }
+    double na, nbv, rho, jx, jy, jz;
+    voxel_state<PREC, ODD>(a, i, na, nbv, rho, jx, jy, jz);
+    double v;
+    switch (field) {
+    case LBM_FIELD_NA: v = na; break;
+    case LBM_FIELD_NB: v = nbv; break;
+    case LBM_FIELD_PHI: v = (na - nbv) / (na + nbv); break;
+    case LBM_FIELD_RHO: v = rho; break;
+    case LBM_FIELD_P: v = rho / 3.0; break;
+    case LBM_FIELD_UX: v = jx + 0.5 * a.F[0]; break;
+    case LBM_FIELD_UY: v = jy + 0.5 * a.F[1]; break;
+    default: v = jz + 0.5 * a.F[2]; break;
     }
     out[i] = v;
 }
 
 int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
 
+dim3 step_grid(const StepArgs& a) {
+    return dim3(a.xcd_remap ? ((a.nblocks + 7) / 8) * 8 : a.nblocks);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
-// Launchers
+// Launchers: dispatch on precision and step parity.
 // ------------------------------------------------------------------------------------------
+#define LBM_DISPATCH(KERNEL, GRID, BLOCK, ...)                                              \
+    do {                                                                                    \
+        if (a.prec == LBM_FP32_DEV) {                                                       \
+            if (odd)                                                                        \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
+            else                                                                            \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false>), GRID, BLOCK, 0, s, __VA_ARGS__); \
+        } else {                                                                            \
+            if (odd)                                                                        \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, true>), GRID, BLOCK, 0, s, __VA_ARGS__);      \
+            else                                                                            \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, false>), GRID, BLOCK, 0, s, __VA_ARGS__);     \
+        }                                                                                   \
+    } while (0)
+
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s) {
-    hipLaunchKernelGGL(init_kernel, dim3(grid_for(a, 256)), dim3(256), 0, s, a, phi0);
     (void)block;
+    if (a.prec == LBM_FP32_DEV)
+        hipLaunchKernelGGL(init_kernel<LBM_FP32_DEV>, dim3(grid_for(a, 256)), dim3(256), 0, s,
+                           a, phi0);
+    else
+        hipLaunchKernelGGL(init_kernel<LBM_FP64>, dim3(grid_for(a, 256)), dim3(256), 0, s, a,
+                           phi0);
     return hipGetLastError();
 }
 
 hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    const dim3 grid(a.xcd_remap ? ((a.nblocks + 7) / 8) * 8 : a.nblocks);
-    if (odd)
-        hipLaunchKernelGGL(phase_kernel<true>, grid, dim3(block), 0, s, a);
-    else
-        hipLaunchKernelGGL(phase_kernel<false>, grid, dim3(block), 0, s, a);
+    LBM_DISPATCH(phase_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
 }
 
 hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    const dim3 grid(a.xcd_remap ? ((a.nblocks + 7) / 8) * 8 : a.nblocks);
-    if (odd)
-        hipLaunchKernelGGL(collide_kernel<true>, grid, dim3(block), 0, s, a);
-    else
-        hipLaunchKernelGGL(collide_kernel<false>, grid, dim3(block), 0, s, a);
+    LBM_DISPATCH(collide_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
                          hipStream_t s) {
-    if (odd)
-        hipLaunchKernelGGL(reduce_kernel<true>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a,
-                           partials);
-    else
-        hipLaunchKernelGGL(reduce_kernel<false>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, a,
-                           partials);
+    LBM_DISPATCH(reduce_kernel, dim3(kRedBlocks), dim3(kRedThreads), a, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, partials, kRedBlocks, out);
@@ -443,12 +504,8 @@ hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* 
 
 hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int block,
                         hipStream_t s) {
-    const dim3 grid(grid_for(a, 256));
     (void)block;
-    if (odd)
-        hipLaunchKernelGGL(field_kernel<true>, grid, dim3(256), 0, s, a, field, out);
-    else
-        hipLaunchKernelGGL(field_kernel<false>, grid, dim3(256), 0, s, a, field, out);
+    LBM_DISPATCH(field_kernel, dim3(grid_for(a, 256)), dim3(256), a, field, out);
     return hipGetLastError();
 }
 

@@ -53,8 +53,9 @@ struct lbm_domain {
     void* f = nullptr;
     void* A = nullptr;
     void* B = nullptr;
-    double* phi = nullptr;
-    double* ntot = nullptr;
+    void* phi = nullptr;      // [N + n_tail] storage type
+    void* ntot = nullptr;     // [N] storage type
+    double* stage = nullptr;  // [ld] doubles: initial phase upload and field read-back
     int32_t* nbr = nullptr;
     double* red_partials = nullptr;
     double* red_out = nullptr;
@@ -89,6 +90,7 @@ struct lbm_domain {
         a.beta = p.beta;
         for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
         a.xcd_remap = xcd_remap ? 1 : 0;
+        a.prec = p.precision;
         return a;
     }
 
@@ -253,8 +255,8 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return fail(LBM_ERR_ARG, "alpha must be >= 0");
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(p.force[c])) return fail(LBM_ERR_ARG, "force must be finite");
-    if (p.precision != LBM_FP64)
-        return fail(LBM_ERR_ARG, "precision not supported by this build");
+    if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV)
+        return fail(LBM_ERR_ARG, "precision must be LBM_FP64 or LBM_FP32_DEV");
     if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
         return fail(LBM_ERR_ARG, "rho_in and rho_out must be positive");
     if (p.bc_z == 1) return fail(LBM_ERR_ARG, "pressure faces are not supported by this build");
@@ -288,16 +290,16 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     d->f = d->dalloc(eb * 19 * ld);
     d->A = d->dalloc(eb * 7 * ld);
     d->B = d->dalloc(eb * 7 * ld);
-    d->phi = (double*)d->dalloc(sizeof(double) * (size_t)(pre.n_pore + pre.n_tail));
-    d->ntot = (double*)d->dalloc(sizeof(double) * ld);
+    d->phi = d->dalloc(eb * (size_t)(pre.n_pore + pre.n_tail));
+    d->ntot = d->dalloc(eb * ld);
+    d->stage = (double*)d->dalloc(sizeof(double) * ld);
     d->nbr = (int32_t*)d->dalloc(sizeof(int32_t) * 18 * ld);
     d->red_partials = (double*)d->dalloc(sizeof(double) * kRedBlocks * kNRed);
     d->red_out = (double*)d->dalloc(sizeof(double) * kNRed);
     d->hist = (double*)d->dalloc(sizeof(double) * (size_t)d->hist_cap * kNRed);
-    // The initial phase is staged in ntot, which the first phase kernel overwrites.
-    double* phi0 = d->ntot;
-    if (!d->f || !d->A || !d->B || !d->phi || !d->ntot || !d->nbr || !d->red_partials ||
-        !d->red_out || !d->hist) {
+    double* phi0 = d->stage;
+    if (!d->f || !d->A || !d->B || !d->phi || !d->ntot || !d->stage || !d->nbr ||
+        !d->red_partials || !d->red_out || !d->hist) {
         d->release();
         return fail(LBM_ERR_OOM, "device allocation failed");
     }
@@ -312,7 +314,11 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
             st = fail(LBM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
     guard(up(d->nbr, pre.nbr.data(), sizeof(int32_t) * pre.nbr.size()), "upload nbr");
-    guard(up(d->phi + pre.n_pore, pre.tail_phi.data(), sizeof(double) * pre.n_tail),
+    std::vector<float> tail32;
+    if (eb == 4) tail32.assign(pre.tail_phi.begin(), pre.tail_phi.end());
+    guard(up((char*)d->phi + eb * pre.n_pore,
+             eb == 4 ? (const void*)tail32.data() : (const void*)pre.tail_phi.data(),
+             eb * pre.n_tail),
           "upload tail");
     guard(up(phi0, pre.phi0.data(), sizeof(double) * pre.n_pore), "upload phi0");
     guard(hipMemsetAsync(d->f, 0, eb * 19 * ld, d->stream), "clear f");
@@ -344,9 +350,8 @@ lbm_status lbm_read_pore_field(lbm_domain* d, int32_t field, double* host_pore) 
     if (field < LBM_FIELD_NA || field > LBM_FIELD_UZ) return fail(LBM_ERR_ARG, "bad field id");
     if (!host_pore) return fail(LBM_ERR_ARG, "host_pore must be non-null");
     const StepArgs a = d->args();
-    // ntot doubles as the staging buffer: the next step's phase kernel rewrites it first.
-    HIP_TRY(launch_field(a, (d->step & 1) != 0, field, d->ntot, d->block, d->stream));
-    HIP_TRY(hipMemcpyAsync(host_pore, d->ntot, sizeof(double) * d->pre.n_pore,
+    HIP_TRY(launch_field(a, (d->step & 1) != 0, field, d->stage, d->block, d->stream));
+    HIP_TRY(hipMemcpyAsync(host_pore, d->stage, sizeof(double) * d->pre.n_pore,
                            hipMemcpyDeviceToHost, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     return LBM_OK;
