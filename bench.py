@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32dev"])
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of autotuning them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -149,6 +151,10 @@ def main():
     n_pore = dom.n_pore
     log("domain: N=%d, device bytes %.2f GB" % (n_pore, dom.info()["device_bytes"] / 1e9))
 
+    tuning = None
+    if not args.no_autotune:
+        tuning = dom.autotune(10)
+        log("autotune: %s" % tuning)
     dom.step(args.warmup)
     torch.cuda.synchronize()
     dom.history()
@@ -201,7 +207,7 @@ def main():
         "config": {"workload": wl["desc"], "grid": list(prob.shape), "n_pore": n_pore,
                    "porosity": round(n_pore / float(np.prod(prob.shape)), 5),
                    "precision": args.precision, "reduce_every": wl["reduce_every"],
-                   "block": block},
+                   "block": block, "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "GB/s (rocprofv3 FETCH_SIZE x2.0 + "

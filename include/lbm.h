@@ -117,6 +117,16 @@ typedef struct {
     int64_t phase_launches, collide_launches, bc_launches;
 } lbm_timing;
 
+/* Launch configuration of the two step kernels. block: threads per workgroup (64, 128 or 256);
+ * schedule: 1 = workgroups take consecutive tiles of the pore list in launch order, 2 = each of
+ * the 8 XCDs takes one contiguous slab of tiles (its L2 then holds the neighbour planes the
+ * stencil re-reads). Results do not depend on the configuration (bitwise). */
+typedef struct {
+    int32_t phase_block, phase_schedule;
+    int32_t collide_block, collide_schedule;
+    double phase_ms, collide_ms;  /* average per launch measured by lbm_autotune, else 0        */
+} lbm_tuning;
+
 typedef struct {
     int64_t n_pore;           /* pore voxels (the sparse list length N)                     */
     int64_t n_solid_tail;     /* solid voxels adjacent to a pore, plus the wall entry        */
@@ -180,6 +190,18 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes);
 lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes);
 
 lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out);
+
+/* Autotuner: times every (block, schedule) candidate of each step kernel over trial_steps >= 2
+ * steps on this domain, applies the fastest, and writes it to *out (nullable). The state, step
+ * counter and reduction history are restored afterwards, so the results of later steps are
+ * unchanged. Synchronises; needs device memory for one copy of the populations (LBM_ERR_OOM
+ * otherwise). */
+lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out);
+
+/* Apply a launch configuration (e.g. one cached from an earlier lbm_autotune on the same GPU,
+ * precision and size class). LBM_ERR_ARG for an unsupported block or schedule. */
+lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t);
+lbm_status lbm_get_tuning(lbm_domain* d, lbm_tuning* out);
 
 /* Host-only inspection of the sparse layout a domain would use (no GPU needed): runs the CPU
  * pre-pass on the same arguments as lbm_domain_create and reports *n_pore and *n_tail. Each

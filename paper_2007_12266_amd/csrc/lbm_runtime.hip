@@ -42,7 +42,8 @@ struct StateHeader {
 struct lbm_domain {
     lbm_params p{};
     Prepass pre;
-    int block = 256;
+    int block = 256;                 // read-back and init kernels
+    lbm_tuning tune{256, 2, 256, 2, 0.0, 0.0};
     lbm_allocator alloc{};
     bool has_alloc = false;
     hipStream_t stream = nullptr;
@@ -71,12 +72,13 @@ struct lbm_domain {
 
     int64_t step = 0;
     bool unstable = false;
-    bool xcd_remap = true;
+    bool record_history = true;
 
-    StepArgs args() const {
+    // Kernel arguments for a launch with `blk` threads per workgroup and schedule `sched`.
+    StepArgs args(int blk = 256, int sched = 1) const {
         StepArgs a{};
         a.N = (int32_t)pre.n_pore;
-        a.nblocks = (int32_t)((pre.n_pore + block - 1) / block);
+        a.nblocks = (int32_t)((pre.n_pore + blk - 1) / blk);
         a.ld = pre.ld;
         a.nbr = nbr;
         a.phi = phi;
@@ -89,7 +91,7 @@ struct lbm_domain {
         a.alpha = p.alpha;
         a.beta = p.beta;
         for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
-        a.xcd_remap = xcd_remap ? 1 : 0;
+        a.xcd_remap = sched == 2 ? 1 : 0;
         a.prec = p.precision;
         return a;
     }
@@ -185,13 +187,16 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
     }
     lbm_status st = LBM_OK;
     for (int64_t s = 0; s < nsteps && st == LBM_OK; ++s) {
-        const StepArgs a = d->args();
+        const lbm_tuning& tu = d->tune;
+        const StepArgs ap = d->args(tu.phase_block, tu.phase_schedule);
+        const StepArgs ac = d->args(tu.collide_block, tu.collide_schedule);
+        const StepArgs a = ac;
         const bool odd = (d->step & 1) != 0;
         Span sp{};
         if (timing) { sp.kind = 0; HIP_TRY(mark(&sp.a)); }
-        HIP_TRY(launch_phase(a, odd, d->block, d->stream));
+        HIP_TRY(launch_phase(ap, odd, tu.phase_block, d->stream));
         if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); sp.kind = 1; HIP_TRY(mark(&sp.a)); }
-        HIP_TRY(launch_collide(a, odd, d->block, d->stream));
+        HIP_TRY(launch_collide(ac, odd, tu.collide_block, d->stream));
         if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
         if (d->p.bc_z == 1) {
             if (timing) { sp.kind = 2; HIP_TRY(mark(&sp.a)); }
@@ -201,7 +206,7 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
             if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
         }
         d->step += 1;
-        if (d->p.reduce_every > 0 && d->step % d->p.reduce_every == 0) {
+        if (d->record_history && d->p.reduce_every > 0 && d->step % d->p.reduce_every == 0) {
             const int slot = d->hist_head;
             st = record_reduction(d, d->hist + (size_t)slot * kNRed);
             d->hist_step[slot] = d->step;
@@ -270,7 +275,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     std::unique_ptr<lbm_domain> d(new (std::nothrow) lbm_domain());
     if (!d) return fail(LBM_ERR_OOM, "host allocation failed");
     d->p = p;
-    d->block = block;
+    d->tune.phase_block = d->tune.collide_block = block;
     std::string err = prepass(p, labels, n_labels, label_kind, label_affinity, voxel_affinity,
                               init_phi, d->pre);
     if (!err.empty()) return fail(LBM_ERR_ARG, err);
@@ -469,7 +474,110 @@ lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out) {
     out->device_bytes = d->device_bytes;
     out->step = d->step;
     out->precision = d->p.precision;
-    out->block_size = d->block;
+    out->block_size = d->tune.collide_block;
+    return LBM_OK;
+}
+
+static bool tuning_ok(const lbm_tuning& t) {
+    auto blk = [](int b) { return b == 64 || b == 128 || b == 256; };
+    auto sch = [](int v) { return v == 1 || v == 2; };
+    return blk(t.phase_block) && blk(t.collide_block) && sch(t.phase_schedule) &&
+           sch(t.collide_schedule);
+}
+
+lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!t || !tuning_ok(*t)) return fail(LBM_ERR_ARG, "unsupported block or schedule");
+    d->tune = *t;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_tuning(lbm_domain* d, lbm_tuning* out) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!out) return fail(LBM_ERR_ARG, "out must be non-null");
+    *out = d->tune;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (trial_steps < 2) return fail(LBM_ERR_ARG, "trial_steps must be >= 2");
+    if (d->unstable) return fail(LBM_ERR_UNSTABLE, "domain is unstable; load a state");
+    trial_steps += trial_steps & 1;  // even: both parities equally
+    const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
+    const size_t bytes = eb * 33 * ld;
+    char* snap = (char*)d->dalloc(bytes);
+    if (!snap) return fail(LBM_ERR_OOM, "no device memory for the autotuner's snapshot");
+    void* arrays[3] = {d->f, d->A, d->B};
+    const size_t rows[3] = {19, 7, 7};
+    auto copy_all = [&](bool save) -> hipError_t {
+        size_t off = 0;
+        for (int k = 0; k < 3; ++k) {
+            const size_t nb = eb * rows[k] * ld;
+            hipError_t e = save ? hipMemcpyAsync(snap + off, arrays[k], nb,
+                                                 hipMemcpyDeviceToDevice, d->stream)
+                                : hipMemcpyAsync(arrays[k], snap + off, nb,
+                                                 hipMemcpyDeviceToDevice, d->stream);
+            if (e != hipSuccess) return e;
+            off += nb;
+        }
+        return hipSuccess;
+    };
+    const int64_t step0 = d->step;
+    const lbm_tuning keep = d->tune;
+    lbm_status st = LBM_OK;
+    hipError_t he = copy_all(true);
+    lbm_tuning best = d->tune;
+    double best_ms[2] = {1e30, 1e30};
+    d->record_history = false;
+    const int blocks[3] = {64, 128, 256};
+    for (int kernel = 0; kernel < 2 && st == LBM_OK && he == hipSuccess; ++kernel) {
+        for (int bi = 0; bi < 3 && st == LBM_OK; ++bi) {
+            for (int sched = 1; sched <= 2 && st == LBM_OK; ++sched) {
+                lbm_tuning t = best;
+                if (kernel == 0) {
+                    t.phase_block = blocks[bi];
+                    t.phase_schedule = sched;
+                } else {
+                    t.collide_block = blocks[bi];
+                    t.collide_schedule = sched;
+                }
+                d->tune = t;
+                lbm_timing tm;
+                st = step_impl(d, 2, &tm);                 // warm-up of this shape
+                if (st == LBM_OK) st = step_impl(d, trial_steps, &tm);
+                if (st != LBM_OK) break;
+                const double ms = kernel == 0 ? tm.phase_ms : tm.collide_ms;
+                if (ms < best_ms[kernel]) {
+                    best_ms[kernel] = ms;
+                    best = t;
+                }
+            }
+        }
+    }
+    d->record_history = true;
+    if (he == hipSuccess) he = copy_all(false);
+    if (he == hipSuccess) he = hipStreamSynchronize(d->stream);
+    d->step = step0;
+    // The snapshot is the domain's last allocation: release it now.
+    if (!d->allocations.empty() && d->allocations.back() == snap) {
+        if (d->has_alloc) d->alloc.free(snap, d->alloc.ctx);
+        else (void)hipFree(snap);
+        d->allocations.pop_back();
+        d->device_bytes -= (int64_t)std::max<size_t>(bytes, 256);
+    }
+    if (he != hipSuccess) {
+        d->tune = keep;
+        return fail(LBM_ERR_DEVICE, std::string("autotune copy: ") + hipGetErrorString(he));
+    }
+    if (st != LBM_OK) {
+        d->tune = keep;
+        return st;
+    }
+    best.phase_ms = best_ms[0];
+    best.collide_ms = best_ms[1];
+    d->tune = best;
+    if (out) *out = best;
     return LBM_OK;
 }
 

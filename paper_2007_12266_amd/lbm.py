@@ -24,7 +24,8 @@ FIELDS = {"Na": 0, "Nb": 1, "phi": 2, "rho": 3, "p": 4, "ux": 5, "uy": 6, "uz": 
 EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_read_pore_field", "lbm_pore_index", "lbm_reduce", "lbm_read_history",
            "lbm_state_save", "lbm_state_load", "lbm_domain_get_info", "lbm_domain_destroy",
-           "lbm_prepass_query", "lbm_last_error", "lbm_version")
+           "lbm_prepass_query", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
+           "lbm_last_error", "lbm_version")
 
 
 class LbmError(RuntimeError):
@@ -70,6 +71,15 @@ class Timing(ctypes.Structure):
                 ("bc_launches", ctypes.c_int64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("phase_block", ctypes.c_int32), ("phase_schedule", ctypes.c_int32),
+                ("collide_block", ctypes.c_int32), ("collide_schedule", ctypes.c_int32),
+                ("phase_ms", ctypes.c_double), ("collide_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Info(ctypes.Structure):
     _fields_ = [("n_pore", ctypes.c_int64), ("n_solid_tail", ctypes.c_int64),
                 ("ld", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
@@ -113,6 +123,9 @@ def load_library(path: str = LIB_PATH):
     L.lbm_domain_destroy.argtypes = [vp]
     L.lbm_prepass_query.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, vp, vp,
                                     ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
+    L.lbm_autotune.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
+    L.lbm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.lbm_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -292,6 +305,24 @@ class Domain:
     def load(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(load_library().lbm_state_load(self.handle, buf, len(blob)))
+        return self
+
+    def autotune(self, trial_steps: int = 10) -> dict:
+        t = Tuning()
+        _check(load_library().lbm_autotune(self.handle, int(trial_steps), ctypes.byref(t)))
+        return t.as_dict()
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(load_library().lbm_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        _check(load_library().lbm_get_tuning(self.handle, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, v)
+        _check(load_library().lbm_set_tuning(self.handle, ctypes.byref(t)))
         return self
 
     def info(self) -> dict:

@@ -242,3 +242,28 @@ def test_grf_256_full_size(lbm):
         assert abs(h["mass_a"] - r0["mass_a"]) <= 1e-12 * r0["mass_a"]
         assert abs(h["mass_b"] - r0["mass_b"]) <= 1e-12 * r0["mass_b"]
     dom.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_autotune_restores_state_and_keeps_results(lbm, precision):
+    prec = lbm.FP64 if precision == "fp64" else lbm.FP32_DEV
+    prob = _random_problem((20, 24, 28), (True, True, True), seed=17)
+    ref = lbm.Domain(prob, precision=prec, reduce_every=5)
+    ref.step(7)
+    ref.step(13)
+    dom = lbm.Domain(prob, precision=prec, reduce_every=5)
+    dom.step(7)
+    before = dom.save()
+    t = dom.autotune(4)
+    assert t["phase_block"] in (64, 128, 256) and t["collide_schedule"] in (1, 2)
+    assert t["phase_ms"] > 0 and t["collide_ms"] > 0
+    assert dom.info()["step"] == 7 and dom.save() == before
+    dom.step(13)
+    assert dom.save() == ref.save()
+    assert [h["step"] for h in dom.history()] == [5, 10, 15, 20]
+    dom.set_tuning(phase_block=64, phase_schedule=1, collide_block=128, collide_schedule=2)
+    assert dom.tuning()["collide_block"] == 128
+    with pytest.raises(lbm.LbmError):
+        dom.set_tuning(collide_block=96)
+    ref.close()
+    dom.close()
