@@ -30,7 +30,8 @@
  *   - velocity ordering inside each D3Q19 group: +x -x +y -y +z -z, (+,+,0) (-,-,0) (+,-,0)
  *     (-,+,0), (+,0,+) (-,0,-) (+,0,-) (-,0,+), (0,+,+) (0,-,-) (0,+,-) (0,-,+).
  *   - z pressure faces (optional): Zou-He on the D3Q19 unknowns at the first and last z plane
- *     with transverse-momentum correction; the inlet plane is pure fluid a, the outlet pure b.
+ *     with transverse-momentum correction; the inlet plane is pure fluid a, the outlet pure b
+ *     (N = 1); across those faces the colour gradient mirrors the plane.
  *
  * State layout: f[q * nvox + v], A[q * nvox + v], B[q * nvox + v], v = x + nx*(y + ny*z).
  * Entries of solid voxels are never read and are left as they are.
@@ -286,12 +287,15 @@ void ora_init(const ora_params* p, const uint8_t* solid, const double* phi0, dou
     }
 }
 
-/* Zou-He pressure condition on one z plane (dir = +1 inlet at z = 0, -1 outlet at z = nz-1).
- * The unknown populations are those with xi_z == dir. Density rho_b is imposed; the in-plane
- * velocity is zero; the transverse momentum correction spreads the tangential imbalance. The
- * D3Q7 populations of the plane are reset to equilibrium at the imposed composition. */
+/* Zou-He pressure condition on one z plane (dir = +1: inlet at z = 0; -1: outlet at z = nz-1),
+ * applied to the streamed populations of that plane. The unknown populations are those with
+ * xi_z == dir (they would come from outside). The imposed density rho_b fixes the normal
+ * momentum j_z from the known populations; the in-plane momentum is set to zero by spreading the
+ * tangential imbalance of the xi_z == 0 populations over the unknown diagonals. The D3Q7
+ * populations of the plane are reset to equilibrium with composition (N_a, N_b) = (na_b,
+ * 1 - na_b) and velocity u = (F_x/2, F_y/2, j_z + F_z/2). */
 static void pressure_plane(const ora_params* p, const uint8_t* solid, double* f, double* A,
-                           double* B, int z, int dir, double rho_b, double Na_b) {
+                           double* B, int z, int dir, double rho_b, double na_b) {
     const long nv = (long)p->nx * p->ny * p->nz;
     for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
@@ -320,14 +324,13 @@ static void pressure_plane(const ora_params* p, const uint8_t* solid, double* f,
                 /* Non-equilibrium bounce-back of the normal part, plus transverse correction. */
                 double val = fl[qb] + 6.0 * t_weight(q) * XI[q][2] * jz;
                 val -= 0.5 * (XI[q][0] * tx + XI[q][1] * ty);
-                fl[q] = val;
+                f[q * nv + v] = val;
             }
-            for (int q = 0; q < 19; ++q) f[q * nv + v] = fl[q];
-            const double uz = jz;
+            const double u[3] = {0.5 * p->force[0], 0.5 * p->force[1], jz + 0.5 * p->force[2]};
             for (int q = 0; q < 7; ++q) {
-                const double eu = XI[q][2] * uz;
-                A[q * nv + v] = w_weight(q) * Na_b * (1.0 + 4.5 * eu);
-                B[q * nv + v] = w_weight(q) * (rho_b - Na_b) * (1.0 + 4.5 * eu);
+                const double eu = XI[q][0] * u[0] + XI[q][1] * u[1] + XI[q][2] * u[2];
+                A[q * nv + v] = w_weight(q) * na_b * (1.0 + 4.5 * eu);
+                B[q * nv + v] = w_weight(q) * (1.0 - na_b) * (1.0 + 4.5 * eu);
             }
         }
 }
@@ -410,7 +413,7 @@ int ora_run(const ora_params* p, const uint8_t* solid, const double* phi_s, doub
                 }
         /* 14. Optional pressure faces. */
         if (p->bc_z == 1) {
-            pressure_plane(p, solid, fn, An, Bn, 0, +1, p->rho_in, p->rho_in);
+            pressure_plane(p, solid, fn, An, Bn, 0, +1, p->rho_in, 1.0);
             pressure_plane(p, solid, fn, An, Bn, p->nz - 1, -1, p->rho_out, 0.0);
         }
         double* t;

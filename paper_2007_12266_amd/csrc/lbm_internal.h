@@ -44,9 +44,13 @@ struct StepArgs {
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s);
 hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s);
 hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s);
-hipError_t launch_pressure_bc(const StepArgs& a, bool odd, const int32_t* inlet, int32_t n_in,
-                              const int32_t* outlet, int32_t n_out, double rho_in,
-                              double rho_out, hipStream_t s);
+hipError_t launch_ghosts(const StepArgs& a, const int32_t* ghost_tail, const int32_t* ghost_src,
+                         int32_t n, hipStream_t s);
+// faces: inlet pore indices (n_in) followed by outlet ones (n_out); next_odd: parity of the
+// step that will read the state the condition is applied to.
+hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* faces,
+                              int32_t n_in, int32_t n_out, double rho_in, double rho_out,
+                              hipStream_t s);
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
                          hipStream_t s);
 hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int block,

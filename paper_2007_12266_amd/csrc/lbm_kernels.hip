@@ -446,6 +446,85 @@ __global__ void __launch_bounds__(256) field_kernel(StepArgs a, int field,
     out[i] = v;
 }
 
+// ------------------------------------------------------------------------------------------
+// Pressure faces. Across the z faces the colour gradient mirrors the plane: tail entries that
+// stand for an out-of-domain z neighbour carry the phi of the in-plane voxel, refreshed after
+// every phase kernel.
+// ------------------------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) ghost_kernel(StepArgs a, const int32_t* __restrict__ tail,
+                                                    const int32_t* __restrict__ src, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    S* ph = (S*)a.phi;
+    ph[a.N + tail[k]] = ph[src[k]];
+}
+
+// Storage index of the incoming population q of voxel i for a step of parity ODD.
+template <bool ODD>
+__device__ __forceinline__ size_t in_slot(const StepArgs& a, int q, int i, int r_up) {
+    if (!ODD || q == 0 || r_up >= a.N) return (size_t)q * a.ld + i;
+    return (size_t)OPP[q] * a.ld + r_up;
+}
+
+// Zou-He pressure condition on the streamed populations of the z = 0 (inlet, first n_in
+// entries of `faces`) and z = nz-1 (outlet) pore voxels, read and written in the layout of the
+// next step (parity ODD). Unknowns (xi_z pointing into the domain) always sit in the voxel's
+// own slot q, because their upstream neighbour is outside. The D3Q7 populations of the plane
+// are reset to equilibrium: pure fluid a (N = 1) at the inlet, pure b at the outlet, with
+// u = (F_x/2, F_y/2, j_z + F_z/2).
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
+                                                          const int32_t* __restrict__ faces,
+                                                          int n_in, int n_out, double rho_in,
+                                                          double rho_out) {
+    using P = Prec<PREC>;
+    using S = typename P::S;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_in + n_out) return;
+    const int i = faces[k];
+    const int dir = k < n_in ? 1 : -1;
+    const double rho_b = k < n_in ? rho_in : rho_out;
+    const double na_b = k < n_in ? 1.0 : 0.0;
+    S* f = (S*)a.f;
+    S* A = (S*)a.A;
+    S* B = (S*)a.B;
+    int r[19];
+    r[0] = i;
+#pragma unroll
+    for (int q = 1; q < 19; ++q) r[q] = nb(a, q, i);
+    double fl[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q)
+        fl[q] = (double)load_in<ODD>(f, a, q, i, r[OPP[q]]) + (P::kDev ? tw(q) : 0.0);
+    double s0 = 0.0, sout = 0.0, tx = 0.0, ty = 0.0;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        if (CZ[q] == 0) {
+            s0 += fl[q];
+            tx += CX[q] * fl[q];
+            ty += CY[q] * fl[q];
+        } else if (CZ[q] == -dir) {
+            sout += fl[q];
+        }
+    }
+    const double jz = dir * (rho_b - s0 - 2.0 * sout);
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        if (CZ[q] != dir) continue;
+        const double val = fl[OPP[q]] + 6.0 * tw(q) * CZ[q] * jz - 0.5 * (CX[q] * tx + CY[q] * ty);
+        f[(size_t)q * a.ld + i] = (S)(val - (P::kDev ? tw(q) : 0.0));
+    }
+    const double u[3] = {0.5 * a.F[0], 0.5 * a.F[1], jz + 0.5 * a.F[2]};
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const double eu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
+        const size_t at = in_slot<ODD>(a, q, i, r[OPP[q]]);
+        A[at] = (S)(ww(q) * na_b * (1.0 + 4.5 * eu));
+        B[at] = (S)(ww(q) * (1.0 - na_b) * (1.0 + 4.5 * eu));
+    }
+}
+
 int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
 
 dim3 step_grid(const StepArgs& a) {
@@ -509,9 +588,28 @@ hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int
     return hipGetLastError();
 }
 
-hipError_t launch_pressure_bc(const StepArgs&, bool, const int32_t*, int32_t, const int32_t*,
-                              int32_t, double, double, hipStream_t) {
-    return hipErrorNotSupported;
+hipError_t launch_ghosts(const StepArgs& a, const int32_t* ghost_tail, const int32_t* ghost_src,
+                         int32_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((n + 255) / 256);
+    if (a.prec == LBM_FP32_DEV)
+        hipLaunchKernelGGL(ghost_kernel<float>, grid, dim3(256), 0, s, a, ghost_tail, ghost_src,
+                           n);
+    else
+        hipLaunchKernelGGL(ghost_kernel<double>, grid, dim3(256), 0, s, a, ghost_tail, ghost_src,
+                           n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* faces,
+                              int32_t n_in, int32_t n_out, double rho_in, double rho_out,
+                              hipStream_t s) {
+    const int n = n_in + n_out;
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((n + 255) / 256);
+    const bool odd = next_odd;
+    LBM_DISPATCH(pressure_bc_kernel, grid, dim3(256), a, faces, n_in, n_out, rho_in, rho_out);
+    return hipGetLastError();
 }
 
 }  // namespace lbm

@@ -65,9 +65,8 @@ struct lbm_domain {
     int32_t hist_head = 0;    // next slot to write
     int32_t hist_count = 0;   // unread entries
     std::vector<int64_t> hist_step;
-    int32_t* inlet = nullptr;
-    int32_t* outlet = nullptr;
-    int32_t* ghost_tail = nullptr;
+    int32_t* faces = nullptr;       // inlet then outlet pore indices (bc_z == 1)
+    int32_t* ghost_tail = nullptr;  // z-face mirror entries of the phi tail
     int32_t* ghost_src = nullptr;
 
     int64_t step = 0;
@@ -195,13 +194,16 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
         Span sp{};
         if (timing) { sp.kind = 0; HIP_TRY(mark(&sp.a)); }
         HIP_TRY(launch_phase(ap, odd, tu.phase_block, d->stream));
+        if (!d->pre.ghost_tail.empty())
+            HIP_TRY(launch_ghosts(ap, d->ghost_tail, d->ghost_src,
+                                  (int32_t)d->pre.ghost_tail.size(), d->stream));
         if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); sp.kind = 1; HIP_TRY(mark(&sp.a)); }
         HIP_TRY(launch_collide(ac, odd, tu.collide_block, d->stream));
         if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
         if (d->p.bc_z == 1) {
             if (timing) { sp.kind = 2; HIP_TRY(mark(&sp.a)); }
-            HIP_TRY(launch_pressure_bc(a, odd, d->inlet, (int32_t)d->pre.inlet.size(),
-                                       d->outlet, (int32_t)d->pre.outlet.size(), d->p.rho_in,
+            HIP_TRY(launch_pressure_bc(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
+                                       (int32_t)d->pre.outlet.size(), d->p.rho_in,
                                        d->p.rho_out, d->stream));
             if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
         }
@@ -264,7 +266,6 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         return fail(LBM_ERR_ARG, "precision must be LBM_FP64 or LBM_FP32_DEV");
     if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
         return fail(LBM_ERR_ARG, "rho_in and rho_out must be positive");
-    if (p.bc_z == 1) return fail(LBM_ERR_ARG, "pressure faces are not supported by this build");
     if (p.reduce_every < 0) return fail(LBM_ERR_ARG, "reduce_every must be >= 0");
     int block = p.block_size == 0 ? 256 : p.block_size;
     if (block != 64 && block != 128 && block != 256)
@@ -309,6 +310,18 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         return fail(LBM_ERR_OOM, "device allocation failed");
     }
     d->hist_step.assign(d->hist_cap, 0);
+    std::vector<int32_t> faces(pre.inlet);
+    faces.insert(faces.end(), pre.outlet.begin(), pre.outlet.end());
+    if (!faces.empty()) d->faces = (int32_t*)d->dalloc(sizeof(int32_t) * faces.size());
+    if (!pre.ghost_tail.empty()) {
+        d->ghost_tail = (int32_t*)d->dalloc(sizeof(int32_t) * pre.ghost_tail.size());
+        d->ghost_src = (int32_t*)d->dalloc(sizeof(int32_t) * pre.ghost_src.size());
+    }
+    if ((!faces.empty() && !d->faces) ||
+        (!pre.ghost_tail.empty() && (!d->ghost_tail || !d->ghost_src))) {
+        d->release();
+        return fail(LBM_ERR_OOM, "device allocation failed");
+    }
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, d->stream)
                      : hipSuccess;
@@ -326,6 +339,14 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
              eb * pre.n_tail),
           "upload tail");
     guard(up(phi0, pre.phi0.data(), sizeof(double) * pre.n_pore), "upload phi0");
+    if (d->faces)
+        guard(up(d->faces, faces.data(), sizeof(int32_t) * faces.size()), "upload faces");
+    if (d->ghost_tail) {
+        guard(up(d->ghost_tail, pre.ghost_tail.data(), sizeof(int32_t) * pre.ghost_tail.size()),
+              "upload ghosts");
+        guard(up(d->ghost_src, pre.ghost_src.data(), sizeof(int32_t) * pre.ghost_src.size()),
+              "upload ghosts");
+    }
     guard(hipMemsetAsync(d->f, 0, eb * 19 * ld, d->stream), "clear f");
     guard(hipMemsetAsync(d->A, 0, eb * 7 * ld, d->stream), "clear A");
     guard(hipMemsetAsync(d->B, 0, eb * 7 * ld, d->stream), "clear B");

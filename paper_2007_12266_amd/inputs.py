@@ -248,3 +248,27 @@ def grf_problem(n: int = 256, seed_geom: int = 3, seed_aff: int = 4, seed_phase:
                            name="grf-%dx%dx%d" % (shape[2], shape[1], shape[0]))
     p.voxel_affinity = aff
     return p
+
+
+def displacement_problem(n: int = 512, shape=None, seed_geom: int = 5, porosity_target: float = 0.2,
+                         corr: float = 4.0, affinity: float = -0.7, reservoir: int = 4,
+                         rho_in: float = 1.03, rho_out: float = 0.97) -> Problem:
+    """Unsteady displacement: fluid a is injected at z = 0 by a pressure face into rock filled
+    with b. GRF rock (as ``grf_rock``) between two solid-free reservoirs of ``reservoir`` planes;
+    x and y periodic, z bounded by the pressure faces (rho_in at z = 0, rho_out at z = nz-1).
+    Walls carry ``affinity`` (-0.7: they prefer b, so a is the non-wetting invader). Initial
+    phase: +1 in the inlet reservoir, -1 elsewhere."""
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    nz, ny, nx = shape
+    rock, _ = grf_rock((nz - 2 * reservoir, ny, nx), corr, porosity_target, seed_geom)
+    solid = np.zeros(shape, np.uint8)
+    solid[reservoir:nz - reservoir] = rock
+    labels = np.where(solid > 0, 0, 1).astype(np.int32)
+    phi0 = -np.ones(shape)
+    phi0[:reservoir] = 1.0
+    return Problem(labels=labels,
+                   label_kind=np.array([KIND_SOLID, KIND_PORE_INIT], dtype=np.int8),
+                   label_affinity=np.array([affinity, 0.0]), init_phi=phi0,
+                   periodic=(True, True, False), force=(0.0, 0.0, 0.0),
+                   wall_affinity=affinity, bc_z=1, rho_in=rho_in, rho_out=rho_out,
+                   name="displacement-%dx%dx%d" % (nx, ny, nz))

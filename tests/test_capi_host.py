@@ -124,3 +124,33 @@ def test_create_validates_parameters_before_touching_the_device():
                                  lbm._ptr(aff), lbm._ptr(vaff), lbm._ptr(iphi), None, None,
                                  ctypes.byref(h))
         assert st == lbm.LBM_ERR_ARG and msg in L.lbm_last_error() and not h.value
+
+
+def test_prepass_pressure_faces_mirror_the_plane():
+    """With pressure faces on z, a neighbour beyond z = 0 or z = nz-1 is a tail entry standing
+    for the in-plane voxel (x + xi_x, y + xi_y, z): a ghost of a pore voxel (initialised with its
+    phase) or the solid's phi_s. Every such entry is >= N, so streaming bounces back there."""
+    prob = _random_problem((6, 7, 8), (True, True, False), seed=5)
+    prob.bc_z = 1
+    res = lbm.prepass_query(prob)
+    n, nbr, tail = res["n_pore"], res["nbr"], res["tail_phi"]
+    shape = prob.shape
+    nz, ny, nx = shape
+    solid = prob.solid_mask()
+    index = -np.ones(solid.size, np.int64)
+    index[res["pore_voxel"]] = np.arange(n)
+    phi0 = prob.phase0().ravel()
+    phis = prob.solid_affinity().ravel()
+    checked = 0
+    for i, v in enumerate(res["pore_voxel"]):
+        z, y, x = np.unravel_index(v, shape)
+        for q in range(1, 19):
+            if 0 <= z + XI[q][2] < nz:
+                continue
+            e = nbr[q - 1, i]
+            assert e >= n
+            m = (x + XI[q][0]) % nx + nx * ((y + XI[q][1]) % ny + ny * z)
+            expect = phi0[m] if solid.ravel()[m] == 0 else phis[m]
+            assert tail[e - n] == expect
+            checked += 1
+    assert checked > 0

@@ -267,3 +267,32 @@ def test_autotune_restores_state_and_keeps_results(lbm, precision):
         dom.set_tuning(collide_block=96)
     ref.close()
     dom.close()
+
+
+@pytest.mark.parametrize("steps", [60, 61])
+def test_pressure_faces_parity(lbm, steps):
+    """Displacement with pressure faces (rho 1.03 / 0.97), walls of affinity -0.7, GRF rock
+    between 4-plane reservoirs, x/y periodic: GPU FP64 vs the oracle, both parities."""
+    prob = inputs.displacement_problem(shape=(40, 20, 18), seed_geom=8, porosity_target=0.3)
+    dom = lbm.Domain(prob)
+    dom.step(steps)
+    gpu = dom.fields()
+    ref = O.state_for(prob).run(steps)
+    _compare(gpu, ref.fields(), prob.solid_mask() == 0)
+    g, r = dom.reduce(), ref.reduce()
+    assert np.isclose(g["mass_a"], r["mass_a"], rtol=1e-12)
+    dom.close()
+
+
+def test_pressure_faces_fp32_dev_tracks_fp64(lbm):
+    prob = inputs.displacement_problem(shape=(48, 24, 24), seed_geom=9, porosity_target=0.3)
+    a = lbm.Domain(prob)
+    b = lbm.Domain(prob, precision=lbm.FP32_DEV)
+    a.step(400)
+    b.step(400)
+    ra, rb = a.reduce(), b.reduce()
+    assert rb["unstable"] == 0
+    assert abs(rb["sw"] - ra["sw"]) <= 1e-4 * ra["sw"], (ra["sw"], rb["sw"])
+    assert abs(rb["qz"] - ra["qz"]) <= 1e-3 * abs(ra["qz"]), (ra["qz"], rb["qz"])
+    a.close()
+    b.close()

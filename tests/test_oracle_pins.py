@@ -410,3 +410,45 @@ def test_reductions_of_uniform_states():
     ca = (na / solid.size * nu * 2e-6 + (n - na) / solid.size * nu * 2e-6) / 0.03
     assert np.isclose(r["ca"], ca, rtol=1e-13)
     assert r["unstable"] == 0
+
+
+def test_pressure_faces_drive_slit_poiseuille():
+    """Single-phase flow between solid planes driven only by the pressure faces (rho 1.01 at
+    z = 0, 0.99 at z = nz-1): the faces hold the imposed density exactly, the steady mass flux is
+    the same through every z plane, and the mid-channel profile is the Poiseuille parabola of the
+    local pressure gradient, u_z(y) = G/(2 nu)(y - 1/2)(H + 1/2 - y), G = -dp/dz, p = rho/3."""
+    H, L, tau = 16, 48, 0.8
+    nu = (tau - 0.5) / 3
+    shape = (L, H + 2, 1)
+    solid = np.zeros(shape, np.uint8)
+    solid[:, 0, :] = solid[:, H + 1, :] = 1
+    p = O.make_params(shape, (True, False, False), tau, tau, 0.005, 0.95, (0, 0, 0), 1.0,
+                      bc_z=1, rho_in=1.01, rho_out=0.99)
+    st = O.State(p, solid, np.ones(shape)).init(np.ones(shape)).run(10000)
+    fl = st.fields()
+    uz, rho = fl["uz"][:, 1:H + 1, 0], fl["rho"][:, 1:H + 1, 0]
+    assert np.allclose(rho[0], 1.01, rtol=0, atol=1e-14)
+    assert np.allclose(rho[-1], 0.99, rtol=0, atol=1e-14)
+    plane = uz.sum(1)
+    assert np.ptp(plane) < 1e-10 * plane.mean() and plane.mean() > 0
+    zm = L // 2
+    G = -(rho[zm + 1].mean() - rho[zm - 1].mean()) / 6.0
+    y = np.arange(1, H + 1)
+    exact = G / (2 * nu) * (y - 0.5) * (H + 0.5 - y)
+    assert np.abs(uz[zm] - exact).max() < 1e-4 * exact.max()
+    # Composition of the faces: pure a at the inlet, pure b at the outlet.
+    assert np.all(fl["phi"][0][solid[0] == 0] == 1.0)
+
+
+def test_pressure_faces_inject_fluid_a():
+    """Two-phase displacement on a small rock: the inlet plane stays pure a, the outlet pure b,
+    and fluid a enters (its mass grows) while the run stays finite."""
+    prob = inputs.displacement_problem(shape=(24, 12, 12), seed_geom=7, porosity_target=0.35)
+    st = O.state_for(prob)
+    r0 = st.reduce()
+    st.run(300)
+    r1 = st.reduce()
+    fl = st.fields()
+    pore = prob.solid_mask() == 0
+    assert np.all(fl["phi"][0][pore[0]] == 1.0) and np.all(fl["phi"][-1][pore[-1]] == -1.0)
+    assert r1["unstable"] == 0 and r1["mass_a"] > r0["mass_a"]
