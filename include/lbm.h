@@ -33,6 +33,7 @@ extern "C" {
 #endif
 
 typedef struct lbm_domain lbm_domain; /* opaque; owned by the library */
+typedef struct lbm_pool lbm_pool;     /* opaque; owned by the library */
 
 typedef enum {
     LBM_OK = 0,
@@ -218,6 +219,51 @@ lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, in
 
 /* Release all device memory of the domain and the handle itself. NULL is accepted. */
 lbm_status lbm_domain_destroy(lbm_domain* d);
+
+/* ---- Pools: many independent domains advanced together ----------------------------------
+ * A pool steps every member domain with one launch per kernel per time step (a persistent grid
+ * striding over the tiles of all members), in chunks captured once as a HIP graph and replayed.
+ * Members keep their own state and parameters; a member's results are bitwise the same as
+ * stepping it alone. Members must share the pool's precision, have bc_z == 0, and have the same
+ * step parity as the pool (a fresh domain joins a pool whose step count is even). While a domain
+ * is a member it runs on the pool's stream and lbm_step on it returns LBM_ERR_STATE; its fields,
+ * reductions and state can still be read. The pool never frees member domains. */
+
+/* Create a pool for up to max_slots members whose device memory (lbm_domain_info.device_bytes)
+ * sums to at most hbm_budget_bytes. chunk_steps (even, >= 2) is the length of the captured step
+ * chunk. hip_stream is nullable (the pool then owns a stream). */
+lbm_status lbm_pool_create(int64_t hbm_budget_bytes, int32_t precision, int32_t max_slots,
+                           int32_t chunk_steps, void* hip_stream, lbm_pool** out);
+
+/* Add a domain; *slot receives its slot index. LBM_ERR_OOM if the budget or the slots are
+ * exhausted; LBM_ERR_STATE for a precision, boundary or parity mismatch or a pooled domain. */
+lbm_status lbm_pool_admit(lbm_pool* pool, lbm_domain* d, int32_t* slot);
+
+/* Remove the member of `slot` (it keeps its state and returns to its own stream). */
+lbm_status lbm_pool_retire(lbm_pool* pool, int32_t slot);
+
+/* Advance every member by nsteps >= 0 steps, asynchronously on the pool's stream. */
+lbm_status lbm_pool_step(lbm_pool* pool, int64_t nsteps);
+
+/* Reduce every member now (one batched launch). out[slot] is written for slots 0..max_count-1
+ * (an empty slot gets n_pore = 0); *count receives the number of slots written. Synchronises.
+ * Each member's values are bitwise those of lbm_reduce on it. */
+lbm_status lbm_pool_reduce(lbm_pool* pool, lbm_reduction* out, int32_t max_count,
+                           int32_t* count);
+
+typedef struct {
+    int32_t max_slots, members, chunk_steps, grid;  /* grid: workgroups of the batched launch */
+    int64_t step, used_bytes, budget_bytes, tiles;
+    int64_t graph_replays, eager_steps;
+} lbm_pool_info;
+lbm_status lbm_pool_get_info(lbm_pool* pool, lbm_pool_info* out);
+
+/* Set the number of workgroups of the batched step kernels (e.g. from an autotuner);
+ * 0 restores the default. Invalidates the captured graph. */
+lbm_status lbm_pool_set_grid(lbm_pool* pool, int32_t grid);
+
+/* Retire every member and free the pool. NULL is accepted. */
+lbm_status lbm_pool_destroy(lbm_pool* pool);
 
 /* Message of the calling thread's last error ("" if none). Valid until its next call. */
 const char* lbm_last_error(void);

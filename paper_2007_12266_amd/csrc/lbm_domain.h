@@ -1,0 +1,120 @@
+// Internal definition of a domain, shared by the runtime (lbm_runtime.hip) and the pool
+// (lbm_pool.hip). Not part of the C-ABI.
+#pragma once
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// Records the calling thread's error message (lbm_last_error) and returns s.
+lbm_status fail(lbm_status s, const std::string& msg);
+
+}  // namespace lbm
+
+struct lbm_domain;
+
+namespace lbm {
+// Turns the kNRed accumulators of a domain's reduction into an lbm_reduction.
+void finish_reduction(const lbm_domain* d, const double* acc, int64_t step, lbm_reduction* r);
+}  // namespace lbm
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return lbm::fail(LBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct lbm_domain {
+    lbm_pool* pool = nullptr;        // set while the domain belongs to a pool
+    hipStream_t own_stream_saved = nullptr;  // its stream while pooled (restored on retire)
+    lbm_params p{};
+    lbm::Prepass pre;
+    int block = 256;                 // read-back and init kernels
+    lbm_tuning tune{256, 2, 256, 2, 0.0, 0.0};
+    lbm_allocator alloc{};
+    bool has_alloc = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<void*> allocations;
+    int64_t device_bytes = 0;
+
+    void* f = nullptr;
+    void* A = nullptr;
+    void* B = nullptr;
+    void* phi = nullptr;      // [N + n_tail] storage type
+    void* ntot = nullptr;     // [N] storage type
+    double* stage = nullptr;  // [ld] doubles: initial phase upload and field read-back
+    int32_t* nbr = nullptr;
+    double* red_partials = nullptr;
+    double* red_out = nullptr;
+    double* hist = nullptr;
+    int32_t hist_cap = 1024;
+    int32_t hist_head = 0;    // next slot to write
+    int32_t hist_count = 0;   // unread entries
+    std::vector<int64_t> hist_step;
+    int32_t* faces = nullptr;       // inlet then outlet pore indices (bc_z == 1)
+    int32_t* ghost_tail = nullptr;  // z-face mirror entries of the phi tail
+    int32_t* ghost_src = nullptr;
+
+    int64_t step = 0;
+    bool unstable = false;
+    bool record_history = true;
+
+    // Kernel arguments for a launch with `blk` threads per workgroup and schedule `sched`.
+    lbm::StepArgs args(int blk = 256, int sched = 1) const {
+        lbm::StepArgs a{};
+        a.N = (int32_t)pre.n_pore;
+        a.nblocks = (int32_t)((pre.n_pore + blk - 1) / blk);
+        a.ld = pre.ld;
+        a.nbr = nbr;
+        a.phi = phi;
+        a.ntot = ntot;
+        a.f = f;
+        a.A = A;
+        a.B = B;
+        a.nu_a = (p.tau_a - 0.5) / 3.0;
+        a.nu_b = (p.tau_b - 0.5) / 3.0;
+        a.alpha = p.alpha;
+        a.beta = p.beta;
+        for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
+        a.xcd_remap = sched == 2 ? 1 : 0;
+        a.prec = p.precision;
+        return a;
+    }
+
+    void* dalloc(size_t bytes) {
+        bytes = std::max<size_t>(bytes, 256);
+        void* ptr = nullptr;
+        if (has_alloc) {
+            ptr = alloc.alloc(bytes, alloc.ctx);
+        } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+            ptr = nullptr;
+        }
+        if (ptr) {
+            allocations.push_back(ptr);
+            device_bytes += (int64_t)bytes;
+        }
+        return ptr;
+    }
+
+    void release() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* ptr : allocations) {
+            if (has_alloc)
+                alloc.free(ptr, alloc.ctx);
+            else
+                (void)hipFree(ptr);
+        }
+        allocations.clear();
+        device_bytes = 0;
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+
+    size_t elem_bytes() const { return p.precision == LBM_FP32_DEV ? 4 : 8; }
+};

@@ -40,6 +40,14 @@ struct StepArgs {
     int32_t prec;       // lbm_precision
 };
 
+// Arguments of the batched (pool) kernels. All arrays live in device memory.
+struct BatchArgs {
+    const StepArgs* doms;       // per-slot kernel arguments (N = 0 for an empty slot)
+    const int32_t* tile_dom;    // slot of each tile
+    const int32_t* tile_first;  // first tile of each slot
+    const int32_t* ntiles;      // number of tiles in use (device scalar)
+};
+
 // Kernel launchers (lbm_kernels.hip). `odd` is the parity of the step being taken.
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s);
 hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s);
@@ -53,6 +61,13 @@ hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* f
                               hipStream_t s);
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
                          hipStream_t s);
+hipError_t launch_phase_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
+                                hipStream_t s);
+hipError_t launch_collide_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
+                                  hipStream_t s);
+// Reductions of slots 0..nslots-1 into out[nslots][kNRed]; partials holds nslots*kRedBlocks rows.
+hipError_t launch_reduce_batched(const BatchArgs& b, int prec, bool odd, int nslots,
+                                 double* partials, double* out, hipStream_t s);
 hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int block,
                         hipStream_t s);
 

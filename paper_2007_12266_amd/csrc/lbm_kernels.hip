@@ -138,11 +138,9 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __r
 // D3Q7 populations; phi = (N_a - N_b)/(N_a + N_b); N = N_a + N_b.
 // ------------------------------------------------------------------------------------------
 template <int PREC, bool ODD>
-__global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
+__device__ __forceinline__ void phase_voxel(const StepArgs& a, int i) {
     using P = Prec<PREC>;
     using S = typename P::S;
-        const int i = logical_block(a) * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
     const S* A = (const S*)a.A;
     const S* B = (const S*)a.B;
     int up[7];
@@ -162,17 +160,21 @@ __global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
     ((S*)a.ntot)[i] = (S)nt;
 }
 
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
+    const int i = logical_block(a) * blockDim.x + threadIdx.x;
+    if (i < a.N) phase_voxel<PREC, ODD>(a, i);
+}
+
 // ------------------------------------------------------------------------------------------
 // Fused colour gradient + MRT collision with interfacial terms and body force + recolouring +
 // AA streaming.
 // ------------------------------------------------------------------------------------------
 template <int PREC, bool ODD>
-__global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
+__device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     using P = Prec<PREC>;
     using S = typename P::S;
     using R = typename P::R;
-    const int i = logical_block(a) * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
     S* f = (S*)a.f;
     S* A = (S*)a.A;
     S* B = (S*)a.B;
@@ -315,6 +317,42 @@ __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
     }
 }
 
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
+    const int i = logical_block(a) * blockDim.x + threadIdx.x;
+    if (i < a.N) collide_voxel<PREC, ODD>(a, i);
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched steps: one launch covers every live domain of a pool. The pore list of each domain is
+// cut into tiles of blockDim.x voxels; tile t belongs to slot tile_dom[t] and is that slot's
+// (t - tile_first[slot])-th tile. A fixed grid strides over the tiles (persistent launch); the
+// tile count is read from device memory so that a captured graph stays valid when the pool's
+// membership changes. Per-voxel arithmetic is the single-domain one, so every domain's result
+// is bitwise the same alone and in the mix.
+// ------------------------------------------------------------------------------------------
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(256) phase_batched(BatchArgs b) {
+    const int nt = *b.ntiles;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int d = b.tile_dom[t];
+        const StepArgs a = b.doms[d];
+        const int i = (t - b.tile_first[d]) * blockDim.x + threadIdx.x;
+        if (i < a.N) phase_voxel<PREC, ODD>(a, i);
+    }
+}
+
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(256) collide_batched(BatchArgs b) {
+    const int nt = *b.ntiles;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int d = b.tile_dom[t];
+        const StepArgs a = b.doms[d];
+        const int i = (t - b.tile_first[d]) * blockDim.x + threadIdx.x;
+        if (i < a.N) collide_voxel<PREC, ODD>(a, i);
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Per-voxel read-out in FP64 from either storage: N_a, N_b, rho, j.
 // ------------------------------------------------------------------------------------------
@@ -359,14 +397,15 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Partial sums of reduction block `blk` (of kRedBlocks): voxels blk*T + tid + k*kRedBlocks*T.
 template <int PREC, bool ODD>
-__global__ void __launch_bounds__(kRedThreads) reduce_kernel(StepArgs a,
-                                                             double* __restrict__ partials) {
+__device__ __forceinline__ void reduce_block(const StepArgs& a, int blk,
+                                             double* __restrict__ partials) {
     double acc[kNRed];
 #pragma unroll
     for (int k = 0; k < kNRed; ++k) acc[k] = 0.0;
-    const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.N; i += stride) {
+    const int stride = kRedBlocks * kRedThreads;
+    for (int i = blk * kRedThreads + threadIdx.x; i < a.N; i += stride) {
         double na, nbv, rho, jx, jy, jz;
         voxel_state<PREC, ODD>(a, i, na, nbv, rho, jx, jy, jz);
         const double phi = (na - nbv) / (na + nbv);
@@ -409,17 +448,36 @@ __global__ void __launch_bounds__(kRedThreads) reduce_kernel(StepArgs a,
     if (threadIdx.x < kNRed) {
         double s = 0.0;
         for (int w = 0; w < kRedThreads / 64; ++w) s += lds[w][threadIdx.x];
-        partials[(size_t)blockIdx.x * kNRed + threadIdx.x] = s;
+        partials[(size_t)blk * kNRed + threadIdx.x] = s;
     }
 }
 
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(kRedThreads) reduce_kernel(StepArgs a,
+                                                             double* __restrict__ partials) {
+    reduce_block<PREC, ODD>(a, blockIdx.x, partials);
+}
+
+// One group of kRedBlocks blocks per pool slot, with the single-domain decomposition, so a
+// slot's sums are bitwise those of lbm_reduce on the domain alone. Empty slots (N = 0) give 0.
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(kRedThreads) reduce_batched(BatchArgs b,
+                                                              double* __restrict__ partials) {
+    const int slot = blockIdx.x / kRedBlocks;
+    const StepArgs a = b.doms[slot];
+    reduce_block<PREC, ODD>(a, blockIdx.x % kRedBlocks,
+                            partials + (size_t)slot * kRedBlocks * kNRed);
+}
+
+// Fixed-order sum of each group's nblocks partials; one workgroup per group.
 __global__ void reduce_final_kernel(const double* __restrict__ partials, int nblocks,
                                     double* __restrict__ out) {
     const int k = threadIdx.x;
     if (k >= kNRed) return;
+    const double* p = partials + (size_t)blockIdx.x * nblocks * kNRed;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * kNRed + k];
-    out[k] = s;
+    for (int b = 0; b < nblocks; ++b) s += p[(size_t)b * kNRed + k];
+    out[(size_t)blockIdx.x * kNRed + k] = s;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -578,6 +636,44 @@ hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, partials, kRedBlocks, out);
+    return hipGetLastError();
+}
+
+#define LBM_DISPATCH_B(KERNEL, GRID, BLOCK, ...)                                            \
+    do {                                                                                    \
+        if (prec == LBM_FP32_DEV) {                                                         \
+            if (odd)                                                                        \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
+            else                                                                            \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false>), GRID, BLOCK, 0, s, __VA_ARGS__); \
+        } else {                                                                            \
+            if (odd)                                                                        \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, true>), GRID, BLOCK, 0, s, __VA_ARGS__);      \
+            else                                                                            \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, false>), GRID, BLOCK, 0, s, __VA_ARGS__);     \
+        }                                                                                   \
+    } while (0)
+
+hipError_t launch_phase_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
+                                hipStream_t s) {
+    LBM_DISPATCH_B(phase_batched, dim3(grid), dim3(block), b);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
+                                  hipStream_t s) {
+    LBM_DISPATCH_B(collide_batched, dim3(grid), dim3(block), b);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batched(const BatchArgs& b, int prec, bool odd, int nslots,
+                                 double* partials, double* out, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    LBM_DISPATCH_B(reduce_batched, dim3(nslots * kRedBlocks), dim3(kRedThreads), b, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(nslots), dim3(64), 0, s, partials, kRedBlocks,
+                       out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,317 @@
+// Pools: many independent domains advanced together by one launch per kernel per step, with
+// the step loop captured once per chunk as a HIP graph. Contracts: include/lbm.h.
+#include <cstring>
+#include <new>
+
+#include "lbm_domain.h"
+
+using namespace lbm;
+
+struct lbm_pool {
+    int32_t precision = LBM_FP64;
+    int32_t max_slots = 0;
+    int32_t chunk = 100;
+    int64_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<lbm_domain*> slots;
+    int64_t step = 0;
+    int32_t grid = 0, default_grid = 0;
+
+    // Device tables of the batched kernels (fixed addresses, so captured graphs stay valid).
+    StepArgs* d_doms = nullptr;
+    int32_t* d_tile_first = nullptr;
+    int32_t* d_tile_dom = nullptr;
+    int32_t* d_ntiles = nullptr;
+    int64_t tile_cap = 0;
+    double* d_partials = nullptr;
+    double* d_red = nullptr;
+    std::vector<StepArgs> h_doms;
+    std::vector<int32_t> h_tile_first, h_tile_dom;
+    int32_t h_ntiles = 0;
+    bool dirty = true;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t replays = 0, eager = 0;
+
+    BatchArgs batch() const { return BatchArgs{d_doms, d_tile_dom, d_tile_first, d_ntiles}; }
+
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+namespace {
+
+constexpr int kPoolBlock = 256;  // voxels per tile = threads per workgroup
+
+int32_t highest_slot(const lbm_pool* p) {
+    int32_t n = 0;
+    for (int32_t s = 0; s < p->max_slots; ++s)
+        if (p->slots[s]) n = s + 1;
+    return n;
+}
+
+// Rebuild and upload the per-slot arguments and the tile table after a membership change.
+lbm_status upload_tables(lbm_pool* p) {
+    p->h_doms.assign(p->max_slots, StepArgs{});
+    p->h_tile_first.assign(p->max_slots, 0);
+    p->h_tile_dom.clear();
+    for (int32_t s = 0; s < p->max_slots; ++s) {
+        lbm_domain* d = p->slots[s];
+        p->h_tile_first[s] = (int32_t)p->h_tile_dom.size();
+        if (!d) continue;
+        p->h_doms[s] = d->args(kPoolBlock, 1);
+        const int64_t nt = (d->pre.n_pore + kPoolBlock - 1) / kPoolBlock;
+        p->h_tile_dom.insert(p->h_tile_dom.end(), (size_t)nt, s);
+    }
+    p->h_ntiles = (int32_t)p->h_tile_dom.size();
+    if ((int64_t)p->h_tile_dom.size() > p->tile_cap) {
+        // Grow the tile table; its address is baked into the captured graph.
+        int64_t cap = std::max<int64_t>(p->tile_cap * 2, (int64_t)p->h_tile_dom.size());
+        int32_t* ptr = nullptr;
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        HIP_TRY(hipMalloc(&ptr, sizeof(int32_t) * cap));
+        if (p->d_tile_dom) (void)hipFree(p->d_tile_dom);
+        p->d_tile_dom = ptr;
+        p->tile_cap = cap;
+        p->drop_graph();
+    }
+    HIP_TRY(hipMemcpyAsync(p->d_doms, p->h_doms.data(), sizeof(StepArgs) * p->max_slots,
+                           hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_tile_first, p->h_tile_first.data(),
+                           sizeof(int32_t) * p->max_slots, hipMemcpyHostToDevice, p->stream));
+    if (p->h_ntiles)
+        HIP_TRY(hipMemcpyAsync(p->d_tile_dom, p->h_tile_dom.data(),
+                               sizeof(int32_t) * p->h_ntiles, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_ntiles, &p->h_ntiles, sizeof(int32_t), hipMemcpyHostToDevice,
+                           p->stream));
+    // The host vectors stay alive and unchanged until the next upload, which first waits for
+    // the stream, so the asynchronous copies never read a buffer being rewritten.
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->dirty = false;
+    return LBM_OK;
+}
+
+lbm_status launch_steps(lbm_pool* p, int64_t first_step, int64_t n) {
+    const BatchArgs b = p->batch();
+    for (int64_t k = 0; k < n; ++k) {
+        const bool odd = ((first_step + k) & 1) != 0;
+        HIP_TRY(launch_phase_batched(b, p->precision, odd, p->grid, kPoolBlock, p->stream));
+        HIP_TRY(launch_collide_batched(b, p->precision, odd, p->grid, kPoolBlock, p->stream));
+    }
+    return LBM_OK;
+}
+
+lbm_status capture(lbm_pool* p) {
+    p->drop_graph();
+    HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    lbm_status st = launch_steps(p, 0, p->chunk);   // chunks start on even steps
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->stream, &g);
+    if (st != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    p->graph = g;
+    HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+void advance_members(lbm_pool* p, int64_t n) {
+    for (lbm_domain* d : p->slots)
+        if (d) d->step += n;
+    p->step += n;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_pool_create(int64_t hbm_budget_bytes, int32_t precision, int32_t max_slots,
+                           int32_t chunk_steps, void* hip_stream, lbm_pool** out) {
+    if (!out) return fail(LBM_ERR_ARG, "out must be non-null");
+    *out = nullptr;
+    if (hbm_budget_bytes <= 0 || max_slots <= 0 || max_slots > 4096)
+        return fail(LBM_ERR_ARG, "need hbm_budget_bytes > 0 and 0 < max_slots <= 4096");
+    if (precision != LBM_FP64 && precision != LBM_FP32_DEV)
+        return fail(LBM_ERR_ARG, "precision must be LBM_FP64 or LBM_FP32_DEV");
+    if (chunk_steps < 2 || (chunk_steps & 1)) return fail(LBM_ERR_ARG, "chunk_steps must be even and >= 2");
+    lbm_pool* p = new (std::nothrow) lbm_pool();
+    if (!p) return fail(LBM_ERR_OOM, "host allocation failed");
+    p->precision = precision;
+    p->max_slots = max_slots;
+    p->chunk = chunk_steps;
+    p->budget = hbm_budget_bytes;
+    p->slots.assign(max_slots, nullptr);
+    auto bail = [&](lbm_status s, const std::string& m) {
+        lbm_pool_destroy(p);
+        return fail(s, m);
+    };
+    if (hip_stream) {
+        p->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(LBM_ERR_DEVICE, "stream creation failed");
+        p->own_stream = true;
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return bail(LBM_ERR_DEVICE, "device query failed");
+    p->default_grid = p->grid = std::max(1, cus) * 8;
+    p->tile_cap = 1 << 16;
+    if (hipMalloc(&p->d_doms, sizeof(StepArgs) * max_slots) != hipSuccess ||
+        hipMalloc(&p->d_tile_first, sizeof(int32_t) * max_slots) != hipSuccess ||
+        hipMalloc(&p->d_tile_dom, sizeof(int32_t) * p->tile_cap) != hipSuccess ||
+        hipMalloc(&p->d_ntiles, sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&p->d_partials, sizeof(double) * kNRed * kRedBlocks * (size_t)max_slots) !=
+            hipSuccess ||
+        hipMalloc(&p->d_red, sizeof(double) * kNRed * (size_t)max_slots) != hipSuccess)
+        return bail(LBM_ERR_OOM, "device allocation failed");
+    if (lbm_status s = upload_tables(p)) {
+        lbm_pool_destroy(p);
+        return s;
+    }
+    *out = p;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_admit(lbm_pool* p, lbm_domain* d, int32_t* slot) {
+    if (!p || !d || !slot) return fail(LBM_ERR_ARG, "null argument");
+    if (d->pool) return fail(LBM_ERR_STATE, "the domain already belongs to a pool");
+    if (d->p.precision != p->precision) return fail(LBM_ERR_STATE, "precision differs from the pool's");
+    if (d->p.bc_z != 0) return fail(LBM_ERR_STATE, "pools take domains without pressure faces");
+    if ((d->step & 1) != (p->step & 1))
+        return fail(LBM_ERR_STATE, "step parity differs from the pool's");
+    if (d->unstable) return fail(LBM_ERR_UNSTABLE, "the domain is unstable");
+    if (p->used + d->device_bytes > p->budget) return fail(LBM_ERR_OOM, "HBM budget exhausted");
+    int32_t s = -1;
+    for (int32_t k = 0; k < p->max_slots && s < 0; ++k)
+        if (!p->slots[k]) s = k;
+    if (s < 0) return fail(LBM_ERR_OOM, "no free slot");
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    d->own_stream_saved = d->stream;
+    d->stream = p->stream;
+    d->pool = p;
+    p->slots[s] = d;
+    p->used += d->device_bytes;
+    p->dirty = true;
+    *slot = s;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_retire(lbm_pool* p, int32_t slot) {
+    if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot])
+        return fail(LBM_ERR_ARG, "no member in that slot");
+    lbm_domain* d = p->slots[slot];
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    d->stream = d->own_stream_saved;
+    d->own_stream_saved = nullptr;
+    d->pool = nullptr;
+    p->slots[slot] = nullptr;
+    p->used -= d->device_bytes;
+    p->dirty = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_step(lbm_pool* p, int64_t nsteps) {
+    if (!p) return fail(LBM_ERR_ARG, "null pool");
+    if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
+    for (lbm_domain* d : p->slots)
+        if (d && d->unstable) return fail(LBM_ERR_UNSTABLE, "a member is unstable; retire it");
+    if (p->dirty)
+        if (lbm_status s = upload_tables(p)) return s;
+    int64_t left = nsteps;
+    while (left > 0) {
+        if (p->h_ntiles == 0) {             // no members: only the step count moves
+            advance_members(p, left);
+            break;
+        }
+        if (left >= p->chunk && (p->step & 1) == 0) {
+            if (!p->exec)
+                if (lbm_status s = capture(p)) return s;
+            HIP_TRY(hipGraphLaunch(p->exec, p->stream));
+            ++p->replays;
+            advance_members(p, p->chunk);
+            left -= p->chunk;
+        } else {
+            if (lbm_status s = launch_steps(p, p->step, 1)) return s;
+            ++p->eager;
+            advance_members(p, 1);
+            left -= 1;
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_reduce(lbm_pool* p, lbm_reduction* out, int32_t max_count, int32_t* count) {
+    if (!p || !count || (max_count > 0 && !out)) return fail(LBM_ERR_ARG, "null argument");
+    if (p->dirty)
+        if (lbm_status s = upload_tables(p)) return s;
+    const int32_t n = std::min(highest_slot(p), std::max(max_count, 0));
+    std::vector<double> acc((size_t)std::max(n, 1) * kNRed);
+    if (n > 0) {
+        HIP_TRY(launch_reduce_batched(p->batch(), p->precision, (p->step & 1) != 0, n,
+                                      p->d_partials, p->d_red, p->stream));
+        HIP_TRY(hipMemcpyAsync(acc.data(), p->d_red, sizeof(double) * kNRed * n,
+                               hipMemcpyDeviceToHost, p->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    for (int32_t s = 0; s < n; ++s) {
+        if (p->slots[s]) {
+            finish_reduction(p->slots[s], &acc[(size_t)s * kNRed], p->slots[s]->step, &out[s]);
+            if (out[s].unstable) p->slots[s]->unstable = true;
+        } else {
+            std::memset(&out[s], 0, sizeof out[s]);
+        }
+    }
+    *count = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_get_info(lbm_pool* p, lbm_pool_info* out) {
+    if (!p || !out) return fail(LBM_ERR_ARG, "null argument");
+    std::memset(out, 0, sizeof *out);
+    out->max_slots = p->max_slots;
+    for (lbm_domain* d : p->slots) out->members += d ? 1 : 0;
+    out->chunk_steps = p->chunk;
+    out->grid = p->grid;
+    out->step = p->step;
+    out->used_bytes = p->used;
+    out->budget_bytes = p->budget;
+    out->tiles = p->dirty ? -1 : p->h_ntiles;
+    out->graph_replays = p->replays;
+    out->eager_steps = p->eager;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_set_grid(lbm_pool* p, int32_t grid) {
+    if (!p || grid < 0 || grid > (1 << 20)) return fail(LBM_ERR_ARG, "bad grid");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->grid = grid ? grid : p->default_grid;
+    p->drop_graph();
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_destroy(lbm_pool* p) {
+    if (!p) return LBM_OK;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    for (int32_t s = 0; s < (int32_t)p->slots.size(); ++s)
+        if (p->slots[s]) (void)lbm_pool_retire(p, s);
+    p->drop_graph();
+    void* bufs[] = {p->d_doms, p->d_tile_first, p->d_tile_dom, p->d_ntiles, p->d_partials,
+                    p->d_red};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+    return LBM_OK;
+}
+
+}  // extern "C"

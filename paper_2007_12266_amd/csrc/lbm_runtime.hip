@@ -9,11 +9,11 @@
 #include <string>
 #include <vector>
 
-#include "lbm_internal.h"
+#include "lbm_domain.h"
 
 using namespace lbm;
 
-namespace {
+namespace lbm {
 
 thread_local std::string g_err;
 
@@ -22,12 +22,9 @@ lbm_status fail(lbm_status s, const std::string& msg) {
     return s;
 }
 
-#define HIP_TRY(expr)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(LBM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace lbm
+
+namespace {
 
 constexpr uint64_t kStateMagic = 0x4c424d434f4c5231ull;  // "LBMCOLR1"
 
@@ -39,93 +36,6 @@ struct StateHeader {
 
 }  // namespace
 
-struct lbm_domain {
-    lbm_params p{};
-    Prepass pre;
-    int block = 256;                 // read-back and init kernels
-    lbm_tuning tune{256, 2, 256, 2, 0.0, 0.0};
-    lbm_allocator alloc{};
-    bool has_alloc = false;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    std::vector<void*> allocations;
-    int64_t device_bytes = 0;
-
-    void* f = nullptr;
-    void* A = nullptr;
-    void* B = nullptr;
-    void* phi = nullptr;      // [N + n_tail] storage type
-    void* ntot = nullptr;     // [N] storage type
-    double* stage = nullptr;  // [ld] doubles: initial phase upload and field read-back
-    int32_t* nbr = nullptr;
-    double* red_partials = nullptr;
-    double* red_out = nullptr;
-    double* hist = nullptr;
-    int32_t hist_cap = 1024;
-    int32_t hist_head = 0;    // next slot to write
-    int32_t hist_count = 0;   // unread entries
-    std::vector<int64_t> hist_step;
-    int32_t* faces = nullptr;       // inlet then outlet pore indices (bc_z == 1)
-    int32_t* ghost_tail = nullptr;  // z-face mirror entries of the phi tail
-    int32_t* ghost_src = nullptr;
-
-    int64_t step = 0;
-    bool unstable = false;
-    bool record_history = true;
-
-    // Kernel arguments for a launch with `blk` threads per workgroup and schedule `sched`.
-    StepArgs args(int blk = 256, int sched = 1) const {
-        StepArgs a{};
-        a.N = (int32_t)pre.n_pore;
-        a.nblocks = (int32_t)((pre.n_pore + blk - 1) / blk);
-        a.ld = pre.ld;
-        a.nbr = nbr;
-        a.phi = phi;
-        a.ntot = ntot;
-        a.f = f;
-        a.A = A;
-        a.B = B;
-        a.nu_a = (p.tau_a - 0.5) / 3.0;
-        a.nu_b = (p.tau_b - 0.5) / 3.0;
-        a.alpha = p.alpha;
-        a.beta = p.beta;
-        for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
-        a.xcd_remap = sched == 2 ? 1 : 0;
-        a.prec = p.precision;
-        return a;
-    }
-
-    void* dalloc(size_t bytes) {
-        bytes = std::max<size_t>(bytes, 256);
-        void* ptr = nullptr;
-        if (has_alloc) {
-            ptr = alloc.alloc(bytes, alloc.ctx);
-        } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
-            ptr = nullptr;
-        }
-        if (ptr) {
-            allocations.push_back(ptr);
-            device_bytes += (int64_t)bytes;
-        }
-        return ptr;
-    }
-
-    void release() {
-        if (stream) (void)hipStreamSynchronize(stream);
-        for (void* ptr : allocations) {
-            if (has_alloc)
-                alloc.free(ptr, alloc.ctx);
-            else
-                (void)hipFree(ptr);
-        }
-        allocations.clear();
-        device_bytes = 0;
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-        stream = nullptr;
-    }
-
-    size_t elem_bytes() const { return p.precision == LBM_FP32_DEV ? 4 : 8; }
-};
 
 namespace {
 
@@ -135,7 +45,10 @@ lbm_status record_reduction(lbm_domain* d, double* out) {
     return LBM_OK;
 }
 
-void finish_reduction(const lbm_domain* d, const double* acc, int64_t step, lbm_reduction* r) {
+}  // namespace
+
+void lbm::finish_reduction(const lbm_domain* d, const double* acc, int64_t step,
+                           lbm_reduction* r) {
     const double N = (double)d->pre.n_pore;
     const double nbox = (double)d->p.nx * d->p.ny * d->p.nz;
     std::memset(r, 0, sizeof *r);
@@ -161,6 +74,8 @@ void finish_reduction(const lbm_domain* d, const double* acc, int64_t step, lbm_
     r->step = step;
     r->unstable = acc[24] > 0 ? 1 : 0;
 }
+
+namespace {
 
 lbm_status check_domain(lbm_domain* d) {
     if (!d) return fail(LBM_ERR_ARG, "null domain");
@@ -362,12 +277,14 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
 
 lbm_status lbm_step(lbm_domain* d, int64_t nsteps) {
     if (lbm_status s = check_domain(d)) return s;
+    if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool; step the pool");
     return step_impl(d, nsteps, nullptr);
 }
 
 lbm_status lbm_step_timed(lbm_domain* d, int64_t nsteps, lbm_timing* out) {
     if (lbm_status s = check_domain(d)) return s;
     if (!out) return fail(LBM_ERR_ARG, "out must be non-null");
+    if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool; step the pool");
     return step_impl(d, nsteps, out);
 }
 
@@ -462,6 +379,7 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
 lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes) {
     if (lbm_status s = check_domain(d)) return s;
     if (!host_buf) return fail(LBM_ERR_ARG, "host_buf must be non-null");
+    if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool; retire it first");
     const size_t eb = d->elem_bytes();
     const size_t n = (size_t)d->pre.n_pore, ld = (size_t)d->pre.ld;
     StateHeader h;
@@ -523,6 +441,7 @@ lbm_status lbm_get_tuning(lbm_domain* d, lbm_tuning* out) {
 lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     if (lbm_status s = check_domain(d)) return s;
     if (trial_steps < 2) return fail(LBM_ERR_ARG, "trial_steps must be >= 2");
+    if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool");
     if (d->unstable) return fail(LBM_ERR_UNSTABLE, "domain is unstable; load a state");
     trial_steps += trial_steps & 1;  // even: both parities equally
     const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
@@ -627,6 +546,7 @@ lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, in
 
 lbm_status lbm_domain_destroy(lbm_domain* d) {
     if (!d) return LBM_OK;
+    if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool; retire it first");
     d->release();
     delete d;
     return LBM_OK;

@@ -25,6 +25,8 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_read_pore_field", "lbm_pore_index", "lbm_reduce", "lbm_read_history",
            "lbm_state_save", "lbm_state_load", "lbm_domain_get_info", "lbm_domain_destroy",
            "lbm_prepass_query", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
+           "lbm_pool_create", "lbm_pool_admit", "lbm_pool_retire", "lbm_pool_step",
+           "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_destroy",
            "lbm_last_error", "lbm_version")
 
 
@@ -87,6 +89,14 @@ class Info(ctypes.Structure):
                 ("block_size", ctypes.c_int32)]
 
 
+class PoolInfo(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("members", ctypes.c_int32),
+                ("chunk_steps", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("step", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("graph_replays", ctypes.c_int64), ("eager_steps", ctypes.c_int64)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -126,6 +136,14 @@ def load_library(path: str = LIB_PATH):
     L.lbm_autotune.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
     L.lbm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.lbm_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.lbm_pool_create.argtypes = [i64, i32, i32, i32, vp, ctypes.POINTER(vp)]
+    L.lbm_pool_admit.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    L.lbm_pool_retire.argtypes = [vp, i32]
+    L.lbm_pool_step.argtypes = [vp, i64]
+    L.lbm_pool_reduce.argtypes = [vp, ctypes.POINTER(Reduction), i32, ctypes.POINTER(i32)]
+    L.lbm_pool_get_info.argtypes = [vp, ctypes.POINTER(PoolInfo)]
+    L.lbm_pool_set_grid.argtypes = [vp, i32]
+    L.lbm_pool_destroy.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -247,7 +265,7 @@ class Domain:
 
     def close(self):
         if getattr(self, "handle", None):
-            load_library().lbm_domain_destroy(self.handle)
+            _check(load_library().lbm_domain_destroy(self.handle))
             self.handle = None
 
     def __del__(self):
@@ -329,3 +347,61 @@ class Domain:
         i = Info()
         _check(load_library().lbm_domain_get_info(self.handle, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in Info._fields_}
+
+
+class Pool:
+    """Many domains stepped together by one launch per kernel per step (wraps lbm_pool*)."""
+
+    def __init__(self, budget_bytes: int, precision: int = FP32_DEV, max_slots: int = 64,
+                 chunk_steps: int = 100, stream=None):
+        L = load_library()
+        h = ctypes.c_void_p()
+        _check(L.lbm_pool_create(int(budget_bytes), int(precision), int(max_slots),
+                                 int(chunk_steps), None if stream is None else
+                                 ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.handle = h
+        self.max_slots = max_slots
+        self.members = {}
+
+    def admit(self, dom: Domain) -> int:
+        slot = ctypes.c_int32()
+        _check(load_library().lbm_pool_admit(self.handle, dom.handle, ctypes.byref(slot)))
+        self.members[slot.value] = dom
+        return slot.value
+
+    def retire(self, slot: int) -> Domain:
+        _check(load_library().lbm_pool_retire(self.handle, int(slot)))
+        return self.members.pop(slot)
+
+    def step(self, n: int):
+        _check(load_library().lbm_pool_step(self.handle, int(n)))
+        return self
+
+    def reduce(self) -> dict:
+        """Reductions of every member, keyed by slot."""
+        arr = (Reduction * self.max_slots)()
+        n = ctypes.c_int32()
+        _check(load_library().lbm_pool_reduce(self.handle, arr, self.max_slots,
+                                              ctypes.byref(n)))
+        return {s: arr[s].as_dict() for s in range(n.value) if s in self.members}
+
+    def info(self) -> dict:
+        i = PoolInfo()
+        _check(load_library().lbm_pool_get_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in PoolInfo._fields_}
+
+    def set_grid(self, grid: int):
+        _check(load_library().lbm_pool_set_grid(self.handle, int(grid)))
+        return self
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().lbm_pool_destroy(self.handle)
+            self.handle = None
+            self.members = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

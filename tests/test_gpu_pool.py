@@ -1,0 +1,132 @@
+"""Pools: uneven domains stepped by one batched launch per kernel, graph-captured chunks.
+
+The per-voxel arithmetic is the single-domain one, so a member's state must be bitwise the same
+as stepping it alone, whatever else is in the pool and however membership changes.
+"""
+import numpy as np
+import pytest
+
+from paper_2007_12266_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_12266_amd import lbm as mod
+    mod.load_library()
+    return mod
+
+
+def _problem(seed, shape, tau=(0.7, 0.7), alpha=0.005, force=(0, 0, 1e-5), sw=0.5, aff=0.3):
+    rng = np.random.default_rng(seed)
+    solid, _ = inputs.grf_rock(shape, 4.0, rng.uniform(0.2, 0.35), seed)
+    labels = np.where(solid > 0, 0, 1).astype(np.int32)
+    return inputs.Problem(labels=labels,
+                          label_kind=np.array([inputs.KIND_SOLID, inputs.KIND_PORE_INIT], np.int8),
+                          label_affinity=np.array([aff, 0.0]),
+                          init_phi=inputs.bernoulli_phase(shape, sw, seed + 1),
+                          periodic=(True, True, True), tau_a=tau[0], tau_b=tau[1], alpha=alpha,
+                          force=force)
+
+
+def _mix():
+    return [_problem(1, (20, 24, 28)),
+            _problem(2, (33, 17, 25), tau=(0.9, 0.6), alpha=0.01, aff=-0.6),
+            _problem(3, (16, 16, 16), force=(1e-5, 0, 0), sw=0.3),
+            _problem(4, (40, 21, 19), aff=0.8),
+            _problem(5, (12, 30, 22), tau=(0.65, 0.8), sw=0.7)]
+
+
+@pytest.mark.parametrize("precision", ["fp32dev", "fp64"])
+def test_members_match_solo_runs_bitwise(lbm, precision):
+    prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
+    probs = _mix()
+    pool = lbm.Pool(1 << 34, precision=prec, max_slots=8, chunk_steps=20)
+    doms = [lbm.Domain(p, precision=prec) for p in probs]
+    slots = [pool.admit(d) for d in doms]
+    pool.step(53)                                  # 2 graph replays + 13 eager steps
+    info = pool.info()
+    assert info["graph_replays"] == 2 and info["eager_steps"] == 13 and info["members"] == 5
+    red = pool.reduce()
+    for p, d, s in zip(probs, doms, slots):
+        solo = lbm.Domain(p, precision=prec)
+        solo.step(53)
+        assert d.info()["step"] == 53
+        assert d.save() == solo.save()
+        assert red[s] == solo.reduce()
+        solo.close()
+    pool.close()
+    for d in doms:
+        d.step(1)                                   # back on their own streams after close
+        d.close()
+
+
+def test_membership_changes_keep_results(lbm):
+    probs = _mix()
+    pool = lbm.Pool(1 << 34, precision=lbm.FP32_DEV, max_slots=3, chunk_steps=10)
+    a, b, c = (lbm.Domain(p, precision=lbm.FP32_DEV) for p in probs[:3])
+    sa, sb = pool.admit(a), pool.admit(b)
+    pool.step(30)
+    pool.retire(sa)
+    sc = pool.admit(c)                              # joins at pool step 30 (even), own step 0
+    assert sc == sa                                 # the freed slot is reused
+    pool.step(24)
+    assert a.info()["step"] == 30 and b.info()["step"] == 54 and c.info()["step"] == 24
+    for dom, prob, n in ((a, probs[0], 30), (b, probs[1], 54), (c, probs[2], 24)):
+        solo = lbm.Domain(prob, precision=lbm.FP32_DEV)
+        solo.step(n)
+        assert dom.save() == solo.save()
+        solo.close()
+    a.step(2)                                       # a retired domain steps on its own again
+    pool.close()
+    for d in (a, b, c):
+        d.close()
+
+
+def test_admission_rules(lbm):
+    probs = _mix()
+    d64 = lbm.Domain(probs[0])
+    d32 = lbm.Domain(probs[1], precision=lbm.FP32_DEV)
+    pool = lbm.Pool(d32.info()["device_bytes"] + 1, precision=lbm.FP32_DEV, max_slots=2,
+                    chunk_steps=2)
+    with pytest.raises(lbm.LbmError) as e:
+        pool.admit(d64)
+    assert e.value.status == lbm.LBM_ERR_STATE                    # precision
+    slot = pool.admit(d32)
+    with pytest.raises(lbm.LbmError) as e:
+        d32.step(1)
+    assert e.value.status == lbm.LBM_ERR_STATE                    # pooled domain
+    with pytest.raises(lbm.LbmError) as e:
+        d32.close()
+    assert e.value.status == lbm.LBM_ERR_STATE
+    big = lbm.Domain(probs[3], precision=lbm.FP32_DEV)
+    with pytest.raises(lbm.LbmError) as e:
+        pool.admit(big)
+    assert e.value.status == lbm.LBM_ERR_OOM                      # budget
+    pool.step(1)
+    small = lbm.Domain(probs[2], precision=lbm.FP32_DEV)
+    pool2 = lbm.Pool(1 << 34, precision=lbm.FP32_DEV, max_slots=1, chunk_steps=2)
+    pool2.step(1)
+    with pytest.raises(lbm.LbmError) as e:
+        pool2.admit(small)
+    assert e.value.status == lbm.LBM_ERR_STATE                    # parity
+    pool2.step(1)
+    pool2.admit(small)
+    with pytest.raises(lbm.LbmError) as e:
+        pool2.admit(big)
+    assert e.value.status == lbm.LBM_ERR_OOM                      # slots
+    disp = lbm.Domain(inputs.displacement_problem(shape=(24, 12, 12), seed_geom=7,
+                                                  porosity_target=0.35),
+                      precision=lbm.FP32_DEV)
+    pool.retire(slot)
+    with pytest.raises(lbm.LbmError) as e:
+        pool.admit(disp)
+    assert e.value.status == lbm.LBM_ERR_STATE                    # pressure faces
+    pool.close()
+    pool2.close()
+    for d in (d64, d32, big, small, disp):
+        d.close()
