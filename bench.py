@@ -113,12 +113,153 @@ def _profiled_traffic(precision: str):
     return None
 
 
+def batch_main(args):
+    """64 independent sub-volumes (edges U{48..160}, porosity U[0.15,0.35], affinity
+    U[-0.9,0.9], Sw U[0.2,0.8], periodic, F_z = 1e-5), 3000 steps each: FP32-deviation storage in
+    one pool (one batched launch per kernel per step, 100-step chunks replayed from a captured
+    HIP graph, FP64 reductions after every chunk) against the plain FP64 path run one volume at
+    a time with reductions every 100 steps. Domain creation (pre-pass and upload) is outside both
+    timed regions."""
+    import torch
+    from paper_2007_12266_amd import inputs, lbm
+
+    steps = args.steps if args.steps_given else 3000
+    chunk = 100
+    t0 = time.perf_counter()
+    probs = inputs.batch_volumes(64)
+    n_tot = sum(p.n_pore() for p in probs)
+    log("64 volumes generated in %.1f s, %d pore voxels" % (time.perf_counter() - t0, n_tot))
+    torch.cuda.set_device(0)
+    doms = [lbm.Domain(p, precision=lbm.FP32_DEV, allocator="hip") for p in probs]
+    budget = sum(d.info()["device_bytes"] for d in doms)
+    pool = lbm.Pool(budget, precision=lbm.FP32_DEV, max_slots=64, chunk_steps=chunk)
+    for d in doms:
+        pool.admit(d)
+    grid = pool.autotune(10)
+    log("pool grid %d" % grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reds = []
+    for _ in range(steps // chunk):
+        pool.step(chunk)
+        reds.append(pool.reduce())
+    torch.cuda.synchronize()
+    t_pool = time.perf_counter() - t0
+    info = pool.info()
+    final32 = reds[-1]
+    pool.close()
+    for d in doms:
+        d.close()
+    log("pool: %d steps in %.2f s (%d graph replays)" % (steps, t_pool, info["graph_replays"]))
+
+    # Baseline: the plain FP64 path, one volume at a time.
+    t_base = 0.0
+    final64 = {}
+    for k, p in enumerate(probs):
+        d = lbm.Domain(p, precision=lbm.FP64, reduce_every=chunk, allocator="hip")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d.step(steps)
+        hist = d.history()
+        torch.cuda.synchronize()
+        t_base += time.perf_counter() - t0
+        final64[k] = hist[-1]
+        d.close()
+    log("fp64 one at a time: %.2f s" % t_base)
+    errs_sw = [abs(final32[k]["sw"] - final64[k]["sw"]) / final64[k]["sw"] for k in range(64)]
+    errs_m = [abs(final32[k]["mass_a"] - final64[k]["mass_a"]) / final64[k]["mass_a"]
+              for k in range(64)]
+    errs_q = [abs(final32[k]["qz"] - final64[k]["qz"]) / max(abs(final64[k]["qz"]), 1e-300)
+              for k in range(64)]
+    out = {
+        "metric": METRIC,
+        "value": round(64 / t_pool, 4),
+        "unit": "solves/s (64 volumes x %d steps)" % steps,
+        "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(t_pool / steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched: 64 GRF sub-volumes, edges U{48..160}, porosity "
+                               "U[0.15,0.35], affinity U[-0.9,0.9], Sw U[0.2,0.8], periodic, "
+                               "Fz=1e-5, FP32-deviation storage, FP64 reductions every 100 steps",
+                   "n_pore_total": n_tot, "chunk_steps": chunk, "pool_grid": grid,
+                   "graph_replays": info["graph_replays"]},
+        "aggregate_mlups": round(n_tot * steps / t_pool / 1e6, 1),
+        "fp64_one_at_a_time": {"seconds": round(t_base, 3), "solves_per_s": round(64 / t_base, 4),
+                               "aggregate_mlups": round(n_tot * steps / t_base / 1e6, 1)},
+        "speedup_vs_fp64_serial": round(t_base / t_pool, 3),
+        "fp32_vs_fp64_final": {"sw_rel_max": max(errs_sw), "mass_a_rel_max": max(errs_m),
+                               "qz_rel_median": float(np.median(errs_q)),
+                               "qz_rel_max": max(errs_q)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_main(args):
+    """Serving: Poisson arrivals (rate 2/s, seed 200) of steady-state solve requests, each a
+    periodic GRF cube of edge L ~ U{64..L_max} with porosity, affinity and Sw drawn as for the
+    batched volumes, run until |Sw(t) - Sw(t-1000)| < 1e-5 or 20000 steps. FP32-deviation
+    storage, FP64 reductions, admission by HBM budget, continuous batching in one pool; the
+    baseline is the plain FP64 path serving the same trace one request at a time."""
+    import torch
+    from paper_2007_12266_amd import inputs, lbm, serve
+
+    count = args.requests
+    lmax = args.serve_lmax
+    t0 = time.perf_counter()
+    reqs = serve.poisson_trace(count, 2.0, 200,
+                               lambda k: inputs.serving_problem(k, seed0=200, edge=(64, lmax)))
+    log("%d requests generated in %.1f s" % (count, time.perf_counter() - t0))
+    torch.cuda.set_device(0)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    srv = serve.Server(budget, precision=lbm.FP32_DEV, chunk=200, graph_chunk=100,
+                       max_slots=64, workers=4)
+    res = srv.run(reqs, realtime=True)
+    info = srv.pool.info()
+    srv.close()
+    st = serve.latency_stats(res)
+    log("served: %s" % st)
+    base = serve.fifo_baseline(reqs, precision=lbm.FP64, chunk=1000)
+    sb = serve.latency_stats(base)
+    log("fp64 fifo: %s" % sb)
+    lups = sum(r.n_pore * r.steps for r in res)
+    span = max(r.completed for r in res) - min(r.arrival for r in res)
+    out = {
+        "metric": METRIC,
+        "value": round(st["solves_per_s"], 4),
+        "unit": "solves/s (continuous batching, FP32-dev)",
+        "n_gpus": 1, "steps": int(sum(r.steps for r in res)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals 2/s (seed 200), %d requests, periodic "
+                               "GRF cubes L~U{64..%d}, porosity U[0.15,0.35], affinity "
+                               "U[-0.9,0.9], Sw U[0.2,0.8], Fz=1e-5, stop at |dSw|<1e-5 per 1000 "
+                               "steps or 20000 steps; HBM budget %.0f GiB"
+                               % (count, lmax, args.serve_budget_gb),
+                   "chunk_steps": 200, "graph_replays": info["graph_replays"]},
+        "latency_p50_s": round(st["p50_s"], 3), "latency_p99_s": round(st["p99_s"], 3),
+        "converged": st["converged"], "pore_lups_total": lups,
+        "aggregate_mlups": round(lups / span / 1e6, 1),
+        "fp64_fifo": {"solves_per_s": round(sb["solves_per_s"], 4),
+                      "latency_p50_s": round(sb["p50_s"], 3),
+                      "latency_p99_s": round(sb["p99_s"], 3), "converged": sb["converged"]},
+        "solves_per_s_ratio_vs_fp64_fifo": round(st["solves_per_s"] / sb["solves_per_s"], 3),
+        "fp32_vs_fp64_final_sw_rel_max": max(abs(a.final["sw"] - b.final["sw"]) / b.final["sw"]
+                                             for a, b in zip(res, base)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="grf256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="grf256",
+                    choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--requests", type=int, default=16, help="serve: number of requests")
+    ap.add_argument("--serve-lmax", type=int, default=192, help="serve: largest cube edge")
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0, help="serve: HBM budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32dev"])
@@ -127,10 +268,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        batch_main(args)
+        return
+    if args.workload == "serve":
+        serve_main(args)
+        return
 
     import torch
     from paper_2007_12266_amd import inputs, lbm

@@ -204,6 +204,14 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out);
 lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t);
 lbm_status lbm_get_tuning(lbm_domain* d, lbm_tuning* out);
 
+/* Host-only: *bytes receives exactly the device memory lbm_domain_create would allocate for
+ * these arguments (runs the CPU pre-pass; no GPU needed). For admission control by HBM budget
+ * before anything is allocated. Same errors as lbm_domain_create's argument checks. */
+lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
+                                int32_t n_labels, const int8_t* label_kind,
+                                const double* label_affinity, const double* voxel_affinity,
+                                const double* init_phi, int64_t* bytes);
+
 /* Host-only inspection of the sparse layout a domain would use (no GPU needed): runs the CPU
  * pre-pass on the same arguments as lbm_domain_create and reports *n_pore and *n_tail. Each
  * nullable output array, if given, must hold: pore_voxel[n_pore] (dense index of each pore
@@ -261,6 +269,12 @@ lbm_status lbm_pool_get_info(lbm_pool* pool, lbm_pool_info* out);
 /* Set the number of workgroups of the batched step kernels (e.g. from an autotuner);
  * 0 restores the default. Invalidates the captured graph. */
 lbm_status lbm_pool_set_grid(lbm_pool* pool, int32_t grid);
+
+/* Autotuner for the batched launch: times each candidate workgroup count (multiples of the
+ * compute-unit count) over trial_steps >= 2 steps of the current members, applies the fastest
+ * and writes it to *grid (nullable). Every member's state and step counter are restored, so
+ * later results are unchanged. Needs device memory for one copy of the members' populations. */
+lbm_status lbm_pool_autotune(lbm_pool* pool, int32_t trial_steps, int32_t* grid);
 
 /* Retire every member and free the pool. NULL is accepted. */
 lbm_status lbm_pool_destroy(lbm_pool* pool);

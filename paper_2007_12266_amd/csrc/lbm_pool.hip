@@ -299,6 +299,91 @@ lbm_status lbm_pool_set_grid(lbm_pool* p, int32_t grid) {
     return LBM_OK;
 }
 
+lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
+    if (!p) return fail(LBM_ERR_ARG, "null pool");
+    if (trial_steps < 2) return fail(LBM_ERR_ARG, "trial_steps must be >= 2");
+    trial_steps += trial_steps & 1;
+    if (p->dirty)
+        if (lbm_status s = upload_tables(p)) return s;
+    // Snapshot every member's populations (device to device).
+    struct Snap { lbm_domain* d; void* buf; size_t bytes; };
+    std::vector<Snap> snaps;
+    lbm_status st = LBM_OK;
+    for (lbm_domain* d : p->slots) {
+        if (!d) continue;
+        const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
+        Snap sn{d, nullptr, eb * 33 * ld};
+        if (hipMalloc(&sn.buf, sn.bytes) != hipSuccess) {
+            st = fail(LBM_ERR_OOM, "no device memory for the autotuner's snapshot");
+            break;
+        }
+        snaps.push_back(sn);
+        size_t off = 0;
+        void* arr[3] = {d->f, d->A, d->B};
+        const size_t rows[3] = {19, 7, 7};
+        for (int k = 0; k < 3 && st == LBM_OK; ++k) {
+            if (hipMemcpyAsync((char*)sn.buf + off, arr[k], eb * rows[k] * ld,
+                               hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+                st = fail(LBM_ERR_DEVICE, "snapshot copy failed");
+            off += eb * rows[k] * ld;
+        }
+    }
+    const int64_t step0 = p->step;
+    std::vector<int64_t> dstep0;
+    for (const Snap& sn : snaps) dstep0.push_back(sn.d->step);
+    const int32_t keep = p->grid;
+    int32_t best = keep;
+    double best_ms = 1e30;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == LBM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(LBM_ERR_DEVICE, "event creation failed");
+    const int mult[5] = {2, 4, 8, 16, 32};
+    for (int c = 0; c < 5 && st == LBM_OK && p->h_ntiles > 0; ++c) {
+        p->grid = std::max(1, p->default_grid / 8) * mult[c];
+        st = launch_steps(p, p->step, 2);                      // warm-up
+        if (st != LBM_OK) break;
+        if (hipEventRecord(e0, p->stream) != hipSuccess) { st = fail(LBM_ERR_DEVICE, "event"); break; }
+        st = launch_steps(p, p->step + 2, trial_steps);
+        if (st != LBM_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(LBM_ERR_DEVICE, "event timing failed");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = p->grid;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    // Restore states; the trial steps came in even numbers, so parities are unchanged.
+    for (size_t k = 0; k < snaps.size(); ++k) {
+        lbm_domain* d = snaps[k].d;
+        const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
+        size_t off = 0;
+        void* arr[3] = {d->f, d->A, d->B};
+        const size_t rows[3] = {19, 7, 7};
+        for (int a = 0; a < 3; ++a) {
+            if (hipMemcpyAsync(arr[a], (char*)snaps[k].buf + off, eb * rows[a] * ld,
+                               hipMemcpyDeviceToDevice, p->stream) != hipSuccess &&
+                st == LBM_OK)
+                st = fail(LBM_ERR_DEVICE, "restore copy failed");
+            off += eb * rows[a] * ld;
+        }
+        d->step = dstep0[k];
+    }
+    p->step = step0;
+    if (hipStreamSynchronize(p->stream) != hipSuccess && st == LBM_OK)
+        st = fail(LBM_ERR_DEVICE, "synchronise failed");
+    for (const Snap& sn : snaps) (void)hipFree(sn.buf);
+    p->grid = st == LBM_OK ? best : keep;
+    p->drop_graph();
+    if (st == LBM_OK && grid) *grid = p->grid;
+    return st;
+}
+
 lbm_status lbm_pool_destroy(lbm_pool* p) {
     if (!p) return LBM_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);

@@ -158,9 +158,39 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
 
 }  // namespace
 
+// Device bytes lbm_domain_create allocates for a pre-passed input (every buffer is rounded up to
+// 256 bytes by lbm_domain::dalloc).
+static int64_t domain_bytes(const lbm_params& p, const Prepass& pre) {
+    const size_t eb = p.precision == LBM_FP32_DEV ? 4 : 8, ld = (size_t)pre.ld;
+    auto r = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
+    int64_t total = r(eb * 19 * ld) + 2 * r(eb * 7 * ld) +
+                    r(eb * (size_t)(pre.n_pore + pre.n_tail)) + r(eb * ld) +
+                    r(sizeof(double) * ld) + r(sizeof(int32_t) * 18 * ld) +
+                    r(sizeof(double) * kRedBlocks * kNRed) + r(sizeof(double) * kNRed) +
+                    r(sizeof(double) * 1024 * kNRed);
+    const size_t faces = pre.inlet.size() + pre.outlet.size();
+    if (faces) total += r(sizeof(int32_t) * faces);
+    if (!pre.ghost_tail.empty()) total += 2 * r(sizeof(int32_t) * pre.ghost_tail.size());
+    return total;
+}
+
 extern "C" {
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
+                                int32_t n_labels, const int8_t* label_kind,
+                                const double* label_affinity, const double* voxel_affinity,
+                                const double* init_phi, int64_t* bytes) {
+    g_err.clear();
+    if (!params || !bytes) return fail(LBM_ERR_ARG, "null argument");
+    Prepass pre;
+    std::string err = prepass(*params, labels, n_labels, label_kind, label_affinity,
+                              voxel_affinity, init_phi, pre);
+    if (!err.empty()) return fail(LBM_ERR_ARG, err);
+    *bytes = domain_bytes(*params, pre);
+    return LBM_OK;
+}
 
 const char* lbm_version(void) { return "colorlbm-gfx950 0.1"; }
 
@@ -270,6 +300,10 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (st != LBM_OK) {
         d->release();
         return st;
+    }
+    if (d->device_bytes != domain_bytes(p, pre)) {
+        d->release();
+        return fail(LBM_ERR_DEVICE, "internal: device footprint estimate out of date");
     }
     *out = d.release();
     return LBM_OK;

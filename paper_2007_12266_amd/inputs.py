@@ -272,3 +272,64 @@ def displacement_problem(n: int = 512, shape=None, seed_geom: int = 5, porosity_
                    periodic=(True, True, False), force=(0.0, 0.0, 0.0),
                    wall_affinity=affinity, bc_z=1, rho_in=rho_in, rho_out=rho_out,
                    name="displacement-%dx%dx%d" % (nx, ny, nz))
+
+
+def batch_volumes(count: int = 64, seed0: int = 100, edge=(48, 160), porosity=(0.15, 0.35),
+                  affinity=(-0.9, 0.9), sw=(0.2, 0.8), corr: float = 4.0,
+                  force=(0.0, 0.0, 1e-5)) -> list:
+    """Independent steady-flow sub-volumes for batched solves: volume k (seed seed0 + k) draws
+    nx, ny, nz ~ U{edge}, porosity ~ U[porosity], wall affinity ~ U[affinity] and Sw ~ U[sw],
+    then a periodic GRF rock and a Bernoulli(Sw) initial phase. If the rock has no z-spanning
+    pore cluster at the drawn porosity, the porosity is raised in steps of 0.02 until it has
+    (the problem's ``name`` records the porosity used)."""
+    out = []
+    for k in range(count):
+        seed = seed0 + k
+        rng = _rng(seed)
+        nx, ny, nz = (int(rng.integers(edge[0], edge[1] + 1)) for _ in range(3))
+        por = float(rng.uniform(*porosity))
+        aff = float(rng.uniform(*affinity))
+        s = float(rng.uniform(*sw))
+        shape = (nz, ny, nx)
+        while True:
+            try:
+                solid, _ = grf_rock(shape, corr, por, seed, max_redraws=3)
+                break
+            except RuntimeError:
+                por += 0.02
+        labels = np.where(solid > 0, 0, 1).astype(np.int32)
+        out.append(Problem(labels=labels,
+                           label_kind=np.array([KIND_SOLID, KIND_PORE_INIT], dtype=np.int8),
+                           label_affinity=np.array([aff, 0.0]),
+                           init_phi=bernoulli_phase(shape, s, seed + 10**7),
+                           periodic=(True, True, True), force=tuple(force),
+                           name="vol%d-%dx%dx%d-por%.3f-aff%+.2f-sw%.2f"
+                                % (k, nx, ny, nz, por, aff, s)))
+    return out
+
+
+def serving_problem(k: int, seed0: int = 200, edge=(64, 384), porosity=(0.15, 0.35),
+                    affinity=(-0.9, 0.9), sw=(0.2, 0.8), corr: float = 4.0,
+                    force=(0.0, 0.0, 1e-5)) -> Problem:
+    """Steady-state solve request k: a periodic GRF cube of edge L ~ U{edge} (seed seed0 + k),
+    porosity, wall affinity and Sw drawn as for the batched volumes."""
+    seed = seed0 + k
+    rng = _rng(seed)
+    L = int(rng.integers(edge[0], edge[1] + 1))
+    por = float(rng.uniform(*porosity))
+    aff = float(rng.uniform(*affinity))
+    s = float(rng.uniform(*sw))
+    shape = (L, L, L)
+    while True:
+        try:
+            solid, _ = grf_rock(shape, corr, por, seed, max_redraws=3)
+            break
+        except RuntimeError:
+            por += 0.02
+    labels = np.where(solid > 0, 0, 1).astype(np.int32)
+    return Problem(labels=labels,
+                   label_kind=np.array([KIND_SOLID, KIND_PORE_INIT], dtype=np.int8),
+                   label_affinity=np.array([aff, 0.0]),
+                   init_phi=bernoulli_phase(shape, s, seed + 10**7),
+                   periodic=(True, True, True), force=tuple(force),
+                   name="req%d-L%d-por%.3f-aff%+.2f-sw%.2f" % (k, L, por, aff, s))

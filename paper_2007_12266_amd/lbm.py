@@ -24,9 +24,10 @@ FIELDS = {"Na": 0, "Nb": 1, "phi": 2, "rho": 3, "p": 4, "ux": 5, "uy": 6, "uz": 
 EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_read_pore_field", "lbm_pore_index", "lbm_reduce", "lbm_read_history",
            "lbm_state_save", "lbm_state_load", "lbm_domain_get_info", "lbm_domain_destroy",
-           "lbm_prepass_query", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
+           "lbm_prepass_query", "lbm_domain_footprint", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
            "lbm_pool_create", "lbm_pool_admit", "lbm_pool_retire", "lbm_pool_step",
-           "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_destroy",
+           "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
+           "lbm_pool_destroy",
            "lbm_last_error", "lbm_version")
 
 
@@ -134,6 +135,8 @@ def load_library(path: str = LIB_PATH):
     L.lbm_prepass_query.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, vp, vp,
                                     ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
     L.lbm_autotune.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
+    L.lbm_domain_footprint.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, vp, vp,
+                                       ctypes.POINTER(i64)]
     L.lbm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.lbm_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.lbm_pool_create.argtypes = [i64, i32, i32, i32, vp, ctypes.POINTER(vp)]
@@ -144,6 +147,7 @@ def load_library(path: str = LIB_PATH):
     L.lbm_pool_get_info.argtypes = [vp, ctypes.POINTER(PoolInfo)]
     L.lbm_pool_set_grid.argtypes = [vp, i32]
     L.lbm_pool_destroy.argtypes = [vp]
+    L.lbm_pool_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -207,6 +211,17 @@ def prepass_query(problem) -> dict:
     _check(L.lbm_prepass_query(*args, _ptr(pv), _ptr(nbr), _ptr(tail)))
     return {"n_pore": n.value, "n_tail": t.value, "pore_voxel": pv, "nbr": nbr,
             "tail_phi": tail}
+
+
+def footprint(problem, precision: int = FP64) -> int:
+    """Device bytes a Domain of this problem would allocate (host-only pre-pass)."""
+    L = load_library()
+    p = make_params(problem, precision)
+    labels, kind, aff, vaff, iphi = _problem_arrays(problem)
+    b = ctypes.c_int64()
+    _check(L.lbm_domain_footprint(ctypes.byref(p), _ptr(labels), int(aff.size), _ptr(kind),
+                                  _ptr(aff), _ptr(vaff), _ptr(iphi), ctypes.byref(b)))
+    return b.value
 
 
 class _TorchAllocator:
@@ -389,6 +404,11 @@ class Pool:
         i = PoolInfo()
         _check(load_library().lbm_pool_get_info(self.handle, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in PoolInfo._fields_}
+
+    def autotune(self, trial_steps: int = 10) -> int:
+        g = ctypes.c_int32()
+        _check(load_library().lbm_pool_autotune(self.handle, int(trial_steps), ctypes.byref(g)))
+        return g.value
 
     def set_grid(self, grid: int):
         _check(load_library().lbm_pool_set_grid(self.handle, int(grid)))
