@@ -30,17 +30,20 @@ if ROOT not in sys.path:
 METRIC = "pore-voxel MLUPS + % HBM roofline; batched solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 
-# Algorithmic bytes per pore voxel and step, by storage precision (E = bytes per stored value):
-# the collide kernel reads 19 f, writes 19 f and 14 recoloured A/B, reads phi and N at the voxel
-# (neighbour phi is reuse) and reads the 18-entry int32 neighbour table; the phase kernel reads
-# 14 A/B and writes phi and N. Whole step: E*(38 f + 28 A/B + 4 phi/N) + 4*18.
+# Algorithmic bytes per pore voxel and step, by storage precision (E = bytes per stored value).
+# The collide kernel reads 19 f, writes 19 f and the 8 D3Q7 moment slots (N_a, N_b, u, G), reads
+# phi and N at the voxel (neighbour phi is reuse) and the 18-entry int32 neighbour table; the
+# phase kernel reads the 8 moment slots (each voxel's once; the six neighbours' are reuse), the
+# 6 axis rows of the neighbour table, and writes phi and N. Whole step: E*(38 + 16 + 4) + 4*24.
+# (Streaming the 14 D3Q7 populations themselves instead of their 8 moments would move
+# E*(38 + 28 + 4) + 4*18: 632 B in FP64, 352 B in FP32.)
 def _bytes(E):
-    return {"collide": E * (19 + 19 + 14 + 2) + 4 * 18,
-            "phase": E * (14 + 2),
-            "step": E * (38 + 28 + 4) + 4 * 18}
+    return {"collide": E * (19 + 19 + 8 + 2) + 4 * 18,
+            "phase": E * (8 + 2) + 4 * 6,
+            "step": E * (38 + 16 + 4) + 4 * 24}
 
 
-BYTES = {"fp64": _bytes(8), "fp32dev": _bytes(4)}   # fp64: 504 / 128 / 632; fp32dev: 288 / 64 / 352
+BYTES = {"fp64": _bytes(8), "fp32dev": _bytes(4)}   # fp64: 456 / 104 / 560; fp32dev: 264 / 64 / 328
 
 
 WORKLOADS = {

@@ -44,8 +44,10 @@ struct lbm_domain {
     int64_t device_bytes = 0;
 
     void* f = nullptr;
-    void* A = nullptr;
-    void* B = nullptr;
+    void* M = nullptr;        // [8][ld] D3Q7 moment slots
+    int32_t* fresh = nullptr; // device flag: the state is the initial one
+    int8_t* face = nullptr;   // [N] pressure-face flags (bc_z == 1 only)
+    int32_t one = 1;          // host source of fresh-flag uploads (outlives the async copy)
     void* phi = nullptr;      // [N + n_tail] storage type
     void* ntot = nullptr;     // [N] storage type
     double* stage = nullptr;  // [ld] doubles: initial phase upload and field read-back
@@ -75,8 +77,9 @@ struct lbm_domain {
         a.phi = phi;
         a.ntot = ntot;
         a.f = f;
-        a.A = A;
-        a.B = B;
+        a.M = M;
+        a.fresh = fresh;
+        a.face = face;
         a.nu_a = (p.tau_a - 0.5) / 3.0;
         a.nu_b = (p.tau_b - 0.5) / 3.0;
         a.alpha = p.alpha;

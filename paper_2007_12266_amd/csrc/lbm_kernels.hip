@@ -11,12 +11,24 @@
 // Kernel design for MI355X:
 //  * Structure of arrays: population q of pore voxel i lives at X[q*ld + i]; one thread per pore
 //    voxel, so every wavefront touches 64 consecutive doubles per population (coalesced).
-//  * AA pattern in place (one copy of every population array). Even steps read the voxel's own
-//    slots and write the post-collision value of direction q into its own slot opp(q). Odd steps
-//    read incoming f_q from slot opp(q) of the upstream neighbour and write f*_q into slot q of
-//    the downstream neighbour. A solid (or out-of-domain) neighbour turns either access into the
-//    voxel's own opposite slot, which is halfway bounce-back. Each thread reads and writes the
-//    same set of addresses, so the pattern is race-free without a second buffer.
+//  * AA pattern in place for the D3Q19 populations (one copy of the array). Even steps read the
+//    voxel's own slots and write the post-collision value of direction q into its own slot
+//    opp(q). Odd steps read incoming f_q from slot opp(q) of the upstream neighbour and write
+//    f*_q into slot q of the downstream neighbour. A solid (or out-of-domain) neighbour turns
+//    either access into the voxel's own opposite slot, which is halfway bounce-back. Each thread
+//    reads and writes the same set of addresses, so the pattern is race-free without a second
+//    buffer.
+//  * The D3Q7 component populations are streamed in moment form. The mass LBEs relax fully: the
+//    seven outgoing A*_q of a voxel are fixed by N_a, u and G = beta (N_a N_b / N) n (and B*_q by
+//    N_b, u, -G). The collide kernel therefore stores those 8 numbers per voxel, coalesced, in
+//    the voxel's own slots, and the phase kernel rebuilds each incoming A_q(x) = A*_q(x - xi_q)
+//    from the upstream neighbour's 8 numbers with the same arithmetic the populations would have
+//    been formed with (at a wall, from the voxel's own opposite outgoing population). This moves
+//    16 values per voxel and step instead of 28, and turns the odd step's 14 scattered A/B writes
+//    into 8 coalesced ones. On the first step of a fresh state the slots hold the initial
+//    densities themselves (a per-domain device flag, cleared by the first collide). The 8 slots
+//    are 8 rows of ld values (SoA); storing each voxel's 8 values contiguously was measured
+//    slower on both kernels.
 //  * The MRT collision is evaluated in its two-relaxation-time form: the relaxation matrix has
 //    one rate (s+ = 1/tau) on every even moment and one rate (s- = 8(2-s+)/(8-s+)) on every odd
 //    one (the conserved moments have zero non-equilibrium part, so their rate is immaterial).
@@ -50,9 +62,6 @@ constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 1
 
 __host__ __device__ constexpr double tw(int q) {   // D3Q19 weights t_q
     return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
-}
-__host__ __device__ constexpr double ww(int q) {   // D3Q7 weights w_q
-    return q == 0 ? 1.0 / 3.0 : 1.0 / 9.0;
 }
 
 // Precision policies. S: storage type of f, A, B, phi, N. R: arithmetic type. kDev: f is stored
@@ -121,15 +130,109 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __r
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     S* f = (S*)a.f;
-    S* A = (S*)a.A;
-    S* B = (S*)a.B;
+    S* M = (S*)a.M;
     const double na = 0.5 * (1.0 + phi0[i]), nbv = 0.5 * (1.0 - phi0[i]);
 #pragma unroll
     for (int q = 0; q < 19; ++q) f[(size_t)q * a.ld + i] = (S)(P::kDev ? 0.0 : tw(q));
+    // A fresh state: the component slots hold the densities (the fresh flag is set by the host).
+    M[i] = (S)na;
+    M[a.ld + i] = (S)nbv;
+#pragma unroll
+    for (int k = 2; k < 8; ++k) M[(size_t)k * a.ld + i] = (S)0;
+}
+
+// Outgoing D3Q7 populations of voxel y along axis direction q (1..6), from its moment slots
+// (N_a, N_b, u_x, u_y, u_z, G_x, G_y, G_z), one row of ld values per slot:
+// A*_q = w_q [N_a (1 + u.xi_q / cs^2) + G.xi_q], B*_q = w_q [N_b (1 + u.xi_q / cs^2) - G.xi_q],
+// cs^2 = 2/9.
+template <typename R, typename S>
+__device__ __forceinline__ void out_ab(const S* __restrict__ M, int64_t ld, int y, int q, R& ao,
+                                       R& bo) {
+    const int c = (q - 1) >> 1;                 // axis of q
+    const R sgn = (q & 1) ? (R)1 : (R)-1;       // +x, +y, +z are the odd q
+    const R na = (R)M[y], nb = (R)M[ld + y];
+    const R uc = (R)M[(size_t)(2 + c) * ld + y];
+    const R gc = (R)M[(size_t)(5 + c) * ld + y];
+    const R eu = (R)4.5 * (sgn * uc);
+    const R en = sgn * gc;
+    ao = (R)(1.0 / 9.0) * (na * ((R)1 + eu) + en);
+    bo = (R)(1.0 / 9.0) * (nb * ((R)1 + eu) - en);
+}
+
+// Component densities N_a, N_b of pore voxel i in the current state: the sum of the incoming
+// D3Q7 populations (rebuilt from the upstream neighbours' moment slots, or from the voxel's own
+// opposite outgoing population where the upstream neighbour is solid: halfway bounce-back).
+// Pressure-face voxels carry their imposed composition; a fresh state its initial densities.
+template <int PREC>
+__device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, double& na,
+                                          double& nbv) {
+    using P = Prec<PREC>;
+    using S = typename P::S;
+    using R = typename P::R;
+    const S* M = (const S*)a.M;
+    R ain[7], bin[7];
+    if (fresh) {
+        // The initial populations are w_q N at rest; summing them (rather than taking N) keeps
+        // the initial phase bitwise equal to a population-based evaluation.
+        const R n0 = (R)M[i], n1 = (R)M[a.ld + i];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const R w = q == 0 ? (R)(1.0 / 3.0) : (R)(1.0 / 9.0);
+            ain[q] = w * n0;
+            bin[q] = w * n1;
+        }
+        na = 0.0;
+        nbv = 0.0;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            na += (double)ain[q];
+            nbv += (double)bin[q];
+        }
+        return;
+    }
+    if (a.face) {
+        const int fc = a.face[i];
+        if (fc) {
+            na = fc == 1 ? 1.0 : 0.0;
+            nbv = 1.0 - na;
+            return;
+        }
+    }
+#pragma unroll
+    for (int q = 1; q < 7; ++q) {
+        const int up = nb(a, OPP[q], i);          // upstream voxel i - xi_q
+        if (up < a.N)
+            out_ab<R>(M, a.ld, up, q, ain[q], bin[q]);
+        else
+            out_ab<R>(M, a.ld, i, OPP[q], ain[q], bin[q]);
+    }
+    if (P::kDev) {
+        // The rest population is what the six moving ones leave of N (the rounded float weights
+        // would otherwise add 1.5e-8 of mass per step); sums in double, see below.
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int q = 1; q < 7; ++q) {
+            R ao, bo;
+            out_ab<R>(M, a.ld, i, q, ao, bo);
+            sa += (double)ao;
+            sb += (double)bo;
+        }
+        ain[0] = (R)0;
+        bin[0] = (R)0;
+        na = (double)M[i] - sa;
+        nbv = (double)M[a.ld + i] - sb;
+    } else {
+        ain[0] = (R)(1.0 / 3.0) * (R)M[i];
+        bin[0] = (R)(1.0 / 3.0) * (R)M[a.ld + i];
+        na = 0.0;
+        nbv = 0.0;
+    }
+    // Accumulated in double in both precisions: a float running sum of seven populations
+    // carries a mean rounding bias of a few 1e-9, which would create that much mass per step.
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-        A[(size_t)q * a.ld + i] = (S)(ww(q) * na);
-        B[(size_t)q * a.ld + i] = (S)(ww(q) * nbv);
+        na += (double)ain[q];
+        nbv += (double)bin[q];
     }
 }
 
@@ -137,24 +240,11 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __r
 // Densities and phase indicator: N_a = sum_q A_q, N_b = sum_q B_q (q = 0..6) of the streamed-in
 // D3Q7 populations; phi = (N_a - N_b)/(N_a + N_b); N = N_a + N_b.
 // ------------------------------------------------------------------------------------------
-template <int PREC, bool ODD>
-__device__ __forceinline__ void phase_voxel(const StepArgs& a, int i) {
-    using P = Prec<PREC>;
-    using S = typename P::S;
-    const S* A = (const S*)a.A;
-    const S* B = (const S*)a.B;
-    int up[7];
-#pragma unroll
-    for (int q = 1; q < 7; ++q) up[q] = ODD ? nb(a, OPP[q], i) : 0;
-    // The sums are accumulated in double in both precisions: a float running sum of seven
-    // populations carries a mean rounding bias of a few 1e-9, which would create that much
-    // mass per step.
-    double na = 0, nbv = 0;
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        na += (double)load_in<ODD>(A, a, q, i, q ? up[q] : 0);
-        nbv += (double)load_in<ODD>(B, a, q, i, q ? up[q] : 0);
-    }
+template <int PREC>
+__device__ __forceinline__ void phase_voxel(const StepArgs& a, int i, bool fresh) {
+    using S = typename Prec<PREC>::S;
+    double na, nbv;
+    densities<PREC>(a, i, fresh, na, nbv);
     const double nt = na + nbv;
     ((S*)a.phi)[i] = (S)((na - nbv) / nt);
     ((S*)a.ntot)[i] = (S)nt;
@@ -163,7 +253,7 @@ __device__ __forceinline__ void phase_voxel(const StepArgs& a, int i) {
 template <int PREC, bool ODD>
 __global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
     const int i = logical_block(a) * blockDim.x + threadIdx.x;
-    if (i < a.N) phase_voxel<PREC, ODD>(a, i);
+    if (i < a.N) phase_voxel<PREC>(a, i, *a.fresh != 0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -176,8 +266,6 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     using S = typename P::S;
     using R = typename P::R;
     S* f = (S*)a.f;
-    S* A = (S*)a.A;
-    S* B = (S*)a.B;
 
     int r[19];
     r[0] = i;
@@ -227,6 +315,25 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
 
     const R phi_i = (R)ph[i];
     const R nt = (R)((const S*)a.ntot)[i];
+    // Recolouring with the flow velocity u = j + F/2 (rho0 = 1): the outgoing D3Q7 populations
+    // are w_q [N_a (1 + u.xi_q/cs^2) + G.xi_q] and w_q [N_b (1 + u.xi_q/cs^2) - G.xi_q] with
+    // G = beta (N_a N_b / N) n; their 8 defining numbers go to the voxel's own moment slots.
+    const R ux = jx + (R)(0.5 * a.F[0]), uy = jy + (R)(0.5 * a.F[1]);
+    const R uz = jz + (R)(0.5 * a.F[2]);
+    const R na = (R)0.5 * nt * ((R)1 + phi_i);
+    const R nbv = (R)0.5 * nt * ((R)1 - phi_i);
+    const R seg = (R)a.beta * na * nbv / nt;
+    S* M = (S*)a.M;
+    const size_t ld = (size_t)a.ld;
+    M[i] = (S)na;
+    M[ld + i] = (S)nbv;
+    M[2 * ld + i] = (S)ux;
+    M[3 * ld + i] = (S)uy;
+    M[4 * ld + i] = (S)uz;
+    M[5 * ld + i] = (S)(seg * nx);
+    M[6 * ld + i] = (S)(seg * ny);
+    M[7 * ld + i] = (S)(seg * nz);
+
     const R nu = (R)0.5 * ((R)1 + phi_i) * (R)a.nu_a + (R)0.5 * ((R)1 - phi_i) * (R)a.nu_b;
     const R sp = (R)1 / ((R)3 * nu + (R)0.5);
     const R sm = (R)8 * ((R)2 - sp) / ((R)8 - sp);
@@ -277,44 +384,9 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
         fs[qb] = fl[qb] - rp + rm - fo;
     }
 
-    // Recolouring with the flow velocity u = j + F/2 (rho0 = 1).
-    const R ux = jx + (R)(0.5 * a.F[0]), uy = jy + (R)(0.5 * a.F[1]);
-    const R uz = jz + (R)(0.5 * a.F[2]);
-    const R na = (R)0.5 * nt * ((R)1 + phi_i);
-    const R nbv = (R)0.5 * nt * ((R)1 - phi_i);
-    const R seg = (R)a.beta * na * nbv / nt;
-    R As[7], Bs[7];
-#pragma unroll
-    for (int q = 1; q < 7; ++q) {
-        const R eu = (R)4.5 * (CX[q] * ux + CY[q] * uy + CZ[q] * uz);
-        const R en = seg * (CX[q] * nx + CY[q] * ny + CZ[q] * nz);
-        As[q] = (R)(1.0 / 9.0) * (na * ((R)1 + eu) + en);
-        Bs[q] = (R)(1.0 / 9.0) * (nbv * ((R)1 + eu) - en);
-    }
-    if (P::kDev) {
-        // In float the rounded weights sum to 1 + 1.5e-8, which would create that much mass
-        // every step. The rest population takes what the moving ones leave (w_0 N exactly in
-        // exact arithmetic, since the velocity and normal terms cancel between opposite pairs).
-        double sa = 0, sb = 0;
-#pragma unroll
-        for (int q = 1; q < 7; ++q) {
-            sa += (double)(S)As[q];
-            sb += (double)(S)Bs[q];
-        }
-        As[0] = (R)((double)na - sa);
-        Bs[0] = (R)((double)nbv - sb);
-    } else {
-        As[0] = (R)(1.0 / 3.0) * na;
-        Bs[0] = (R)(1.0 / 3.0) * nbv;
-    }
-
 #pragma unroll
     for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, r[q], (S)fs[q]);
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        store_out<ODD>(A, a, q, i, r[q], (S)As[q]);
-        store_out<ODD>(B, a, q, i, r[q], (S)Bs[q]);
-    }
+    if (i == 0) *a.fresh = 0;        // the state now holds outgoing moments
 }
 
 template <int PREC, bool ODD>
@@ -338,7 +410,7 @@ __global__ void __launch_bounds__(256) phase_batched(BatchArgs b) {
         const int d = b.tile_dom[t];
         const StepArgs a = b.doms[d];
         const int i = (t - b.tile_first[d]) * blockDim.x + threadIdx.x;
-        if (i < a.N) phase_voxel<PREC, ODD>(a, i);
+        if (i < a.N) phase_voxel<PREC>(a, i, *a.fresh != 0);
     }
 }
 
@@ -362,19 +434,11 @@ __device__ __forceinline__ void voxel_state(const StepArgs& a, int i, double& na
     using P = Prec<PREC>;
     using S = typename P::S;
     const S* f = (const S*)a.f;
-    const S* A = (const S*)a.A;
-    const S* B = (const S*)a.B;
     int r[19];
     r[0] = i;
 #pragma unroll
     for (int q = 1; q < 19; ++q) r[q] = ODD ? nb(a, q, i) : 0;
-    na = 0.0;
-    nbv = 0.0;
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        na += (double)load_in<ODD>(A, a, q, i, r[OPP[q]]);
-        nbv += (double)load_in<ODD>(B, a, q, i, r[OPP[q]]);
-    }
+    densities<PREC>(a, i, *a.fresh != 0, na, nbv);
     rho = 0.0;
     jx = jy = jz = 0.0;
 #pragma unroll
@@ -518,19 +582,12 @@ __global__ void __launch_bounds__(256) ghost_kernel(StepArgs a, const int32_t* _
     ph[a.N + tail[k]] = ph[src[k]];
 }
 
-// Storage index of the incoming population q of voxel i for a step of parity ODD.
-template <bool ODD>
-__device__ __forceinline__ size_t in_slot(const StepArgs& a, int q, int i, int r_up) {
-    if (!ODD || q == 0 || r_up >= a.N) return (size_t)q * a.ld + i;
-    return (size_t)OPP[q] * a.ld + r_up;
-}
-
 // Zou-He pressure condition on the streamed populations of the z = 0 (inlet, first n_in
 // entries of `faces`) and z = nz-1 (outlet) pore voxels, read and written in the layout of the
 // next step (parity ODD). Unknowns (xi_z pointing into the domain) always sit in the voxel's
-// own slot q, because their upstream neighbour is outside. The D3Q7 populations of the plane
-// are reset to equilibrium: pure fluid a (N = 1) at the inlet, pure b at the outlet, with
-// u = (F_x/2, F_y/2, j_z + F_z/2).
+// own slot q, because their upstream neighbour is outside. The composition of the face planes
+// (pure a, N = 1, at the inlet; pure b at the outlet) is imposed where densities are formed
+// (the per-voxel face flag), which equals resetting their D3Q7 populations to equilibrium.
 template <int PREC, bool ODD>
 __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
                                                           const int32_t* __restrict__ faces,
@@ -543,10 +600,7 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
     const int i = faces[k];
     const int dir = k < n_in ? 1 : -1;
     const double rho_b = k < n_in ? rho_in : rho_out;
-    const double na_b = k < n_in ? 1.0 : 0.0;
     S* f = (S*)a.f;
-    S* A = (S*)a.A;
-    S* B = (S*)a.B;
     int r[19];
     r[0] = i;
 #pragma unroll
@@ -572,14 +626,6 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
         if (CZ[q] != dir) continue;
         const double val = fl[OPP[q]] + 6.0 * tw(q) * CZ[q] * jz - 0.5 * (CX[q] * tx + CY[q] * ty);
         f[(size_t)q * a.ld + i] = (S)(val - (P::kDev ? tw(q) : 0.0));
-    }
-    const double u[3] = {0.5 * a.F[0], 0.5 * a.F[1], jz + 0.5 * a.F[2]};
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        const double eu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
-        const size_t at = in_slot<ODD>(a, q, i, r[OPP[q]]);
-        A[at] = (S)(ww(q) * na_b * (1.0 + 4.5 * eu));
-        B[at] = (S)(ww(q) * (1.0 - na_b) * (1.0 + 4.5 * eu));
     }
 }
 

@@ -312,20 +312,20 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
     for (lbm_domain* d : p->slots) {
         if (!d) continue;
         const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
-        Snap sn{d, nullptr, eb * 33 * ld};
+        Snap sn{d, nullptr, eb * 27 * ld + sizeof(int32_t)};
         if (hipMalloc(&sn.buf, sn.bytes) != hipSuccess) {
             st = fail(LBM_ERR_OOM, "no device memory for the autotuner's snapshot");
             break;
         }
         snaps.push_back(sn);
         size_t off = 0;
-        void* arr[3] = {d->f, d->A, d->B};
-        const size_t rows[3] = {19, 7, 7};
+        void* arr[3] = {d->f, d->M, d->fresh};
+        const size_t sizes[3] = {eb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
         for (int k = 0; k < 3 && st == LBM_OK; ++k) {
-            if (hipMemcpyAsync((char*)sn.buf + off, arr[k], eb * rows[k] * ld,
-                               hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+            if (hipMemcpyAsync((char*)sn.buf + off, arr[k], sizes[k], hipMemcpyDeviceToDevice,
+                               p->stream) != hipSuccess)
                 st = fail(LBM_ERR_DEVICE, "snapshot copy failed");
-            off += eb * rows[k] * ld;
+            off += sizes[k];
         }
     }
     const int64_t step0 = p->step;
@@ -363,14 +363,14 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
         lbm_domain* d = snaps[k].d;
         const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
         size_t off = 0;
-        void* arr[3] = {d->f, d->A, d->B};
-        const size_t rows[3] = {19, 7, 7};
+        void* arr[3] = {d->f, d->M, d->fresh};
+        const size_t sizes[3] = {eb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
         for (int a = 0; a < 3; ++a) {
-            if (hipMemcpyAsync(arr[a], (char*)snaps[k].buf + off, eb * rows[a] * ld,
+            if (hipMemcpyAsync(arr[a], (char*)snaps[k].buf + off, sizes[a],
                                hipMemcpyDeviceToDevice, p->stream) != hipSuccess &&
                 st == LBM_OK)
                 st = fail(LBM_ERR_DEVICE, "restore copy failed");
-            off += eb * rows[a] * ld;
+            off += sizes[a];
         }
         d->step = dstep0[k];
     }

@@ -26,7 +26,8 @@ lbm_status fail(lbm_status s, const std::string& msg) {
 
 namespace {
 
-constexpr uint64_t kStateMagic = 0x4c424d434f4c5231ull;  // "LBMCOLR1"
+constexpr uint64_t kStateMagic = 0x4c424d434f4c5232ull;  // "LBMCOLR2"
+constexpr int kStateRows = 27;  // 19 D3Q19 populations + 8 D3Q7 moment slots
 
 struct StateHeader {
     uint64_t magic;
@@ -163,13 +164,13 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
 static int64_t domain_bytes(const lbm_params& p, const Prepass& pre) {
     const size_t eb = p.precision == LBM_FP32_DEV ? 4 : 8, ld = (size_t)pre.ld;
     auto r = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
-    int64_t total = r(eb * 19 * ld) + 2 * r(eb * 7 * ld) +
+    int64_t total = r(eb * 19 * ld) + r(eb * 8 * ld) + r(sizeof(int32_t)) +
                     r(eb * (size_t)(pre.n_pore + pre.n_tail)) + r(eb * ld) +
                     r(sizeof(double) * ld) + r(sizeof(int32_t) * 18 * ld) +
                     r(sizeof(double) * kRedBlocks * kNRed) + r(sizeof(double) * kNRed) +
                     r(sizeof(double) * 1024 * kNRed);
     const size_t faces = pre.inlet.size() + pre.outlet.size();
-    if (faces) total += r(sizeof(int32_t) * faces);
+    if (faces) total += r(sizeof(int32_t) * faces) + r(sizeof(int8_t) * ld);
     if (!pre.ghost_tail.empty()) total += 2 * r(sizeof(int32_t) * pre.ghost_tail.size());
     return total;
 }
@@ -239,8 +240,8 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     const size_t eb = d->elem_bytes();
     const size_t ld = (size_t)pre.ld;
     d->f = d->dalloc(eb * 19 * ld);
-    d->A = d->dalloc(eb * 7 * ld);
-    d->B = d->dalloc(eb * 7 * ld);
+    d->M = d->dalloc(eb * 8 * ld);
+    d->fresh = (int32_t*)d->dalloc(sizeof(int32_t));
     d->phi = d->dalloc(eb * (size_t)(pre.n_pore + pre.n_tail));
     d->ntot = d->dalloc(eb * ld);
     d->stage = (double*)d->dalloc(sizeof(double) * ld);
@@ -249,7 +250,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     d->red_out = (double*)d->dalloc(sizeof(double) * kNRed);
     d->hist = (double*)d->dalloc(sizeof(double) * (size_t)d->hist_cap * kNRed);
     double* phi0 = d->stage;
-    if (!d->f || !d->A || !d->B || !d->phi || !d->ntot || !d->stage || !d->nbr ||
+    if (!d->f || !d->M || !d->fresh || !d->phi || !d->ntot || !d->stage || !d->nbr ||
         !d->red_partials || !d->red_out || !d->hist) {
         d->release();
         return fail(LBM_ERR_OOM, "device allocation failed");
@@ -257,12 +258,19 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     d->hist_step.assign(d->hist_cap, 0);
     std::vector<int32_t> faces(pre.inlet);
     faces.insert(faces.end(), pre.outlet.begin(), pre.outlet.end());
-    if (!faces.empty()) d->faces = (int32_t*)d->dalloc(sizeof(int32_t) * faces.size());
+    std::vector<int8_t> face_flags;
+    if (!faces.empty()) {
+        d->faces = (int32_t*)d->dalloc(sizeof(int32_t) * faces.size());
+        d->face = (int8_t*)d->dalloc(sizeof(int8_t) * ld);
+        face_flags.assign(ld, 0);
+        for (int32_t v : pre.inlet) face_flags[v] = 1;
+        for (int32_t v : pre.outlet) face_flags[v] = 2;
+    }
     if (!pre.ghost_tail.empty()) {
         d->ghost_tail = (int32_t*)d->dalloc(sizeof(int32_t) * pre.ghost_tail.size());
         d->ghost_src = (int32_t*)d->dalloc(sizeof(int32_t) * pre.ghost_src.size());
     }
-    if ((!faces.empty() && !d->faces) ||
+    if ((!faces.empty() && (!d->faces || !d->face)) ||
         (!pre.ghost_tail.empty() && (!d->ghost_tail || !d->ghost_src))) {
         d->release();
         return fail(LBM_ERR_OOM, "device allocation failed");
@@ -284,8 +292,11 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
              eb * pre.n_tail),
           "upload tail");
     guard(up(phi0, pre.phi0.data(), sizeof(double) * pre.n_pore), "upload phi0");
-    if (d->faces)
+    if (d->faces) {
         guard(up(d->faces, faces.data(), sizeof(int32_t) * faces.size()), "upload faces");
+        guard(up(d->face, face_flags.data(), sizeof(int8_t) * ld), "upload face flags");
+    }
+    guard(up(d->fresh, &d->one, sizeof(int32_t)), "set fresh");
     if (d->ghost_tail) {
         guard(up(d->ghost_tail, pre.ghost_tail.data(), sizeof(int32_t) * pre.ghost_tail.size()),
               "upload ghosts");
@@ -293,8 +304,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
               "upload ghosts");
     }
     guard(hipMemsetAsync(d->f, 0, eb * 19 * ld, d->stream), "clear f");
-    guard(hipMemsetAsync(d->A, 0, eb * 7 * ld, d->stream), "clear A");
-    guard(hipMemsetAsync(d->B, 0, eb * 7 * ld, d->stream), "clear B");
+    guard(hipMemsetAsync(d->M, 0, eb * 8 * ld, d->stream), "clear M");
     if (st == LBM_OK) guard(launch_init(d->args(), phi0, d->block, d->stream), "init kernel");
     if (st == LBM_OK) guard(hipStreamSynchronize(d->stream), "create sync");
     if (st != LBM_OK) {
@@ -389,7 +399,7 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
     if (!nbytes) return fail(LBM_ERR_ARG, "nbytes must be non-null");
     const size_t eb = d->elem_bytes();
     const size_t n = (size_t)d->pre.n_pore, ld = (size_t)d->pre.ld;
-    const size_t need = sizeof(StateHeader) + eb * 33 * n;
+    const size_t need = sizeof(StateHeader) + eb * kStateRows * n;
     if (!host_buf) {
         *nbytes = need;
         return LBM_OK;
@@ -398,13 +408,12 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
     StateHeader h{kStateMagic, d->pre.n_pore, d->pre.n_tail, d->step, d->p.precision, (int32_t)eb};
     std::memcpy(host_buf, &h, sizeof h);
     char* dst = (char*)host_buf + sizeof h;
-    const void* arrays[3] = {d->f, d->A, d->B};
-    const int rows[3] = {19, 7, 7};
-    for (int k = 0; k < 3; ++k) {
-        HIP_TRY(hipMemcpy2DAsync(dst, eb * n, arrays[k], eb * ld, eb * n, rows[k],
-                                 hipMemcpyDeviceToHost, d->stream));
-        dst += eb * n * rows[k];
-    }
+    // f: 19 rows and M: 8 rows, each of n values (pitch ld on the device).
+    HIP_TRY(hipMemcpy2DAsync(dst, eb * n, d->f, eb * ld, eb * n, 19, hipMemcpyDeviceToHost,
+                             d->stream));
+    dst += eb * n * 19;
+    HIP_TRY(hipMemcpy2DAsync(dst, eb * n, d->M, eb * ld, eb * n, 8, hipMemcpyDeviceToHost,
+                             d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     *nbytes = need;
     return LBM_OK;
@@ -421,17 +430,19 @@ lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes) {
     std::memcpy(&h, host_buf, sizeof h);
     if (h.magic != kStateMagic || h.n_pore != d->pre.n_pore || h.n_tail != d->pre.n_tail ||
         h.precision != d->p.precision || h.elem_bytes != (int32_t)eb ||
-        nbytes != sizeof h + eb * 33 * n)
+        nbytes != sizeof h + eb * kStateRows * n)
         return fail(LBM_ERR_STATE, "state does not match this domain");
     const char* src = (const char*)host_buf + sizeof h;
-    void* arrays[3] = {d->f, d->A, d->B};
-    const int rows[3] = {19, 7, 7};
-    for (int k = 0; k < 3; ++k) {
-        HIP_TRY(hipMemcpy2DAsync(arrays[k], eb * ld, src, eb * n, eb * n, rows[k],
-                                 hipMemcpyHostToDevice, d->stream));
-        src += eb * n * rows[k];
-    }
+    HIP_TRY(hipMemcpy2DAsync(d->f, eb * ld, src, eb * n, eb * n, 19, hipMemcpyHostToDevice,
+                             d->stream));
+    src += eb * n * 19;
+    HIP_TRY(hipMemcpy2DAsync(d->M, eb * ld, src, eb * n, eb * n, 8, hipMemcpyHostToDevice,
+                             d->stream));
+    d->one = h.step == 0 ? 1 : 0;            // a step-0 state is the initial one
+    HIP_TRY(hipMemcpyAsync(d->fresh, &d->one, sizeof(int32_t), hipMemcpyHostToDevice,
+                           d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
+    d->one = 1;
     d->step = h.step;
     d->unstable = false;
     d->hist_count = 0;
@@ -479,15 +490,15 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     if (d->unstable) return fail(LBM_ERR_UNSTABLE, "domain is unstable; load a state");
     trial_steps += trial_steps & 1;  // even: both parities equally
     const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
-    const size_t bytes = eb * 33 * ld;
+    const size_t bytes = eb * kStateRows * ld + 256;
     char* snap = (char*)d->dalloc(bytes);
     if (!snap) return fail(LBM_ERR_OOM, "no device memory for the autotuner's snapshot");
-    void* arrays[3] = {d->f, d->A, d->B};
-    const size_t rows[3] = {19, 7, 7};
+    void* arrays[3] = {d->f, d->M, d->fresh};
+    const size_t sizes[3] = {eb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
     auto copy_all = [&](bool save) -> hipError_t {
         size_t off = 0;
         for (int k = 0; k < 3; ++k) {
-            const size_t nb = eb * rows[k] * ld;
+            const size_t nb = sizes[k];
             hipError_t e = save ? hipMemcpyAsync(snap + off, arrays[k], nb,
                                                  hipMemcpyDeviceToDevice, d->stream)
                                 : hipMemcpyAsync(arrays[k], snap + off, nb,
