@@ -30,20 +30,33 @@ if ROOT not in sys.path:
 METRIC = "pore-voxel MLUPS + % HBM roofline; batched solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 
-# Algorithmic bytes per pore voxel and step, by storage precision (E = bytes per stored value).
-# The collide kernel reads 19 f, writes 19 f and the 8 D3Q7 moment slots (N_a, N_b, u, G), reads
-# phi and N at the voxel (neighbour phi is reuse) and the 18-entry int32 neighbour table; the
-# phase kernel reads the 8 moment slots (each voxel's once; the six neighbours' are reuse), the
-# 6 axis rows of the neighbour table, and writes phi and N. Whole step: E*(38 + 16 + 4) + 4*24.
-# (Streaming the 14 D3Q7 populations themselves instead of their 8 moments would move
-# E*(38 + 28 + 4) + 4*18: 632 B in FP64, 352 B in FP32.)
-def _bytes(E):
-    return {"collide": E * (19 + 19 + 8 + 2) + 4 * 18,
-            "phase": E * (8 + 2) + 4 * 6,
+# Algorithmic bytes per pore voxel and step, by storage precision (E = bytes per stored value)
+# and neighbour lookup. The collide kernel reads 19 f, writes 19 f and the 8 D3Q7 moment slots
+# (N_a, N_b, u, G), reads phi and N at the voxel (neighbour phi is reuse) and its neighbours'
+# indices; the phase kernel reads the 8 moment slots (each voxel's once; the six neighbours' are
+# reuse), its neighbours' indices, and writes phi and N. The indices cost 4*18 (collide) and
+# 4*6 (phase) bytes per voxel with the int32 table; with the rank lookup, 4 bytes of packed
+# coordinates per voxel plus one pass over the 32-byte row segments (nz*ny*ceil(nx/64) of them,
+# counted per launch, about 0.5/porosity bytes per pore voxel).
+# FP64: 456 / 104 / 560 B per voxel with the table, 388 / 84 / 472 with the rank lookup;
+# FP32-dev: 264 / 64 / 328 and 196 / 44 / 240.
+# (Streaming the 14 D3Q7 populations themselves instead of their 8 moments would add 6E to the
+# collide and phase kernels each.)
+def _bytes(E, rank):
+    if rank:
+        return {"collide": E * (19 + 19 + 8 + 2) + 4, "phase": E * (8 + 2) + 4,
+                "step": E * (38 + 16 + 4) + 8}
+    return {"collide": E * (19 + 19 + 8 + 2) + 4 * 18, "phase": E * (8 + 2) + 4 * 6,
             "step": E * (38 + 16 + 4) + 4 * 24}
 
 
-BYTES = {"fp64": _bytes(8), "fp32dev": _bytes(4)}   # fp64: 456 / 104 / 560; fp32dev: 264 / 64 / 328
+def launch_bytes(precision, rank, n_pore, shape):
+    """Algorithmic bytes of one collide launch, one phase launch and one whole step."""
+    per = _bytes(8 if precision == "fp64" else 4, rank)
+    nz, ny, nx = shape
+    rows = nz * ny * ((nx + 63) // 64) * 32 if rank else 0
+    return {"collide": per["collide"] * n_pore + rows, "phase": per["phase"] * n_pore + rows,
+            "step": per["step"] * n_pore + 2 * rows, "per_voxel": per, "row_bytes": rows}
 
 
 WORKLOADS = {
@@ -95,9 +108,9 @@ def _cpu_model() -> str:
     return platform.machine()
 
 
-def _profiled_traffic(precision: str):
+def _profiled_traffic(precision: str, neighbours: str):
     """Calibrated collide-kernel HBM bytes per pore voxel from the committed rocprofv3 summary,
-    if it was measured on the current kernel source; else None."""
+    if it was measured on the current kernel source with the same neighbour lookup; else None."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "collide_phase_grf256_%s.md" % precision)
     src = os.path.join(ROOT, "paper_2007_12266_amd", "csrc", "lbm_kernels.hip")
@@ -105,11 +118,13 @@ def _profiled_traffic(precision: str):
         vals = {}
         for line in open(prof):
             if ":" in line and line.strip().split(":")[0] in (
-                    "traffic_collide_bytes_per_voxel", "kernel_source_sha256_prefix"):
+                    "traffic_collide_bytes_per_voxel", "kernel_source_sha256_prefix",
+                    "neighbours"):
                 k, v = line.strip().split(":", 1)
                 vals[k] = v.strip()
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if digest.startswith(vals["kernel_source_sha256_prefix"]):
+        if (digest.startswith(vals["kernel_source_sha256_prefix"])
+                and vals["neighbours"] == neighbours):
             return float(vals["traffic_collide_bytes_per_voxel"])
     except (OSError, KeyError, ValueError):
         pass
@@ -266,6 +281,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32dev"])
+    ap.add_argument("--neighbours", default="auto", choices=["auto", "table", "rank"],
+                    help="neighbour lookup: int32 table or rank of row-segment bit masks")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of autotuning them")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -298,7 +315,9 @@ def main():
     with torch.cuda.stream(stream):
         dom = lbm.Domain(prob, reduce_every=wl["reduce_every"], block_size=args.block,
                          stream=stream.cuda_stream,
-                         precision=lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV)
+                         precision=lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV,
+                         neighbour_mode={"auto": lbm.NBR_AUTO, "table": lbm.NBR_TABLE,
+                                         "rank": lbm.NBR_RANK}[args.neighbours])
     n_pore = dom.n_pore
     log("domain: N=%d, device bytes %.2f GB" % (n_pore, dom.info()["device_bytes"] / 1e9))
 
@@ -326,11 +345,13 @@ def main():
     ksteps = min(args.steps, 200)
     timing = dom.step_timed(ksteps)
     coll_s = timing["collide_ms"] / 1e3
-    nbytes = BYTES[args.precision]
-    achieved = nbytes["collide"] * n_pore / coll_s / 1e9
-    tb = _profiled_traffic(args.precision) if args.workload == "grf256" else None
+    rank = dom.info()["neighbour_mode"] == lbm.NBR_RANK
+    nbytes = launch_bytes(args.precision, rank, n_pore, prob.shape)
+    achieved = nbytes["collide"] / coll_s / 1e9
+    tb = (_profiled_traffic(args.precision, "rank" if rank else "table")
+          if args.workload == "grf256" else None)
     traffic = None if tb is None else round(tb * n_pore / coll_s / 1e9, 1)
-    step_gbs = nbytes["step"] * n_pore / (ms_per_step / 1e3) / 1e9
+    step_gbs = nbytes["step"] / (ms_per_step / 1e3) / 1e9
 
     if args.copy_calibration:
         a = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
@@ -364,9 +385,11 @@ def main():
                      "traffic": traffic, "traffic_unit": "GB/s (rocprofv3 FETCH_SIZE x2.0 + "
                      "WRITE_SIZE x1.0 per voxel, over this run's kernel time)",
                      "kernel": "collide_kernel",
-                     "bytes_per_voxel": nbytes["collide"],
+                     "bytes_per_voxel": nbytes["per_voxel"]["collide"],
+                     "row_bytes_per_launch": nbytes["row_bytes"],
+                     "neighbours": "rank" if rank else "table",
                      "kernel_ms": round(timing["collide_ms"], 5)},
-        "step_hbm": {"bytes_per_voxel": nbytes["step"], "achieved_gbs": round(step_gbs, 1),
+        "step_hbm": {"bytes_per_voxel": nbytes["per_voxel"]["step"], "achieved_gbs": round(step_gbs, 1),
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                      "phase_ms": round(timing["phase_ms"], 5)},
         "reductions": {"recorded": len(hist), "sw": red["sw"], "qz": red["qz"],

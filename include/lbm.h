@@ -46,6 +46,15 @@ typedef enum {
 
 typedef enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 } lbm_precision;
 
+/* How the kernels find a pore voxel's 18 D3Q19 neighbours. TABLE: an int32 table of 18 entries
+ * per pore voxel, read every step (72 bytes per voxel and step). RANK: computed from the voxel's
+ * packed coordinate and a per-64-voxel record of the image (pore and solid bitmasks with running
+ * indices: about 0.5 byte per image voxel, read through the caches), 4 bytes per voxel and step
+ * and 68 bytes less device memory per pore voxel, but slower on MI355X (the lookup adds a
+ * dependent load to every gather); needs nx <= 1024 and ny, nz <= 2048. AUTO takes TABLE.
+ * Results are bitwise identical. */
+typedef enum { LBM_NBR_AUTO = 0, LBM_NBR_TABLE = 1, LBM_NBR_RANK = 2 } lbm_neighbour_mode;
+
 /* Label kinds (section "Initial conditions and wetting maps": every voxel carries an integer
  * label naming its material). */
 typedef enum {
@@ -85,7 +94,8 @@ typedef struct {
     int32_t precision;       /* lbm_precision                                               */
     double rho_in, rho_out;  /* imposed densities of the pressure faces (bc_z == 1)         */
     int32_t reduce_every;    /* lbm_step records a reduction every this many steps (0: off) */
-    int32_t block_size;      /* threads per workgroup (64..1024, multiple of 64); 0: auto   */
+    int32_t block_size;      /* threads per workgroup (64, 128 or 256); 0: auto             */
+    int32_t neighbour_mode;  /* lbm_neighbour_mode                                        */
 } lbm_params;
 
 /* Reductions over the pore voxels (section "Analysis framework", integral measures, and the
@@ -136,6 +146,8 @@ typedef struct {
     int64_t step;             /* completed steps                                             */
     int32_t precision;        /* lbm_precision                                               */
     int32_t block_size;       /* threads per workgroup in use                                */
+    int32_t neighbour_mode;   /* LBM_NBR_TABLE or LBM_NBR_RANK                               */
+    int32_t pad_;
 } lbm_domain_info;
 
 /* Create a domain from a labelled image (sections "Initial conditions and wetting maps" and
@@ -218,7 +230,9 @@ lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
  * voxel, pore order), nbr[18 * n_pore] (row q-1 holds the neighbour of every pore voxel along
  * D3Q19 velocity q = 1..18: a pore index < n_pore, or n_pore + t for tail entry t, a solid or
  * wall neighbour), tail_phi[n_tail] (phi_s of each tail entry; entry 0 is the wall outside
- * non-periodic faces). Call once with NULL arrays to learn the sizes. */
+ * non-periodic faces). Call once with NULL arrays to learn the sizes. Where the rank lookup
+ * applies, the query also replays it for every pore voxel and direction against this table and
+ * returns LBM_ERR_STATE if the two disagree (an internal error, never expected). */
 lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, int32_t n_labels,
                              const int8_t* label_kind, const double* label_affinity,
                              const double* voxel_affinity, const double* init_phi,

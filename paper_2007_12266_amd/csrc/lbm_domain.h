@@ -51,7 +51,10 @@ struct lbm_domain {
     void* phi = nullptr;      // [N + n_tail] storage type
     void* ntot = nullptr;     // [N] storage type
     double* stage = nullptr;  // [ld] doubles: initial phase upload and field read-back
-    int32_t* nbr = nullptr;
+    int32_t* nbr = nullptr;        // [18][ld] (table mode)
+    uint32_t* coord = nullptr;     // [ld] packed coordinates (rank mode)
+    lbm::RowWord* words = nullptr; // row segments (rank mode)
+    bool rank = false;
     double* red_partials = nullptr;
     double* red_out = nullptr;
     double* hist = nullptr;
@@ -86,6 +89,14 @@ struct lbm_domain {
         a.beta = p.beta;
         for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
         a.xcd_remap = sched == 2 ? 1 : 0;
+        a.coord = rank ? coord : nullptr;
+        a.words = rank ? words : nullptr;
+        a.nx = p.nx;
+        a.ny = p.ny;
+        a.nz = p.nz;
+        a.W = pre.words_per_row;
+        a.periodic = (p.periodic[0] ? 1 : 0) | (p.periodic[1] ? 2 : 0) | (p.periodic[2] ? 4 : 0);
+        a.bc_z = p.bc_z;
         a.prec = p.precision;
         return a;
     }

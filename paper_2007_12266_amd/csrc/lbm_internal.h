@@ -39,6 +39,12 @@ struct StepArgs {
     double F[3];
     int32_t xcd_remap;  // 1: map consecutive logical blocks to the same XCD
     int32_t prec;       // lbm_precision
+    // Rank lookup of neighbours (used instead of nbr when words != null):
+    const uint32_t* coord;   // [ld] packed (x, y, z) of each pore voxel
+    const RowWord* words;    // [nz][ny][W] 64-voxel row segments
+    int32_t nx, ny, nz, W;
+    int32_t periodic;        // bit a set: axis a is periodic
+    int32_t bc_z;            // 1: z neighbours beyond the faces mirror the plane
 };
 
 // Arguments of the batched (pool) kernels. All arrays live in device memory.

@@ -88,9 +88,76 @@ __device__ __forceinline__ int logical_block(const StepArgs& a) {
     return (b & 7) * per + (b >> 3);
 }
 
-// Neighbour of voxel i along direction q (1..18): pore index (< N) or N + tail index.
-__device__ __forceinline__ int nb(const StepArgs& a, int q, int i) {
-    return a.nbr[(size_t)(q - 1) * a.ld + i];
+// Neighbour lookup, fixed at compile time for the single-domain step kernels and chosen per
+// domain at run time (words != null selects the rank lookup) where domains of either kind meet.
+enum { NB_DYN = 0, NB_TABLE = 1, NB_RANK = 2 };
+
+template <int NB>
+__device__ __forceinline__ bool use_table(const StepArgs& a) {
+    return NB == NB_TABLE || (NB == NB_DYN && !a.words);
+}
+
+// Coordinates of pore voxel i (rank lookup only).
+struct Pos {
+    int x, y, z;
+};
+
+template <int NB = NB_DYN>
+__device__ __forceinline__ Pos pos_of(const StepArgs& a, int i) {
+    if (use_table<NB>(a)) return Pos{0, 0, 0};
+    const uint32_t c = a.coord[i];
+    return Pos{(int)(c & ((1u << kCoordXBits) - 1)),
+               (int)((c >> kCoordXBits) & ((1u << kCoordYBits) - 1)),
+               (int)(c >> (kCoordXBits + kCoordYBits))};
+}
+
+// Pore index, or N + tail index for a solid, of the in-domain voxel (x, y, z): the segment's
+// first index plus the number of pore (or tail-solid) voxels before x in the segment.
+__device__ __forceinline__ int rank_index(const StepArgs& a, int x, int y, int z) {
+    const RowWord rw = a.words[((size_t)y + (size_t)a.ny * z) * a.W + (x >> 6)];
+    const int b = x & 63;
+    const uint64_t below = (1ull << b) - 1ull;
+    if ((rw.pore >> b) & 1ull) return rw.pore_base + __popcll(rw.pore & below);
+    return a.N + rw.tail_base + __popcll(rw.tail & below);
+}
+
+// Neighbour of pore voxel i along direction q (1..18) for the colour gradient: a pore index
+// (< N) or N + tail index (a solid's phi_s, or the wall's). `mirror` is set for a z neighbour
+// beyond a pressure face in the rank lookup: its phi is the in-plane voxel's, but streaming
+// bounces back there (stream index N). With the explicit table, such neighbours are tail
+// ghosts, already >= N.
+template <int NB = NB_DYN>
+__device__ __forceinline__ int nb(const StepArgs& a, int q, int i, Pos p, bool& mirror) {
+    mirror = false;
+    if (use_table<NB>(a)) return a.nbr[(size_t)(q - 1) * a.ld + i];
+    int cx = p.x + CX[q], cy = p.y + CY[q], cz = p.z + CZ[q];
+    if (CX[q] && (cx < 0 || cx >= a.nx)) {
+        if (!(a.periodic & 1)) return a.N;
+        cx = cx < 0 ? cx + a.nx : cx - a.nx;
+    }
+    if (CY[q] && (cy < 0 || cy >= a.ny)) {
+        if (!(a.periodic & 2)) return a.N;
+        cy = cy < 0 ? cy + a.ny : cy - a.ny;
+    }
+    if (CZ[q] && (cz < 0 || cz >= a.nz)) {
+        if (a.periodic & 4) {
+            cz = cz < 0 ? cz + a.nz : cz - a.nz;
+        } else if (a.bc_z) {
+            cz = p.z;
+            mirror = true;
+        } else {
+            return a.N;
+        }
+    }
+    return rank_index(a, cx, cy, cz);
+}
+
+// Streaming neighbour of pore voxel i along q: a pore index, or >= N for a wall (bounce-back).
+template <int NB = NB_DYN>
+__device__ __forceinline__ int nb_stream(const StepArgs& a, int q, int i, Pos p) {
+    bool mirror;
+    const int r = nb<NB>(a, q, i, p, mirror);
+    return mirror ? a.N : r;
 }
 
 // Incoming population q of voxel i (D3Q19 or D3Q7 array X).
@@ -163,7 +230,7 @@ __device__ __forceinline__ void out_ab(const S* __restrict__ M, int64_t ld, int 
 // D3Q7 populations (rebuilt from the upstream neighbours' moment slots, or from the voxel's own
 // opposite outgoing population where the upstream neighbour is solid: halfway bounce-back).
 // Pressure-face voxels carry their imposed composition; a fresh state its initial densities.
-template <int PREC>
+template <int PREC, int NB = NB_DYN>
 __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, double& na,
                                           double& nbv) {
     using P = Prec<PREC>;
@@ -171,6 +238,7 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
     using R = typename P::R;
     const S* M = (const S*)a.M;
     R ain[7], bin[7];
+    const Pos pos = pos_of<NB>(a, i);
     if (fresh) {
         // The initial populations are w_q N at rest; summing them (rather than taking N) keeps
         // the initial phase bitwise equal to a population-based evaluation.
@@ -200,7 +268,7 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
     }
 #pragma unroll
     for (int q = 1; q < 7; ++q) {
-        const int up = nb(a, OPP[q], i);          // upstream voxel i - xi_q
+        const int up = nb_stream<NB>(a, OPP[q], i, pos);   // upstream voxel i - xi_q
         if (up < a.N)
             out_ab<R>(M, a.ld, up, q, ain[q], bin[q]);
         else
@@ -240,37 +308,46 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
 // Densities and phase indicator: N_a = sum_q A_q, N_b = sum_q B_q (q = 0..6) of the streamed-in
 // D3Q7 populations; phi = (N_a - N_b)/(N_a + N_b); N = N_a + N_b.
 // ------------------------------------------------------------------------------------------
-template <int PREC>
+template <int PREC, int NB = NB_DYN>
 __device__ __forceinline__ void phase_voxel(const StepArgs& a, int i, bool fresh) {
     using S = typename Prec<PREC>::S;
     double na, nbv;
-    densities<PREC>(a, i, fresh, na, nbv);
+    densities<PREC, NB>(a, i, fresh, na, nbv);
     const double nt = na + nbv;
     ((S*)a.phi)[i] = (S)((na - nbv) / nt);
     ((S*)a.ntot)[i] = (S)nt;
 }
 
-template <int PREC, bool ODD>
+template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
     const int i = logical_block(a) * blockDim.x + threadIdx.x;
-    if (i < a.N) phase_voxel<PREC>(a, i, *a.fresh != 0);
+    if (i < a.N) phase_voxel<PREC, NB>(a, i, *a.fresh != 0);
 }
 
 // ------------------------------------------------------------------------------------------
 // Fused colour gradient + MRT collision with interfacial terms and body force + recolouring +
 // AA streaming.
 // ------------------------------------------------------------------------------------------
-template <int PREC, bool ODD>
+template <int PREC, bool ODD, int NB = NB_DYN>
 __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     using P = Prec<PREC>;
     using S = typename P::S;
     using R = typename P::R;
     S* f = (S*)a.f;
 
-    int r[19];
+    int r[19];           // gradient neighbours (phi index)
+    uint32_t mirror = 0; // bit q: streaming along q bounces back although r[q] is a pore index
     r[0] = i;
+    {
+        const Pos pos = pos_of<NB>(a, i);
 #pragma unroll
-    for (int q = 1; q < 19; ++q) r[q] = nb(a, q, i);
+        for (int q = 1; q < 19; ++q) {
+            bool m;
+            r[q] = nb<NB>(a, q, i, pos, m);
+            mirror |= (m ? 1u : 0u) << q;
+        }
+    }
+#define RS(q) (((mirror >> (q)) & 1u) ? a.N : r[(q)])
 
     // Colour gradient: weight 1 on the axis links and 1/2 on the diagonals, so that C -> 6 grad
     // phi and the flat-interface tension is exactly 6 alpha. Each component is accumulated in
@@ -300,7 +377,7 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     // Incoming populations (f, or f - t in deviation storage).
     R fl[19];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) fl[q] = (R)load_in<ODD>(f, a, q, i, r[OPP[q]]);
+    for (int q = 0; q < 19; ++q) fl[q] = (R)load_in<ODD>(f, a, q, i, RS(OPP[q]));
 
     // rho (or rho - 1 in deviation storage) and j.
     R rho = 0, jx = 0, jy = 0, jz = 0;
@@ -385,14 +462,15 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     }
 
 #pragma unroll
-    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, r[q], (S)fs[q]);
+    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, RS(q), (S)fs[q]);
+#undef RS
     if (i == 0) *a.fresh = 0;        // the state now holds outgoing moments
 }
 
-template <int PREC, bool ODD>
+template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
     const int i = logical_block(a) * blockDim.x + threadIdx.x;
-    if (i < a.N) collide_voxel<PREC, ODD>(a, i);
+    if (i < a.N) collide_voxel<PREC, ODD, NB>(a, i);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -436,8 +514,9 @@ __device__ __forceinline__ void voxel_state(const StepArgs& a, int i, double& na
     const S* f = (const S*)a.f;
     int r[19];
     r[0] = i;
+    const Pos pos = pos_of(a, i);
 #pragma unroll
-    for (int q = 1; q < 19; ++q) r[q] = ODD ? nb(a, q, i) : 0;
+    for (int q = 1; q < 19; ++q) r[q] = ODD ? nb_stream(a, q, i, pos) : 0;
     densities<PREC>(a, i, *a.fresh != 0, na, nbv);
     rho = 0.0;
     jx = jy = jz = 0.0;
@@ -603,8 +682,9 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
     S* f = (S*)a.f;
     int r[19];
     r[0] = i;
+    const Pos pos = pos_of(a, i);
 #pragma unroll
-    for (int q = 1; q < 19; ++q) r[q] = nb(a, q, i);
+    for (int q = 1; q < 19; ++q) r[q] = nb_stream(a, q, i, pos);
     double fl[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q)
@@ -638,7 +718,7 @@ dim3 step_grid(const StepArgs& a) {
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
-// Launchers: dispatch on precision and step parity.
+// Launchers: dispatch on precision and step parity (the step kernels also on the lookup).
 // ------------------------------------------------------------------------------------------
 #define LBM_DISPATCH(KERNEL, GRID, BLOCK, ...)                                              \
     do {                                                                                    \
@@ -655,6 +735,21 @@ dim3 step_grid(const StepArgs& a) {
         }                                                                                   \
     } while (0)
 
+#define LBM_DISPATCH_NB(KERNEL, GRID, BLOCK, ...)                                                  \
+    do {                                                                                           \
+        if (a.prec == LBM_FP32_DEV) {                                                              \
+            if (odd)                                                                               \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true, NB>), GRID, BLOCK, 0, s, __VA_ARGS__);\
+            else                                                                                   \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false, NB>), GRID, BLOCK, 0, s, __VA_ARGS__);\
+        } else {                                                                                   \
+            if (odd)                                                                               \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, true, NB>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
+            else                                                                                   \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, false, NB>), GRID, BLOCK, 0, s, __VA_ARGS__); \
+        }                                                                                          \
+    } while (0)
+
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s) {
     (void)block;
     if (a.prec == LBM_FP32_DEV)
@@ -666,14 +761,27 @@ hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    LBM_DISPATCH(phase_kernel, step_grid(a), dim3(block), a);
+// Step kernels: also on the neighbour lookup, fixed per domain.
+template <int NB>
+hipError_t launch_phase_nb(const StepArgs& a, bool odd, int block, hipStream_t s) {
+    LBM_DISPATCH_NB(phase_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
 }
 
-hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    LBM_DISPATCH(collide_kernel, step_grid(a), dim3(block), a);
+template <int NB>
+hipError_t launch_collide_nb(const StepArgs& a, bool odd, int block, hipStream_t s) {
+    LBM_DISPATCH_NB(collide_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
+}
+
+hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s) {
+    return a.words ? launch_phase_nb<NB_RANK>(a, odd, block, s)
+                   : launch_phase_nb<NB_TABLE>(a, odd, block, s);
+}
+
+hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s) {
+    return a.words ? launch_collide_nb<NB_RANK>(a, odd, block, s)
+                   : launch_collide_nb<NB_TABLE>(a, odd, block, s);
 }
 
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,

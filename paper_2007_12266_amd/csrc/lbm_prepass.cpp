@@ -89,15 +89,39 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
         out.phi0[i] = ph;
     }
 
-    // Tail: entry 0 is the wall; solid neighbours and z-face ghosts are appended on first use.
-    out.tail_phi.push_back(p.wall_affinity);
-    std::unordered_map<int64_t, int32_t> solid_tail;   // dense voxel -> tail index
-    std::unordered_map<int64_t, int32_t> ghost_of;     // dense voxel mirrored -> tail index
+    // Tail: entry 0 is the wall; then every solid voxel that is a D3Q19 neighbour of a pore
+    // voxel, in dense order (so its tail index is a rank); z-face ghosts are appended on use.
+    const int dims[3] = {p.nx, p.ny, p.nz};
     auto solid_phi = [&](int64_t v) -> double {
         return voxel_affinity ? voxel_affinity[v] : label_affinity[labels[v]];
     };
+    std::vector<int32_t> tidx(nvox, 0);         // tail index of each tail solid (0: none)
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t v = out.pore_voxel[i];
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / (nx * ny));
+        for (int q = 1; q < 19; ++q) {
+            int c[3] = {x + CX[q], y + CY[q], z + CZ[q]};
+            bool outside = false;
+            for (int a = 0; a < 3; ++a)
+                if (c[a] < 0 || c[a] >= dims[a]) {
+                    if (p.periodic[a]) c[a] = (c[a] + dims[a]) % dims[a];
+                    else outside = true;
+                }
+            if (outside) continue;
+            const int64_t w = (int64_t)c[0] + nx * ((int64_t)c[1] + ny * (int64_t)c[2]);
+            if (pidx[w] < 0) tidx[w] = 1;
+        }
+    }
+    out.tail_phi.push_back(p.wall_affinity);
+    for (int64_t v = 0; v < nvox; ++v) {
+        if (!tidx[v]) continue;
+        const double ps = solid_phi(v);
+        if (!(ps >= -1.0 && ps <= 1.0)) return fmt("affinity of solid voxel %lld is outside [-1, 1]", v);
+        tidx[v] = (int32_t)out.tail_phi.size();
+        out.tail_phi.push_back(ps);
+    }
+    std::unordered_map<int64_t, int32_t> ghost_of;     // dense voxel mirrored -> tail index
     out.nbr.assign((size_t)18 * out.ld, (int32_t)n);  // padding lanes point at the wall
-    const int dims[3] = {p.nx, p.ny, p.nz};
     for (int64_t i = 0; i < n; ++i) {
         const int64_t v = out.pore_voxel[i];
         const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / (nx * ny));
@@ -134,33 +158,15 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
                             out.ghost_tail.push_back(t);
                             out.ghost_src.push_back(pidx[m]);
                         } else {
-                            const double ps = solid_phi(m);
-                            if (!(ps >= -1.0 && ps <= 1.0))
-                                return fmt("voxel_affinity[%lld] is outside [-1, 1]", m);
-                            out.tail_phi.push_back(ps);
+                            // The in-plane mirror is itself a neighbour, so it is a tail solid.
+                            out.tail_phi.push_back(out.tail_phi[tidx[m]]);
                         }
                     }
                     entry = (int32_t)(n + t);
                 }
             } else {
                 const int64_t w = (int64_t)c[0] + nx * ((int64_t)c[1] + ny * (int64_t)c[2]);
-                if (pidx[w] >= 0) {
-                    entry = pidx[w];
-                } else {
-                    auto it = solid_tail.find(w);
-                    int32_t t;
-                    if (it != solid_tail.end()) {
-                        t = it->second;
-                    } else {
-                        const double ps = solid_phi(w);
-                        if (!(ps >= -1.0 && ps <= 1.0))
-                            return fmt("affinity of solid voxel %lld is outside [-1, 1]", w);
-                        t = (int32_t)out.tail_phi.size();
-                        solid_tail.emplace(w, t);
-                        out.tail_phi.push_back(ps);
-                    }
-                    entry = (int32_t)(n + t);
-                }
+                entry = pidx[w] >= 0 ? pidx[w] : (int32_t)(n + tidx[w]);
             }
             out.nbr[(size_t)(q - 1) * out.ld + i] = entry;
         }
@@ -170,8 +176,86 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
         }
     }
     out.n_tail = (int64_t)out.tail_phi.size();
+
+    // Rank lookup: packed coordinates and 64-voxel row segments.
+    out.rank_ok = nx <= (1 << kCoordXBits) && ny <= (1 << kCoordYBits) && nz <= (1 << kCoordZBits);
+    if (out.rank_ok) {
+        const int64_t W = (nx + 63) / 64;
+        out.words_per_row = (int32_t)W;
+        out.words.assign((size_t)(ny * nz * W), RowWord{0, 0, 0, 0, 0});
+        int32_t next_pore = 0, next_tail = 1;
+        for (int64_t r = 0; r < ny * nz; ++r)
+            for (int64_t w = 0; w < W; ++w) {
+                RowWord& rw = out.words[(size_t)(r * W + w)];
+                rw.pore_base = next_pore;
+                rw.tail_base = next_tail;
+                for (int b = 0; b < 64 && 64 * w + b < nx; ++b) {
+                    const int64_t v = r * nx + 64 * w + b;
+                    if (pidx[v] >= 0) {
+                        rw.pore |= 1ull << b;
+                        ++next_pore;
+                    } else if (tidx[v]) {
+                        rw.tail |= 1ull << b;
+                        ++next_tail;
+                    }
+                }
+            }
+        out.coord.assign((size_t)out.ld, 0u);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t v = out.pore_voxel[i];
+            const uint32_t x = (uint32_t)(v % nx), y = (uint32_t)((v / nx) % ny);
+            const uint32_t z = (uint32_t)(v / (nx * ny));
+            out.coord[i] = x | (y << kCoordXBits) | (z << (kCoordXBits + kCoordYBits));
+        }
+    }
     if (n + out.n_tail >= (int64_t)std::numeric_limits<int32_t>::max())
         return "pore voxels plus solid tail exceed int32 indexing";
+    return "";
+}
+
+std::string check_rank_lookup(const lbm_params& p, const Prepass& pre) {
+    if (!pre.rank_ok) return "";
+    const int64_t ny = p.ny, W = pre.words_per_row, n = pre.n_pore;
+    auto rank = [&](int64_t x, int64_t y, int64_t z) -> int64_t {
+        const RowWord& rw = pre.words[(size_t)((y + ny * z) * W + (x >> 6))];
+        const int b = (int)(x & 63);
+        const uint64_t below = (1ull << b) - 1ull;
+        if ((rw.pore >> b) & 1ull) return rw.pore_base + __builtin_popcountll(rw.pore & below);
+        return n + rw.tail_base + __builtin_popcountll(rw.tail & below);
+    };
+    std::unordered_map<int64_t, int64_t> ghost_src;   // table ghost entry -> mirrored index
+    for (size_t k = 0; k < pre.ghost_tail.size(); ++k)
+        ghost_src[n + pre.ghost_tail[k]] = pre.ghost_src[k];
+    const int dims[3] = {p.nx, p.ny, p.nz};
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t c = pre.coord[i];
+        const int x = (int)(c & ((1u << kCoordXBits) - 1));
+        const int y = (int)((c >> kCoordXBits) & ((1u << kCoordYBits) - 1));
+        const int z = (int)(c >> (kCoordXBits + kCoordYBits));
+        if ((int64_t)x + (int64_t)p.nx * ((int64_t)y + ny * z) != pre.pore_voxel[i])
+            return fmt("packed coordinate of pore %lld is wrong", i);
+        for (int q = 1; q < 19; ++q) {
+            int cc[3] = {x + CX[q], y + CY[q], z + CZ[q]};
+            bool wall = false, mirror = false;
+            for (int a = 0; a < 3 && !wall; ++a)
+                if (cc[a] < 0 || cc[a] >= dims[a]) {
+                    if (p.periodic[a]) cc[a] = (cc[a] + dims[a]) % dims[a];
+                    else if (a == 2 && p.bc_z == 1) { cc[2] = z; mirror = true; }
+                    else wall = true;
+                }
+            const int64_t got = wall ? n : rank(cc[0], cc[1], cc[2]);
+            int64_t want = pre.nbr[(size_t)(q - 1) * pre.ld + i];
+            if (mirror) {
+                // The table holds a ghost of the mirrored voxel: a pore's ghost, or (for a
+                // solid mirror) a copy of that solid's phi_s.
+                auto it = ghost_src.find(want);
+                if (it != ghost_src.end()) want = it->second;
+                else if (got >= n && pre.tail_phi[want - n] == pre.tail_phi[got - n]) want = got;
+            }
+            if (got != want)
+                return fmt("rank lookup differs from the table at pore %lld, direction %lld", i, q);
+        }
+    }
     return "";
 }
 

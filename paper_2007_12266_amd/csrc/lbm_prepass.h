@@ -10,6 +10,20 @@
 
 namespace lbm {
 
+// One 64-voxel segment of an image row (y, z), x in [64 w, 64 w + 64): which voxels are pores,
+// which are tail solids (solids next to a pore), and the index of the first of each in the
+// segment. A neighbour's index is then a base plus a population count (rank lookup).
+struct alignas(32) RowWord {
+    uint64_t pore;       // bit b: voxel 64 w + b is a pore voxel
+    uint64_t tail;       // bit b: voxel 64 w + b is a solid with an entry in the phi tail
+    int32_t pore_base;   // pore index of the first pore voxel of the segment (or the next one)
+    int32_t tail_base;   // tail index of the first tail solid of the segment (or the next one)
+    uint64_t pad;        // 32-byte records
+};
+
+// Packed voxel coordinate: x | y << 10 | z << 21 (nx <= 1024, ny <= 2048, nz <= 2048).
+constexpr int kCoordXBits = 10, kCoordYBits = 11, kCoordZBits = 11;
+
 struct Prepass {
     int64_t n_pore = 0;                 // N
     int64_t n_tail = 0;                 // entries of the solid/wall tail of the phi array
@@ -23,11 +37,22 @@ struct Prepass {
     std::vector<int32_t> ghost_src;     //   with pressure boundaries): tail index, pore index
     std::vector<double> phi0;           // initial phase of each pore voxel
     std::vector<int32_t> inlet, outlet; // pore indices on z = 0 and z = nz-1 (bc_z == 1)
+    // Rank lookup (built when the image fits the packed coordinate):
+    bool rank_ok = false;
+    int32_t words_per_row = 0;          // ceil(nx / 64)
+    std::vector<RowWord> words;         // [nz][ny][words_per_row]
+    std::vector<uint32_t> coord;        // [ld] packed coordinate of each pore voxel
 };
 
 // Validates the inputs and builds `out`. Returns "" on success, else an error message.
 std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels,
                     const int8_t* label_kind, const double* label_affinity,
                     const double* voxel_affinity, const double* init_phi, Prepass& out);
+
+// Replays the rank lookup for every pore voxel and direction and compares it with the table
+// (table ghosts stand for z-face mirrors and are compared by the mirrored voxel). Returns ""
+// when they agree (or the rank lookup does not apply), else a description of the first
+// mismatch. Host-only; used by lbm_prepass_query.
+std::string check_rank_lookup(const lbm_params& p, const Prepass& pre);
 
 }  // namespace lbm

@@ -110,7 +110,7 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
         Span sp{};
         if (timing) { sp.kind = 0; HIP_TRY(mark(&sp.a)); }
         HIP_TRY(launch_phase(ap, odd, tu.phase_block, d->stream));
-        if (!d->pre.ghost_tail.empty())
+        if (!d->rank && !d->pre.ghost_tail.empty())
             HIP_TRY(launch_ghosts(ap, d->ghost_tail, d->ghost_src,
                                   (int32_t)d->pre.ghost_tail.size(), d->stream));
         if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); sp.kind = 1; HIP_TRY(mark(&sp.a)); }
@@ -161,12 +161,19 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
 
 // Device bytes lbm_domain_create allocates for a pre-passed input (every buffer is rounded up to
 // 256 bytes by lbm_domain::dalloc).
+static bool uses_rank(const lbm_params& p, const Prepass& pre) {
+    return pre.rank_ok && p.neighbour_mode == LBM_NBR_RANK;
+}
+
 static int64_t domain_bytes(const lbm_params& p, const Prepass& pre) {
     const size_t eb = p.precision == LBM_FP32_DEV ? 4 : 8, ld = (size_t)pre.ld;
     auto r = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
+    const int64_t nbr = uses_rank(p, pre)
+                            ? r(sizeof(uint32_t) * ld) + r(sizeof(RowWord) * pre.words.size())
+                            : r(sizeof(int32_t) * 18 * ld);
     int64_t total = r(eb * 19 * ld) + r(eb * 8 * ld) + r(sizeof(int32_t)) +
                     r(eb * (size_t)(pre.n_pore + pre.n_tail)) + r(eb * ld) +
-                    r(sizeof(double) * ld) + r(sizeof(int32_t) * 18 * ld) +
+                    r(sizeof(double) * ld) + nbr +
                     r(sizeof(double) * kRedBlocks * kNRed) + r(sizeof(double) * kNRed) +
                     r(sizeof(double) * 1024 * kNRed);
     const size_t faces = pre.inlet.size() + pre.outlet.size();
@@ -179,6 +186,9 @@ extern "C" {
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
+static const char* const kRankLimits =
+    "rank neighbour lookup needs nx <= 1024 and ny, nz <= 2048";
+
 lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
                                 int32_t n_labels, const int8_t* label_kind,
                                 const double* label_affinity, const double* voxel_affinity,
@@ -189,6 +199,8 @@ lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
     std::string err = prepass(*params, labels, n_labels, label_kind, label_affinity,
                               voxel_affinity, init_phi, pre);
     if (!err.empty()) return fail(LBM_ERR_ARG, err);
+    if (params->neighbour_mode == LBM_NBR_RANK && !pre.rank_ok)
+        return fail(LBM_ERR_ARG, kRankLimits);
     *bytes = domain_bytes(*params, pre);
     return LBM_OK;
 }
@@ -213,6 +225,8 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
         return fail(LBM_ERR_ARG, "rho_in and rho_out must be positive");
     if (p.reduce_every < 0) return fail(LBM_ERR_ARG, "reduce_every must be >= 0");
+    if (p.neighbour_mode < LBM_NBR_AUTO || p.neighbour_mode > LBM_NBR_RANK)
+        return fail(LBM_ERR_ARG, "neighbour_mode must be a lbm_neighbour_mode");
     int block = p.block_size == 0 ? 256 : p.block_size;
     if (block != 64 && block != 128 && block != 256)
         return fail(LBM_ERR_ARG, "block_size must be 0, 64, 128 or 256");
@@ -226,6 +240,9 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     std::string err = prepass(p, labels, n_labels, label_kind, label_affinity, voxel_affinity,
                               init_phi, d->pre);
     if (!err.empty()) return fail(LBM_ERR_ARG, err);
+    if (p.neighbour_mode == LBM_NBR_RANK && !d->pre.rank_ok)
+        return fail(LBM_ERR_ARG, kRankLimits);
+    d->rank = uses_rank(p, d->pre);
     if (alloc) {
         d->alloc = *alloc;
         d->has_alloc = true;
@@ -245,12 +262,18 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     d->phi = d->dalloc(eb * (size_t)(pre.n_pore + pre.n_tail));
     d->ntot = d->dalloc(eb * ld);
     d->stage = (double*)d->dalloc(sizeof(double) * ld);
-    d->nbr = (int32_t*)d->dalloc(sizeof(int32_t) * 18 * ld);
+    if (d->rank) {
+        d->coord = (uint32_t*)d->dalloc(sizeof(uint32_t) * ld);
+        d->words = (RowWord*)d->dalloc(sizeof(RowWord) * pre.words.size());
+    } else {
+        d->nbr = (int32_t*)d->dalloc(sizeof(int32_t) * 18 * ld);
+    }
     d->red_partials = (double*)d->dalloc(sizeof(double) * kRedBlocks * kNRed);
     d->red_out = (double*)d->dalloc(sizeof(double) * kNRed);
     d->hist = (double*)d->dalloc(sizeof(double) * (size_t)d->hist_cap * kNRed);
     double* phi0 = d->stage;
-    if (!d->f || !d->M || !d->fresh || !d->phi || !d->ntot || !d->stage || !d->nbr ||
+    if (!d->f || !d->M || !d->fresh || !d->phi || !d->ntot || !d->stage ||
+        (d->rank ? (!d->coord || !d->words) : !d->nbr) ||
         !d->red_partials || !d->red_out || !d->hist) {
         d->release();
         return fail(LBM_ERR_OOM, "device allocation failed");
@@ -284,7 +307,12 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         if (e != hipSuccess && st == LBM_OK)
             st = fail(LBM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
-    guard(up(d->nbr, pre.nbr.data(), sizeof(int32_t) * pre.nbr.size()), "upload nbr");
+    if (d->rank) {
+        guard(up(d->coord, pre.coord.data(), sizeof(uint32_t) * pre.coord.size()), "upload coord");
+        guard(up(d->words, pre.words.data(), sizeof(RowWord) * pre.words.size()), "upload words");
+    } else {
+        guard(up(d->nbr, pre.nbr.data(), sizeof(int32_t) * pre.nbr.size()), "upload nbr");
+    }
     std::vector<float> tail32;
     if (eb == 4) tail32.assign(pre.tail_phi.begin(), pre.tail_phi.end());
     guard(up((char*)d->phi + eb * pre.n_pore,
@@ -459,6 +487,8 @@ lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out) {
     out->step = d->step;
     out->precision = d->p.precision;
     out->block_size = d->tune.collide_block;
+    out->neighbour_mode = d->rank ? LBM_NBR_RANK : LBM_NBR_TABLE;
+    out->pad_ = 0;
     return LBM_OK;
 }
 
@@ -577,6 +607,8 @@ lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, in
     std::string err = prepass(*params, labels, n_labels, label_kind, label_affinity,
                               voxel_affinity, init_phi, pre);
     if (!err.empty()) return fail(LBM_ERR_ARG, err);
+    err = check_rank_lookup(*params, pre);
+    if (!err.empty()) return fail(LBM_ERR_STATE, "internal: " + err);
     *n_pore = pre.n_pore;
     *n_tail = pre.n_tail;
     if (pore_voxel) std::copy(pre.pore_voxel.begin(), pre.pore_voxel.end(), pore_voxel);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE, LBM_ERR_STATE = range(6)
 FP64, FP32_DEV = 0, 1
+NBR_AUTO, NBR_TABLE, NBR_RANK = 0, 1, 2
 FIELDS = {"Na": 0, "Nb": 1, "phi": 2, "rho": 3, "p": 4, "ux": 5, "uy": 6, "uz": 7}
 
 # Every symbol include/lbm.h declares.
@@ -45,7 +46,8 @@ class Params(ctypes.Structure):
                 ("force", ctypes.c_double * 3), ("wall_affinity", ctypes.c_double),
                 ("bc_z", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
-                ("reduce_every", ctypes.c_int32), ("block_size", ctypes.c_int32)]
+                ("reduce_every", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("neighbour_mode", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class Reduction(ctypes.Structure):
@@ -87,7 +89,8 @@ class Info(ctypes.Structure):
     _fields_ = [("n_pore", ctypes.c_int64), ("n_solid_tail", ctypes.c_int64),
                 ("ld", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("step", ctypes.c_int64), ("precision", ctypes.c_int32),
-                ("block_size", ctypes.c_int32)]
+                ("block_size", ctypes.c_int32), ("neighbour_mode", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class PoolInfo(ctypes.Structure):
@@ -167,7 +170,7 @@ def _ptr(a: Optional[np.ndarray]):
 
 
 def make_params(problem, precision: int = FP64, reduce_every: int = 0,
-                block_size: int = 0) -> Params:
+                block_size: int = 0, neighbour_mode: int = NBR_AUTO) -> Params:
     """lbm_params of an ``inputs.Problem``."""
     p = Params()
     p.nz, p.ny, p.nx = problem.shape
@@ -182,6 +185,7 @@ def make_params(problem, precision: int = FP64, reduce_every: int = 0,
     p.rho_in, p.rho_out = problem.rho_in, problem.rho_out
     p.reduce_every = reduce_every
     p.block_size = block_size
+    p.neighbour_mode = neighbour_mode
     return p
 
 
@@ -213,10 +217,10 @@ def prepass_query(problem) -> dict:
             "tail_phi": tail}
 
 
-def footprint(problem, precision: int = FP64) -> int:
+def footprint(problem, precision: int = FP64, neighbour_mode: int = NBR_AUTO) -> int:
     """Device bytes a Domain of this problem would allocate (host-only pre-pass)."""
     L = load_library()
-    p = make_params(problem, precision)
+    p = make_params(problem, precision, neighbour_mode=neighbour_mode)
     labels, kind, aff, vaff, iphi = _problem_arrays(problem)
     b = ctypes.c_int64()
     _check(L.lbm_domain_footprint(ctypes.byref(p), _ptr(labels), int(aff.size), _ptr(kind),
@@ -251,11 +255,12 @@ class Domain:
     """One colour-LBM domain on the GPU (wraps lbm_domain*)."""
 
     def __init__(self, problem, precision: int = FP64, reduce_every: int = 0,
-                 block_size: int = 0, allocator: str = "torch", stream=None):
+                 block_size: int = 0, allocator: str = "torch", stream=None,
+                 neighbour_mode: int = NBR_AUTO):
         L = load_library()
         self.problem = problem
         self.shape = problem.shape
-        p = make_params(problem, precision, reduce_every, block_size)
+        p = make_params(problem, precision, reduce_every, block_size, neighbour_mode)
         self.params = p
         labels, kind, aff, vaff, iphi = _problem_arrays(problem)
         self._torch_alloc = None

@@ -154,3 +154,22 @@ def test_prepass_pressure_faces_mirror_the_plane():
             assert tail[e - n] == expect
             checked += 1
     assert checked > 0
+
+
+def test_footprint_depends_on_the_neighbour_lookup():
+    """The rank lookup stores 4 B per pore voxel plus 32 B per 64-voxel row segment instead of
+    the 72 B/voxel table; grids beyond its 10/11/11-bit coordinates fall back to the table."""
+    prob = inputs.sphere_problem(n=32)
+    table = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_TABLE)
+    rank = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_RANK)
+    auto = lbm.footprint(prob, lbm.FP64)
+    assert auto == table > rank
+    n = lbm.prepass_query(prob)["n_pore"]
+    assert table - rank >= 60 * n
+    wide = inputs.Problem(labels=np.ones((2, 1, 1030), np.int32),
+                          label_kind=np.array([inputs.KIND_SOLID, inputs.KIND_FLUID_A], np.int8),
+                          label_affinity=np.array([0.0, 0.0]), periodic=(True, True, True))
+    assert lbm.footprint(wide, lbm.FP64) == lbm.footprint(wide, lbm.FP64,
+                                                          neighbour_mode=lbm.NBR_TABLE)
+    with pytest.raises(lbm.LbmError):
+        lbm.footprint(wide, lbm.FP64, neighbour_mode=lbm.NBR_RANK)

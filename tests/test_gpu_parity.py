@@ -64,12 +64,16 @@ def spheres32():
     return inputs.sphere_problem(n=32)
 
 
+@pytest.mark.parametrize("mode", ["rank", "table"])
 @pytest.mark.parametrize("steps", [200, 199])
-def test_sphere_pack_parity(lbm, spheres32, steps):
+def test_sphere_pack_parity(lbm, spheres32, steps, mode):
     """32^3 random spheres, periodic x/y, walls in z, affinity +0.5, tau 0.7, alpha 0.005,
-    beta 0.95, F_z = 1e-5, random phase at Sw = 0.5: 200 steps (and 199, the other AA parity)."""
+    beta 0.95, F_z = 1e-5, random phase at Sw = 0.5: 200 steps (and 199, the other AA parity),
+    with either neighbour lookup."""
     prob = spheres32
-    dom = lbm.Domain(prob)
+    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    dom = lbm.Domain(prob, neighbour_mode=nm)
+    assert dom.info()["neighbour_mode"] == nm
     dom.step(steps)
     gpu = dom.fields()
     ref = O.state_for(prob).run(steps).fields()
@@ -78,14 +82,16 @@ def test_sphere_pack_parity(lbm, spheres32, steps):
     dom.close()
 
 
+@pytest.mark.parametrize("mode", ["rank", "table"])
 @pytest.mark.parametrize("block", [64, 128, 256])
 @pytest.mark.parametrize("periodic", [(True, False, True), (False, True, False)])
-def test_ragged_domains_all_block_sizes(lbm, block, periodic):
+def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
     """Pore counts that are not multiples of the block, several tiles, mixed periodicity,
     per-voxel affinity, unequal viscosities (nu varies with phi), force in all components."""
     prob = _random_problem((13, 21, 19), periodic, seed=101 + periodic.index(False))
     steps = 37
-    dom = lbm.Domain(prob, block_size=block)
+    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    dom = lbm.Domain(prob, block_size=block, neighbour_mode=nm)
     assert dom.n_pore % 64 != 0 and dom.n_pore > 4 * block
     dom.step(steps)
     gpu = dom.fields()
@@ -269,12 +275,15 @@ def test_autotune_restores_state_and_keeps_results(lbm, precision):
     dom.close()
 
 
+@pytest.mark.parametrize("mode", ["rank", "table"])
 @pytest.mark.parametrize("steps", [60, 61])
-def test_pressure_faces_parity(lbm, steps):
+def test_pressure_faces_parity(lbm, steps, mode):
     """Displacement with pressure faces (rho 1.03 / 0.97), walls of affinity -0.7, GRF rock
-    between 4-plane reservoirs, x/y periodic: GPU FP64 vs the oracle, both parities."""
+    between 4-plane reservoirs, x/y periodic: GPU FP64 vs the oracle, both parities, with
+    either neighbour lookup (mirrored z neighbours through ghosts or computed)."""
     prob = inputs.displacement_problem(shape=(40, 20, 18), seed_geom=8, porosity_target=0.3)
-    dom = lbm.Domain(prob)
+    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    dom = lbm.Domain(prob, neighbour_mode=nm)
     dom.step(steps)
     gpu = dom.fields()
     ref = O.state_for(prob).run(steps)
@@ -296,3 +305,33 @@ def test_pressure_faces_fp32_dev_tracks_fp64(lbm):
     assert abs(rb["qz"] - ra["qz"]) <= 1e-3 * abs(ra["qz"]), (ra["qz"], rb["qz"])
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_neighbour_lookups_are_bitwise_identical(lbm, precision):
+    """The table and the rank lookup name the same neighbours, so every stored value agrees
+    bitwise: walls in every direction, periodic wraps, and mirrored pressure faces."""
+    prec = lbm.FP64 if precision == "fp64" else lbm.FP32_DEV
+    probs = [_random_problem((29, 14, 23), (False, False, False), seed=61),
+             _random_problem((70, 9, 11), (True, False, True), seed=62),
+             inputs.displacement_problem(shape=(30, 18, 16), seed_geom=63, porosity_target=0.35)]
+    for prob in probs:
+        blobs, reds = [], []
+        for nm in (lbm.NBR_TABLE, lbm.NBR_RANK):
+            dom = lbm.Domain(prob, precision=prec, neighbour_mode=nm)
+            dom.step(23)
+            blobs.append(dom.save())
+            reds.append(dom.reduce())
+            dom.close()
+        assert blobs[0] == blobs[1]
+        assert reds[0] == reds[1]
+
+
+def test_auto_mode_and_footprints(lbm):
+    prob = _random_problem((17, 18, 19), (True, True, True), seed=5)
+    dom = lbm.Domain(prob)
+    assert dom.info()["neighbour_mode"] == lbm.NBR_TABLE
+    dom.close()
+    table = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_TABLE)
+    rank = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_RANK)
+    assert rank < table

@@ -46,14 +46,17 @@ def test_members_match_solo_runs_bitwise(lbm, precision):
     prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
     probs = _mix()
     pool = lbm.Pool(1 << 34, precision=prec, max_slots=8, chunk_steps=20)
-    doms = [lbm.Domain(p, precision=prec) for p in probs]
+    # Members alternate between the two neighbour lookups; each solo run uses the other one.
+    modes = [lbm.NBR_RANK if k % 2 == 0 else lbm.NBR_TABLE for k in range(len(probs))]
+    doms = [lbm.Domain(p, precision=prec, neighbour_mode=m) for p, m in zip(probs, modes)]
     slots = [pool.admit(d) for d in doms]
     pool.step(53)                                  # 2 graph replays + 13 eager steps
     info = pool.info()
     assert info["graph_replays"] == 2 and info["eager_steps"] == 13 and info["members"] == 5
     red = pool.reduce()
-    for p, d, s in zip(probs, doms, slots):
-        solo = lbm.Domain(p, precision=prec)
+    for p, d, s, m in zip(probs, doms, slots, modes):
+        assert d.info()["neighbour_mode"] == m
+        solo = lbm.Domain(p, precision=prec, neighbour_mode=lbm.NBR_RANK + lbm.NBR_TABLE - m)
         solo.step(53)
         assert d.info()["step"] == 53
         assert d.save() == solo.save()
