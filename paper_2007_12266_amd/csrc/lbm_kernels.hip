@@ -208,28 +208,41 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __r
     for (int k = 2; k < 8; ++k) M[(size_t)k * a.ld + i] = (S)0;
 }
 
-// Outgoing D3Q7 populations of voxel y along axis direction q (1..6), from its moment slots
-// (N_a, N_b, u_x, u_y, u_z, G_x, G_y, G_z), one row of ld values per slot:
-// A*_q = w_q [N_a (1 + u.xi_q / cs^2) + G.xi_q], B*_q = w_q [N_b (1 + u.xi_q / cs^2) - G.xi_q],
-// cs^2 = 2/9.
-template <typename R, typename S>
-__device__ __forceinline__ void out_ab(const S* __restrict__ M, int64_t ld, int y, int q, R& ao,
-                                       R& bo) {
-    const int c = (q - 1) >> 1;                 // axis of q
-    const R sgn = (q & 1) ? (R)1 : (R)-1;       // +x, +y, +z are the odd q
-    const R na = (R)M[y], nb = (R)M[ld + y];
-    const R uc = (R)M[(size_t)(2 + c) * ld + y];
-    const R gc = (R)M[(size_t)(5 + c) * ld + y];
+// s + v with no contraction into a preceding product.
+__device__ __forceinline__ double add_rounded(double s, double v) {
+#pragma clang fp contract(off)
+    return s + v;
+}
+
+// Outgoing D3Q7 populations along an axis direction of sign sgn (+1 or -1), from one voxel's
+// moment slots (N_a, N_b, u_c, G_c for the direction's axis c):
+// A* = w [N_a (1 + sgn u_c / cs^2) + sgn G_c], B* = w [N_b (1 + sgn u_c / cs^2) - sgn G_c],
+// w = 1/9, cs^2 = 2/9.
+template <typename R>
+__device__ __forceinline__ void ab_out(R na, R nb, R uc, R gc, R sgn, R& ao, R& bo) {
     const R eu = (R)4.5 * (sgn * uc);
     const R en = sgn * gc;
     ao = (R)(1.0 / 9.0) * (na * ((R)1 + eu) + en);
     bo = (R)(1.0 / 9.0) * (nb * ((R)1 + eu) - en);
 }
 
+// The same for direction q (1..6) of voxel y, read from the moment slots (one row of ld values
+// per slot: N_a, N_b, u_x, u_y, u_z, G_x, G_y, G_z).
+template <typename R, typename S>
+__device__ __forceinline__ void out_ab(const S* __restrict__ M, int64_t ld, int y, int q, R& ao,
+                                       R& bo) {
+    const int c = (q - 1) >> 1;                 // axis of q
+    ab_out<R>((R)M[y], (R)M[ld + y], (R)M[(size_t)(2 + c) * ld + y],
+              (R)M[(size_t)(5 + c) * ld + y], (q & 1) ? (R)1 : (R)-1, ao, bo);  // +x, +y, +z odd
+}
+
 // Component densities N_a, N_b of pore voxel i in the current state: the sum of the incoming
 // D3Q7 populations (rebuilt from the upstream neighbours' moment slots, or from the voxel's own
 // opposite outgoing population where the upstream neighbour is solid: halfway bounce-back).
 // Pressure-face voxels carry their imposed composition; a fresh state its initial densities.
+// All six neighbour indices are read first and every slot load is unconditional (a solid
+// upstream neighbour selects the voxel's own slots and flips the sign), so the loads of one
+// voxel are in flight together.
 template <int PREC, int NB = NB_DYN>
 __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, double& na,
                                           double& nbv) {
@@ -238,7 +251,6 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
     using R = typename P::R;
     const S* M = (const S*)a.M;
     R ain[7], bin[7];
-    const Pos pos = pos_of<NB>(a, i);
     if (fresh) {
         // The initial populations are w_q N at rest; summing them (rather than taking N) keeps
         // the initial phase bitwise equal to a population-based evaluation.
@@ -258,6 +270,10 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
         }
         return;
     }
+    const Pos pos = pos_of<NB>(a, i);
+    int up[7];
+#pragma unroll
+    for (int q = 1; q < 7; ++q) up[q] = nb_stream<NB>(a, OPP[q], i, pos);  // voxel i - xi_q
     if (a.face) {
         const int fc = a.face[i];
         if (fc) {
@@ -266,13 +282,20 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
             return;
         }
     }
+    R sna[7], snb[7], suc[7], sgc[7];
 #pragma unroll
     for (int q = 1; q < 7; ++q) {
-        const int up = nb_stream<NB>(a, OPP[q], i, pos);   // upstream voxel i - xi_q
-        if (up < a.N)
-            out_ab<R>(M, a.ld, up, q, ain[q], bin[q]);
-        else
-            out_ab<R>(M, a.ld, i, OPP[q], ain[q], bin[q]);
+        const int c = (q - 1) >> 1;
+        const int y = up[q] < a.N ? up[q] : i;
+        sna[q] = (R)M[y];
+        snb[q] = (R)M[a.ld + y];
+        suc[q] = (R)M[(size_t)(2 + c) * a.ld + y];
+        sgc[q] = (R)M[(size_t)(5 + c) * a.ld + y];
+    }
+#pragma unroll
+    for (int q = 1; q < 7; ++q) {
+        const R sq = (q & 1) ? (R)1 : (R)-1;
+        ab_out<R>(sna[q], snb[q], suc[q], sgc[q], up[q] < a.N ? sq : -sq, ain[q], bin[q]);
     }
     if (P::kDev) {
         // The rest population is what the six moving ones leave of N (the rounded float weights
@@ -297,10 +320,12 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
     }
     // Accumulated in double in both precisions: a float running sum of seven populations
     // carries a mean rounding bias of a few 1e-9, which would create that much mass per step.
+    // Each population is rounded on its own before it enters the sum (no fused multiply-add
+    // across the two), as in an evaluation that stores the populations.
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
-        na += (double)ain[q];
-        nbv += (double)bin[q];
+        na = add_rounded(na, (double)ain[q]);
+        nbv = add_rounded(nbv, (double)bin[q]);
     }
 }
 
