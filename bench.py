@@ -68,7 +68,62 @@ WORKLOADS = {
                    desc="steady two-fluid flow, 512^3 GRF rock (corr 4, porosity 0.2, "
                         "percolating), affinity U[-0.9,0.9], Sw=0.5, Fz=1e-5, periodic, "
                         "reductions every 100 steps"),
+    "disp512": dict(n=512, seed_geom=5, reduce_every=100, displacement=True,
+                    desc="unsteady displacement, 512^3 GRF rock (corr 4, porosity 0.2, "
+                         "percolating) between 4-plane reservoirs, wall affinity -0.7, "
+                         "pressure faces rho 1.03 (inlet, injects fluid a) / 0.97, x/y "
+                         "periodic, reductions every 100 steps"),
 }
+
+
+def make_problem(wl, n=None):
+    from paper_2007_12266_amd import inputs
+    n = n or wl["n"]
+    if wl.get("displacement"):
+        return inputs.displacement_problem(n=n, seed_geom=wl["seed_geom"])
+    return inputs.grf_problem(n=n, seed_geom=wl["seed_geom"], seed_aff=wl["seed_aff"],
+                              seed_phase=wl["seed_phase"])
+
+
+def front_position(phi) -> float:
+    """Equivalent front position of fluid a, in planes from the inlet: the sum over z planes
+    of the plane's smooth saturation, mean of (1 + phi)/2 over its pore voxels (a sharp front
+    after k fully invaded planes gives k)."""
+    s = np.nanmean((1.0 + phi) * 0.5, axis=(1, 2))
+    return float(np.nansum(s))
+
+
+def precision_study(prob, steps: int, every: int, torch, lbm) -> dict:
+    """FP32-deviation against FP64 on the same problem: both advance side by side and every
+    `every` steps the saturation, the Darcy flux and the front position are compared."""
+    doms = {k: lbm.Domain(prob, precision=p, allocator="hip")
+            for k, p in (("fp64", lbm.FP64), ("fp32dev", lbm.FP32_DEV))}
+    rows = []
+    for t in range(every, steps + 1, every):
+        rec = {"step": t}
+        for k, d in doms.items():
+            d.step(every)
+            r = d.reduce()
+            rec[k] = {"sw": r["sw"], "qz": r["qz"], "zf": front_position(d.field("phi")),
+                      "unstable": r["unstable"], "mass_a": r["mass_a"]}
+        rows.append(rec)
+        log("precision study step %d: Sw %.6f / %.6f, qz %.4e / %.4e, zf %.3f / %.3f"
+            % (t, rec["fp64"]["sw"], rec["fp32dev"]["sw"], rec["fp64"]["qz"],
+               rec["fp32dev"]["qz"], rec["fp64"]["zf"], rec["fp32dev"]["zf"]))
+    for d in doms.values():
+        d.close()
+
+    def rel(k):
+        return max(abs(r["fp32dev"][k] - r["fp64"][k]) / abs(r["fp64"][k]) for r in rows)
+    last = rows[-1]
+    return {"steps": steps, "every": every,
+            "sw_rel_max": rel("sw"), "qz_rel_max": rel("qz"),
+            "zf_abs_max_planes": max(abs(r["fp32dev"]["zf"] - r["fp64"]["zf"]) for r in rows),
+            "unstable": max(r[k]["unstable"] for r in rows for k in ("fp64", "fp32dev")),
+            "final": {"fp64": last["fp64"], "fp32dev": last["fp32dev"]},
+            "series": [[r["step"], r["fp64"]["sw"], r["fp32dev"]["sw"], r["fp64"]["qz"],
+                        r["fp32dev"]["qz"], r["fp64"]["zf"], r["fp32dev"]["zf"]]
+                       for r in rows]}
 
 
 def log(msg):
@@ -287,6 +342,9 @@ def main():
                     help="keep the default launch shapes instead of autotuning them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
+                    help="also run FP32-deviation beside FP64 for STEPS steps from the initial "
+                         "state, comparing Sw, Darcy flux and front position every 100 steps")
     args = ap.parse_args()
     args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.gpus != 1:
@@ -306,8 +364,7 @@ def main():
     wl = WORKLOADS[args.workload]
     log("generating %s" % args.workload)
     t0 = time.perf_counter()
-    prob = inputs.grf_problem(n=wl["n"], seed_geom=wl["seed_geom"], seed_aff=wl["seed_aff"],
-                              seed_phase=wl["seed_phase"])
+    prob = make_problem(wl)
     log("rock ready in %.1f s, porosity %.4f" % (time.perf_counter() - t0,
                                                   prob.n_pore() / np.prod(prob.shape)))
     torch.cuda.set_device(0)
@@ -395,9 +452,15 @@ def main():
         "reductions": {"recorded": len(hist), "sw": red["sw"], "qz": red["qz"],
                        "unstable": red["unstable"]},
     }
+    if args.precision_study:
+        out["fp32_vs_fp64"] = precision_study(prob, args.precision_study, 100, torch, lbm)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(prob)
+        sample = prob if wl["n"] <= 256 else make_problem(wl, n=256)
+        out["cpu_baseline"] = cpu_baseline(sample)
+        if sample is not prob:
+            out["cpu_baseline"]["sample"] += " (the same generator at 256^3, which bounds the " \
+                                             "dense oracle's memory and set-up time)"
     print(json.dumps(out), flush=True)
 
 

@@ -178,11 +178,10 @@ __device__ __forceinline__ void store_out(S* __restrict__ X, const StepArgs& a, 
     } else if (!ODD) {
         X[(size_t)OPP[q] * a.ld + i] = v;
     } else {
-        // r_down: neighbour along q, the downstream voxel i + xi_q.
-        if (r_down < a.N)
-            X[(size_t)q * a.ld + r_down] = v;
-        else
-            X[(size_t)OPP[q] * a.ld + i] = v;
+        // r_down: neighbour along q, the downstream voxel i + xi_q; a wall sends the population
+        // back into the voxel's own opposite slot. One store to the selected address.
+        const bool in = r_down < a.N;
+        X[in ? (size_t)q * a.ld + r_down : (size_t)OPP[q] * a.ld + i] = v;
     }
 }
 

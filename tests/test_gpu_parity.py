@@ -293,6 +293,24 @@ def test_pressure_faces_parity(lbm, steps, mode):
     dom.close()
 
 
+def test_displacement_generator_at_128_over_500_steps(lbm):
+    """The 512^3 displacement workload's generator at 128^3 (GRF rock seed 5 between 4-plane
+    reservoirs, walls of affinity -0.7, pressure faces 1.03 / 0.97, fluid a injected): FP64 GPU
+    against the oracle after 500 steps, while the front is moving into the rock."""
+    prob = inputs.displacement_problem(n=128, seed_geom=5)
+    dom = lbm.Domain(prob)
+    dom.step(500)
+    gpu = dom.fields()
+    ref = O.state_for(prob).run(500)
+    errs = _compare(gpu, ref.fields(), prob.solid_mask() == 0)
+    print("displacement 128^3, 500 steps: N=%d, errors %s" % (dom.n_pore, errs))
+    g, r = dom.reduce(), ref.reduce()
+    for k in ("mass_a", "mass_b", "sw"):
+        assert np.isclose(g[k], r[k], rtol=1e-12, atol=0), (k, g[k], r[k])
+    assert g["sw"] > 0.05                       # fluid a has entered
+    dom.close()
+
+
 def test_pressure_faces_fp32_dev_tracks_fp64(lbm):
     prob = inputs.displacement_problem(shape=(48, 24, 24), seed_geom=9, porosity_target=0.3)
     a = lbm.Domain(prob)
