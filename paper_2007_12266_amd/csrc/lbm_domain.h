@@ -44,7 +44,7 @@ struct lbm_domain {
     int64_t device_bytes = 0;
 
     void* f = nullptr;
-    void* M = nullptr;        // [8][ld] D3Q7 moment slots
+    void* M = nullptr;        // [4][ld][2] D3Q7 moment slot pairs
     int32_t* fresh = nullptr; // device flag: the state is the initial one
     int8_t* face = nullptr;   // [N] pressure-face flags (bc_z == 1 only)
     int32_t one = 1;          // host source of fresh-flag uploads (outlives the async copy)

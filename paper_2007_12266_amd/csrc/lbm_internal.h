@@ -31,7 +31,8 @@ struct StepArgs {
     void* phi;          // [N + n_tail] in the storage type; the tail holds phi_s
     void* ntot;         // [N] in the storage type
     void* f;            // [19][ld] populations (storage type per precision)
-    void* M;            // [8][ld] D3Q7 moment slots: N_a, N_b, u_x, u_y, u_z, G_x, G_y, G_z
+    void* M;            // [4][ld][2] D3Q7 moment slot pairs: (N_a, N_b), (u_x, G_x), (u_y, G_y),
+                        // (u_z, G_z)
     int32_t* fresh;     // device flag: 1 while the state is the initial one
     const int8_t* face; // per pore voxel: 0, 1 (inlet face), 2 (outlet face); null without faces
     double nu_a, nu_b;  // kinematic viscosities

@@ -88,6 +88,27 @@ __device__ __forceinline__ int logical_block(const StepArgs& a) {
     return (b & 7) * per + (b >> 3);
 }
 
+// The D3Q7 moment slots of a voxel are stored as four pairs, one row of 2*ld values per pair:
+// (N_a, N_b), (u_x, G_x), (u_y, G_y), (u_z, G_z). What a neighbour contributes along one axis is
+// two pairs, each a single 16-byte (FP64) or 8-byte (FP32) access.
+template <typename S> struct PairOf;
+template <> struct PairOf<double> { using T = double2; };
+template <> struct PairOf<float> { using T = float2; };
+
+template <typename S>
+__device__ __forceinline__ typename PairOf<S>::T load_pair(const S* __restrict__ M, size_t ld,
+                                                          int k, int y) {
+    return reinterpret_cast<const typename PairOf<S>::T*>(M)[(size_t)k * ld + y];
+}
+
+template <typename S>
+__device__ __forceinline__ void store_pair(S* __restrict__ M, size_t ld, int k, int i, S x, S y) {
+    typename PairOf<S>::T v;
+    v.x = x;
+    v.y = y;
+    reinterpret_cast<typename PairOf<S>::T*>(M)[(size_t)k * ld + i] = v;
+}
+
 // Neighbour lookup, fixed at compile time for the single-domain step kernels and chosen per
 // domain at run time (words != null selects the rank lookup) where domains of either kind meet.
 enum { NB_DYN = 0, NB_TABLE = 1, NB_RANK = 2 };
@@ -201,10 +222,9 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __r
 #pragma unroll
     for (int q = 0; q < 19; ++q) f[(size_t)q * a.ld + i] = (S)(P::kDev ? 0.0 : tw(q));
     // A fresh state: the component slots hold the densities (the fresh flag is set by the host).
-    M[i] = (S)na;
-    M[a.ld + i] = (S)nbv;
+    store_pair<S>(M, a.ld, 0, i, (S)na, (S)nbv);
 #pragma unroll
-    for (int k = 2; k < 8; ++k) M[(size_t)k * a.ld + i] = (S)0;
+    for (int k = 1; k < 4; ++k) store_pair<S>(M, a.ld, k, i, (S)0, (S)0);
 }
 
 // s + v with no contraction into a preceding product.
@@ -225,14 +245,14 @@ __device__ __forceinline__ void ab_out(R na, R nb, R uc, R gc, R sgn, R& ao, R& 
     bo = (R)(1.0 / 9.0) * (nb * ((R)1 + eu) - en);
 }
 
-// The same for direction q (1..6) of voxel y, read from the moment slots (one row of ld values
-// per slot: N_a, N_b, u_x, u_y, u_z, G_x, G_y, G_z).
+// The same for direction q (1..6) of voxel y, read from its moment slots.
 template <typename R, typename S>
 __device__ __forceinline__ void out_ab(const S* __restrict__ M, int64_t ld, int y, int q, R& ao,
                                        R& bo) {
     const int c = (q - 1) >> 1;                 // axis of q
-    ab_out<R>((R)M[y], (R)M[ld + y], (R)M[(size_t)(2 + c) * ld + y],
-              (R)M[(size_t)(5 + c) * ld + y], (q & 1) ? (R)1 : (R)-1, ao, bo);  // +x, +y, +z odd
+    const auto n = load_pair<S>(M, ld, 0, y);
+    const auto g = load_pair<S>(M, ld, 1 + c, y);
+    ab_out<R>((R)n.x, (R)n.y, (R)g.x, (R)g.y, (q & 1) ? (R)1 : (R)-1, ao, bo);  // +x, +y, +z odd
 }
 
 // Component densities N_a, N_b of pore voxel i in the current state: the sum of the incoming
@@ -253,7 +273,8 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
     if (fresh) {
         // The initial populations are w_q N at rest; summing them (rather than taking N) keeps
         // the initial phase bitwise equal to a population-based evaluation.
-        const R n0 = (R)M[i], n1 = (R)M[a.ld + i];
+        const auto own = load_pair<S>(M, a.ld, 0, i);
+        const R n0 = (R)own.x, n1 = (R)own.y;
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
             const R w = q == 0 ? (R)(1.0 / 3.0) : (R)(1.0 / 9.0);
@@ -286,10 +307,12 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
     for (int q = 1; q < 7; ++q) {
         const int c = (q - 1) >> 1;
         const int y = up[q] < a.N ? up[q] : i;
-        sna[q] = (R)M[y];
-        snb[q] = (R)M[a.ld + y];
-        suc[q] = (R)M[(size_t)(2 + c) * a.ld + y];
-        sgc[q] = (R)M[(size_t)(5 + c) * a.ld + y];
+        const auto n = load_pair<S>(M, a.ld, 0, y);
+        const auto g = load_pair<S>(M, a.ld, 1 + c, y);
+        sna[q] = (R)n.x;
+        snb[q] = (R)n.y;
+        suc[q] = (R)g.x;
+        sgc[q] = (R)g.y;
     }
 #pragma unroll
     for (int q = 1; q < 7; ++q) {
@@ -309,11 +332,13 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
         }
         ain[0] = (R)0;
         bin[0] = (R)0;
-        na = (double)M[i] - sa;
-        nbv = (double)M[a.ld + i] - sb;
+        const auto own = load_pair<S>(M, a.ld, 0, i);
+        na = (double)own.x - sa;
+        nbv = (double)own.y - sb;
     } else {
-        ain[0] = (R)(1.0 / 3.0) * (R)M[i];
-        bin[0] = (R)(1.0 / 3.0) * (R)M[a.ld + i];
+        const auto own = load_pair<S>(M, a.ld, 0, i);
+        ain[0] = (R)(1.0 / 3.0) * (R)own.x;
+        bin[0] = (R)(1.0 / 3.0) * (R)own.y;
         na = 0.0;
         nbv = 0.0;
     }
@@ -426,14 +451,10 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     const R seg = (R)a.beta * na * nbv / nt;
     S* M = (S*)a.M;
     const size_t ld = (size_t)a.ld;
-    M[i] = (S)na;
-    M[ld + i] = (S)nbv;
-    M[2 * ld + i] = (S)ux;
-    M[3 * ld + i] = (S)uy;
-    M[4 * ld + i] = (S)uz;
-    M[5 * ld + i] = (S)(seg * nx);
-    M[6 * ld + i] = (S)(seg * ny);
-    M[7 * ld + i] = (S)(seg * nz);
+    store_pair<S>(M, ld, 0, i, (S)na, (S)nbv);
+    store_pair<S>(M, ld, 1, i, (S)ux, (S)(seg * nx));
+    store_pair<S>(M, ld, 2, i, (S)uy, (S)(seg * ny));
+    store_pair<S>(M, ld, 3, i, (S)uz, (S)(seg * nz));
 
     const R nu = (R)0.5 * ((R)1 + phi_i) * (R)a.nu_a + (R)0.5 * ((R)1 - phi_i) * (R)a.nu_b;
     const R sp = (R)1 / ((R)3 * nu + (R)0.5);

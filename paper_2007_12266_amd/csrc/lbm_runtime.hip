@@ -26,7 +26,7 @@ lbm_status fail(lbm_status s, const std::string& msg) {
 
 namespace {
 
-constexpr uint64_t kStateMagic = 0x4c424d434f4c5232ull;  // "LBMCOLR2"
+constexpr uint64_t kStateMagic = 0x4c424d434f4c5233ull;  // "LBMCOLR3"
 constexpr int kStateRows = 27;  // 19 D3Q19 populations + 8 D3Q7 moment slots
 
 struct StateHeader {
@@ -436,12 +436,12 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
     StateHeader h{kStateMagic, d->pre.n_pore, d->pre.n_tail, d->step, d->p.precision, (int32_t)eb};
     std::memcpy(host_buf, &h, sizeof h);
     char* dst = (char*)host_buf + sizeof h;
-    // f: 19 rows and M: 8 rows, each of n values (pitch ld on the device).
+    // f: 19 rows of n values and M: 4 rows of n value pairs (pitch ld on the device).
     HIP_TRY(hipMemcpy2DAsync(dst, eb * n, d->f, eb * ld, eb * n, 19, hipMemcpyDeviceToHost,
                              d->stream));
     dst += eb * n * 19;
-    HIP_TRY(hipMemcpy2DAsync(dst, eb * n, d->M, eb * ld, eb * n, 8, hipMemcpyDeviceToHost,
-                             d->stream));
+    HIP_TRY(hipMemcpy2DAsync(dst, 2 * eb * n, d->M, 2 * eb * ld, 2 * eb * n, 4,
+                             hipMemcpyDeviceToHost, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     *nbytes = need;
     return LBM_OK;
@@ -464,8 +464,8 @@ lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes) {
     HIP_TRY(hipMemcpy2DAsync(d->f, eb * ld, src, eb * n, eb * n, 19, hipMemcpyHostToDevice,
                              d->stream));
     src += eb * n * 19;
-    HIP_TRY(hipMemcpy2DAsync(d->M, eb * ld, src, eb * n, eb * n, 8, hipMemcpyHostToDevice,
-                             d->stream));
+    HIP_TRY(hipMemcpy2DAsync(d->M, 2 * eb * ld, src, 2 * eb * n, 2 * eb * n, 4,
+                             hipMemcpyHostToDevice, d->stream));
     d->one = h.step == 0 ? 1 : 0;            // a step-0 state is the initial one
     HIP_TRY(hipMemcpyAsync(d->fresh, &d->one, sizeof(int32_t), hipMemcpyHostToDevice,
                            d->stream));
