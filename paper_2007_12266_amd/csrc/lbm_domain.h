@@ -51,7 +51,7 @@ struct lbm_domain {
     void* phi = nullptr;      // [N + n_tail] storage type
     void* ntot = nullptr;     // [N] storage type
     double* stage = nullptr;  // [ld] doubles: initial phase upload and field read-back
-    int32_t* nbr = nullptr;        // [18][ld] (table mode)
+    int32_t* nbr = nullptr;        // [9][ld][2] (table mode)
     uint32_t* coord = nullptr;     // [ld] packed coordinates (rank mode)
     lbm::RowWord* words = nullptr; // row segments (rank mode)
     bool rank = false;

@@ -27,7 +27,7 @@ struct StepArgs {
     int32_t N;          // pore voxels
     int32_t nblocks;    // logical workgroups covering N
     int64_t ld;         // leading dimension of population arrays
-    const int32_t* nbr; // [18][ld]
+    const int32_t* nbr; // [9][ld][2]: neighbours along (q, q + 1) for q = 1, 3, ..., 17
     void* phi;          // [N + n_tail] in the storage type; the tail holds phi_s
     void* ntot;         // [N] in the storage type
     void* f;            // [19][ld] populations (storage type per precision)

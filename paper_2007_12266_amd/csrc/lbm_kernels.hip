@@ -150,7 +150,11 @@ __device__ __forceinline__ int rank_index(const StepArgs& a, int x, int y, int z
 template <int NB = NB_DYN>
 __device__ __forceinline__ int nb(const StepArgs& a, int q, int i, Pos p, bool& mirror) {
     mirror = false;
-    if (use_table<NB>(a)) return a.nbr[(size_t)(q - 1) * a.ld + i];
+    if (use_table<NB>(a)) {
+        // Opposite directions (q, q + 1 for odd q) share one 8-byte entry.
+        const int2 e = reinterpret_cast<const int2*>(a.nbr)[(size_t)((q - 1) >> 1) * a.ld + i];
+        return (q & 1) ? e.x : e.y;
+    }
     int cx = p.x + CX[q], cy = p.y + CY[q], cz = p.z + CZ[q];
     if (CX[q] && (cx < 0 || cx >= a.nx)) {
         if (!(a.periodic & 1)) return a.N;

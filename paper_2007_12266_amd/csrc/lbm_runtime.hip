@@ -307,11 +307,21 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         if (e != hipSuccess && st == LBM_OK)
             st = fail(LBM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
+    // The table goes to the device with each pair of opposite directions (q, q + 1 for odd q)
+    // interleaved: row p holds (nbr[2p+1], nbr[2p+2]) of every voxel, one 8-byte load.
+    std::vector<int32_t> nbr2;
     if (d->rank) {
         guard(up(d->coord, pre.coord.data(), sizeof(uint32_t) * pre.coord.size()), "upload coord");
         guard(up(d->words, pre.words.data(), sizeof(RowWord) * pre.words.size()), "upload words");
     } else {
-        guard(up(d->nbr, pre.nbr.data(), sizeof(int32_t) * pre.nbr.size()), "upload nbr");
+        const size_t ld = (size_t)pre.ld;
+        nbr2.resize(18 * ld);
+        for (size_t pr = 0; pr < 9; ++pr)
+            for (size_t i = 0; i < ld; ++i) {
+                nbr2[(pr * ld + i) * 2] = pre.nbr[(2 * pr) * ld + i];
+                nbr2[(pr * ld + i) * 2 + 1] = pre.nbr[(2 * pr + 1) * ld + i];
+            }
+        guard(up(d->nbr, nbr2.data(), sizeof(int32_t) * nbr2.size()), "upload nbr");
     }
     std::vector<float> tail32;
     if (eb == 4) tail32.assign(pre.tail_phi.begin(), pre.tail_phi.end());
@@ -336,6 +346,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (st == LBM_OK) guard(launch_init(d->args(), phi0, d->block, d->stream), "init kernel");
     if (st == LBM_OK) guard(hipStreamSynchronize(d->stream), "create sync");
     if (st != LBM_OK) {
+        (void)hipStreamSynchronize(d->stream);   // no copy may outlive its host staging vector
         d->release();
         return st;
     }
