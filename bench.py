@@ -280,19 +280,26 @@ def serve_main(args):
     count = args.requests
     lmax = args.serve_lmax
     t0 = time.perf_counter()
-    reqs = serve.poisson_trace(count, 2.0, 200,
-                               lambda k: inputs.serving_problem(k, seed0=200, edge=(64, lmax)))
+    def make(k):
+        prob = inputs.serving_problem(k, seed0=200, edge=(64, lmax))
+        log("request %d: %s" % (k, prob.name))
+        return prob
+    reqs = serve.poisson_trace(count, 2.0, 200, make)
     log("%d requests generated in %.1f s" % (count, time.perf_counter() - t0))
     torch.cuda.set_device(0)
     budget = int(args.serve_budget_gb * (1 << 30))
     srv = serve.Server(budget, precision=lbm.FP32_DEV, chunk=200, graph_chunk=100,
                        max_slots=64, workers=4)
-    res = srv.run(reqs, realtime=True)
+    def done(tag):
+        return lambda r: log("%s: request %d (%d pore voxels) done after %d steps, latency "
+                             "%.2f s" % (tag, r.rid, r.n_pore, r.steps, r.latency))
+    res = srv.run(reqs, realtime=True, on_result=done("served"))
     info = srv.pool.info()
     srv.close()
     st = serve.latency_stats(res)
     log("served: %s" % st)
-    base = serve.fifo_baseline(reqs, precision=lbm.FP64, chunk=1000)
+    base = serve.fifo_baseline(reqs, precision=lbm.FP64, chunk=1000,
+                               on_result=done("fp64 fifo"))
     sb = serve.latency_stats(base)
     log("fp64 fifo: %s" % sb)
     lups = sum(r.n_pore * r.steps for r in res)

@@ -69,10 +69,12 @@ hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* f
                               hipStream_t s);
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
                          hipStream_t s);
-hipError_t launch_phase_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
-                                hipStream_t s);
-hipError_t launch_collide_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
-                                  hipStream_t s);
+// lookup: LBM_NBR_TABLE or LBM_NBR_RANK when every member uses that neighbour lookup, else
+// LBM_NBR_AUTO (each tile tests its domain's lookup at run time).
+hipError_t launch_phase_batched(const BatchArgs& b, int prec, bool odd, int lookup, int grid,
+                                int block, hipStream_t s);
+hipError_t launch_collide_batched(const BatchArgs& b, int prec, bool odd, int lookup, int grid,
+                                  int block, hipStream_t s);
 // Reductions of slots 0..nslots-1 into out[nslots][kNRed]; partials holds nslots*kRedBlocks rows.
 hipError_t launch_reduce_batched(const BatchArgs& b, int prec, bool odd, int nslots,
                                  double* partials, double* out, hipStream_t s);

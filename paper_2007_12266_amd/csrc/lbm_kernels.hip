@@ -530,25 +530,46 @@ __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
 // membership changes. Per-voxel arithmetic is the single-domain one, so every domain's result
 // is bitwise the same alone and in the mix.
 // ------------------------------------------------------------------------------------------
-template <int PREC, bool ODD>
+// The tile table and the per-slot arguments are read-only during a launch and every index into
+// them is uniform over the workgroup: reading them through the constant address space lets the
+// compiler use scalar loads, so a slot's arguments live in scalar registers.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
+// A whole record through the constant address space, one 32-bit word at a time (the compiler
+// merges the words into wide scalar loads).
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "record size must be a multiple of 4 bytes");
+    T out;
+    const auto* src = as_const(reinterpret_cast<const int32_t*>(p));
+    int32_t* dst = reinterpret_cast<int32_t*>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+    return out;
+}
+
+template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) phase_batched(BatchArgs b) {
-    const int nt = *b.ntiles;
+    const int nt = *as_const(b.ntiles);
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-        const int d = b.tile_dom[t];
-        const StepArgs a = b.doms[d];
-        const int i = (t - b.tile_first[d]) * blockDim.x + threadIdx.x;
-        if (i < a.N) phase_voxel<PREC>(a, i, *a.fresh != 0);
+        const int d = as_const(b.tile_dom)[t];
+        const StepArgs a = load_const(b.doms + d);
+        const int i = (t - as_const(b.tile_first)[d]) * blockDim.x + threadIdx.x;
+        if (i < a.N) phase_voxel<PREC, NB>(a, i, *a.fresh != 0);
     }
 }
 
-template <int PREC, bool ODD>
+template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) collide_batched(BatchArgs b) {
-    const int nt = *b.ntiles;
+    const int nt = *as_const(b.ntiles);
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-        const int d = b.tile_dom[t];
-        const StepArgs a = b.doms[d];
-        const int i = (t - b.tile_first[d]) * blockDim.x + threadIdx.x;
-        if (i < a.N) collide_voxel<PREC, ODD>(a, i);
+        const int d = as_const(b.tile_dom)[t];
+        const StepArgs a = load_const(b.doms + d);
+        const int i = (t - as_const(b.tile_first)[d]) * blockDim.x + threadIdx.x;
+        if (i < a.N) collide_voxel<PREC, ODD, NB>(a, i);
     }
 }
 
@@ -857,15 +878,44 @@ hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* 
         }                                                                                   \
     } while (0)
 
-hipError_t launch_phase_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
-                                hipStream_t s) {
-    LBM_DISPATCH_B(phase_batched, dim3(grid), dim3(block), b);
+#define LBM_DISPATCH_B_NB(KERNEL, GRID, BLOCK, ...)                                         \
+    do {                                                                                    \
+        if (lookup == LBM_NBR_TABLE)                                                        \
+            LBM_DISPATCH_B3(KERNEL, NB_TABLE, GRID, BLOCK, __VA_ARGS__);                    \
+        else if (lookup == LBM_NBR_RANK)                                                    \
+            LBM_DISPATCH_B3(KERNEL, NB_RANK, GRID, BLOCK, __VA_ARGS__);                     \
+        else                                                                                \
+            LBM_DISPATCH_B3(KERNEL, NB_DYN, GRID, BLOCK, __VA_ARGS__);                      \
+    } while (0)
+
+#define LBM_DISPATCH_B3(KERNEL, NBV, GRID, BLOCK, ...)                                      \
+    do {                                                                                    \
+        if (prec == LBM_FP32_DEV) {                                                         \
+            if (odd)                                                                        \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true, NBV>), GRID, BLOCK, 0, s,    \
+                                   __VA_ARGS__);                                            \
+            else                                                                            \
+                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false, NBV>), GRID, BLOCK, 0, s,   \
+                                   __VA_ARGS__);                                            \
+        } else {                                                                            \
+            if (odd)                                                                        \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, true, NBV>), GRID, BLOCK, 0, s,        \
+                                   __VA_ARGS__);                                            \
+            else                                                                            \
+                hipLaunchKernelGGL((KERNEL<LBM_FP64, false, NBV>), GRID, BLOCK, 0, s,       \
+                                   __VA_ARGS__);                                            \
+        }                                                                                   \
+    } while (0)
+
+hipError_t launch_phase_batched(const BatchArgs& b, int prec, bool odd, int lookup, int grid,
+                                int block, hipStream_t s) {
+    LBM_DISPATCH_B_NB(phase_batched, dim3(grid), dim3(block), b);
     return hipGetLastError();
 }
 
-hipError_t launch_collide_batched(const BatchArgs& b, int prec, bool odd, int grid, int block,
-                                  hipStream_t s) {
-    LBM_DISPATCH_B(collide_batched, dim3(grid), dim3(block), b);
+hipError_t launch_collide_batched(const BatchArgs& b, int prec, bool odd, int lookup, int grid,
+                                  int block, hipStream_t s) {
+    LBM_DISPATCH_B_NB(collide_batched, dim3(grid), dim3(block), b);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct lbm_pool {
     std::vector<StepArgs> h_doms;
     std::vector<int32_t> h_tile_first, h_tile_dom;
     int32_t h_ntiles = 0;
+    int32_t lookup = LBM_NBR_TABLE;   // the members' common neighbour lookup, else AUTO (mixed)
     bool dirty = true;
 
     hipGraph_t graph = nullptr;
@@ -70,6 +71,21 @@ lbm_status upload_tables(lbm_pool* p) {
         p->h_tile_dom.insert(p->h_tile_dom.end(), (size_t)nt, s);
     }
     p->h_ntiles = (int32_t)p->h_tile_dom.size();
+    // The step kernels are specialised on the neighbour lookup when all members share it; a
+    // change of that choice invalidates the captured graph.
+    int n_rank = 0, n_members = 0;
+    for (lbm_domain* d : p->slots)
+        if (d) {
+            ++n_members;
+            n_rank += d->rank ? 1 : 0;
+        }
+    const int32_t lookup = n_rank == 0 ? LBM_NBR_TABLE
+                           : n_rank == n_members ? LBM_NBR_RANK : LBM_NBR_AUTO;
+    if (lookup != p->lookup) {
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        p->drop_graph();
+        p->lookup = lookup;
+    }
     if ((int64_t)p->h_tile_dom.size() > p->tile_cap) {
         // Grow the tile table; its address is baked into the captured graph.
         int64_t cap = std::max<int64_t>(p->tile_cap * 2, (int64_t)p->h_tile_dom.size());
@@ -101,8 +117,10 @@ lbm_status launch_steps(lbm_pool* p, int64_t first_step, int64_t n) {
     const BatchArgs b = p->batch();
     for (int64_t k = 0; k < n; ++k) {
         const bool odd = ((first_step + k) & 1) != 0;
-        HIP_TRY(launch_phase_batched(b, p->precision, odd, p->grid, kPoolBlock, p->stream));
-        HIP_TRY(launch_collide_batched(b, p->precision, odd, p->grid, kPoolBlock, p->stream));
+        HIP_TRY(launch_phase_batched(b, p->precision, odd, p->lookup, p->grid, kPoolBlock,
+                                     p->stream));
+        HIP_TRY(launch_collide_batched(b, p->precision, odd, p->lookup, p->grid, kPoolBlock,
+                                       p->stream));
     }
     return LBM_OK;
 }

@@ -22,7 +22,7 @@ import collections
 import concurrent.futures as cf
 import dataclasses
 import time
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import numpy as np
 
@@ -84,8 +84,10 @@ class Server:
     def _build(self, req: Request) -> lbm.Domain:
         return lbm.Domain(req.problem, precision=self.precision, allocator="hip")
 
-    def run(self, requests: List[Request], realtime: bool = True) -> List[Result]:
-        """Serve `requests`; with realtime=False every request is taken to have arrived."""
+    def run(self, requests: List[Request], realtime: bool = True,
+            on_result: Optional[Callable[[Result], None]] = None) -> List[Result]:
+        """Serve `requests`; with realtime=False every request is taken to have arrived.
+        `on_result`, if given, is called with each result as it completes."""
         for r in requests:
             if r.check_every % self.chunk:
                 raise ValueError("check_every must be a multiple of the chunk")
@@ -159,6 +161,8 @@ class Server:
                     state = dom.save() if self.keep_state else None
                     results.append(Result(req.rid, req.arrival, admitted, done, steps,
                                           bool(converged), dom.n_pore, r, state))
+                    if on_result:
+                        on_result(results[-1])
                     dom.close()
                     reserved -= need
                     del live[slot]
@@ -186,8 +190,8 @@ def solve_alone(req: Request, precision: int, chunk: int = 200) -> Result:
             return res
 
 
-def fifo_baseline(requests: List[Request], precision: int = lbm.FP64,
-                  chunk: int = 1000) -> List[Result]:
+def fifo_baseline(requests: List[Request], precision: int = lbm.FP64, chunk: int = 1000,
+                  on_result: Optional[Callable[[Result], None]] = None) -> List[Result]:
     """One request at a time in arrival order on the plain path (no pool), in real time."""
     t0 = time.perf_counter()
     out = []
@@ -201,6 +205,8 @@ def fifo_baseline(requests: List[Request], precision: int = lbm.FP64,
         res.completed = time.perf_counter() - t0
         res.state = None
         out.append(res)
+        if on_result:
+            on_result(res)
     return out
 
 

@@ -68,10 +68,16 @@ def test_members_match_solo_runs_bitwise(lbm, precision):
         d.close()
 
 
-def test_membership_changes_keep_results(lbm):
+@pytest.mark.parametrize("lookups", ["table", "rank-joins"])
+def test_membership_changes_keep_results(lbm, lookups):
+    """Members leave and join between graph chunks. With "rank-joins" the pool's kernels change
+    from the table specialisation to the mixed one when a rank-lookup member joins (the
+    captured graph is rebuilt)."""
     probs = _mix()
     pool = lbm.Pool(1 << 34, precision=lbm.FP32_DEV, max_slots=3, chunk_steps=10)
-    a, b, c = (lbm.Domain(p, precision=lbm.FP32_DEV) for p in probs[:3])
+    mode_c = lbm.NBR_RANK if lookups == "rank-joins" else lbm.NBR_TABLE
+    a, b = (lbm.Domain(p, precision=lbm.FP32_DEV) for p in probs[:2])
+    c = lbm.Domain(probs[2], precision=lbm.FP32_DEV, neighbour_mode=mode_c)
     sa, sb = pool.admit(a), pool.admit(b)
     pool.step(30)
     pool.retire(sa)
