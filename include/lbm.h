@@ -189,6 +189,43 @@ lbm_status lbm_pore_index(lbm_domain* d, int64_t* host_index);
 /* Reduce the current state (see lbm_reduction). Synchronises. */
 lbm_status lbm_reduce(lbm_domain* d, lbm_reduction* out);
 
+/* Steady-state flow control (section "Steady-state" simulation protocol of the paper: total
+ * capillary number, body-force adaptation F <- (Ca* / Ca) F capped at a factor of two, and the
+ * steady-state test on the change of Ca over an interval t').
+ *
+ * lbm_set_force replaces the body force F (lattice units) from the next step on; for a pooled
+ * domain, from its pool's next step. Errors: LBM_ERR_ARG for a null or non-finite force. */
+lbm_status lbm_set_force(lbm_domain* d, const double force[3]);
+
+typedef struct {
+    double ca_target;     /* Ca* > 0: after relax_steps, F <- clamp(Ca* / Ca) F; 0 keeps F       */
+    double max_factor;    /* bound of one rescaling: the factor lies in [1/max_factor,
+                           * max_factor] (the paper uses 2); >= 1. Ca == 0 rescales by it    */
+    double tol;           /* steady when |Ca(t) - Ca(t - interval)| / Ca(t) < tol               */
+    int64_t relax_steps;  /* steps before the rescaling (also taken when ca_target == 0)       */
+    int64_t interval;     /* t', steps between two Ca measurements of the steady test; > 0     */
+    int64_t max_steps;    /* cap on the steps of this call (relaxation included); > 0          */
+} lbm_steady_params;
+
+typedef struct {
+    int64_t steps;        /* steps taken by this call                                        */
+    int32_t converged;    /* 1 if the steady test passed, 0 if max_steps was reached first   */
+    int32_t rescales;     /* force rescalings applied (0 or 1)                               */
+    double ca;            /* Ca of the final state                                           */
+    double delta_ca;      /* last |Ca(t) - Ca(t - interval)| / Ca(t); -1 if never measured   */
+    double factor;        /* the rescaling factor applied (1 if none)                        */
+    double force[3];      /* body force at the end                                           */
+    lbm_reduction last;   /* reduction of the final state                                    */
+} lbm_steady_result;
+
+/* Run one steady-state point: relax_steps steps, then (ca_target > 0) one force rescaling from
+ * the measured Ca, then steps in blocks of `interval` with a Ca measurement after each, until
+ * the relative change of Ca between two consecutive measurements falls below tol or max_steps
+ * steps have been taken. Ca is the total capillary number of lbm_reduction (FP64). Synchronises
+ * after each block. Errors: LBM_ERR_ARG (bad parameters), LBM_ERR_STATE (pooled domain: step
+ * the pool), LBM_ERR_UNSTABLE (a measurement saw a non-finite value). */
+lbm_status lbm_run_steady(lbm_domain* d, const lbm_steady_params* sp, lbm_steady_result* out);
+
 /* Reductions recorded by lbm_step (every reduce_every steps) since the last call, oldest
  * first, at most max_count of them; *count receives the number written. Synchronises. */
 lbm_status lbm_read_history(lbm_domain* d, lbm_reduction* out, int32_t max_count,

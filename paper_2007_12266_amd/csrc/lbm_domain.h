@@ -20,6 +20,8 @@ struct lbm_domain;
 namespace lbm {
 // Turns the kNRed accumulators of a domain's reduction into an lbm_reduction.
 void finish_reduction(const lbm_domain* d, const double* acc, int64_t step, lbm_reduction* r);
+// A member's launch arguments changed: the pool re-uploads them before its next step.
+void pool_member_changed(lbm_pool* p);
 }  // namespace lbm
 
 #define HIP_TRY(expr)                                                                        \

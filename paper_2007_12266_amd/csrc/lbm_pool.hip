@@ -46,6 +46,10 @@ struct lbm_pool {
     }
 };
 
+namespace lbm {
+void pool_member_changed(lbm_pool* p) { p->dirty = true; }
+}  // namespace lbm
+
 namespace {
 
 constexpr int kPoolBlock = 256;  // voxels per tile = threads per workgroup

@@ -413,6 +413,77 @@ lbm_status lbm_reduce(lbm_domain* d, lbm_reduction* out) {
     return LBM_OK;
 }
 
+lbm_status lbm_set_force(lbm_domain* d, const double force[3]) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!force) return fail(LBM_ERR_ARG, "force must be non-null");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(force[a])) return fail(LBM_ERR_ARG, "force must be finite");
+    for (int a = 0; a < 3; ++a) d->p.force[a] = force[a];
+    if (d->pool) pool_member_changed(d->pool);
+    return LBM_OK;
+}
+
+// Steady-state flow control: relaxation, one capped force rescaling towards the target total
+// capillary number, then the relative change of Ca over each interval as the steady test.
+lbm_status lbm_run_steady(lbm_domain* d, const lbm_steady_params* sp, lbm_steady_result* out) {
+    if (lbm_status s = check_domain(d)) return s;
+    if (!sp || !out) return fail(LBM_ERR_ARG, "null argument");
+    if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool; step the pool");
+    if (!(sp->ca_target >= 0.0) || !std::isfinite(sp->ca_target) || !(sp->max_factor >= 1.0) ||
+        !std::isfinite(sp->max_factor) || !(sp->tol > 0.0) || sp->relax_steps < 0 ||
+        sp->interval <= 0 || sp->max_steps <= 0)
+        return fail(LBM_ERR_ARG, "steady-state parameters out of range");
+    std::memset(out, 0, sizeof *out);
+    out->delta_ca = -1.0;
+    out->factor = 1.0;
+    auto measure = [&](lbm_reduction* r) -> lbm_status {
+        if (lbm_status s = lbm_reduce(d, r)) return s;
+        if (r->unstable) return fail(LBM_ERR_UNSTABLE, "non-finite state during the steady run");
+        return LBM_OK;
+    };
+    lbm_reduction r{};
+    int64_t t = 0;
+    const int64_t relax = std::min(sp->relax_steps, sp->max_steps);
+    if (relax > 0) {
+        if (lbm_status s = lbm_step(d, relax)) return s;
+        t += relax;
+    }
+    if (sp->ca_target > 0.0) {
+        if (lbm_status s = measure(&r)) return s;
+        double f = r.ca > 0.0 ? sp->ca_target / r.ca : sp->max_factor;
+        f = std::min(std::max(f, 1.0 / sp->max_factor), sp->max_factor);
+        double force[3];
+        for (int a = 0; a < 3; ++a) force[a] = f * d->p.force[a];
+        if (lbm_status s = lbm_set_force(d, force)) return s;
+        out->factor = f;
+        out->rescales = 1;
+    }
+    bool have_prev = false;     // also: r describes the final state with the final force
+    double prev = 0.0;
+    while (t < sp->max_steps) {
+        const int64_t n = std::min(sp->interval, sp->max_steps - t);
+        if (lbm_status s = lbm_step(d, n)) return s;
+        t += n;
+        if (lbm_status s = measure(&r)) return s;
+        if (have_prev && r.ca > 0.0) {
+            out->delta_ca = std::fabs(r.ca - prev) / r.ca;
+            if (out->delta_ca < sp->tol) {
+                out->converged = 1;
+                break;
+            }
+        }
+        prev = r.ca;
+        have_prev = true;
+    }
+    if (!have_prev)
+        if (lbm_status s = measure(&r)) return s;   // no block ran after the relaxation
+    out->steps = t;
+    out->ca = r.ca;
+    for (int a = 0; a < 3; ++a) out->force[a] = d->p.force[a];
+    out->last = r;
+    return LBM_OK;
+}
+
 lbm_status lbm_read_history(lbm_domain* d, lbm_reduction* out, int32_t max_count,
                             int32_t* count) {
     if (lbm_status s = check_domain(d)) return s;

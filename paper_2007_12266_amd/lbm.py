@@ -28,7 +28,7 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_prepass_query", "lbm_domain_footprint", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
            "lbm_pool_create", "lbm_pool_admit", "lbm_pool_retire", "lbm_pool_step",
            "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
-           "lbm_pool_destroy",
+           "lbm_pool_destroy", "lbm_set_force", "lbm_run_steady",
            "lbm_last_error", "lbm_version")
 
 
@@ -67,6 +67,24 @@ class Reduction(ctypes.Structure):
             for c, ax in enumerate("xyz"):
                 d[name + ax] = arr[c]
         return d
+
+
+class SteadyParams(ctypes.Structure):
+    _fields_ = [("ca_target", ctypes.c_double), ("max_factor", ctypes.c_double),
+                ("tol", ctypes.c_double), ("relax_steps", ctypes.c_int64),
+                ("interval", ctypes.c_int64), ("max_steps", ctypes.c_int64)]
+
+
+class SteadyResult(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("converged", ctypes.c_int32),
+                ("rescales", ctypes.c_int32), ("ca", ctypes.c_double),
+                ("delta_ca", ctypes.c_double), ("factor", ctypes.c_double),
+                ("force", ctypes.c_double * 3), ("last", Reduction)]
+
+    def as_dict(self) -> dict:
+        return {"steps": self.steps, "converged": bool(self.converged),
+                "rescales": self.rescales, "ca": self.ca, "delta_ca": self.delta_ca,
+                "factor": self.factor, "force": tuple(self.force), "last": self.last.as_dict()}
 
 
 class Timing(ctypes.Structure):
@@ -125,6 +143,8 @@ def load_library(path: str = LIB_PATH):
     L.lbm_domain_create.argtypes = [ctypes.POINTER(Params), vp, i32, vp, vp, vp, vp,
                                     ctypes.POINTER(Allocator), vp, ctypes.POINTER(vp)]
     L.lbm_step.argtypes = [vp, i64]
+    L.lbm_set_force.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.lbm_run_steady.argtypes = [vp, ctypes.POINTER(SteadyParams), ctypes.POINTER(SteadyResult)]
     L.lbm_step_timed.argtypes = [vp, i64, ctypes.POINTER(Timing)]
     L.lbm_read_field.argtypes = [vp, i32, dp]
     L.lbm_read_pore_field.argtypes = [vp, i32, dp]
@@ -349,6 +369,21 @@ class Domain:
         t = Tuning()
         _check(load_library().lbm_autotune(self.handle, int(trial_steps), ctypes.byref(t)))
         return t.as_dict()
+
+    def set_force(self, force):
+        """Replace the body force from the next step on."""
+        f = (ctypes.c_double * 3)(*[float(x) for x in force])
+        _check(load_library().lbm_set_force(self.handle, f))
+
+    def run_steady(self, ca_target: float = 0.0, relax_steps: int = 0, interval: int = 1000,
+                   tol: float = 1e-3, max_steps: int = 100000, max_factor: float = 2.0) -> dict:
+        """One steady-state point: relax, rescale F towards Ca* (capped), then step in blocks of
+        `interval` until |dCa|/Ca < tol or max_steps (lbm_run_steady)."""
+        sp = SteadyParams(float(ca_target), float(max_factor), float(tol), int(relax_steps),
+                          int(interval), int(max_steps))
+        out = SteadyResult()
+        _check(load_library().lbm_run_steady(self.handle, ctypes.byref(sp), ctypes.byref(out)))
+        return out.as_dict()
 
     def tuning(self) -> dict:
         t = Tuning()

@@ -173,3 +173,12 @@ def test_footprint_depends_on_the_neighbour_lookup():
                                                           neighbour_mode=lbm.NBR_TABLE)
     with pytest.raises(lbm.LbmError):
         lbm.footprint(wide, lbm.FP64, neighbour_mode=lbm.NBR_RANK)
+
+
+def test_steady_calls_reject_null_handles():
+    L = lbm.load_library()
+    f = (ctypes.c_double * 3)(0.0, 0.0, 1e-5)
+    assert L.lbm_set_force(None, f) == lbm.LBM_ERR_ARG
+    sp = lbm.SteadyParams(1e-3, 2.0, 1e-2, 10, 10, 100)
+    out = lbm.SteadyResult()
+    assert L.lbm_run_steady(None, ctypes.byref(sp), ctypes.byref(out)) == lbm.LBM_ERR_ARG

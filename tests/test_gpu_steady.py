@@ -1,0 +1,129 @@
+"""Steady-state flow control (the paper's steady-state protocol: total capillary number Ca,
+body-force rescaling F <- (Ca*/Ca) F capped at a factor of two after a relaxation interval, and
+the steady test |Ca(t) - Ca(t - t')| / Ca(t) < tol) through lbm_run_steady, against the same
+protocol driven on the FP64 oracle by the code below, written from the paper independently of
+the library."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2007_12266_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FIELDS = ("Na", "Nb", "phi", "rho", "ux", "uy", "uz")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_12266_amd import lbm as mod
+    mod.load_library()
+    return mod
+
+
+def oracle_steady(prob, ca_target, relax, interval, tol, max_steps, max_factor=2.0):
+    st = O.state_for(prob)
+    t = 0
+    st.run(relax)
+    t += relax
+    factor = 1.0
+    if ca_target > 0:
+        ca = st.reduce()["ca"]
+        factor = ca_target / ca if ca > 0 else max_factor
+        factor = min(max(factor, 1.0 / max_factor), max_factor)
+        for a in range(3):
+            st.params.force[a] *= factor
+    prev, converged, dcas = None, False, []
+    while t < max_steps:
+        n = min(interval, max_steps - t)
+        st.run(n)
+        t += n
+        ca = st.reduce()["ca"]
+        if prev is not None and ca > 0:
+            dcas.append(abs(ca - prev) / ca)
+            if dcas[-1] < tol:
+                converged = True
+                break
+        prev = ca
+    return st, t, converged, factor, dcas
+
+
+def _check_fields(gpu, ref, pore, tol=1e-12):
+    for k in FIELDS:
+        g, r = gpu[k][pore], ref[k][pore]
+        err = np.abs(g - r).max() / max(np.abs(r).max(), 1e-3 if k[0] == "u" else 0.0)
+        assert err <= tol, (k, err)
+
+
+def test_force_adaptation_and_steady_test_match_the_protocol_on_the_oracle(lbm):
+    """Sphere pack, Ca* = 1e-3: the force is rescaled by Ca*/Ca = 1.396 after 100 steps and
+    the run is steady (dCa < 1e-2 over 50 steps) at step 450."""
+    prob = inputs.sphere_problem(n=32)
+    args = dict(ca_target=1e-3, relax=100, interval=50, tol=1e-2, max_steps=800)
+    st, t, conv, factor, dcas = oracle_steady(prob, **args)
+    assert all(abs(d - args["tol"]) > 1e-4 for d in dcas)   # decisions are well separated
+    dom = lbm.Domain(prob)
+    res = dom.run_steady(ca_target=args["ca_target"], relax_steps=args["relax"],
+                         interval=args["interval"], tol=args["tol"],
+                         max_steps=args["max_steps"])
+    assert res["steps"] == t and res["converged"] == conv and res["rescales"] == 1
+    assert conv and t == 450
+    assert abs(res["factor"] - factor) <= 1e-12 * factor
+    assert res["force"][2] == pytest.approx(prob.force[2] * factor, rel=1e-12)
+    assert abs(res["delta_ca"] - dcas[-1]) <= 1e-9
+    r = st.reduce()
+    assert res["ca"] == pytest.approx(r["ca"], rel=1e-11)
+    assert dom.info()["step"] == t
+    _check_fields(dom.fields(), st.fields(), prob.solid_mask() == 0)
+    dom.close()
+
+
+def test_factor_cap_and_step_ceiling(lbm):
+    """Ca* far above Ca: the rescaling is capped at 2; a tolerance that is never met stops the
+    run at max_steps; without a target the force is left alone."""
+    prob = inputs.sphere_problem(n=32)
+    st, t, conv, factor, _ = oracle_steady(prob, 1.0, 20, 20, 1e-12, 70)
+    assert factor == 2.0 and not conv and t == 70
+    dom = lbm.Domain(prob)
+    res = dom.run_steady(ca_target=1.0, relax_steps=20, interval=20, tol=1e-12, max_steps=70)
+    assert res["factor"] == 2.0 and not res["converged"] and res["steps"] == 70
+    assert res["force"][2] == 2.0 * prob.force[2]
+    _check_fields(dom.fields(), st.fields(), prob.solid_mask() == 0)
+    res = dom.run_steady(relax_steps=10, interval=10, tol=1e-12, max_steps=30)
+    assert res["rescales"] == 0 and res["factor"] == 1.0 and res["steps"] == 30
+    assert res["force"][2] == 2.0 * prob.force[2]
+    with pytest.raises(lbm.LbmError):
+        dom.run_steady(interval=0)
+    dom.close()
+
+
+def test_set_force_matches_oracle_and_pool(lbm):
+    """A force change between steps: the single domain, a pooled copy (graph-captured chunks)
+    and the oracle agree."""
+    prob = inputs.sphere_problem(n=32)
+    st = O.state_for(prob)
+    st.run(12)
+    new = (2e-6, -1e-6, 3e-5)
+    for a in range(3):
+        st.params.force[a] = new[a]
+    st.run(30)
+    dom = lbm.Domain(prob)
+    dom.step(12)
+    dom.set_force(new)
+    dom.step(30)
+    _check_fields(dom.fields(), st.fields(), prob.solid_mask() == 0)
+    pooled = lbm.Domain(prob)
+    pool = lbm.Pool(1 << 32, precision=lbm.FP64, max_slots=2, chunk_steps=10)
+    pool.admit(pooled)
+    pool.step(12)
+    pooled.set_force(new)
+    pool.step(30)
+    pool.close()
+    assert pooled.save() == dom.save()
+    with pytest.raises(lbm.LbmError):
+        dom.set_force((np.nan, 0.0, 0.0))
+    dom.close()
+    pooled.close()
