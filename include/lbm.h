@@ -129,9 +129,9 @@ typedef struct {
 } lbm_timing;
 
 /* Launch configuration of the two step kernels. block: threads per workgroup (64, 128 or 256);
- * schedule: 1 = workgroups take consecutive tiles of the pore list in launch order, 2 = each of
- * the 8 XCDs takes one contiguous slab of tiles (its L2 then holds the neighbour planes the
- * stencil re-reads). Results do not depend on the configuration (bitwise). */
+ * schedule: 1 = workgroups take consecutive tiles of the pore list in launch order, 2 = XCD-aware
+ * order: each of the 8 XCDs takes runs of 16 consecutive tiles, the runs interleaved, so that
+ * neighbouring tiles share an L2. Results do not depend on the configuration (bitwise). */
 typedef struct {
     int32_t phase_block, phase_schedule;
     int32_t collide_block, collide_schedule;

@@ -38,7 +38,7 @@ struct StepArgs {
     double nu_a, nu_b;  // kinematic viscosities
     double alpha, beta;
     double F[3];
-    int32_t xcd_remap;  // 1: map consecutive logical blocks to the same XCD
+    int32_t xcd_remap;  // 1: XCD-aware order (runs of consecutive tiles per XCD)
     int32_t prec;       // lbm_precision
     // Rank lookup of neighbours (used instead of nbr when words != null):
     const uint32_t* coord;   // [ld] packed (x, y, z) of each pore voxel

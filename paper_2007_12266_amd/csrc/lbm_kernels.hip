@@ -36,13 +36,14 @@
 //    M^-1 S M = s+ P_even + s- P_odd, so the 19x19 transforms reduce to sums and differences of
 //    opposite pairs. The equilibrium in population space is the second-order polynomial plus the
 //    image of the alpha|C| moment terms under M^-1 (closed form below).
-//  * Workgroup -> tile mapping is XCD-aware: the hardware deals workgroups round-robin to the 8
-//    XCDs, so logical block b is taken by hardware block (b % per) * 8 + b / per. Each XCD then
-//    sweeps one contiguous slab of the pore list and its L2 keeps the phi planes that the
-//    gradient stencil re-reads.
-//  * Two storage precisions share every kernel body through a precision policy: FP64 stores f, A,
-//    B, phi and N in double and computes in double; FP32-deviation stores f as the deviation
-//    f_q - t_q from the rest equilibrium (rho0 = 1), A, B, phi and N as float, and computes in
+//  * Workgroup -> tile mapping can be XCD-aware: the hardware deals workgroups round-robin to
+//    the 8 XCDs, so each XCD is given runs of kXcdChunk consecutive tiles, the XCDs' runs
+//    interleaved. Neighbouring tiles then share an L2 (the cache lines a wave's scattered
+//    accesses leave half used are completed by the next tile on the same XCD) while all XCDs
+//    still stream through the pore list together.
+//  * Two storage precisions share every kernel body through a precision policy: FP64 stores f,
+//    the moment slots, phi and N in double and computes in double; FP32-deviation stores f as the
+//    deviation f_q - t_q from the rest equilibrium (rho0 = 1), the rest as float, and computes in
 //    float on those deviations. The two-rate collision is invariant under that shift (t_q is
 //    the same for q and opp(q)), so the same formulas serve both.
 //  * No MFMA: nothing here is a dense contraction. The kernel is bound by HBM traffic.
@@ -81,11 +82,16 @@ template <> struct Prec<LBM_FP32_DEV> {
     static constexpr double kCMin = 1e-5;
 };
 
+constexpr int kXcdChunk = 16;   // consecutive tiles per XCD run
+
+// Hardware block b runs on XCD b % 8 as that XCD's (b / 8)-th block; it takes logical tile
+// ((j / C) * 8 + x) * C + j % C (x = b % 8, j = b / 8, C = kXcdChunk). With gridDim.x a
+// multiple of 8 C this is a bijection of [0, gridDim.x).
 __device__ __forceinline__ int logical_block(const StepArgs& a) {
     const int b = blockIdx.x;
     if (!a.xcd_remap) return b;
-    const int per = (int)(gridDim.x >> 3);  // gridDim.x is a multiple of 8 when remapping
-    return (b & 7) * per + (b >> 3);
+    const int x = b & 7, j = b >> 3;
+    return ((j / kXcdChunk) * 8 + x) * kXcdChunk + (j % kXcdChunk);
 }
 
 // The D3Q7 moment slots of a voxel are stored as four pairs, one row of 2*ld values per pair:
@@ -782,7 +788,8 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
 int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
 
 dim3 step_grid(const StepArgs& a) {
-    return dim3(a.xcd_remap ? ((a.nblocks + 7) / 8) * 8 : a.nblocks);
+    const int g = 8 * kXcdChunk;    // XCD-aware order: whole runs on every XCD
+    return dim3(a.xcd_remap ? ((a.nblocks + g - 1) / g) * g : a.nblocks);
 }
 
 }  // namespace
