@@ -209,7 +209,7 @@ def batch_main(args):
     for d in doms:
         pool.admit(d)
     grid = pool.autotune(10)
-    log("pool grid %d" % grid)
+    log("pool grid %d, tile order %s" % (grid, "xcd" if pool.info()["order"] else "linear"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reds = []
@@ -256,6 +256,7 @@ def batch_main(args):
                                "U[0.15,0.35], affinity U[-0.9,0.9], Sw U[0.2,0.8], periodic, "
                                "Fz=1e-5, FP32-deviation storage, FP64 reductions every 100 steps",
                    "n_pore_total": n_tot, "chunk_steps": chunk, "pool_grid": grid,
+                   "pool_order": "xcd" if info["order"] else "linear",
                    "graph_replays": info["graph_replays"]},
         "aggregate_mlups": round(n_tot * steps / t_pool / 1e6, 1),
         "fp64_one_at_a_time": {"seconds": round(t_base, 3), "solves_per_s": round(64 / t_base, 4),

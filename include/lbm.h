@@ -314,6 +314,7 @@ typedef struct {
     int32_t max_slots, members, chunk_steps, grid;  /* grid: workgroups of the batched launch */
     int64_t step, used_bytes, budget_bytes, tiles;
     int64_t graph_replays, eager_steps;
+    int32_t order, pad_;      /* tile order of the batched launch (see lbm_pool_set_order)  */
 } lbm_pool_info;
 lbm_status lbm_pool_get_info(lbm_pool* pool, lbm_pool_info* out);
 
@@ -321,10 +322,17 @@ lbm_status lbm_pool_get_info(lbm_pool* pool, lbm_pool_info* out);
  * 0 restores the default. Invalidates the captured graph. */
 lbm_status lbm_pool_set_grid(lbm_pool* pool, int32_t grid);
 
+/* Tile order of the batched step kernels: 0 = tiles in launch order, 1 = XCD-aware order (each
+ * of the 8 XCDs takes runs of 16 consecutive tiles, the runs interleaved; the launch is rounded
+ * up to whole runs). Results do not depend on it (bitwise). Invalidates the captured graph.
+ * LBM_ERR_ARG for another value. */
+lbm_status lbm_pool_set_order(lbm_pool* pool, int32_t order);
+
 /* Autotuner for the batched launch: times each candidate workgroup count (multiples of the
- * compute-unit count) over trial_steps >= 2 steps of the current members, applies the fastest
- * and writes it to *grid (nullable). Every member's state and step counter are restored, so
- * later results are unchanged. Needs device memory for one copy of the members' populations. */
+ * compute-unit count) in both tile orders over trial_steps >= 2 steps of the current members,
+ * applies the fastest pair and writes the workgroup count to *grid (nullable; the order is in
+ * lbm_pool_info). Every member's state and step counter are restored, so later results are
+ * unchanged. Needs device memory for one copy of the members' populations. */
 lbm_status lbm_pool_autotune(lbm_pool* pool, int32_t trial_steps, int32_t* grid);
 
 /* Retire every member and free the pool. NULL is accepted. */

@@ -49,11 +49,16 @@ struct StepArgs {
 };
 
 // Arguments of the batched (pool) kernels. All arrays live in device memory.
+// XCD-aware tile order: the hardware deals workgroups round-robin to the 8 XCDs; each XCD is
+// given runs of kXcdRun consecutive tiles, the runs interleaved (grid a multiple of 8 kXcdRun).
+constexpr int kXcdRun = 16;
+
 struct BatchArgs {
     const StepArgs* doms;       // per-slot kernel arguments (N = 0 for an empty slot)
     const int32_t* tile_dom;    // slot of each tile
     const int32_t* tile_first;  // first tile of each slot
     const int32_t* ntiles;      // number of tiles in use (device scalar)
+    int32_t xcd;                // 1: XCD-aware tile order (grid a multiple of 8 * 16)
 };
 
 // Kernel launchers (lbm_kernels.hip). `odd` is the parity of the step being taken.

@@ -37,7 +37,7 @@
 //    opposite pairs. The equilibrium in population space is the second-order polynomial plus the
 //    image of the alpha|C| moment terms under M^-1 (closed form below).
 //  * Workgroup -> tile mapping can be XCD-aware: the hardware deals workgroups round-robin to
-//    the 8 XCDs, so each XCD is given runs of kXcdChunk consecutive tiles, the XCDs' runs
+//    the 8 XCDs, so each XCD is given runs of kXcdRun consecutive tiles, the XCDs' runs
 //    interleaved. Neighbouring tiles then share an L2 (the cache lines a wave's scattered
 //    accesses leave half used are completed by the next tile on the same XCD) while all XCDs
 //    still stream through the pore list together.
@@ -82,16 +82,16 @@ template <> struct Prec<LBM_FP32_DEV> {
     static constexpr double kCMin = 1e-5;
 };
 
-constexpr int kXcdChunk = 16;   // consecutive tiles per XCD run
-
 // Hardware block b runs on XCD b % 8 as that XCD's (b / 8)-th block; it takes logical tile
-// ((j / C) * 8 + x) * C + j % C (x = b % 8, j = b / 8, C = kXcdChunk). With gridDim.x a
+// ((j / C) * 8 + x) * C + j % C (x = b % 8, j = b / 8, C = kXcdRun). With gridDim.x a
 // multiple of 8 C this is a bijection of [0, gridDim.x).
-__device__ __forceinline__ int logical_block(const StepArgs& a) {
-    const int b = blockIdx.x;
-    if (!a.xcd_remap) return b;
+__device__ __forceinline__ int xcd_run_tile(int b) {
     const int x = b & 7, j = b >> 3;
-    return ((j / kXcdChunk) * 8 + x) * kXcdChunk + (j % kXcdChunk);
+    return ((j / kXcdRun) * 8 + x) * kXcdRun + (j % kXcdRun);
+}
+
+__device__ __forceinline__ int logical_block(const StepArgs& a) {
+    return a.xcd_remap ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
 }
 
 // The D3Q7 moment slots of a voxel are stored as four pairs, one row of 2*ld values per pair:
@@ -560,7 +560,8 @@ __device__ __forceinline__ T load_const(const T* p) {
 template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) phase_batched(BatchArgs b) {
     const int nt = *as_const(b.ntiles);
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int first = b.xcd ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
+    for (int t = first; t < nt; t += gridDim.x) {
         const int d = as_const(b.tile_dom)[t];
         const StepArgs a = load_const(b.doms + d);
         const int i = (t - as_const(b.tile_first)[d]) * blockDim.x + threadIdx.x;
@@ -571,7 +572,8 @@ __global__ void __launch_bounds__(256) phase_batched(BatchArgs b) {
 template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) collide_batched(BatchArgs b) {
     const int nt = *as_const(b.ntiles);
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int first = b.xcd ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
+    for (int t = first; t < nt; t += gridDim.x) {
         const int d = as_const(b.tile_dom)[t];
         const StepArgs a = load_const(b.doms + d);
         const int i = (t - as_const(b.tile_first)[d]) * blockDim.x + threadIdx.x;
@@ -788,7 +790,7 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
 int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
 
 dim3 step_grid(const StepArgs& a) {
-    const int g = 8 * kXcdChunk;    // XCD-aware order: whole runs on every XCD
+    const int g = 8 * kXcdRun;    // XCD-aware order: whole runs on every XCD
     return dim3(a.xcd_remap ? ((a.nblocks + g - 1) / g) * g : a.nblocks);
 }
 

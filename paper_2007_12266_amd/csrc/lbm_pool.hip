@@ -17,6 +17,7 @@ struct lbm_pool {
     std::vector<lbm_domain*> slots;
     int64_t step = 0;
     int32_t grid = 0, default_grid = 0;
+    int32_t order = 0;                // 0: linear tile order, 1: XCD-aware runs
 
     // Device tables of the batched kernels (fixed addresses, so captured graphs stay valid).
     StepArgs* d_doms = nullptr;
@@ -36,7 +37,14 @@ struct lbm_pool {
     hipGraphExec_t exec = nullptr;
     int64_t replays = 0, eager = 0;
 
-    BatchArgs batch() const { return BatchArgs{d_doms, d_tile_dom, d_tile_first, d_ntiles}; }
+    BatchArgs batch() const {
+        return BatchArgs{d_doms, d_tile_dom, d_tile_first, d_ntiles, order};
+    }
+    // Workgroups of the batched launch: the XCD-aware order needs whole runs on every XCD.
+    int32_t launch_grid() const {
+        const int32_t g = 8 * kXcdRun;
+        return order ? (grid + g - 1) / g * g : grid;
+    }
 
     void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -121,10 +129,10 @@ lbm_status launch_steps(lbm_pool* p, int64_t first_step, int64_t n) {
     const BatchArgs b = p->batch();
     for (int64_t k = 0; k < n; ++k) {
         const bool odd = ((first_step + k) & 1) != 0;
-        HIP_TRY(launch_phase_batched(b, p->precision, odd, p->lookup, p->grid, kPoolBlock,
-                                     p->stream));
-        HIP_TRY(launch_collide_batched(b, p->precision, odd, p->lookup, p->grid, kPoolBlock,
-                                       p->stream));
+        HIP_TRY(launch_phase_batched(b, p->precision, odd, p->lookup, p->launch_grid(),
+                                     kPoolBlock, p->stream));
+        HIP_TRY(launch_collide_batched(b, p->precision, odd, p->lookup, p->launch_grid(),
+                                       kPoolBlock, p->stream));
     }
     return LBM_OK;
 }
@@ -310,6 +318,15 @@ lbm_status lbm_pool_get_info(lbm_pool* p, lbm_pool_info* out) {
     out->tiles = p->dirty ? -1 : p->h_ntiles;
     out->graph_replays = p->replays;
     out->eager_steps = p->eager;
+    out->order = p->order;
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_set_order(lbm_pool* p, int32_t order) {
+    if (!p || (order != 0 && order != 1)) return fail(LBM_ERR_ARG, "order must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->order = order;
+    p->drop_graph();
     return LBM_OK;
 }
 
@@ -353,15 +370,16 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
     const int64_t step0 = p->step;
     std::vector<int64_t> dstep0;
     for (const Snap& sn : snaps) dstep0.push_back(sn.d->step);
-    const int32_t keep = p->grid;
-    int32_t best = keep;
+    const int32_t keep = p->grid, keep_order = p->order;
+    int32_t best = keep, best_order = keep_order;
     double best_ms = 1e30;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == LBM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         st = fail(LBM_ERR_DEVICE, "event creation failed");
     const int mult[5] = {2, 4, 8, 16, 32};
-    for (int c = 0; c < 5 && st == LBM_OK && p->h_ntiles > 0; ++c) {
-        p->grid = std::max(1, p->default_grid / 8) * mult[c];
+    for (int c = 0; c < 10 && st == LBM_OK && p->h_ntiles > 0; ++c) {
+        p->grid = std::max(1, p->default_grid / 8) * mult[c % 5];
+        p->order = c / 5;
         st = launch_steps(p, p->step, 2);                      // warm-up
         if (st != LBM_OK) break;
         if (hipEventRecord(e0, p->stream) != hipSuccess) { st = fail(LBM_ERR_DEVICE, "event"); break; }
@@ -376,6 +394,7 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
         if (ms < best_ms) {
             best_ms = ms;
             best = p->grid;
+            best_order = p->order;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -401,6 +420,7 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
         st = fail(LBM_ERR_DEVICE, "synchronise failed");
     for (const Snap& sn : snaps) (void)hipFree(sn.buf);
     p->grid = st == LBM_OK ? best : keep;
+    p->order = st == LBM_OK ? best_order : keep_order;
     p->drop_graph();
     if (st == LBM_OK && grid) *grid = p->grid;
     return st;

@@ -28,7 +28,7 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_prepass_query", "lbm_domain_footprint", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
            "lbm_pool_create", "lbm_pool_admit", "lbm_pool_retire", "lbm_pool_step",
            "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
-           "lbm_pool_destroy", "lbm_set_force", "lbm_run_steady",
+           "lbm_pool_destroy", "lbm_pool_set_order", "lbm_set_force", "lbm_run_steady",
            "lbm_last_error", "lbm_version")
 
 
@@ -116,7 +116,8 @@ class PoolInfo(ctypes.Structure):
                 ("chunk_steps", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("step", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
                 ("budget_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
-                ("graph_replays", ctypes.c_int64), ("eager_steps", ctypes.c_int64)]
+                ("graph_replays", ctypes.c_int64), ("eager_steps", ctypes.c_int64),
+                ("order", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -169,6 +170,7 @@ def load_library(path: str = LIB_PATH):
     L.lbm_pool_reduce.argtypes = [vp, ctypes.POINTER(Reduction), i32, ctypes.POINTER(i32)]
     L.lbm_pool_get_info.argtypes = [vp, ctypes.POINTER(PoolInfo)]
     L.lbm_pool_set_grid.argtypes = [vp, i32]
+    L.lbm_pool_set_order.argtypes = [vp, i32]
     L.lbm_pool_destroy.argtypes = [vp]
     L.lbm_pool_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.lbm_last_error.restype = ctypes.c_char_p
@@ -452,6 +454,11 @@ class Pool:
 
     def set_grid(self, grid: int):
         _check(load_library().lbm_pool_set_grid(self.handle, int(grid)))
+        return self
+
+    def set_order(self, order: int):
+        """0: tiles in launch order; 1: XCD-aware runs of tiles."""
+        _check(load_library().lbm_pool_set_order(self.handle, int(order)))
         return self
 
     def close(self):

@@ -46,6 +46,7 @@ def test_members_match_solo_runs_bitwise(lbm, precision):
     prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
     probs = _mix()
     pool = lbm.Pool(1 << 34, precision=prec, max_slots=8, chunk_steps=20)
+    pool.set_order(1 if precision == "fp64" else 0)     # both tile orders are covered
     # Members alternate between the two neighbour lookups; each solo run uses the other one.
     modes = [lbm.NBR_RANK if k % 2 == 0 else lbm.NBR_TABLE for k in range(len(probs))]
     doms = [lbm.Domain(p, precision=prec, neighbour_mode=m) for p, m in zip(probs, modes)]
@@ -138,4 +139,29 @@ def test_admission_rules(lbm):
     pool.close()
     pool2.close()
     for d in (d64, d32, big, small, disp):
+        d.close()
+
+
+def test_pool_autotune_restores_members(lbm):
+    """The pool autotuner times grids in both tile orders on the members themselves and then
+    restores every member: later results equal solo runs bitwise."""
+    probs = _mix()[:3]
+    pool = lbm.Pool(1 << 34, precision=lbm.FP32_DEV, max_slots=4, chunk_steps=10)
+    doms = [lbm.Domain(p, precision=lbm.FP32_DEV) for p in probs]
+    for d in doms:
+        pool.admit(d)
+    pool.step(10)
+    before = [d.save() for d in doms]
+    grid = pool.autotune(4)
+    info = pool.info()
+    assert grid > 0 and info["grid"] == grid and info["order"] in (0, 1) and info["step"] == 10
+    assert [d.save() for d in doms] == before
+    pool.step(20)
+    for p, d in zip(probs, doms):
+        solo = lbm.Domain(p, precision=lbm.FP32_DEV)
+        solo.step(30)
+        assert d.save() == solo.save()
+        solo.close()
+    pool.close()
+    for d in doms:
         d.close()
