@@ -22,8 +22,9 @@ Readings (the paper leaves these open; the HIP path implements the same ones):
     N_a = N (1 + phi') / 2, N_b = N (1 - phi') / 2 with the voxel's current N = N_a + N_b, the
     D3Q7 populations at rest (A_q = w_q N_a, B_q = w_q N_b); the flow populations are kept;
   * volume V(Omega) counts pore voxels; the growth factor for a target volume ratio Delta is
-    the linear rescaling of a unit trial, delta = (Delta - 1) / (V(Omega_a (+) 1) / V - 1) for
-    Delta > 1 and delta = (1 - Delta) / (V(Omega_a (-) 1) / V - 1) for Delta < 1.
+    the linear rescaling of a unit trial u = +1 (Delta >= 1) or -1 (Delta < 1):
+    delta = u (Delta - 1) / (V(Omega_a morphed by u) / V - 1), capped at |delta| <= radius - 2
+    so that the new interface stays where the distance map is exact.
 """
 from __future__ import annotations
 
@@ -82,15 +83,16 @@ def volume(Phi, pore, delta=0.0):
     return int(np.count_nonzero(pore & (Phi - delta < 0.0)))
 
 
-def growth_factor(Phi, pore, target_ratio):
-    """delta that changes V(Omega_a) by target_ratio, from a unit trial rescaled linearly."""
+def growth_factor(Phi, pore, target_ratio, radius=6):
+    """delta that changes V(Omega_a) by target_ratio, from a unit trial rescaled linearly;
+    returns (delta, V, V of the unit trial)."""
     v0 = volume(Phi, pore, 0.0)
     unit = 1.0 if target_ratio >= 1.0 else -1.0
     v1 = volume(Phi, pore, unit)
-    rate = v1 / v0 - 1.0
-    if rate == 0.0:
-        return unit
-    return unit * (target_ratio - 1.0) / rate if unit > 0 else unit * (1.0 - target_ratio) / rate
+    rate = v1 / v0 - 1.0 if v0 > 0 else 0.0
+    delta = unit if rate == 0.0 else unit * (target_ratio - 1.0) / rate
+    cap = radius - 2.0
+    return min(max(delta, -cap), cap), v0, v1
 
 
 def apply_to_state(state, beta, periodic, delta, radius=6, band=2.5):

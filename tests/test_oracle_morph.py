@@ -91,10 +91,19 @@ def test_growth_factor_rescales_a_unit_trial():
     pore = _box(shape)
     Phi, _ = morph.signed_distance(phi, pore, BETA, (True, True, True), radius=6)
     v0, v1 = morph.volume(Phi, pore, 0.0), morph.volume(Phi, pore, 1.0)
-    assert morph.growth_factor(Phi, pore, 1.2) == pytest.approx(0.2 / (v1 / v0 - 1.0))
     vm = morph.volume(Phi, pore, -1.0)
-    assert morph.growth_factor(Phi, pore, 0.9) == pytest.approx(-0.1 / (vm / v0 - 1.0))
     assert vm < v0 < v1
+    # growth: a positive delta whose linear interpolation between the unit trial and no
+    # change gives the target ratio
+    delta, a0, a1 = morph.growth_factor(Phi, pore, 1.2)
+    assert (a0, a1) == (v0, v1) and 0 < delta < 1
+    assert 1.0 + (v1 / v0 - 1.0) * delta == pytest.approx(1.2)
+    # shrinking: a negative delta, interpolated towards the unit erosion
+    delta, a0, am = morph.growth_factor(Phi, pore, 0.9)
+    assert am == vm and -1 < delta < 0
+    assert 1.0 + (vm / v0 - 1.0) * (-delta) == pytest.approx(0.9)
+    # a target beyond the trusted band is capped at radius - 2
+    assert morph.growth_factor(Phi, pore, 50.0, radius=6)[0] == 4.0
 
 
 def test_apply_keeps_total_density_and_flow():
