@@ -226,6 +226,64 @@ typedef struct {
  * the pool), LBM_ERR_UNSTABLE (a measurement saw a non-finite value). */
 lbm_status lbm_run_steady(lbm_domain* d, const lbm_steady_params* sp, lbm_steady_result* out);
 
+/* Morphological growth of fluid a (section "Shell Aggregation Protocol"): the distance map
+ * Phi_a of the fluid (negative inside a) is built from the phase field -- the closed form of
+ * the equilibrium interface profile, -(1/(2 beta)) ln((1 + phi)/(1 - phi)), where
+ * |phi| < tanh(band beta), elsewhere -/+(d - 1/2) with d the distance between voxel centres to
+ * the nearest voxel across the boundary of {pore voxels with phi > 0} (solid voxels and the
+ * outside of non-periodic faces lie outside it), searched within `radius`; the map is moved by
+ * delta (> 0 dilates fluid a, < 0 erodes it), the phase becomes the equilibrium profile of the
+ * moved map, phi' = 2 e / (1 + e) - 1 with e = exp(-2 beta (Phi_a - delta)) (voxels with
+ * nothing across the boundary within the radius keep their phase), and the densities restart
+ * at rest with N_a = N (1 + phi')/2, N_b = N (1 - phi')/2 and the voxel's current N. The flow
+ * populations, the step counter and the history are kept. The first call allocates work
+ * buffers (nx*ny*nz bytes plus 17 bytes per pore voxel) that stay with the domain. Errors:
+ * LBM_ERR_ARG (parameters), LBM_ERR_STATE (pooled domain), LBM_ERR_OOM. Synchronises. */
+typedef struct {
+    double delta;          /* growth distance in voxels; |delta| <= radius - 2; unused when
+                            * target_ratio > 0                                               */
+    double target_ratio;   /* > 0: delta for this ratio of the volume of fluid a, from a unit
+                            * trial (delta = +-1) rescaled linearly, capped at radius - 2     */
+    double band;           /* half-width of the closed-form band in voxels, in (0, radius]   */
+    int32_t radius;        /* search radius of the far-field distance, 2..12                  */
+    int32_t pad_;
+} lbm_morph_params;
+
+typedef struct {
+    double delta;            /* growth distance applied                                      */
+    int64_t volume_before;   /* pore voxels inside fluid a before (Phi_a < 0)                */
+    int64_t volume_unit;     /* inside after the unit trial (target_ratio > 0), else 0       */
+    int64_t volume_after;    /* inside the moved map (Phi_a - delta < 0)                      */
+} lbm_morph_result;
+
+lbm_status lbm_morph(lbm_domain* d, const lbm_morph_params* mp, lbm_morph_result* out);
+
+/* Pore voxels with phi > 0 in the current state (the volume of fluid a). Synchronises. */
+lbm_status lbm_phase_volume(lbm_domain* d, int64_t* volume);
+
+/* The shell aggregation protocol: until the volume of fluid a has reached target_ratio times
+ * its volume at the call (at least, when growing; at most, when shrinking), apply lbm_morph with
+ * the remaining ratio as its target and relax for relax_steps LB steps; at most max_rounds
+ * applications. */
+enum { LBM_SHELL_MAX_DELTAS = 32 };
+typedef struct {
+    double target_ratio;   /* V_end / V_start of fluid a: > 1 grows it, < 1 shrinks it       */
+    double band;           /* as in lbm_morph_params                                          */
+    int32_t radius;        /* as in lbm_morph_params                                          */
+    int32_t max_rounds;    /* >= 1                                                            */
+    int64_t relax_steps;   /* LB steps after each application, >= 0                          */
+} lbm_shell_params;
+
+typedef struct {
+    int32_t rounds;        /* applications made                                               */
+    int32_t reached;       /* 1 if the target volume was reached                              */
+    int64_t steps;         /* LB steps taken                                                  */
+    int64_t volume_start, volume_end;   /* pore voxels with phi > 0 before and after          */
+    double deltas[LBM_SHELL_MAX_DELTAS];  /* growth distance of each application (first 32)  */
+} lbm_shell_result;
+
+lbm_status lbm_shell_aggregate(lbm_domain* d, const lbm_shell_params* sp, lbm_shell_result* out);
+
 /* Reductions recorded by lbm_step (every reduce_every steps) since the last call, oldest
  * first, at most max_count of them; *count receives the number written. Synchronises. */
 lbm_status lbm_read_history(lbm_domain* d, lbm_reduction* out, int32_t max_count,

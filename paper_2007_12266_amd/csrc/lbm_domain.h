@@ -12,6 +12,8 @@ namespace lbm {
 
 // Records the calling thread's error message (lbm_last_error) and returns s.
 lbm_status fail(lbm_status s, const std::string& msg);
+// Clears the calling thread's error message (at the start of every entry point).
+void clear_error();
 
 }  // namespace lbm
 
@@ -67,6 +69,13 @@ struct lbm_domain {
     int32_t* faces = nullptr;       // inlet then outlet pore indices (bc_z == 1)
     int32_t* ghost_tail = nullptr;  // z-face mirror entries of the phi tail
     int32_t* ghost_src = nullptr;
+
+    // Work buffers of the morphological growth step, allocated on its first use.
+    uint8_t* morph_label = nullptr;  // [nx*ny*nz] 1 where a pore voxel has phi > 0
+    int64_t* morph_vox = nullptr;    // [N] dense index of each pore voxel
+    double* morph_dist = nullptr;    // [N] signed distance map Phi_a
+    int8_t* morph_far = nullptr;     // [N] 1: no voxel across the boundary within the radius
+    long long* morph_count = nullptr;  // [kMorphBlocks] partial counts
 
     int64_t step = 0;
     bool unstable = false;

@@ -22,6 +22,8 @@ lbm_status fail(lbm_status s, const std::string& msg) {
     return s;
 }
 
+void clear_error() { g_err.clear(); }
+
 }  // namespace lbm
 
 namespace {

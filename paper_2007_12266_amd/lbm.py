@@ -29,6 +29,7 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_pool_create", "lbm_pool_admit", "lbm_pool_retire", "lbm_pool_step",
            "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
            "lbm_pool_destroy", "lbm_pool_set_order", "lbm_set_force", "lbm_run_steady",
+           "lbm_morph", "lbm_phase_volume", "lbm_shell_aggregate",
            "lbm_last_error", "lbm_version")
 
 
@@ -85,6 +86,31 @@ class SteadyResult(ctypes.Structure):
         return {"steps": self.steps, "converged": bool(self.converged),
                 "rescales": self.rescales, "ca": self.ca, "delta_ca": self.delta_ca,
                 "factor": self.factor, "force": tuple(self.force), "last": self.last.as_dict()}
+
+
+class MorphParams(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("target_ratio", ctypes.c_double),
+                ("band", ctypes.c_double), ("radius", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class MorphResult(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("volume_before", ctypes.c_int64),
+                ("volume_unit", ctypes.c_int64), ("volume_after", ctypes.c_int64)]
+
+
+SHELL_MAX_DELTAS = 32
+
+
+class ShellParams(ctypes.Structure):
+    _fields_ = [("target_ratio", ctypes.c_double), ("band", ctypes.c_double),
+                ("radius", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
+                ("relax_steps", ctypes.c_int64)]
+
+
+class ShellResult(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("reached", ctypes.c_int32),
+                ("steps", ctypes.c_int64), ("volume_start", ctypes.c_int64),
+                ("volume_end", ctypes.c_int64), ("deltas", ctypes.c_double * SHELL_MAX_DELTAS)]
 
 
 class Timing(ctypes.Structure):
@@ -145,6 +171,10 @@ def load_library(path: str = LIB_PATH):
                                     ctypes.POINTER(Allocator), vp, ctypes.POINTER(vp)]
     L.lbm_step.argtypes = [vp, i64]
     L.lbm_set_force.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.lbm_morph.argtypes = [vp, ctypes.POINTER(MorphParams), ctypes.POINTER(MorphResult)]
+    L.lbm_phase_volume.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.lbm_shell_aggregate.argtypes = [vp, ctypes.POINTER(ShellParams),
+                                      ctypes.POINTER(ShellResult)]
     L.lbm_run_steady.argtypes = [vp, ctypes.POINTER(SteadyParams), ctypes.POINTER(SteadyResult)]
     L.lbm_step_timed.argtypes = [vp, i64, ctypes.POINTER(Timing)]
     L.lbm_read_field.argtypes = [vp, i32, dp]
@@ -386,6 +416,34 @@ class Domain:
         out = SteadyResult()
         _check(load_library().lbm_run_steady(self.handle, ctypes.byref(sp), ctypes.byref(out)))
         return out.as_dict()
+
+    def morph(self, delta: float = 0.0, target_ratio: float = 0.0, radius: int = 6,
+              band: float = 2.5) -> dict:
+        """One morphological change of fluid a by delta voxels (or towards a volume ratio)."""
+        mp = MorphParams(float(delta), float(target_ratio), float(band), int(radius), 0)
+        r = MorphResult()
+        _check(load_library().lbm_morph(self.handle, ctypes.byref(mp), ctypes.byref(r)))
+        return {"delta": r.delta, "volume_before": r.volume_before,
+                "volume_unit": r.volume_unit, "volume_after": r.volume_after}
+
+    def phase_volume(self) -> int:
+        """Pore voxels with phi > 0 (the volume of fluid a)."""
+        v = ctypes.c_int64()
+        _check(load_library().lbm_phase_volume(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def shell_aggregate(self, target_ratio: float, relax_steps: int = 1000,
+                        max_rounds: int = 8, radius: int = 6, band: float = 2.5) -> dict:
+        """The shell aggregation protocol: morph and relax until the volume of fluid a has
+        changed by target_ratio (lbm_shell_aggregate)."""
+        sp = ShellParams(float(target_ratio), float(band), int(radius), int(max_rounds),
+                         int(relax_steps))
+        r = ShellResult()
+        _check(load_library().lbm_shell_aggregate(self.handle, ctypes.byref(sp),
+                                                  ctypes.byref(r)))
+        return {"rounds": r.rounds, "reached": bool(r.reached), "steps": r.steps,
+                "volume_start": r.volume_start, "volume_end": r.volume_end,
+                "deltas": [r.deltas[k] for k in range(min(r.rounds, SHELL_MAX_DELTAS))]}
 
     def tuning(self) -> dict:
         t = Tuning()

@@ -1,0 +1,153 @@
+"""Morphological growth (shell aggregation protocol) on the GPU against the NumPy oracle of the
+same readings (oracle/morph.py, pinned separately): volumes exactly, phase and densities to
+1e-12 after the change and after LB relaxation, the unit-trial growth factor, the protocol loop,
+and the invariances (FP32 storage keeps N; both neighbour lookups agree bitwise)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import morph as OM
+from paper_2007_12266_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FIELDS = ("Na", "Nb", "phi", "rho", "ux", "uy", "uz")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_12266_amd import lbm as mod
+    mod.load_library()
+    return mod
+
+
+def _compare(gpu, ref, pore, tol=1e-12):
+    for k in FIELDS:
+        g, r = gpu[k][pore], ref[k][pore]
+        scale = max(np.abs(r).max(), 1e-3 if k[0] == "u" else 0.0)
+        err = np.abs(g - r).max() / scale
+        assert err <= tol, (k, err)
+
+
+def _problem():
+    # 32^3 sphere pack with walls in z (both face kinds), random phase, body force
+    return inputs.sphere_problem(n=32)
+
+
+def _oracle_after(prob, steps):
+    return O.state_for(prob).run(steps)
+
+
+@pytest.mark.parametrize("delta", [0.8, -1.3])
+def test_morph_matches_oracle(lbm, delta):
+    prob = _problem()
+    pore = prob.solid_mask() == 0
+    st = _oracle_after(prob, 30)
+    dom = lbm.Domain(prob)
+    dom.step(30)
+    res = dom.morph(delta=delta, radius=6, band=2.5)
+    new, Phi, far = OM.apply_to_state(st, prob.beta, prob.periodic, delta, radius=6, band=2.5)
+    assert res["volume_before"] == OM.volume(Phi, pore, 0.0)
+    assert res["volume_after"] == OM.volume(Phi, pore, delta)
+    assert res["delta"] == delta
+    _compare(dom.fields(), st.fields(), pore)
+    assert dom.info()["step"] == 30
+    dom.step(25)
+    st.run(25)
+    _compare(dom.fields(), st.fields(), pore)
+    dom.close()
+
+
+def test_growth_factor_from_unit_trial(lbm):
+    prob = _problem()
+    pore = prob.solid_mask() == 0
+    st = _oracle_after(prob, 40)
+    dom = lbm.Domain(prob)
+    dom.step(40)
+    res = dom.morph(target_ratio=1.15, radius=6)
+    fl = st.fields()
+    phi = np.where(pore, fl["phi"], np.nan)
+    Phi, far = OM.signed_distance(phi, pore, prob.beta, prob.periodic, radius=6)
+    delta, v0, v1 = OM.growth_factor(Phi, pore, 1.15, radius=6)
+    assert (res["volume_before"], res["volume_unit"]) == (v0, v1)
+    assert res["delta"] == pytest.approx(delta, rel=1e-12)
+    OM.apply_to_state(st, prob.beta, prob.periodic, delta, radius=6)
+    _compare(dom.fields(), st.fields(), pore)
+    dom.close()
+
+
+def test_shell_aggregation_protocol_matches_oracle(lbm):
+    """Grow fluid a by 30%: morph towards the remaining ratio, relax 20 steps, repeat."""
+    prob = _problem()
+    pore = prob.solid_mask() == 0
+    st = _oracle_after(prob, 30)
+    dom = lbm.Domain(prob)
+    dom.step(30)
+    res = dom.shell_aggregate(1.3, relax_steps=20, max_rounds=5, radius=6)
+    # the protocol on the oracle
+    v = int(((st.fields()["phi"] > 0) & pore).sum())
+    v_start, goal, rounds, deltas = v, 1.3 * v, 0, []
+    for _ in range(5):
+        if v >= goal:
+            break
+        fl = st.fields()
+        phi = np.where(pore, fl["phi"], np.nan)
+        Phi, _ = OM.signed_distance(phi, pore, prob.beta, prob.periodic, radius=6)
+        delta, _, _ = OM.growth_factor(Phi, pore, goal / v, radius=6)
+        OM.apply_to_state(st, prob.beta, prob.periodic, delta, radius=6)
+        deltas.append(delta)
+        rounds += 1
+        st.run(20)
+        v = int(((st.fields()["phi"] > 0) & pore).sum())
+    assert res["volume_start"] == v_start and res["rounds"] == rounds
+    assert res["volume_end"] == v and res["reached"] == (v >= goal)
+    assert np.allclose(res["deltas"], deltas, rtol=1e-12, atol=0)
+    assert res["steps"] == 20 * rounds
+    _compare(dom.fields(), st.fields(), pore)
+    assert res["volume_end"] > res["volume_start"]
+    dom.close()
+
+
+def test_fp32_keeps_density_and_lookups_agree(lbm):
+    prob = _problem()
+    pore = prob.solid_mask() == 0
+    d32 = lbm.Domain(prob, precision=lbm.FP32_DEV)
+    d32.step(30)
+    before = d32.fields()
+    res = d32.morph(delta=1.0)
+    after = d32.fields()
+    tot0, tot1 = before["Na"] + before["Nb"], after["Na"] + after["Nb"]
+    assert np.abs(tot1 - tot0)[pore].max() < 1e-6
+    assert res["volume_after"] > res["volume_before"]
+    d32.step(10)
+    assert d32.reduce()["unstable"] == 0
+    d32.close()
+    blobs = []
+    for nm in (lbm.NBR_TABLE, lbm.NBR_RANK):
+        d = lbm.Domain(prob, neighbour_mode=nm)
+        d.step(20)
+        d.morph(delta=-0.7)
+        d.step(5)
+        blobs.append(d.save())
+        d.close()
+    assert blobs[0] == blobs[1]
+
+
+def test_morph_argument_checks(lbm):
+    prob = _problem()
+    dom = lbm.Domain(prob)
+    for kw in (dict(delta=1.0, radius=1), dict(delta=4.5, radius=6),
+               dict(delta=0.5, band=0.0), dict(target_ratio=-1.0)):
+        with pytest.raises(lbm.LbmError) as e:
+            dom.morph(**kw)
+        assert e.value.status == lbm.LBM_ERR_ARG
+    pool = lbm.Pool(1 << 32, precision=lbm.FP64, max_slots=1, chunk_steps=10)
+    pool.admit(dom)
+    with pytest.raises(lbm.LbmError) as e:
+        dom.morph(delta=0.5)
+    assert e.value.status == lbm.LBM_ERR_STATE
+    pool.close()
+    dom.close()
