@@ -93,6 +93,33 @@ def front_position(phi) -> float:
     return float(np.nansum(s))
 
 
+def morph_study(prob, args, torch, lbm) -> dict:
+    """Wall time of lbm_morph (first call, which allocates its work buffers, and later calls)
+    and of lbm_phase_volume on the workload after 100 steps."""
+    dom = lbm.Domain(prob, precision=lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV,
+                     allocator="hip")
+    dom.step(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first = dom.morph(delta=0.5)
+    t_first = time.perf_counter() - t0
+    times = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        res = dom.morph(delta=0.5)
+        times.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dom.phase_volume()
+    t_vol = (time.perf_counter() - t0) / 5
+    dom.close()
+    return {"ms_first_call": round(t_first * 1e3, 2),
+            "ms_per_call": round(min(times) * 1e3, 2),
+            "ms_phase_volume": round(t_vol * 1e3, 3),
+            "volume_before": first["volume_before"], "volume_after": first["volume_after"],
+            "last": res}
+
+
 def precision_study(prob, steps: int, every: int, torch, lbm) -> dict:
     """FP32-deviation against FP64 on the same problem: both advance side by side and every
     `every` steps the saturation, the Darcy flux and the front position are compared."""
@@ -350,6 +377,9 @@ def main():
                     help="keep the default launch shapes instead of autotuning them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--morph-study", action="store_true",
+                    help="also time the morphological growth step (dilation by 0.5 voxel) "
+                         "and the phase-volume count on the same workload")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="also run FP32-deviation beside FP64 for STEPS steps from the initial "
                          "state, comparing Sw, Darcy flux and front position every 100 steps")
@@ -462,6 +492,8 @@ def main():
     }
     if args.precision_study:
         out["fp32_vs_fp64"] = precision_study(prob, args.precision_study, 100, torch, lbm)
+    if args.morph_study:
+        out["morph"] = morph_study(prob, args, torch, lbm)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         sample = prob if wl["n"] <= 256 else make_problem(wl, n=256)
