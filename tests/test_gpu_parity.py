@@ -311,6 +311,22 @@ def test_displacement_generator_at_128_over_500_steps(lbm):
     dom.close()
 
 
+def test_centrifuge_configuration(lbm):
+    """The paper's centrifuge analogue: reservoirs at equal pressure (no pressure drop) and a
+    body force that drives the fluids through the sample: pressure faces with rho_in = rho_out
+    plus F_z, GPU FP64 against the oracle."""
+    import dataclasses
+    base = inputs.displacement_problem(shape=(36, 16, 16), seed_geom=12, porosity_target=0.3)
+    prob = dataclasses.replace(base, rho_in=1.0, rho_out=1.0, force=(0.0, 0.0, 2e-5))
+    dom = lbm.Domain(prob)
+    dom.step(80)
+    ref = O.state_for(prob).run(80)
+    _compare(dom.fields(), ref.fields(), prob.solid_mask() == 0)
+    g, r = dom.reduce(), ref.reduce()
+    assert np.isclose(g["qz"], r["qz"], rtol=1e-11, atol=0)
+    dom.close()
+
+
 def test_pressure_faces_fp32_dev_tracks_fp64(lbm):
     prob = inputs.displacement_problem(shape=(48, 24, 24), seed_geom=9, porosity_target=0.3)
     a = lbm.Domain(prob)
