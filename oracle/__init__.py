@@ -31,8 +31,9 @@ class OraParams(ctypes.Structure):
                 ("tau_a", ctypes.c_double), ("tau_b", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("wall_affinity", ctypes.c_double),
-                ("bc_z", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double)]
+                ("bc_z", ctypes.c_int32), ("inlet_mode", ctypes.c_int32),
+                ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("flux_in", ctypes.c_double)]
 
 
 def build(force: bool = False) -> str:
@@ -80,7 +81,7 @@ def _d(a):
 
 def make_params(shape, periodic=(True, True, True), tau_a=0.7, tau_b=0.7, alpha=0.005,
                 beta=0.95, force=(0.0, 0.0, 0.0), wall_affinity=0.0, bc_z=0, rho_in=1.0,
-                rho_out=1.0) -> OraParams:
+                rho_out=1.0, inlet_mode=0, flux_in=0.0) -> OraParams:
     nz, ny, nx = shape
     p = OraParams()
     p.nx, p.ny, p.nz = nx, ny, nz
@@ -91,6 +92,7 @@ def make_params(shape, periodic=(True, True, True), tau_a=0.7, tau_b=0.7, alpha=
     p.wall_affinity = wall_affinity
     p.bc_z = bc_z
     p.rho_in, p.rho_out = rho_in, rho_out
+    p.inlet_mode, p.flux_in = inlet_mode, float(flux_in)
     return p
 
 
@@ -98,7 +100,8 @@ def params_of(problem) -> OraParams:
     """Oracle parameters of an ``inputs.Problem``."""
     return make_params(problem.shape, problem.periodic, problem.tau_a, problem.tau_b,
                        problem.alpha, problem.beta, problem.force, problem.wall_affinity,
-                       problem.bc_z, problem.rho_in, problem.rho_out)
+                       problem.bc_z, problem.rho_in, problem.rho_out, problem.inlet_mode,
+                       problem.flux_in)
 
 
 def moment_basis():

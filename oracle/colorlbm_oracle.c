@@ -59,8 +59,9 @@ typedef struct {
     double force[3];
     double wall_affinity;
     int32_t bc_z;          /* 0: none; 1: pressure faces at z = 0 (inlet) and z = nz-1 (outlet) */
-    int32_t pad_;
+    int32_t inlet_mode;    /* with bc_z == 1: 0 = inlet density rho_in; 1 = inlet flux flux_in */
     double rho_in, rho_out;
+    double flux_in;        /* inlet_mode 1: sum of u_z over the inlet plane's pore voxels */
 } ora_params;
 
 /* D3Q19 velocity set of the d3q19 equation, grouped as rest, axes, then three diagonal planes. */
@@ -342,6 +343,29 @@ static void pressure_plane(const ora_params* p, const uint8_t* solid, double* f,
         }
 }
 
+/* Flux inlet (the flux boundary condition: a total volumetric flow rate over the whole inlet,
+ * the velocity free to vary across it): the inlet density for which the pressure condition at
+ * z = 0 gives sum over the plane's pore voxels of u_z = j_z + F_z/2 equal to flux_in, where
+ * j_z = rho - s0 - 2 sout per voxel (as in pressure_plane). */
+static double inlet_density(const ora_params* p, const uint8_t* solid, const double* f) {
+    const long nv = (long)p->nx * p->ny * p->nz;
+    double s = 0.0;
+    long n = 0;
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            const long v = (long)x + (long)p->nx * (long)y;   /* z = 0 */
+            if (solid[v]) continue;
+            double s0 = 0.0, sout = 0.0;
+            for (int q = 0; q < 19; ++q) {
+                if (XI[q][2] == 0) s0 += f[q * nv + v];
+                else if (XI[q][2] == -1) sout += f[q * nv + v];
+            }
+            s += s0 + 2.0 * sout;
+            ++n;
+        }
+    return (p->flux_in - (double)n * 0.5 * p->force[2] + s) / (double)n;
+}
+
 /* Run nsteps time steps in place on (f, A, B). Returns 0 on success, -1 on allocation failure. */
 int ora_run(const ora_params* p, const uint8_t* solid, const double* phi_s, double* f, double* A,
             double* B, int nsteps) {
@@ -420,7 +444,8 @@ int ora_run(const ora_params* p, const uint8_t* solid, const double* phi_s, doub
                 }
         /* 14. Optional pressure faces. */
         if (p->bc_z == 1) {
-            pressure_plane(p, solid, fn, An, Bn, 0, +1, p->rho_in, 1.0);
+            const double rho_in = p->inlet_mode == 1 ? inlet_density(p, solid, fn) : p->rho_in;
+            pressure_plane(p, solid, fn, An, Bn, 0, +1, rho_in, 1.0);
             pressure_plane(p, solid, fn, An, Bn, p->nz - 1, -1, p->rho_out, 0.0);
         }
         double* t;

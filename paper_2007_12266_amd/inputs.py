@@ -176,6 +176,8 @@ class Problem:
     force: tuple = (0.0, 0.0, 0.0)
     wall_affinity: float = 0.0
     bc_z: int = 0
+    inlet_mode: int = 0               # with bc_z = 1: 0 imposes rho_in, 1 imposes flux_in
+    flux_in: float = 0.0              # sum of u_z over the inlet plane's pore voxels
     rho_in: float = 1.0
     rho_out: float = 1.0
     name: str = ""

@@ -452,3 +452,23 @@ def test_pressure_faces_inject_fluid_a():
     pore = prob.solid_mask() == 0
     assert np.all(fl["phi"][0][pore[0]] == 1.0) and np.all(fl["phi"][-1][pore[-1]] == -1.0)
     assert r1["unstable"] == 0 and r1["mass_a"] > r0["mass_a"]
+
+
+def test_flux_inlet_holds_the_total_flow_rate():
+    """Flux inlet (reading R19): after every step the flow velocity u_z summed over the inlet
+    plane's pore voxels equals the imposed flux, with one density over the whole plane, while
+    the velocity varies across it (it is not a per-voxel velocity condition)."""
+    import dataclasses
+    base = inputs.displacement_problem(shape=(30, 12, 14), seed_geom=21, porosity_target=0.3)
+    n_in = int((base.solid_mask()[0] == 0).sum())
+    prob = dataclasses.replace(base, inlet_mode=1, flux_in=0.01 * n_in, force=(0.0, 0.0, 3e-6))
+    st = O.state_for(prob)
+    for k in range(3):
+        st.run(7)
+        fl = st.fields()
+        pore0 = prob.solid_mask()[0] == 0
+        uz = fl["uz"][0][pore0]
+        assert abs(uz.sum() - prob.flux_in) <= 1e-12 * prob.flux_in
+        rho0 = fl["rho"][0][pore0]
+        assert np.ptp(rho0) <= 1e-13
+        assert np.ptp(uz) > 1e-4                   # the velocity adapts across the inlet
