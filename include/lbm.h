@@ -96,6 +96,11 @@ typedef struct {
     int32_t reduce_every;    /* lbm_step records a reduction every this many steps (0: off) */
     int32_t block_size;      /* threads per workgroup (64, 128 or 256); 0: auto             */
     int32_t neighbour_mode;  /* lbm_neighbour_mode                                        */
+    int32_t inlet_mode;      /* with bc_z == 1: 0 imposes rho_in at the inlet; 1 imposes the */
+                             /* total flow rate flux_in (the paper's flux condition: every    */
+                             /* step the inlet density is the one for which u_z summed over  */
+                             /* the inlet plane's pore voxels equals flux_in)                 */
+    double flux_in;          /* inlet_mode 1: imposed sum of u_z over the inlet plane         */
 } lbm_params;
 
 /* Reductions over the pore voxels (section "Analysis framework", integral measures, and the

@@ -67,6 +67,7 @@ struct lbm_domain {
     int32_t hist_count = 0;   // unread entries
     std::vector<int64_t> hist_step;
     int32_t* faces = nullptr;       // inlet then outlet pore indices (bc_z == 1)
+    double* inlet_rho = nullptr;    // device scalar: this step's inlet density (flux inlet)
     int32_t* ghost_tail = nullptr;  // z-face mirror entries of the phi tail
     int32_t* ghost_src = nullptr;
 

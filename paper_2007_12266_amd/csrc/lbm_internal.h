@@ -69,9 +69,14 @@ hipError_t launch_ghosts(const StepArgs& a, const int32_t* ghost_tail, const int
                          int32_t n, hipStream_t s);
 // faces: inlet pore indices (n_in) followed by outlet ones (n_out); next_odd: parity of the
 // step that will read the state the condition is applied to.
+// rho_in_dev (nullable): device scalar that replaces rho_in (flux inlet).
 hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* faces,
                               int32_t n_in, int32_t n_out, double rho_in, double rho_out,
-                              hipStream_t s);
+                              const double* rho_in_dev, hipStream_t s);
+// Flux inlet: the inlet density for which the flow velocity summed over the n_in inlet voxels
+// (faces[0..n_in)) equals flux, written to *rho_in_dev (one workgroup, fixed order).
+hipError_t launch_inlet_density(const StepArgs& a, bool next_odd, const int32_t* faces,
+                                int32_t n_in, double flux, double* rho_in_dev, hipStream_t s);
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
                          hipStream_t s);
 // lookup: LBM_NBR_TABLE or LBM_NBR_RANK when every member uses that neighbour lookup, else

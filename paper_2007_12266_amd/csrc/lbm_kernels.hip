@@ -749,14 +749,15 @@ template <int PREC, bool ODD>
 __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
                                                           const int32_t* __restrict__ faces,
                                                           int n_in, int n_out, double rho_in,
-                                                          double rho_out) {
+                                                          double rho_out,
+                                                          const double* __restrict__ rho_in_dev) {
     using P = Prec<PREC>;
     using S = typename P::S;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_in + n_out) return;
     const int i = faces[k];
     const int dir = k < n_in ? 1 : -1;
-    const double rho_b = k < n_in ? rho_in : rho_out;
+    const double rho_b = k < n_in ? (rho_in_dev ? *rho_in_dev : rho_in) : rho_out;
     S* f = (S*)a.f;
     int r[19];
     r[0] = i;
@@ -785,6 +786,47 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
         const double val = fl[OPP[q]] + 6.0 * tw(q) * CZ[q] * jz - 0.5 * (CX[q] * tx + CY[q] * ty);
         f[(size_t)q * a.ld + i] = (S)(val - (P::kDev ? tw(q) : 0.0));
     }
+}
+
+// Flux inlet: sum over the inlet voxels of s0 + 2 sout (the known part of each voxel's
+// j_z = rho - s0 - 2 sout under the pressure condition), then the density that makes the summed
+// flow velocity u_z = j_z + F_z/2 equal the imposed flux. One workgroup of kInletThreads
+// threads with a fixed stride and a fixed tree order.
+constexpr int kInletThreads = 1024;
+
+template <int PREC, bool ODD>
+__global__ void __launch_bounds__(kInletThreads) inlet_density_kernel(
+    StepArgs a, const int32_t* __restrict__ faces, int n_in, double flux,
+    double* __restrict__ rho_in_dev) {
+    using P = Prec<PREC>;
+    using S = typename P::S;
+    __shared__ double acc[kInletThreads];
+    const S* f = (const S*)a.f;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n_in; k += kInletThreads) {
+        const int i = faces[k];
+        int r[19];
+        r[0] = i;
+        const Pos pos = pos_of(a, i);
+#pragma unroll
+        for (int q = 1; q < 19; ++q) r[q] = nb_stream(a, q, i, pos);
+        double s0 = 0.0, sout = 0.0;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const double fq = (double)load_in<ODD>(f, a, q, i, r[OPP[q]]) + (P::kDev ? tw(q) : 0.0);
+            if (CZ[q] == 0) s0 += fq;
+            else if (CZ[q] == -1) sout += fq;
+        }
+        s += s0 + 2.0 * sout;
+    }
+    acc[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kInletThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) acc[threadIdx.x] += acc[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        rho_in_dev[0] = (flux - (double)n_in * 0.5 * a.F[2] + acc[0]) / (double)n_in;
 }
 
 int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
@@ -961,12 +1003,22 @@ hipError_t launch_ghosts(const StepArgs& a, const int32_t* ghost_tail, const int
 
 hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* faces,
                               int32_t n_in, int32_t n_out, double rho_in, double rho_out,
-                              hipStream_t s) {
+                              const double* rho_in_dev, hipStream_t s) {
     const int n = n_in + n_out;
     if (n <= 0) return hipSuccess;
     const dim3 grid((n + 255) / 256);
     const bool odd = next_odd;
-    LBM_DISPATCH(pressure_bc_kernel, grid, dim3(256), a, faces, n_in, n_out, rho_in, rho_out);
+    LBM_DISPATCH(pressure_bc_kernel, grid, dim3(256), a, faces, n_in, n_out, rho_in, rho_out,
+                 rho_in_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_inlet_density(const StepArgs& a, bool next_odd, const int32_t* faces,
+                                int32_t n_in, double flux, double* rho_in_dev, hipStream_t s) {
+    if (n_in <= 0) return hipSuccess;
+    const bool odd = next_odd;
+    LBM_DISPATCH(inlet_density_kernel, dim3(1), dim3(kInletThreads), a, faces, n_in, flux,
+                 rho_in_dev);
     return hipGetLastError();
 }
 

@@ -120,9 +120,12 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
         if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
         if (d->p.bc_z == 1) {
             if (timing) { sp.kind = 2; HIP_TRY(mark(&sp.a)); }
+            if (d->inlet_rho)
+                HIP_TRY(launch_inlet_density(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
+                                             d->p.flux_in, d->inlet_rho, d->stream));
             HIP_TRY(launch_pressure_bc(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
                                        (int32_t)d->pre.outlet.size(), d->p.rho_in,
-                                       d->p.rho_out, d->stream));
+                                       d->p.rho_out, d->inlet_rho, d->stream));
             if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
         }
         d->step += 1;
@@ -180,6 +183,7 @@ static int64_t domain_bytes(const lbm_params& p, const Prepass& pre) {
                     r(sizeof(double) * 1024 * kNRed);
     const size_t faces = pre.inlet.size() + pre.outlet.size();
     if (faces) total += r(sizeof(int32_t) * faces) + r(sizeof(int8_t) * ld);
+    if (faces && p.inlet_mode == 1) total += r(sizeof(double));
     if (!pre.ghost_tail.empty()) total += 2 * r(sizeof(int32_t) * pre.ghost_tail.size());
     return total;
 }
@@ -226,6 +230,10 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         return fail(LBM_ERR_ARG, "precision must be LBM_FP64 or LBM_FP32_DEV");
     if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
         return fail(LBM_ERR_ARG, "rho_in and rho_out must be positive");
+    if (p.inlet_mode != 0 && p.inlet_mode != 1)
+        return fail(LBM_ERR_ARG, "inlet_mode must be 0 or 1");
+    if (p.inlet_mode == 1 && (p.bc_z != 1 || !std::isfinite(p.flux_in)))
+        return fail(LBM_ERR_ARG, "a flux inlet needs bc_z == 1 and a finite flux_in");
     if (p.reduce_every < 0) return fail(LBM_ERR_ARG, "reduce_every must be >= 0");
     if (p.neighbour_mode < LBM_NBR_AUTO || p.neighbour_mode > LBM_NBR_RANK)
         return fail(LBM_ERR_ARG, "neighbour_mode must be a lbm_neighbour_mode");
@@ -287,6 +295,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (!faces.empty()) {
         d->faces = (int32_t*)d->dalloc(sizeof(int32_t) * faces.size());
         d->face = (int8_t*)d->dalloc(sizeof(int8_t) * ld);
+        if (p.inlet_mode == 1) d->inlet_rho = (double*)d->dalloc(sizeof(double));
         face_flags.assign(ld, 0);
         for (int32_t v : pre.inlet) face_flags[v] = 1;
         for (int32_t v : pre.outlet) face_flags[v] = 2;
@@ -295,7 +304,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         d->ghost_tail = (int32_t*)d->dalloc(sizeof(int32_t) * pre.ghost_tail.size());
         d->ghost_src = (int32_t*)d->dalloc(sizeof(int32_t) * pre.ghost_src.size());
     }
-    if ((!faces.empty() && (!d->faces || !d->face)) ||
+    if ((!faces.empty() && (!d->faces || !d->face || (p.inlet_mode == 1 && !d->inlet_rho))) ||
         (!pre.ghost_tail.empty() && (!d->ghost_tail || !d->ghost_src))) {
         d->release();
         return fail(LBM_ERR_OOM, "device allocation failed");

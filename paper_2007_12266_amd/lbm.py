@@ -48,7 +48,8 @@ class Params(ctypes.Structure):
                 ("bc_z", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
                 ("reduce_every", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("neighbour_mode", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("neighbour_mode", ctypes.c_int32), ("inlet_mode", ctypes.c_int32),
+                ("flux_in", ctypes.c_double)]
 
 
 class Reduction(ctypes.Structure):
@@ -233,6 +234,8 @@ def make_params(problem, precision: int = FP64, reduce_every: int = 0,
     p.alpha, p.beta = problem.alpha, problem.beta
     p.wall_affinity = problem.wall_affinity
     p.bc_z = problem.bc_z
+    p.inlet_mode = getattr(problem, "inlet_mode", 0)
+    p.flux_in = float(getattr(problem, "flux_in", 0.0))
     p.precision = precision
     p.rho_in, p.rho_out = problem.rho_in, problem.rho_out
     p.reduce_every = reduce_every

@@ -182,3 +182,20 @@ def test_steady_calls_reject_null_handles():
     sp = lbm.SteadyParams(1e-3, 2.0, 1e-2, 10, 10, 100)
     out = lbm.SteadyResult()
     assert L.lbm_run_steady(None, ctypes.byref(sp), ctypes.byref(out)) == lbm.LBM_ERR_ARG
+
+
+def test_flux_inlet_needs_pressure_faces():
+    """Checked before the device is touched: a flux inlet without pressure faces, an unknown
+    inlet mode, a non-finite flux."""
+    L = lbm.load_library()
+    prob = _random_problem((4, 4, 4), (True, True, True), seed=2)
+    labels, kind, aff, vaff, iphi = lbm._problem_arrays(prob)
+    for mode, bc_z, flux, msg in ((1, 0, 1.0, b"flux inlet"), (2, 0, 0.0, b"inlet_mode"),
+                                  (1, 1, float("nan"), b"flux")):
+        p = lbm.make_params(prob)
+        p.inlet_mode, p.bc_z, p.flux_in = mode, bc_z, flux
+        h = ctypes.c_void_p()
+        st = L.lbm_domain_create(ctypes.byref(p), lbm._ptr(labels), 2, lbm._ptr(kind),
+                                 lbm._ptr(aff), lbm._ptr(vaff), lbm._ptr(iphi), None, None,
+                                 ctypes.byref(h))
+        assert st == lbm.LBM_ERR_ARG and msg in L.lbm_last_error() and not h.value

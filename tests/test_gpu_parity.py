@@ -311,6 +311,30 @@ def test_displacement_generator_at_128_over_500_steps(lbm):
     dom.close()
 
 
+@pytest.mark.parametrize("mode,steps", [("table", 40), ("table", 41), ("rank", 41)])
+def test_flux_inlet_parity(lbm, mode, steps):
+    """Flux inlet (the paper's flux boundary condition, reading R19): the inlet density is
+    chosen every step so that u_z summed over the inlet plane equals the imposed flux. GPU FP64
+    against the oracle, both step parities, both neighbour lookups; the flux itself holds."""
+    import dataclasses
+    base = inputs.displacement_problem(shape=(30, 12, 14), seed_geom=21, porosity_target=0.3)
+    n_in = int((base.solid_mask()[0] == 0).sum())
+    prob = dataclasses.replace(base, inlet_mode=1, flux_in=0.01 * n_in, force=(0.0, 0.0, 3e-6))
+    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    dom = lbm.Domain(prob, neighbour_mode=nm)
+    dom.step(steps)
+    gpu = dom.fields()
+    ref = O.state_for(prob).run(steps)
+    _compare(gpu, ref.fields(), prob.solid_mask() == 0)
+    pore0 = prob.solid_mask()[0] == 0
+    assert abs(gpu["uz"][0][pore0].sum() - prob.flux_in) <= 1e-12 * prob.flux_in
+    dom.close()
+    d32 = lbm.Domain(prob, precision=lbm.FP32_DEV, neighbour_mode=nm)
+    d32.step(steps)
+    assert abs(d32.field("uz")[0][pore0].sum() - prob.flux_in) <= 1e-5 * prob.flux_in
+    d32.close()
+
+
 def test_centrifuge_configuration(lbm):
     """The paper's centrifuge analogue: reservoirs at equal pressure (no pressure drop) and a
     body force that drives the fluids through the sample: pressure faces with rho_in = rho_out
