@@ -27,8 +27,13 @@
 //    16 values per voxel and step instead of 28, and turns the odd step's 14 scattered A/B writes
 //    into 8 coalesced ones. On the first step of a fresh state the slots hold the initial
 //    densities themselves (a per-domain device flag, cleared by the first collide). The 8 slots
-//    are 8 rows of ld values (SoA); storing each voxel's 8 values contiguously was measured
-//    slower on both kernels.
+//    are stored as 4 rows of value pairs, (N_a, N_b), (u_x, G_x), (u_y, G_y), (u_z, G_z), so
+//    that what a neighbour contributes along one axis is two wide loads; storing each voxel's
+//    8 values contiguously was measured slower on both kernels.
+//  * Neighbours come from an int32 table with opposite directions interleaved (one 8-byte load
+//    per pair), or from the voxel's packed coordinate and per-64-voxel row records (the rank
+//    lookup: less memory, a dependent load more, measured slower). The step kernels are
+//    compiled for each lookup.
 //  * The MRT collision is evaluated in its two-relaxation-time form: the relaxation matrix has
 //    one rate (s+ = 1/tau) on every even moment and one rate (s- = 8(2-s+)/(8-s+)) on every odd
 //    one (the conserved moments have zero non-equilibrium part, so their rate is immaterial).
@@ -65,9 +70,9 @@ __host__ __device__ constexpr double tw(int q) {   // D3Q19 weights t_q
     return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-// Precision policies. S: storage type of f, A, B, phi, N. R: arithmetic type. kDev: f is stored
-// as f_q - t_q. kCMin: smallest resolved colour-gradient magnitude (a few orders above the
-// rounding noise of C in that precision); a smaller |C| counts as zero.
+// Precision policies. S: storage type of f, the moment slots, phi, N. R: arithmetic type.
+// kDev: f is stored as f_q - t_q. kCMin: smallest resolved colour-gradient magnitude (a few
+// orders above the rounding noise of C in that precision); a smaller |C| counts as zero.
 template <int PREC> struct Prec;
 template <> struct Prec<LBM_FP64> {
     using S = double;
