@@ -28,13 +28,14 @@ void clear_error() { g_err.clear(); }
 
 namespace {
 
-constexpr uint64_t kStateMagic = 0x4c424d434f4c5233ull;  // "LBMCOLR3"
+constexpr uint64_t kStateMagic = 0x4c424d434f4c5234ull;  // "LBMCOLR4"
 constexpr int kStateRows = 27;  // 19 D3Q19 populations + 8 D3Q7 moment slots
 
 struct StateHeader {
     uint64_t magic;
     int64_t n_pore, n_tail, step;
     int32_t precision, elem_bytes;
+    int32_t fresh, pad_;   // 1: the moment slots hold densities of a state at rest (see init)
 };
 
 }  // namespace
@@ -526,7 +527,11 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
         return LBM_OK;
     }
     if (*nbytes < need) return fail(LBM_ERR_ARG, "state buffer too small");
-    StateHeader h{kStateMagic, d->pre.n_pore, d->pre.n_tail, d->step, d->p.precision, (int32_t)eb};
+    int32_t fresh = 0;
+    HIP_TRY(hipMemcpyAsync(&fresh, d->fresh, sizeof fresh, hipMemcpyDeviceToHost, d->stream));
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    StateHeader h{kStateMagic, d->pre.n_pore, d->pre.n_tail, d->step, d->p.precision, (int32_t)eb,
+                  fresh, 0};
     std::memcpy(host_buf, &h, sizeof h);
     char* dst = (char*)host_buf + sizeof h;
     // f: 19 rows of n values and M: 4 rows of n value pairs (pitch ld on the device).
@@ -559,7 +564,7 @@ lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes) {
     src += eb * n * 19;
     HIP_TRY(hipMemcpy2DAsync(d->M, 2 * eb * ld, src, 2 * eb * n, 2 * eb * n, 4,
                              hipMemcpyHostToDevice, d->stream));
-    d->one = h.step == 0 ? 1 : 0;            // a step-0 state is the initial one
+    d->one = h.fresh ? 1 : 0;                // a state at rest (initial, or after lbm_morph)
     HIP_TRY(hipMemcpyAsync(d->fresh, &d->one, sizeof(int32_t), hipMemcpyHostToDevice,
                            d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));

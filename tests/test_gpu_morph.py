@@ -151,3 +151,21 @@ def test_morph_argument_checks(lbm):
     assert e.value.status == lbm.LBM_ERR_STATE
     pool.close()
     dom.close()
+
+
+def test_state_saved_right_after_a_morph_resumes_bitwise(lbm):
+    """Right after lbm_morph the moment slots hold the new densities at rest; the saved state
+    records that, so a domain loaded from it continues exactly like the original."""
+    prob = _problem()
+    a = lbm.Domain(prob)
+    a.step(25)
+    a.morph(delta=0.6)
+    blob = a.save()
+    b = lbm.Domain(prob)
+    b.load(blob)
+    assert b.info()["step"] == 25
+    a.step(9)
+    b.step(9)
+    assert a.save() == b.save()
+    a.close()
+    b.close()
