@@ -101,6 +101,11 @@ typedef struct {
                              /* step the inlet density is the one for which u_z summed over  */
                              /* the inlet plane's pore voxels equals flux_in)                 */
     double flux_in;          /* inlet_mode 1: imposed sum of u_z over the inlet plane         */
+    int32_t order_rows;      /* pore numbering: blocks of R rows of y, each block plane by    */
+                             /* plane and row by row (neighbours one plane away stay close); */
+                             /* 0 = 16 rows; R >= ny = dense order (z, y, x). Results do not */
+                             /* depend on it.                                                 */
+    int32_t pad_;
 } lbm_params;
 
 /* Reductions over the pore voxels (section "Analysis framework", integral measures, and the

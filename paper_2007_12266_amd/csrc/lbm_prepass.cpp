@@ -6,8 +6,10 @@
 // indicator in the colour gradient; pore voxels carry the fluids.
 //
 // Layout produced for the kernels:
-//  * pore voxels are numbered in dense order (z, then y, then x fastest), so that each
-//    wavefront covers a run of consecutive voxels along x;
+//  * pore voxels are numbered row by row (x fastest), so that each wavefront covers runs of
+//    consecutive voxels along x; the rows are taken plane by plane within blocks of
+//    `order_rows` rows (16 by default; ny or more gives the dense order), so that neighbours
+//    one plane away sit close in the pore list and are reused from the cache;
 //  * nbr[(q-1)*ld + i] is the pore index of the neighbour of pore i along xi_q, or N + t where
 //    t indexes the "tail" of the phi array: tail entry 0 is the wall outside non-periodic faces
 //    (phi = wall_affinity), the others are the solid voxels adjacent to a pore (phi = phi_s);
@@ -57,18 +59,29 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
     if (!(p.wall_affinity >= -1.0 && p.wall_affinity <= 1.0))
         return "wall_affinity is outside [-1, 1]";
 
-    // Pore numbering in dense order.
-    std::vector<int32_t> pidx(nvox, -1);
-    int64_t n = 0;
+    if (p.order_rows < 0) return "order_rows must be >= 0";
     for (int64_t v = 0; v < nvox; ++v) {
         const int32_t l = labels[v];
         if (l < 0 || l >= n_labels) return fmt("labels[%lld] = %lld is out of range", v, l);
-        if (label_kind[l] != LBM_LABEL_SOLID) {
-            if (n >= (int64_t)std::numeric_limits<int32_t>::max() / 2)
-                return "too many pore voxels for int32 indexing";
-            pidx[v] = (int32_t)n++;
-        }
     }
+    // Pore numbering: blocks of `order_rows` consecutive rows (y; 0 takes kDefaultOrderRows),
+    // each block plane by plane (z), each plane row by row, each row along x. Blocks of ny or
+    // more rows give the dense order. Blocks bring the neighbours one plane away closer in the
+    // pore list (a block's plane instead of a whole plane apart), so they are still in the L2
+    // when they are reused; every row's pore voxels stay consecutive.
+    std::vector<int32_t> pidx(nvox, -1);
+    int64_t n = 0;
+    const int64_t rows = std::min<int64_t>(p.order_rows > 0 ? p.order_rows : kDefaultOrderRows, ny);
+    for (int64_t y0 = 0; y0 < ny; y0 += rows)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = y0; y < std::min(y0 + rows, ny); ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    const int64_t v = x + nx * (y + ny * z);
+                    if (label_kind[labels[v]] == LBM_LABEL_SOLID) continue;
+                    if (n >= (int64_t)std::numeric_limits<int32_t>::max() / 2)
+                        return "too many pore voxels for int32 indexing";
+                    pidx[v] = (int32_t)n++;
+                }
     if (n == 0) return "the image has no pore voxel";
     out = Prepass();
     out.n_pore = n;
@@ -183,17 +196,21 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
         const int64_t W = (nx + 63) / 64;
         out.words_per_row = (int32_t)W;
         out.words.assign((size_t)(ny * nz * W), RowWord{0, 0, 0, 0, 0});
-        int32_t next_pore = 0, next_tail = 1;
+        // A segment's pore voxels are consecutive in the pore list (rows stay whole in every
+        // numbering) and its tail solids consecutive in the tail (dense order), so each base is
+        // the index of the segment's first one.
+        int32_t next_tail = 1;
         for (int64_t r = 0; r < ny * nz; ++r)
             for (int64_t w = 0; w < W; ++w) {
                 RowWord& rw = out.words[(size_t)(r * W + w)];
-                rw.pore_base = next_pore;
                 rw.tail_base = next_tail;
+                bool first = true;
                 for (int b = 0; b < 64 && 64 * w + b < nx; ++b) {
                     const int64_t v = r * nx + 64 * w + b;
                     if (pidx[v] >= 0) {
+                        if (first) rw.pore_base = pidx[v];
+                        first = false;
                         rw.pore |= 1ull << b;
-                        ++next_pore;
                     } else if (tidx[v]) {
                         rw.tail |= 1ull << b;
                         ++next_tail;

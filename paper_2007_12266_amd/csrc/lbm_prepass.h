@@ -10,6 +10,9 @@
 
 namespace lbm {
 
+// Rows of y per block of the pore numbering when lbm_params.order_rows is 0.
+constexpr int kDefaultOrderRows = 16;
+
 // One 64-voxel segment of an image row (y, z), x in [64 w, 64 w + 64): which voxels are pores,
 // which are tail solids (solids next to a pore), and the index of the first of each in the
 // segment. A neighbour's index is then a base plus a population count (rank lookup).

@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
                 ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
                 ("reduce_every", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("neighbour_mode", ctypes.c_int32), ("inlet_mode", ctypes.c_int32),
-                ("flux_in", ctypes.c_double)]
+                ("flux_in", ctypes.c_double), ("order_rows", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class Reduction(ctypes.Structure):
@@ -223,7 +224,8 @@ def _ptr(a: Optional[np.ndarray]):
 
 
 def make_params(problem, precision: int = FP64, reduce_every: int = 0,
-                block_size: int = 0, neighbour_mode: int = NBR_AUTO) -> Params:
+                block_size: int = 0, neighbour_mode: int = NBR_AUTO,
+                order_rows: int = 0) -> Params:
     """lbm_params of an ``inputs.Problem``."""
     p = Params()
     p.nz, p.ny, p.nx = problem.shape
@@ -241,6 +243,7 @@ def make_params(problem, precision: int = FP64, reduce_every: int = 0,
     p.reduce_every = reduce_every
     p.block_size = block_size
     p.neighbour_mode = neighbour_mode
+    p.order_rows = order_rows
     return p
 
 
@@ -255,10 +258,10 @@ def _problem_arrays(problem):
     return labels, kind, aff, vaff, iphi
 
 
-def prepass_query(problem) -> dict:
+def prepass_query(problem, order_rows: int = 0) -> dict:
     """Host-only pre-pass of a problem: pore list, neighbour table [18, N] and phi tail."""
     L = load_library()
-    p = make_params(problem)
+    p = make_params(problem, order_rows=order_rows)
     labels, kind, aff, vaff, iphi = _problem_arrays(problem)
     n, t = ctypes.c_int64(), ctypes.c_int64()
     args = (ctypes.byref(p), _ptr(labels), int(aff.size), _ptr(kind), _ptr(aff), _ptr(vaff),
@@ -272,10 +275,11 @@ def prepass_query(problem) -> dict:
             "tail_phi": tail}
 
 
-def footprint(problem, precision: int = FP64, neighbour_mode: int = NBR_AUTO) -> int:
+def footprint(problem, precision: int = FP64, neighbour_mode: int = NBR_AUTO,
+              order_rows: int = 0) -> int:
     """Device bytes a Domain of this problem would allocate (host-only pre-pass)."""
     L = load_library()
-    p = make_params(problem, precision, neighbour_mode=neighbour_mode)
+    p = make_params(problem, precision, neighbour_mode=neighbour_mode, order_rows=order_rows)
     labels, kind, aff, vaff, iphi = _problem_arrays(problem)
     b = ctypes.c_int64()
     _check(L.lbm_domain_footprint(ctypes.byref(p), _ptr(labels), int(aff.size), _ptr(kind),
@@ -311,11 +315,11 @@ class Domain:
 
     def __init__(self, problem, precision: int = FP64, reduce_every: int = 0,
                  block_size: int = 0, allocator: str = "torch", stream=None,
-                 neighbour_mode: int = NBR_AUTO):
+                 neighbour_mode: int = NBR_AUTO, order_rows: int = 0):
         L = load_library()
         self.problem = problem
         self.shape = problem.shape
-        p = make_params(problem, precision, reduce_every, block_size, neighbour_mode)
+        p = make_params(problem, precision, reduce_every, block_size, neighbour_mode, order_rows)
         self.params = p
         labels, kind, aff, vaff, iphi = _problem_arrays(problem)
         self._torch_alloc = None

@@ -169,7 +169,7 @@ def test_unstable_state_is_detected_and_cleared_by_load(lbm):
     dom.step(3)
     good = dom.save()
     poisoned = bytearray(good)
-    hdr = 8 + 8 * 3 + 8
+    hdr = len(good) - 8 * 27 * dom.n_pore                  # header, then 19 f rows, 8 slot rows
     poisoned[hdr:hdr + 8] = np.array([np.nan]).tobytes()   # f_0 of the first pore voxel
     dom.load(bytes(poisoned))
     assert dom.reduce()["unstable"] == 1
