@@ -34,29 +34,67 @@ __global__ void __launch_bounds__(256) morph_label_kernel(int n, const int64_t* 
     if (i < n) label[vox[i]] = phi[i] > (S)0 ? 1 : 0;
 }
 
-// Label of (x, y, z) with periodic wrap; outside a non-periodic face: 0 (not fluid a).
-__device__ __forceinline__ int label_at(const uint8_t* __restrict__ label, int x, int y, int z,
-                                        int nx, int ny, int nz, int periodic) {
-    if (x < 0 || x >= nx) {
-        if (!(periodic & 1)) return 0;
-        x = x < 0 ? x + nx : x - nx;
+// Fluid-a bits of every image row: bit b of word w of row (y, z) is the label of x = 64 w + b.
+__global__ void __launch_bounds__(256) morph_pack_kernel(int64_t nrows, int nx, int words,
+                                                         const uint8_t* __restrict__ label,
+                                                         uint64_t* __restrict__ bits) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nrows * words) return;
+    const int64_t row = k / words;
+    const int w = (int)(k % words);
+    const uint8_t* src = label + row * nx + 64 * w;
+    const int nb = min(64, nx - 64 * w);
+    uint64_t m = 0;
+    for (int b = 0; b < nb; ++b) m |= (uint64_t)(src[b] & 1) << b;
+    bits[k] = m;
+}
+
+// Smallest |dx| <= radius such that the label at x + dx in row `row` differs from `own`
+// (radius + 1 if none). Outside a non-periodic x face the label is 0 (not fluid a).
+__device__ __forceinline__ int row_nearest(const uint64_t* __restrict__ bits, int64_t row, int x,
+                                           int nx, int words, bool xper, int own, int radius) {
+    const uint64_t* r = bits + row * words;
+    if (x - radius >= 0 && x + radius < nx) {
+        // Window of 2 radius + 1 bits starting at x - radius (radius <= 12: within two words).
+        const int lo = x - radius;
+        const int w = lo >> 6, sh = lo & 63;
+        uint64_t win = r[w] >> sh;
+        if (sh && w + 1 < words) win |= r[w + 1] << (64 - sh);
+        const int width = 2 * radius + 1;
+        uint64_t opp = own ? ~win : win;
+        opp &= (width == 64 ? ~0ull : ((1ull << width) - 1ull));
+        int best = radius + 1;
+        const uint64_t right = opp >> radius;              // dx >= 0
+        if (right) best = __ffsll((long long)right) - 1;
+        const uint64_t left = opp & ((1ull << radius) - 1ull);   // dx < 0
+        if (left) best = min(best, radius - (63 - __clzll((long long)left)));
+        return best;
     }
-    if (y < 0 || y >= ny) {
-        if (!(periodic & 2)) return 0;
-        y = y < 0 ? y + ny : y - ny;
-    }
-    if (z < 0 || z >= nz) {
-        if (!(periodic & 4)) return 0;
-        z = z < 0 ? z + nz : z - nz;
-    }
-    return label[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z)];
+    for (int dx = 0; dx <= radius; ++dx)
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            if (dx == 0 && sgn) continue;
+            int xx = sgn ? x - dx : x + dx;
+            int lab;
+            if (xx < 0 || xx >= nx) {
+                if (!xper) {
+                    lab = 0;
+                } else {
+                    xx = xx < 0 ? xx + nx : xx - nx;
+                    lab = (int)((r[xx >> 6] >> (xx & 63)) & 1ull);
+                }
+            } else {
+                lab = (int)((r[xx >> 6] >> (xx & 63)) & 1ull);
+            }
+            if (lab != own) return dx;
+        }
+    return radius + 1;
 }
 
 template <typename S>
 __global__ void __launch_bounds__(256) morph_distance_kernel(
     int n, int nx, int ny, int nz, int periodic, const int64_t* __restrict__ vox,
-    const S* __restrict__ phi, const uint8_t* __restrict__ label, double beta, double phi_band,
-    int radius, double* __restrict__ dist, int8_t* __restrict__ far) {
+    const S* __restrict__ phi, const uint64_t* __restrict__ bits, int words, double beta,
+    double phi_band, int radius, double* __restrict__ dist, int8_t* __restrict__ far) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double ph = (double)phi[i];
@@ -73,15 +111,28 @@ __global__ void __launch_bounds__(256) morph_distance_kernel(
     for (int dz = -radius; dz <= radius; ++dz) {
         const int z2 = dz * dz;
         if (z2 >= best) continue;
+        int zz = z + dz;
+        bool zin = zz >= 0 && zz < nz;
+        if (!zin && (periodic & 4)) {
+            zz = zz < 0 ? zz + nz : zz - nz;
+            zin = true;
+        }
         for (int dy = -radius; dy <= radius; ++dy) {
             const int zy2 = z2 + dy * dy;
             if (zy2 >= best) continue;
-            for (int dx = -radius; dx <= radius; ++dx) {
-                const int d2 = zy2 + dx * dx;
-                if (d2 >= best) continue;
-                if (label_at(label, x + dx, y + dy, z + dz, nx, ny, nz, periodic) != own)
-                    best = d2;
+            int yy = y + dy;
+            bool yin = yy >= 0 && yy < ny;
+            if (!yin && (periodic & 2)) {
+                yy = yy < 0 ? yy + ny : yy - ny;
+                yin = true;
             }
+            int dx;
+            if (!zin || !yin)
+                dx = own ? 0 : radius + 1;   // a row outside the domain is not fluid a
+            else
+                dx = row_nearest(bits, (int64_t)yy + (int64_t)ny * zz, x, nx, words,
+                                 (periodic & 1) != 0, own, radius);
+            if (dx <= radius) best = min(best, zy2 + dx * dx);
         }
     }
     if (best > r2max) {
@@ -161,8 +212,10 @@ lbm_status ensure_buffers(lbm_domain* d) {
     d->morph_dist = (double*)d->dalloc(sizeof(double) * (size_t)n);
     d->morph_far = (int8_t*)d->dalloc((size_t)n);
     d->morph_count = (long long*)d->dalloc(sizeof(long long) * kMorphBlocks);
+    const int64_t words = (int64_t)d->p.ny * d->p.nz * ((d->p.nx + 63) / 64);
+    d->morph_bits = (uint64_t*)d->dalloc(sizeof(uint64_t) * (size_t)words);
     if (!d->morph_label || !d->morph_vox || !d->morph_dist || !d->morph_far ||
-        !d->morph_count) {
+        !d->morph_count || !d->morph_bits) {
         d->morph_label = nullptr;   // the partial allocations stay with the domain
         return fail(LBM_ERR_OOM, "no device memory for the morphological work buffers");
     }
@@ -221,10 +274,15 @@ lbm_status distance_map(lbm_domain* d, const lbm_morph_params& mp) {
     HIP_TRY(hipGetLastError());
     const int periodic =
         (d->p.periodic[0] ? 1 : 0) | (d->p.periodic[1] ? 2 : 0) | (d->p.periodic[2] ? 4 : 0);
+    const int words = (d->p.nx + 63) / 64;
+    const int64_t nrows = (int64_t)d->p.ny * d->p.nz;
+    hipLaunchKernelGGL(morph_pack_kernel, dim3(blocks_for(nrows * words)), dim3(256), 0,
+                       d->stream, nrows, d->p.nx, words, d->morph_label, d->morph_bits);
+    HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(morph_distance_kernel<S>, dim3(blocks_for(n)), dim3(256), 0, d->stream,
                        n, d->p.nx, d->p.ny, d->p.nz, periodic, d->morph_vox, (const S*)d->phi,
-                       d->morph_label, d->p.beta, std::tanh(mp.band * d->p.beta), mp.radius,
-                       d->morph_dist, d->morph_far);
+                       d->morph_bits, words, d->p.beta, std::tanh(mp.band * d->p.beta),
+                       mp.radius, d->morph_dist, d->morph_far);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
