@@ -169,3 +169,22 @@ def test_state_saved_right_after_a_morph_resumes_bitwise(lbm):
     assert a.save() == b.save()
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("periodic", [(False, True, False), (True, False, True)])
+def test_morph_walls_and_wraps_in_every_axis(lbm, periodic):
+    """Walls and periodic wraps on x (the row-word search's window and edge paths) and on y, z
+    (rows outside the domain): volumes and fields equal the oracle's."""
+    import dataclasses
+    prob = dataclasses.replace(_problem(), periodic=periodic)
+    pore = prob.solid_mask() == 0
+    st = _oracle_after(prob, 20)
+    dom = lbm.Domain(prob)
+    dom.step(20)
+    for delta in (1.4, -2.0):
+        res = dom.morph(delta=delta, radius=5)
+        _, Phi, _ = OM.apply_to_state(st, prob.beta, prob.periodic, delta, radius=5)
+        assert res["volume_before"] == OM.volume(Phi, pore, 0.0)
+        assert res["volume_after"] == OM.volume(Phi, pore, delta)
+        _compare(dom.fields(), st.fields(), pore)
+    dom.close()
