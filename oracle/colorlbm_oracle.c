@@ -36,9 +36,9 @@
  * Pins (tests, independent of these formulas) cover the moment basis, isotropy, fixed points,
  * conservation, the colour perturbation, recolouring, Poiseuille flow, the flat-interface
  * tension and profile, the Laplace law, contact angles, symmetries, pressure-driven slit flow and
- * an independent brute-force implementation. Two readings have no value the paper prints to pin
- * them: the unlisted equilibria away from the single-phase limit, and the composition imposed at
- * the pressure faces beyond "a enters, b leaves" -- parity unpinned for those two choices.
+ * an independent brute-force implementation; the unlisted equilibria are pinned to the published
+ * D3Q19 equilibria of d'Humieres et al. (2002). One reading has no value to pin it: the
+ * composition imposed at the pressure faces beyond "a enters, b leaves" -- parity unpinned there.
  *
  * State layout: f[q * nvox + v], A[q * nvox + v], B[q * nvox + v], v = x + nx*(y + ny*z).
  * Entries of solid voxels are never read and are left as they are.

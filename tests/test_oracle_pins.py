@@ -472,3 +472,32 @@ def test_flux_inlet_holds_the_total_flow_rate():
         rho0 = fl["rho"][0][pore0]
         assert np.ptp(rho0) <= 1e-13
         assert np.ptp(uz) > 1e-4                   # the velocity adapts across the inlet
+
+
+def test_equilibrium_moments_are_the_published_ones():
+    """Reading R5 pinned to its source: the moments (in the oracle's basis) of the second-order
+    polynomial equilibrium are the published d'Humieres equilibria (golden file); together with
+    the fixed-point pin above, the oracle's collision uses exactly those equilibria."""
+    M, _, _ = O.moment_basis()
+    xi, t, _, _ = _d3q19()
+    rows = []
+    for line in open(os.path.join(GOLDEN, "d3q19_equilibrium_moments.txt")):
+        if line.strip() and not line.startswith("#"):
+            rows.append(line.split())
+    assert len(rows) == 19
+    rng = np.random.default_rng(11)
+    for _ in range(4):
+        rho = 1 + 0.1 * rng.standard_normal()
+        j = 0.05 * rng.standard_normal(3)
+        feq = t * (rho + 3 * xi @ j + 4.5 * (xi @ j) ** 2 - 1.5 * j @ j)
+        m = M @ feq
+        jj = j @ j
+        for k, r in enumerate(rows):
+            if r[1] == "product":
+                a, b = ("xyz".index(r[2][1]), "xyz".index(r[3][1]))
+                want = j[a] * j[b]
+            else:
+                c = [float(x) for x in r[1:]]
+                want = (c[0] * rho + c[1] * jj + c[2] * j[0] + c[3] * j[1] + c[4] * j[2]
+                        + c[5] * (3 * j[0] ** 2 - jj) + c[6] * (j[1] ** 2 - j[2] ** 2))
+            assert abs(m[k] - want) <= 1e-14, (r[0], m[k], want)
