@@ -406,6 +406,73 @@ lbm_status lbm_pool_autotune(lbm_pool* pool, int32_t trial_steps, int32_t* grid)
 /* Retire every member and free the pool. NULL is accepted. */
 lbm_status lbm_pool_destroy(lbm_pool* pool);
 
+/* ---- Image pre-processing (section "Initial conditions and wetting maps": morphological
+ * drainage and the mixed-wet relabelling; section "Simulation protocol for steady-state flow":
+ * the mixing region at the inlet and outlet). These turn a segmented image into the labels and
+ * initial fluids of lbm_domain_create. Dense host images in and out (index x + nx*(y + ny*z));
+ * the work runs on the current HIP device, on hip_stream (nullable: the null stream), with
+ * device memory the call allocates and frees itself; every call is synchronous. Distances are
+ * Euclidean between voxel centres, handled squared as exact integers. Sizes: 1 <= nx, ny, nz
+ * <= 16384 and nx*ny*nz < 2^31. Errors: LBM_ERR_ARG (sizes, values), LBM_ERR_OOM,
+ * LBM_ERR_DEVICE (no device, or a HIP call failed). */
+
+/* Squared Euclidean distance transform: dist_sq[v] = min |v - w|^2 over the voxels w with
+ * feature[w] != 0, counting periodic images on axes with periodic[a] != 0; bit a of wall_axes
+ * (1: x, 2: y, 4: z) adds a plane of feature voxels just outside both faces of that axis when
+ * it is not periodic. dist_sq[v] = -1 where there is no feature at all. */
+lbm_status lbm_prep_distance(int32_t nx, int32_t ny, int32_t nz, const int32_t periodic[3],
+                             int32_t wall_axes, const uint8_t* feature, int32_t* dist_sq,
+                             void* hip_stream);
+
+typedef struct {
+    double target_sw;   /* water (wetting-fluid) saturation to reach, in [0, 1)              */
+    int32_t inlet;      /* 1: only sphere centres connected through face-adjacent centres to */
+                        /* the z = 0 plane count (needs periodic[2] == 0); 0: every centre   */
+    int32_t pad_;
+} lbm_drain_params;
+
+typedef struct {
+    int32_t radius_sq;      /* chosen k = R^2                                                */
+    int32_t max_radius_sq;  /* largest D^2 over the pore voxels                              */
+    int32_t evaluations;    /* drainage evaluations the radius search made                    */
+    int32_t pad_;
+    int64_t n_pore, n_nw;   /* pore voxels; voxels given to the non-wetting fluid             */
+    double sw;              /* 1 - n_nw / n_pore                                             */
+} lbm_drain_result;
+
+/* Morphological drainage (the sphere-placing operation of Adalsteinsson and Hilpert, 2006,
+ * which the paper uses for its initial fluid configurations). D(x) is the distance from pore
+ * voxel x to the nearest solid voxel (pore[x] == 0), or to a plane of wall voxels just outside
+ * each non-periodic face (except the two z faces when dp->inlet is set: those border the fluid
+ * reservoirs). A sphere of radius R = sqrt(k) fits at x when D^2(x) >= k; the non-wetting
+ * region is every pore voxel closer than R to a fitting centre (with dp->inlet, to a centre
+ * connected to the z = 0 plane). k is the largest integer in [1, max D^2] whose water
+ * saturation 1 - |nw| / |pore| is <= dp->target_sw, found by bisection over k; k = 1 when none
+ * is. On success nw[nx*ny*nz] holds 1 on the non-wetting voxels and 0 elsewhere, and *out the
+ * radius and counts. Extra errors: LBM_ERR_ARG with no pore voxel, or with neither a solid voxel
+ * nor a wall (unbounded distances). */
+lbm_status lbm_prep_drain(int32_t nx, int32_t ny, int32_t nz, const int32_t periodic[3],
+                          const uint8_t* pore, const lbm_drain_params* dp, uint8_t* nw,
+                          lbm_drain_result* out, void* hip_stream);
+
+/* Mixed-wet relabelling: labels_out = labels, except that every solid voxel (label_kind of its
+ * label == LBM_LABEL_SOLID) whose distance to the nearest voxel with nw != 0 (periodic images on
+ * periodic axes) is at most dist takes new_label (the paper relabels within 2 voxel units of the
+ * oil). labels in [0, n_labels); new_label >= 0 (it may be a label not yet in the table);
+ * 0 <= dist <= 16384. labels_out may equal labels. */
+lbm_status lbm_prep_relabel(int32_t nx, int32_t ny, int32_t nz, const int32_t periodic[3],
+                            const int32_t* labels, int32_t n_labels, const int8_t* label_kind,
+                            const uint8_t* nw, double dist, int32_t new_label,
+                            int32_t* labels_out, void* hip_stream);
+
+/* Mixing region along z: labels_out = labels, except that in the first nmix planes a solid
+ * voxel takes pore_label where the last plane (z = nz-1) of labels is pore at the same (x, y),
+ * and in the last nmix planes where the first plane (z = 0) is pore. 0 <= nmix <= nz;
+ * pore_label in [0, n_labels) with a pore kind. labels_out may equal labels. */
+lbm_status lbm_prep_mixing_layer(int32_t nx, int32_t ny, int32_t nz, const int32_t* labels,
+                                 int32_t n_labels, const int8_t* label_kind, int32_t nmix,
+                                 int32_t pore_label, int32_t* labels_out, void* hip_stream);
+
 /* Message of the calling thread's last error ("" if none). Valid until its next call. */
 const char* lbm_last_error(void);
 

@@ -30,6 +30,7 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
            "lbm_pool_destroy", "lbm_pool_set_order", "lbm_set_force", "lbm_run_steady",
            "lbm_morph", "lbm_phase_volume", "lbm_shell_aggregate",
+           "lbm_prep_distance", "lbm_prep_drain", "lbm_prep_relabel", "lbm_prep_mixing_layer",
            "lbm_last_error", "lbm_version")
 
 
@@ -113,6 +114,17 @@ class ShellResult(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("reached", ctypes.c_int32),
                 ("steps", ctypes.c_int64), ("volume_start", ctypes.c_int64),
                 ("volume_end", ctypes.c_int64), ("deltas", ctypes.c_double * SHELL_MAX_DELTAS)]
+
+
+class DrainParams(ctypes.Structure):
+    _fields_ = [("target_sw", ctypes.c_double), ("inlet", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+class DrainResult(ctypes.Structure):
+    _fields_ = [("radius_sq", ctypes.c_int32), ("max_radius_sq", ctypes.c_int32),
+                ("evaluations", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("n_pore", ctypes.c_int64), ("n_nw", ctypes.c_int64), ("sw", ctypes.c_double)]
 
 
 class Timing(ctypes.Structure):
@@ -205,6 +217,13 @@ def load_library(path: str = LIB_PATH):
     L.lbm_pool_set_order.argtypes = [vp, i32]
     L.lbm_pool_destroy.argtypes = [vp]
     L.lbm_pool_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    i32p = ctypes.POINTER(i32)
+    L.lbm_prep_distance.argtypes = [i32, i32, i32, i32p, i32, vp, vp, vp]
+    L.lbm_prep_drain.argtypes = [i32, i32, i32, i32p, vp, ctypes.POINTER(DrainParams), vp,
+                                 ctypes.POINTER(DrainResult), vp]
+    L.lbm_prep_relabel.argtypes = [i32, i32, i32, i32p, vp, i32, vp, vp, ctypes.c_double, i32,
+                                   vp, vp]
+    L.lbm_prep_mixing_layer.argtypes = [i32, i32, i32, vp, i32, vp, i32, i32, vp, vp]
     L.lbm_last_error.restype = ctypes.c_char_p
     L.lbm_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -537,3 +556,71 @@ class Pool:
             self.close()
         except Exception:
             pass
+
+
+# ---- Image pre-processing (lbm_prep_*): dense [z, y, x] host arrays in and out. -------------
+
+def _periodic3(periodic):
+    return (ctypes.c_int32 * 3)(*[1 if p else 0 for p in periodic])
+
+
+def _stream_handle(stream):
+    return None if stream is None else ctypes.c_void_p(stream)
+
+
+def prep_distance(feature: np.ndarray, periodic=(False, False, False), wall_axes: int = 0,
+                  stream=None) -> np.ndarray:
+    """Squared Euclidean distance to the nearest nonzero voxel of feature (int32, -1 where
+    there is none); wall_axes bit a adds wall planes outside non-periodic axis a."""
+    f = np.ascontiguousarray(feature, dtype=np.uint8)
+    nz, ny, nx = f.shape
+    out = np.empty(f.shape, dtype=np.int32)
+    _check(load_library().lbm_prep_distance(nx, ny, nz, _periodic3(periodic), int(wall_axes),
+                                            _ptr(f), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def prep_drain(pore: np.ndarray, periodic=(False, False, False), target_sw: float = 0.5,
+               inlet: bool = False, stream=None):
+    """Morphological drainage to a target water saturation; returns (nw mask, result dict)."""
+    m = np.ascontiguousarray(pore, dtype=np.uint8)
+    nz, ny, nx = m.shape
+    nw = np.empty(m.shape, dtype=np.uint8)
+    dp = DrainParams(float(target_sw), 1 if inlet else 0, 0)
+    r = DrainResult()
+    _check(load_library().lbm_prep_drain(nx, ny, nz, _periodic3(periodic), _ptr(m),
+                                         ctypes.byref(dp), _ptr(nw), ctypes.byref(r),
+                                         _stream_handle(stream)))
+    return nw.astype(bool), {"k": r.radius_sq, "kmax": r.max_radius_sq,
+                             "evaluations": r.evaluations, "n_pore": r.n_pore,
+                             "n_nw": r.n_nw, "sw": r.sw}
+
+
+def prep_relabel(labels: np.ndarray, label_kind: np.ndarray, nw: np.ndarray,
+                 periodic=(False, False, False), dist: float = 2.0, new_label: int = 0,
+                 stream=None) -> np.ndarray:
+    """Solid voxels within dist of the non-wetting mask take new_label."""
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    kind = np.ascontiguousarray(label_kind, dtype=np.int8)
+    m = np.ascontiguousarray(nw, dtype=np.uint8)
+    if m.shape != lab.shape:
+        raise ValueError("nw and labels differ in shape")
+    nz, ny, nx = lab.shape
+    out = np.empty(lab.shape, dtype=np.int32)
+    _check(load_library().lbm_prep_relabel(nx, ny, nz, _periodic3(periodic), _ptr(lab),
+                                           len(kind), _ptr(kind), _ptr(m), float(dist),
+                                           int(new_label), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def prep_mixing_layer(labels: np.ndarray, label_kind: np.ndarray, nmix: int, pore_label: int,
+                      stream=None) -> np.ndarray:
+    """Open the first and last nmix z planes where the opposite face is pore."""
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    kind = np.ascontiguousarray(label_kind, dtype=np.int8)
+    nz, ny, nx = lab.shape
+    out = np.empty(lab.shape, dtype=np.int32)
+    _check(load_library().lbm_prep_mixing_layer(nx, ny, nz, _ptr(lab), len(kind), _ptr(kind),
+                                                int(nmix), int(pore_label), _ptr(out),
+                                                _stream_handle(stream)))
+    return out
