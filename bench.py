@@ -120,6 +120,37 @@ def morph_study(prob, args, torch, lbm) -> dict:
             "last": res}
 
 
+def prep_study(prob, lbm) -> dict:
+    """Wall time of the image pre-processing calls on the workload's image: morphological
+    drainage to Sw = 0.5 (from the z = 0 plane when z is not periodic), the distance transform
+    of the solid, the mixed-wet relabelling within 2 voxels of the drained fluid and a mixing
+    layer of 4 planes. The calls take host images, so each time includes the PCIe copies and the
+    call's own device allocations; rocprofv3 gives the kernel times."""
+    from paper_2007_12266_amd import inputs
+    pore = prob.label_kind[prob.labels] != inputs.KIND_SOLID
+    per = tuple(bool(p) for p in prob.periodic)
+    inlet = not per[2]
+
+    def best_of(fn, reps=3):
+        out, times = None, []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            times.append(time.perf_counter() - t0)
+        return out, round(min(times) * 1e3, 2)
+
+    (nw, r), t_drain = best_of(lambda: lbm.prep_drain(pore, per, 0.5, inlet=inlet))
+    log("prep: drainage k=%d sw=%.4f in %.1f ms" % (r["k"], r["sw"], t_drain))
+    _, t_dist = best_of(lambda: lbm.prep_distance(~pore, per, wall_axes=0 if inlet else 7))
+    new_label = len(prob.label_kind)
+    relab, t_rel = best_of(lambda: lbm.prep_relabel(prob.labels, prob.label_kind, nw, per, 2.0,
+                                                     new_label))
+    _, t_mix = best_of(lambda: lbm.prep_mixing_layer(prob.labels, prob.label_kind, 4, 1))
+    return {"voxels": int(pore.size), "inlet": inlet, "drain": r, "ms_drain": t_drain,
+            "ms_distance": t_dist, "ms_relabel": t_rel, "ms_mixing_layer": t_mix,
+            "relabelled": int((relab == new_label).sum())}
+
+
 def precision_study(prob, steps: int, every: int, torch, lbm) -> dict:
     """FP32-deviation against FP64 on the same problem: both advance side by side and every
     `every` steps the saturation, the Darcy flux and the front position are compared."""
@@ -387,6 +418,9 @@ def main():
     ap.add_argument("--morph-study", action="store_true",
                     help="also time the morphological growth step (dilation by 0.5 voxel) "
                          "and the phase-volume count on the same workload")
+    ap.add_argument("--prep-study", action="store_true",
+                    help="also time the image pre-processing calls (drainage, distance "
+                         "transform, relabelling, mixing layer) on the workload's image")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="also run FP32-deviation beside FP64 for STEPS steps from the initial "
                          "state, comparing Sw, Darcy flux and front position every 100 steps")
@@ -501,6 +535,8 @@ def main():
         out["fp32_vs_fp64"] = precision_study(prob, args.precision_study, 100, torch, lbm)
     if args.morph_study:
         out["morph"] = morph_study(prob, args, torch, lbm)
+    if args.prep_study:
+        out["prep"] = prep_study(prob, lbm)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         sample = prob if wl["n"] <= 256 else make_problem(wl, n=256)

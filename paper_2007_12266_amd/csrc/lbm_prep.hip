@@ -9,16 +9,24 @@
 // min over (y', z') of [g(x; y', z')^2 + (y - y')^2 + (z - z')^2], g the distance along the
 // row. The row pass finds g from the rows packed as 64-voxel bit words (find-first-set on whole
 // words); the y and z passes search outward from each voxel and stop once d^2 reaches the best
-// value so far, which is exact because every candidate at offset d costs at least d^2. With a
-// cap c (only distances below c matter) every value is clipped at c and the searches stop at c.
-// Coordinates are int32, squared distances int32 with kInf = 2^30 - 1 for "none": sizes up to
-// 16384 keep kInf + n^2 below 2^31.
+// value so far, which is exact because every candidate at offset d costs at least d^2. The
+// first four offsets are loaded together so that the common short search is one round trip.
+// With a cap c (only distances below c matter) every value is clipped at c and the searches
+// stop at c. Squared distances are int32 with kInf = 2^30 - 1 for "none": sizes up to 16384
+// keep kInf + n^2 below 2^31.
 //
-// Connectivity of the sphere centres to the inlet plane: reach bits start at the centres of
-// the z = 0 plane and grow to a fixed point by fills along x (carry propagation through runs of
-// set bits inside a word, words in order), then along y and z (one thread per column of words,
-// sweeping up and down). Each round's popcount (fixed grid, fixed order) tells when the set
-// stops growing. All reductions are deterministic.
+// Per-voxel kernels run on a 2-D grid: blockIdx.x is the image row (y, z), blockIdx.y the
+// chunk of x, so no thread divides a 64-bit index. Bit rows are packed by one wave per 64-voxel
+// word with a ballot.
+//
+// Connectivity of the sphere centres to the inlet plane: union-find labelling. Every centre
+// starts under the first voxel of its run of centres along x; runs that touch across a -y or
+// -z face (or the periodic x face) are united by linking the larger root under the smaller
+// with atomicMin, retrying from the new parent when another thread linked first. A parent index is never larger than its child,
+// so every find walks a strictly decreasing chain and ends. After the merges each label is
+// replaced by its root, the roots of the z = 0 plane are flagged, and a centre is reached when
+// its root is flagged. Counts use fixed-shape block sums and a fixed-order final sum, so every
+// result is deterministic.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -35,23 +43,41 @@ constexpr int32_t kInf = 0x3fffffff;
 constexpr int kMaxDim = 16384;
 constexpr int kPrepBlocks = 512;
 constexpr int kPrepThreads = 256;
-constexpr int kMaxRounds = 1 << 20;
+constexpr int kSumThreads = 1024;
 
 struct Box {
     int nx, ny, nz, W;   // W: 64-bit words per row
     int64_t nvox;        // nx*ny*nz
     int64_t nwords;      // ny*nz*W
     int per;             // bit a: axis a periodic
+    int tpb;             // threads per workgroup of the per-voxel kernels
+    int chunks;          // workgroups per row
 };
-
-int grid_for(int64_t n, int threads = 256) {
-    return (int)((n + threads - 1) / threads);
-}
 
 // ---------------------------------------------------------------------------------------------
 // Kernels
 
-// One 64-voxel word of a row per thread: bit b of word w of row r is pred(r*nx + 64w + b).
+// The voxel of this thread in the 2-D grid of the per-voxel kernels.
+struct VoxelIdx {
+    int64_t v;
+    int row, x;
+    bool active;
+};
+
+__device__ __forceinline__ VoxelIdx voxel_of(const Box& b) {
+    VoxelIdx r;
+    r.row = (int)blockIdx.x;
+    r.x = (int)blockIdx.y * (int)blockDim.x + (int)threadIdx.x;
+    r.active = r.x < b.nx;
+    r.v = (int64_t)r.row * b.nx + r.x;
+    return r;
+}
+
+__device__ __forceinline__ bool bit_at(const uint64_t* __restrict__ bits, const Box& b, int row,
+                                       int x) {
+    return (bits[(int64_t)row * b.W + (x >> 6)] >> (x & 63)) & 1ull;
+}
+
 struct FeatureNonzero {
     const uint8_t* m;
     __device__ bool operator()(int64_t v) const { return m[v] != 0; }
@@ -66,18 +92,37 @@ struct FeatureCentre {   // pore voxel where a sphere of squared radius k fits
     int32_t k;
     __device__ bool operator()(int64_t v) const { return pore[v] != 0 && d2[v] >= k; }
 };
+struct FeatureReached {  // centre whose component touches the z = 0 plane
+    const int32_t* label;
+    const uint8_t* flag;
+    __device__ bool operator()(int64_t v) const {
+        const int32_t l = label[v];
+        return l >= 0 && flag[l] != 0;
+    }
+};
+
+// Four consecutive 64-voxel words per wave (their loads in flight together): lane i holds bit i
+// of each (x = 64 w + i of the word's row).
+constexpr int kWordsPerWave = 4;
 
 template <typename P>
 __global__ void __launch_bounds__(256) pack_kernel(Box b, P pred, uint64_t* __restrict__ bits) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= b.nwords) return;
-    const int64_t row = k / b.W;
-    const int w = (int)(k % b.W);
-    const int64_t v0 = row * b.nx + 64 * w;
-    const int nb = min(64, b.nx - 64 * w);
-    uint64_t m = 0;
-    for (int i = 0; i < nb; ++i) m |= (uint64_t)(pred(v0 + i) ? 1 : 0) << i;
-    bits[k] = m;
+    const int64_t word0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kWordsPerWave;
+    const int lane = threadIdx.x & 63;
+    if (word0 >= b.nwords) return;   // the whole wave
+    bool p[kWordsPerWave];
+#pragma unroll
+    for (int j = 0; j < kWordsPerWave; ++j) {
+        const int64_t word = word0 + j;
+        const int row = (int)(word / b.W);
+        const int x = 64 * (int)(word - (int64_t)row * b.W) + lane;
+        p[j] = word < b.nwords && x < b.nx && pred((int64_t)row * b.nx + x);
+    }
+#pragma unroll
+    for (int j = 0; j < kWordsPerWave; ++j) {
+        const uint64_t m = __ballot(p[j]);
+        if (lane == j && word0 + j < b.nwords) bits[word0 + j] = m;
+    }
 }
 
 // First set bit at a position in [p, e] of a row (p <= e), or -1.
@@ -113,65 +158,80 @@ __device__ __forceinline__ int last_set(const uint64_t* __restrict__ r, int s, i
 }
 
 // Row pass: out[v] = min(g^2, cap), g = distance along x to the nearest feature bit in the
-// row (wrapping when x is periodic), searched to at most `lim` voxels.
+// row (wrapping when x is periodic), searched to at most `lim` voxels. The words w-1, w, w+1
+// around x are read together and settle almost every voxel; the full word-by-word search runs
+// only for a direction they leave open.
 __global__ void __launch_bounds__(256) edt_row_kernel(Box b, const uint64_t* __restrict__ bits,
                                                       int lim, int32_t cap,
                                                       int32_t* __restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= b.nvox) return;
-    const int64_t row = v / b.nx;
-    const int x = (int)(v - row * b.nx);
-    const uint64_t* r = bits + row * b.W;
+    const VoxelIdx t = voxel_of(b);
+    if (!t.active) return;
+    const uint64_t* r = bits + (int64_t)t.row * b.W;
     const bool per = (b.per & 1) != 0;
-    const int nx = b.nx;
+    const int nx = b.nx, x = t.x;
+    const int w = x >> 6, sh = x & 63;
+    const uint64_t cur = r[w];
+    const uint64_t lo = w > 0 ? r[w - 1] : 0ull;
+    const uint64_t hi = w + 1 < b.W ? r[w + 1] : 0ull;
     int d = kInf;
-    int q = first_set(r, x, min(nx - 1, x + lim));
-    if (q >= 0) {
-        d = q - x;
-    } else if (per && x + lim >= nx && x > 0) {
-        q = first_set(r, 0, min(x - 1, x + lim - nx));
-        if (q >= 0) d = q + nx - x;
+    bool right_open = false, left_open = false;
+    // right: bits >= x in this word, then the next word
+    const uint64_t rc = cur >> sh;
+    if (rc) {
+        d = __ffsll((long long)rc) - 1;
+    } else if (hi) {
+        d = 64 - sh + __ffsll((long long)hi) - 1;
+    } else {
+        right_open = true;
     }
-    q = last_set(r, max(0, x - lim), x);
-    if (q >= 0) {
-        d = min(d, x - q);
-    } else if (per && x - lim < 0 && x < nx - 1) {
-        q = last_set(r, max(x + 1, x - lim + nx), nx - 1);
-        if (q >= 0) d = min(d, x + nx - q);
+    // left: bits <= x in this word, then the previous word
+    const uint64_t lc = sh == 63 ? cur : (cur & ((1ull << (sh + 1)) - 1ull));
+    if (lc) {
+        d = min(d, sh - (63 - __clzll((long long)lc)));
+    } else if (lo) {
+        d = min(d, sh + 1 + __clzll((long long)lo));
+    } else {
+        left_open = true;
     }
-    out[v] = d == kInf ? cap : min(d * d, cap);
+    // A hit is the nearest feature on its side without wrapping, so it is never worse than a
+    // wrapped one on that side; a hit beyond lim gives d^2 > cap (capped) or is matched by the
+    // search on the other side (periodic), so the result is min(d^2, cap) either way. An open
+    // side is searched in full only when what lies beyond the window (a further word, or the
+    // wrap through the periodic face) is within the limit and could still be nearer than d.
+    int rb = w + 1 < b.W ? 128 - sh : kInf;
+    int lb = w > 0 ? sh + 65 : kInf;
+    if (per) {
+        rb = min(rb, nx - x);
+        lb = min(lb, x + 1);
+    }
+    if (right_open && rb <= lim && d > rb) {
+        int q = first_set(r, x, min(nx - 1, x + lim));
+        if (q >= 0) {
+            d = min(d, q - x);
+        } else if (per && x + lim >= nx && x > 0) {
+            q = first_set(r, 0, min(x - 1, x + lim - nx));
+            if (q >= 0) d = min(d, q + nx - x);
+        }
+    }
+    if (left_open && lb <= lim && d > lb) {
+        int q = last_set(r, max(0, x - lim), x);
+        if (q >= 0) {
+            d = min(d, x - q);
+        } else if (per && x - lim < 0 && x < nx - 1) {
+            q = last_set(r, max(x + 1, x - lim + nx), nx - 1);
+            if (q >= 0) d = min(d, x + nx - q);
+        }
+    }
+    out[t.v] = d >= kInf ? cap : min(d * d, cap);
 }
 
-// Line pass along axis `ax` (1: y, 2: z): out[v] = min(cap, min_d in[v + d e_ax] + d^2), and
-// with `walls` also the squared distances to the wall planes outside every non-periodic axis in
-// the mask.
-__global__ void __launch_bounds__(256) edt_line_kernel(Box b, int ax, int32_t cap, int walls,
-                                                       const int32_t* __restrict__ in,
-                                                       int32_t* __restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= b.nvox) return;
-    const int64_t plane = (int64_t)b.nx * b.ny;
-    const int z = (int)(v / plane);
-    const int64_t rem = v - (int64_t)z * plane;
-    const int y = (int)(rem / b.nx);
-    const int x = (int)(rem - (int64_t)y * b.nx);
-    const int n = ax == 1 ? b.ny : b.nz;
-    const int c = ax == 1 ? y : z;
-    const int64_t stride = ax == 1 ? (int64_t)b.nx : plane;
-    const bool per = ((b.per >> ax) & 1) != 0;
-    const int64_t base = v - (int64_t)c * stride;
-    int best = in[v];
-    if (walls) {
-        const int cx[3] = {x, y, z};
-        const int nn[3] = {b.nx, b.ny, b.nz};
-        for (int a = 0; a < 3; ++a)
-            if (((walls >> a) & 1) && !((b.per >> a) & 1)) {
-                const int lo = cx[a] + 1, hi = nn[a] - cx[a];
-                best = min(best, min(lo * lo, hi * hi));
-            }
-    }
+// Continues min over d >= d0 of in[base + ((c + d) mod n) stride] + d^2 (offsets outside a
+// non-periodic line are skipped) from `best`, stopping once d^2 reaches best.
+__device__ __forceinline__ int line_min_from(const int32_t* __restrict__ in, int64_t base,
+                                             int64_t stride, int c, int n, bool per, int best,
+                                             int d0) {
     const int lim = per ? n / 2 : max(c, n - 1 - c);
-    for (int d = 1; d <= lim; ++d) {
+    for (int d = d0; d <= lim; ++d) {
         const int d2 = d * d;
         if (d2 >= best) break;
         int a = c + d, e = c - d;
@@ -180,138 +240,208 @@ __global__ void __launch_bounds__(256) edt_line_kernel(Box b, int ax, int32_t ca
         if (a >= 0) best = min(best, in[base + (int64_t)a * stride] + d2);
         if (e >= 0) best = min(best, in[base + (int64_t)e * stride] + d2);
     }
-    out[v] = min(best, cap);
+    return best;
 }
 
-// Reach bits of the centres in the z = 0 plane.
-__global__ void __launch_bounds__(256) seed_kernel(Box b, const uint64_t* __restrict__ centre,
-                                                   uint64_t* __restrict__ reach) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= b.nwords) return;
-    reach[k] = k < (int64_t)b.ny * b.W ? centre[k] : 0ull;
+__device__ __forceinline__ int wall_min(const Box& b, int walls, int x, int y, int z, int best) {
+    const int cx[3] = {x, y, z};
+    const int nn[3] = {b.nx, b.ny, b.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (((walls >> a) & 1) && !((b.per >> a) & 1)) {
+            const int lo = cx[a] + 1, hi = nn[a] - cx[a];
+            best = min(best, min(lo * lo, hi * hi));
+        }
+    return best;
 }
 
-// Fills bits of m upward (towards bit 63) from the seeds s (s inside m): every run of set bits
-// of m that holds a seed becomes set from its lowest seed on. Adding s to m carries from each
-// seed through the end of its run; the bits that flipped inside m are the filled ones.
-__device__ __forceinline__ uint64_t fill_up(uint64_t m, uint64_t s) {
-    return (((m + s) ^ m) & m) | s;
-}
+// Line pass along axis `ax` (1: y, 2: z) over kSeg consecutive positions c0 .. c0+kSeg-1 of one
+// line per thread: the window in[c0-4 .. c0+kSeg+3] is read at once, so offsets up to 4 cost no
+// further load, and larger ones (only where the best value so far exceeds 25) continue from
+// memory. A window value of a wrapped position further than half a period is an upper bound of
+// that position's term, never below the minimum, so it may stay in.
+//   MODE 0: out[v] = min(cap, best), with the wall-plane terms of `walls`;
+//   MODE 1 (z pass of the drainage dilation): a pore voxel is non-wetting when best < cap (the
+//           squared radius); writes nw when it is not null and the count of each workgroup
+//           (kPrepThreads threads).
+constexpr int kSeg = 8;
 
-__device__ __forceinline__ void row_fill(const uint64_t* __restrict__ cm, uint64_t* __restrict__ rr,
-                                         int W) {
-    uint64_t carry = 0;
-    for (int w = 0; w < W; ++w) {
-        const uint64_t m = cm[w];
-        const uint64_t f = fill_up(m, (rr[w] | carry) & m);
-        rr[w] = f;
-        carry = f >> 63;
-    }
-    carry = 0;
-    for (int w = W - 1; w >= 0; --w) {
-        const uint64_t m = __builtin_bitreverse64(cm[w]);
-        const uint64_t f = fill_up(m, (__builtin_bitreverse64(rr[w]) | carry) & m);
-        rr[w] = __builtin_bitreverse64(f);
-        carry = f >> 63;
-    }
-}
-
-// Fill along x: one thread per row.
-__global__ void __launch_bounds__(256) fill_x_kernel(Box b, const uint64_t* __restrict__ centre,
-                                                     uint64_t* __restrict__ reach) {
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= (int64_t)b.ny * b.nz) return;
-    const uint64_t* cm = centre + row * b.W;
-    uint64_t* rr = reach + row * b.W;
-    row_fill(cm, rr, b.W);
-    if (b.per & 1) {
-        // A run through the periodic x face: seed each end from the other, fill again.
-        const int lw = (b.nx - 1) >> 6, lb = (b.nx - 1) & 63;
-        const bool first = rr[0] & 1ull, last = (rr[lw] >> lb) & 1ull;
-        if (last && (cm[0] & 1ull)) rr[0] |= 1ull;
-        if (first && ((cm[lw] >> lb) & 1ull)) rr[lw] |= 1ull << lb;
-        row_fill(cm, rr, b.W);
-    }
-}
-
-// Sweep of one column of words along y (ax == 1) or z (ax == 2), up then down; on a periodic
-// axis each direction continues once more through the face while it still changes something.
-__global__ void __launch_bounds__(256) sweep_kernel(Box b, int ax,
-                                                    const uint64_t* __restrict__ centre,
-                                                    uint64_t* __restrict__ reach) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int other = ax == 1 ? b.nz : b.ny;
-    if (t >= (int64_t)b.W * other) return;
-    const int w = (int)(t % b.W);
-    const int o = (int)(t / b.W);
+template <int MODE>
+__global__ void __launch_bounds__(256) edt_seg_kernel(Box b, int ax, int32_t cap, int walls,
+                                                      const int32_t* __restrict__ in,
+                                                      int32_t* __restrict__ out,
+                                                      const uint8_t* __restrict__ pore,
+                                                      uint8_t* __restrict__ nw,
+                                                      int* __restrict__ part) {
+    const int x = (int)blockIdx.y * (int)blockDim.x + (int)threadIdx.x;
+    const bool active = x < b.nx;
     const int n = ax == 1 ? b.ny : b.nz;
-    const int64_t stride = ax == 1 ? (int64_t)b.W : (int64_t)b.W * b.ny;
-    const int64_t base = ax == 1 ? (int64_t)o * b.ny * b.W + w : (int64_t)o * b.W + w;
+    const int nseg = (n + kSeg - 1) / kSeg;
+    const int seg = (int)blockIdx.x % nseg;
+    const int o = (int)blockIdx.x / nseg;   // z when ax == 1, y when ax == 2
+    const int64_t stride = ax == 1 ? (int64_t)b.nx : (int64_t)b.nx * b.ny;
+    const int64_t base = ax == 1 ? (int64_t)o * b.ny * b.nx + x : (int64_t)o * b.nx + x;
     const bool per = ((b.per >> ax) & 1) != 0;
-    for (int dir = 0; dir < 2; ++dir) {
-        const int step = dir == 0 ? 1 : -1;
-        int c = dir == 0 ? 0 : n - 1;
-        uint64_t prev = reach[base + (int64_t)c * stride];
-        for (int i = 1; i < n; ++i) {
-            c += step;
-            const int64_t k = base + (int64_t)c * stride;
-            const uint64_t r = reach[k] | (centre[k] & prev);
-            reach[k] = r;
-            prev = r;
+    const int c0 = seg * kSeg;
+    int cnt = 0;
+    if (active) {
+        int win[kSeg + 8];
+#pragma unroll
+        for (int j = 0; j < kSeg + 8; ++j) {
+            int c = c0 - 4 + j;
+            if (c < 0 || c >= n) c = per ? ((c % n) + n) % n : -1;
+            win[j] = c >= 0 ? in[base + (int64_t)c * stride] : kInf;
         }
-        if (!per) continue;
-        for (int i = 0; i < n; ++i) {
-            c += step;
-            if (c == n) c = 0;
-            if (c < 0) c = n - 1;
-            const int64_t k = base + (int64_t)c * stride;
-            const uint64_t old = reach[k];
-            const uint64_t r = old | (centre[k] & prev);
-            if (r == old) break;
-            reach[k] = r;
-            prev = r;
+#pragma unroll
+        for (int i = 0; i < kSeg; ++i) {
+            const int c = c0 + i;
+            if (c >= n) break;
+            const int64_t v = base + (int64_t)c * stride;
+            if (MODE == 1 && !pore[v]) {
+                if (nw) nw[v] = 0;
+                continue;
+            }
+            int best = win[i + 4];
+            if (walls) best = wall_min(b, walls, x, ax == 1 ? c : o, ax == 1 ? o : c, best);
+#pragma unroll
+            for (int d = 1; d <= 4; ++d)
+                best = min(best, min(win[i + 4 + d], win[i + 4 - d]) + d * d);
+            if (best > 25) best = line_min_from(in, base, stride, c, n, per, best, 5);
+            if (MODE == 0) {
+                out[v] = min(best, cap);
+            } else {
+                const bool f = best < cap;
+                cnt += f ? 1 : 0;
+                if (nw) nw[v] = f ? 1 : 0;
+            }
+        }
+    }
+    if (MODE == 1) {
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+        __shared__ int ws[kPrepThreads / 64];
+        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int i = 0; i < kPrepThreads / 64; ++i) t += ws[i];
+            part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
         }
     }
 }
 
-// Popcount of the reach bits: per-block partial sums in a fixed order.
-__global__ void __launch_bounds__(kPrepThreads) popcount_kernel(int64_t n,
-                                                               const uint64_t* __restrict__ bits,
-                                                               long long* __restrict__ part) {
-    __shared__ long long sh[kPrepThreads];
+// Fixed-order sum of n partial counts (one workgroup of kSumThreads threads).
+__global__ void __launch_bounds__(kSumThreads) sum_kernel(const int* __restrict__ part,
+                                                          int64_t n, long long* __restrict__ out) {
+    __shared__ long long sh[kSumThreads];
     long long s = 0;
-    for (int64_t k = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x; k < n;
-         k += (int64_t)kPrepBlocks * kPrepThreads)
-        s += __popcll(bits[k]);
+    for (int64_t i = threadIdx.x; i < n; i += kSumThreads) s += part[i];
     sh[threadIdx.x] = s;
     __syncthreads();
-    for (int h = kPrepThreads / 2; h > 0; h >>= 1) {
+    for (int h = kSumThreads / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) out[0] = sh[0];
 }
 
-// Non-wetting voxels for squared radius k (pore voxels with e2 < k), written to nw when it is
-// not null, and their count per block.
-__global__ void __launch_bounds__(kPrepThreads) drain_count_kernel(
-    int64_t n, const uint8_t* __restrict__ pore, const int32_t* __restrict__ e2, int32_t k,
-    uint8_t* __restrict__ nw, long long* __restrict__ part) {
-    __shared__ long long sh[kPrepThreads];
-    long long s = 0;
-    for (int64_t v = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x; v < n;
-         v += (int64_t)kPrepBlocks * kPrepThreads) {
-        const bool in = pore[v] != 0 && e2[v] < k;
-        s += in ? 1 : 0;
-        if (nw) nw[v] = in ? 1 : 0;
+// ---- union-find labelling of the centres
+
+__device__ __forceinline__ int32_t label_load(const int32_t* L, int32_t i) {
+    return __hip_atomic_load(L + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of i: parents are never larger than their children, so the walk strictly decreases.
+__device__ __forceinline__ int32_t find_root(const int32_t* L, int32_t i) {
+    int32_t p = label_load(L, i);
+    while (p != i) {
+        i = p;
+        p = label_load(L, i);
     }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = kPrepThreads / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-        __syncthreads();
+    return i;
+}
+
+// Link the components of centres a and b (the larger root goes under the smaller). A failed
+// link means another thread gave the root a parent first; the loop continues from there.
+__device__ void unite(int32_t* L, int32_t a, int32_t b) {
+    while (true) {
+        a = find_root(L, a);
+        b = find_root(L, b);
+        if (a == b) return;
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        const int32_t old = atomicMin(L + b, a);
+        if (old == b) return;
+        b = old;
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// First voxel of the run of consecutive centres along x (within the row, no wrap) that
+// holds x: one past the last non-centre before x, or 0.
+__device__ __forceinline__ int run_start(const uint64_t* __restrict__ r, int x) {
+    int w = x >> 6;
+    const int sh = x & 63;
+    uint64_t m = sh ? (~r[w] & ((1ull << sh) - 1ull)) : 0ull;
+    while (!m && w > 0) m = ~r[--w];
+    if (!m) return 0;
+    return (w << 6) + 64 - __clzll((long long)m);
+}
+
+// Every centre starts under the first voxel of its run along x (a parent no larger than the
+// child), so a run is one component before any union.
+__global__ void __launch_bounds__(256) ccl_init_kernel(Box b, const uint64_t* __restrict__ centre,
+                                                       int32_t* __restrict__ L) {
+    const VoxelIdx t = voxel_of(b);
+    if (!t.active) return;
+    const uint64_t* r = centre + (int64_t)t.row * b.W;
+    const bool c = (r[t.x >> 6] >> (t.x & 63)) & 1ull;
+    L[t.v] = c ? (int32_t)((int64_t)t.row * b.nx + run_start(r, t.x)) : -1;
+}
+
+// Unions across the -y and -z faces (and the periodic x face). Two runs that overlap are
+// united once, at the first overlapping x: where both left neighbours are centres too, the
+// pair to the left has already linked the same two runs.
+__global__ void __launch_bounds__(256) ccl_merge_kernel(Box b, const uint64_t* __restrict__ centre,
+                                                        int32_t* L) {
+    const VoxelIdx t = voxel_of(b);
+    if (!t.active || !bit_at(centre, b, t.row, t.x)) return;
+    const int y = t.row % b.ny, z = t.row / b.ny;
+    const int32_t v = (int32_t)t.v;
+    const bool left = t.x > 0 && bit_at(centre, b, t.row, t.x - 1);
+    if (t.x == 0 && (b.per & 1) && b.nx > 1 && bit_at(centre, b, t.row, b.nx - 1))
+        unite(L, v, (int32_t)((int64_t)t.row * b.nx + b.nx - 1));
+    int yn = y - 1;
+    if (yn < 0 && (b.per & 2)) yn = b.ny - 1;
+    if (yn >= 0 && yn != y) {
+        const int rn = z * b.ny + yn;
+        if (bit_at(centre, b, rn, t.x) && !(left && bit_at(centre, b, rn, t.x - 1)))
+            unite(L, v, (int32_t)((int64_t)rn * b.nx + t.x));
+    }
+    int zn = z - 1;
+    if (zn < 0 && (b.per & 4)) zn = b.nz - 1;
+    if (zn >= 0 && zn != z) {
+        const int rn = zn * b.ny + y;
+        if (bit_at(centre, b, rn, t.x) && !(left && bit_at(centre, b, rn, t.x - 1)))
+            unite(L, v, (int32_t)((int64_t)rn * b.nx + t.x));
+    }
+}
+
+__global__ void __launch_bounds__(256) ccl_compress_kernel(Box b, int32_t* L) {
+    const VoxelIdx t = voxel_of(b);
+    if (!t.active) return;
+    const int32_t l = L[t.v];
+    if (l >= 0) L[t.v] = find_root(L, l);
+}
+
+// Flag the roots of the centres in the z = 0 plane (rows 0 .. ny-1). Every writer stores 1.
+__global__ void __launch_bounds__(256) ccl_mark_kernel(Box b, const int32_t* __restrict__ L,
+                                                       uint8_t* __restrict__ flag) {
+    const VoxelIdx t = voxel_of(b);
+    if (!t.active || t.row >= b.ny) return;
+    const int32_t l = L[t.v];
+    if (l >= 0) flag[l] = 1;
 }
 
 // Largest d2 over pore voxels and the pore count, per block.
@@ -344,34 +474,34 @@ __global__ void __launch_bounds__(kPrepThreads) pore_max_kernel(int64_t n,
     }
 }
 
-__global__ void __launch_bounds__(256) relabel_kernel(int64_t n, const int32_t* __restrict__ labels,
+__global__ void __launch_bounds__(256) relabel_kernel(Box b, const int32_t* __restrict__ labels,
                                                       const int8_t* __restrict__ kind,
                                                       const int32_t* __restrict__ e2,
                                                       int32_t within, int32_t new_label,
                                                       int32_t* __restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const int32_t l = labels[v];
-    out[v] = (kind[l] == LBM_LABEL_SOLID && e2[v] <= within) ? new_label : l;
+    const VoxelIdx t = voxel_of(b);
+    if (!t.active) return;
+    const int32_t l = labels[t.v];
+    out[t.v] = (kind[l] == LBM_LABEL_SOLID && e2[t.v] <= within) ? new_label : l;
 }
 
 __global__ void __launch_bounds__(256) mixing_kernel(Box b, const int32_t* __restrict__ labels,
                                                      const int8_t* __restrict__ kind, int nmix,
                                                      int32_t pore_label,
                                                      int32_t* __restrict__ out) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= b.nvox) return;
+    const VoxelIdx t = voxel_of(b);
+    if (!t.active) return;
     const int64_t plane = (int64_t)b.nx * b.ny;
-    const int z = (int)(v / plane);
-    const int64_t xy = v - (int64_t)z * plane;
-    const int32_t l = labels[v];
+    const int z = t.row / b.ny;
+    const int64_t xy = t.v - (int64_t)z * plane;
+    const int32_t l = labels[t.v];
     bool open = false;
     if (kind[l] == LBM_LABEL_SOLID) {
         if (z < nmix && kind[labels[(int64_t)(b.nz - 1) * plane + xy]] != LBM_LABEL_SOLID)
             open = true;
         if (z >= b.nz - nmix && kind[labels[xy]] != LBM_LABEL_SOLID) open = true;
     }
-    out[v] = open ? pore_label : l;
+    out[t.v] = open ? pore_label : l;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -421,7 +551,16 @@ lbm_status check_box(int32_t nx, int32_t ny, int32_t nz, const int32_t* periodic
     if (periodic)
         for (int a = 0; a < 3; ++a)
             if (periodic[a]) b->per |= 1 << a;
+    b->tpb = std::min(kPrepThreads, 64 * b->W);
+    b->chunks = (nx + b->tpb - 1) / b->tpb;
     return LBM_OK;
+}
+
+// Grid of the per-voxel kernels (one workgroup per row and chunk of x) and of the bit packing.
+dim3 vox_grid(const Box& b) { return dim3((unsigned)(b.ny * b.nz), (unsigned)b.chunks); }
+dim3 pack_grid(const Box& b) {
+    const int64_t per_block = 4 * kWordsPerWave;   // four waves of kWordsPerWave words
+    return dim3((unsigned)((b.nwords + per_block - 1) / per_block));
 }
 
 lbm_status check_labels(const Box& b, const int32_t* labels, int32_t n_labels,
@@ -437,101 +576,106 @@ lbm_status check_labels(const Box& b, const int32_t* labels, int32_t n_labels,
     return LBM_OK;
 }
 
-// Squared distance transform of the feature bits into out (tmp is a second buffer of nvox);
+// Row search limit: the largest distance along x that can still be below the cap.
+int row_limit(const Box& b, int32_t cap) {
+    int lim = (b.per & 1) ? b.nx / 2 : b.nx - 1;
+    if (cap < kInf) lim = (int)std::min<int64_t>(lim, (int64_t)std::sqrt((double)cap) + 1);
+    return lim;
+}
+
+// Grid of the line passes along axis ax: one workgroup per (line group, segment, chunk of x).
+dim3 seg_grid(const Box& b, int ax) {
+    const int n = ax == 1 ? b.ny : b.nz, other = ax == 1 ? b.nz : b.ny;
+    return dim3((unsigned)(other * ((n + kSeg - 1) / kSeg)), (unsigned)b.chunks);
+}
+int64_t seg_blocks(const Box& b, int ax) {
+    const dim3 g = seg_grid(b, ax);
+    return (int64_t)g.x * g.y;
+}
+
+// Row and y passes of the transform of the feature bits: leaves the y-pass result in mid
+// (row-pass scratch in tmp).
+lbm_status edt_xy(const Box& b, const uint64_t* bits, int32_t cap, int32_t* tmp, int32_t* mid,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(edt_row_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, bits, row_limit(b, cap),
+                       cap, tmp);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(edt_seg_kernel<0>, seg_grid(b, 1), dim3(b.tpb), 0, s, b, 1, cap, 0,
+                       (const int32_t*)tmp, mid, nullptr, nullptr, nullptr);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+// Full squared distance transform of the feature bits into out (tmp: a second buffer of nvox);
 // values at or above cap are clipped to cap.
 lbm_status edt(const Box& b, const uint64_t* bits, int32_t cap, int walls, int32_t* tmp,
                int32_t* out, hipStream_t s) {
-    // Row search limit: the largest distance that can still be below the cap.
-    int lim = (b.per & 1) ? b.nx / 2 : b.nx - 1;
-    if (cap < kInf) lim = std::min<int64_t>(lim, (int64_t)std::sqrt((double)cap) + 1);
-    const int g = grid_for(b.nvox);
-    hipLaunchKernelGGL(edt_row_kernel, dim3(g), dim3(256), 0, s, b, bits, lim, cap, out);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(edt_line_kernel, dim3(g), dim3(256), 0, s, b, 1, cap, 0,
-                       (const int32_t*)out, tmp);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(edt_line_kernel, dim3(g), dim3(256), 0, s, b, 2, cap, walls,
-                       (const int32_t*)tmp, out);
+    if (lbm_status st = edt_xy(b, bits, cap, out, tmp, s)) return st;
+    hipLaunchKernelGGL(edt_seg_kernel<0>, seg_grid(b, 2), dim3(b.tpb), 0, s, b, 2, cap, walls,
+                       (const int32_t*)tmp, out, nullptr, nullptr, nullptr);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
-}
-
-lbm_status read_parts(const long long* dev, int count, long long* host, hipStream_t s) {
-    HIP_TRY(hipMemcpyAsync(host, dev, sizeof(long long) * (size_t)count, hipMemcpyDeviceToHost,
-                           s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return LBM_OK;
-}
-
-lbm_status popcount(const Box& b, const uint64_t* bits, long long* part, int64_t* out,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(popcount_kernel, dim3(kPrepBlocks), dim3(kPrepThreads), 0, s, b.nwords,
-                       bits, part);
-    HIP_TRY(hipGetLastError());
-    long long h[kPrepBlocks];
-    if (lbm_status st = read_parts(part, kPrepBlocks, h, s)) return st;
-    int64_t t = 0;
-    for (int i = 0; i < kPrepBlocks; ++i) t += h[i];
-    *out = t;
-    return LBM_OK;
-}
-
-// Grow reach (seeded with the centres of the z = 0 plane) through face-adjacent centres to a
-// fixed point.
-lbm_status connect_to_inlet(const Box& b, const uint64_t* centre, uint64_t* reach,
-                            long long* part, hipStream_t s) {
-    hipLaunchKernelGGL(seed_kernel, dim3(grid_for(b.nwords)), dim3(256), 0, s, b, centre, reach);
-    HIP_TRY(hipGetLastError());
-    int64_t count = -1;
-    for (int round = 0; round < kMaxRounds; ++round) {
-        hipLaunchKernelGGL(fill_x_kernel, dim3(grid_for((int64_t)b.ny * b.nz)), dim3(256), 0, s,
-                           b, centre, reach);
-        HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(sweep_kernel, dim3(grid_for((int64_t)b.W * b.nz)), dim3(256), 0, s, b,
-                           1, centre, reach);
-        HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(sweep_kernel, dim3(grid_for((int64_t)b.W * b.ny)), dim3(256), 0, s, b,
-                           2, centre, reach);
-        HIP_TRY(hipGetLastError());
-        int64_t c = 0;
-        if (lbm_status st = popcount(b, reach, part, &c, s)) return st;
-        if (c == count) return LBM_OK;
-        count = c;
-    }
-    return fail(LBM_ERR_DEVICE, "inlet connectivity did not reach a fixed point");
 }
 
 struct DrainBuffers {
     uint8_t* pore;
-    int32_t* d2;
-    int32_t* e2;
-    int32_t* tmp;
+    int32_t* d2;      // squared distance to the solid
+    int32_t* tmp;     // transform scratch
+    int32_t* mid;     // transform scratch
+    int32_t* label;   // union-find labels
+    uint8_t* flag;    // roots that touch the inlet plane
     uint64_t* centre;
     uint64_t* reach;
-    long long* part;
+    int* part;        // per-workgroup counts
+    long long* part2; // pore maximum and count per block; final sums
 };
+
+// Reach bits: the centres whose face-connected component touches the z = 0 plane.
+lbm_status connect_to_inlet(const Box& b, const DrainBuffers& db, hipStream_t s) {
+    hipLaunchKernelGGL(ccl_init_kernel, vox_grid(b), dim3(b.tpb), 0, s, b,
+                       (const uint64_t*)db.centre, db.label);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(ccl_merge_kernel, vox_grid(b), dim3(b.tpb), 0, s, b,
+                       (const uint64_t*)db.centre, db.label);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(ccl_compress_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, db.label);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemsetAsync(db.flag, 0, (size_t)b.nvox, s));
+    hipLaunchKernelGGL(ccl_mark_kernel, vox_grid(b), dim3(b.tpb), 0, s, b,
+                       (const int32_t*)db.label, db.flag);
+    HIP_TRY(hipGetLastError());
+    FeatureReached fr{db.label, db.flag};
+    hipLaunchKernelGGL(pack_kernel<FeatureReached>, pack_grid(b), dim3(256), 0, s, b, fr,
+                       db.reach);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
 
 // Non-wetting count for squared radius k; writes the mask to nw_dev when it is not null.
 lbm_status drain_eval(const Box& b, const DrainBuffers& db, int32_t k, bool inlet,
                       uint8_t* nw_dev, int64_t* n_nw, hipStream_t s) {
     FeatureCentre fc{db.pore, db.d2, k};
-    hipLaunchKernelGGL(pack_kernel<FeatureCentre>, dim3(grid_for(b.nwords)), dim3(256), 0, s, b,
-                       fc, db.centre);
+    hipLaunchKernelGGL(pack_kernel<FeatureCentre>, pack_grid(b), dim3(256), 0, s, b, fc,
+                       db.centre);
     HIP_TRY(hipGetLastError());
     const uint64_t* feat = db.centre;
     if (inlet) {
-        if (lbm_status st = connect_to_inlet(b, db.centre, db.reach, db.part, s)) return st;
+        if (lbm_status st = connect_to_inlet(b, db, s)) return st;
         feat = db.reach;
     }
-    if (lbm_status st = edt(b, feat, k, 0, db.tmp, db.e2, s)) return st;
-    hipLaunchKernelGGL(drain_count_kernel, dim3(kPrepBlocks), dim3(kPrepThreads), 0, s, b.nvox,
-                       (const uint8_t*)db.pore, (const int32_t*)db.e2, k, nw_dev, db.part);
+    if (lbm_status st = edt_xy(b, feat, k, db.tmp, db.mid, s)) return st;
+    // kPrepThreads per workgroup (its block sum needs them all): whenever b.tpb is smaller,
+    // there is one chunk per row, which 256 threads cover as well.
+    hipLaunchKernelGGL(edt_seg_kernel<1>, seg_grid(b, 2), dim3(kPrepThreads), 0, s, b, 2, k, 0,
+                       (const int32_t*)db.mid, nullptr, (const uint8_t*)db.pore, nw_dev, db.part);
     HIP_TRY(hipGetLastError());
-    long long h[kPrepBlocks];
-    if (lbm_status st = read_parts(db.part, kPrepBlocks, h, s)) return st;
-    int64_t t = 0;
-    for (int i = 0; i < kPrepBlocks; ++i) t += h[i];
-    *n_nw = t;
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kSumThreads), 0, s, (const int*)db.part,
+                       seg_blocks(b, 2), db.part2);
+    HIP_TRY(hipGetLastError());
+    long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, db.part2, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_nw = h;
     return LBM_OK;
 }
 
@@ -553,7 +697,7 @@ lbm_status lbm_prep_distance(int32_t nx, int32_t ny, int32_t nz, const int32_t p
     int32_t* out = sc.get<int32_t>(b.nvox);
     if (!f || !bits || !tmp || !out) return sc.failed("the transform");
     HIP_TRY(hipMemcpyAsync(f, feature, (size_t)b.nvox, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(pack_kernel<FeatureNonzero>, dim3(grid_for(b.nwords)), dim3(256), 0, s, b,
+    hipLaunchKernelGGL(pack_kernel<FeatureNonzero>, pack_grid(b), dim3(256), 0, s, b,
                        FeatureNonzero{f}, bits);
     HIP_TRY(hipGetLastError());
     if (lbm_status st = edt(b, bits, kInf, wall_axes, tmp, out, s)) return st;
@@ -582,27 +726,35 @@ lbm_status lbm_prep_drain(int32_t nx, int32_t ny, int32_t nz, const int32_t peri
     DrainBuffers db{};
     db.pore = sc.get<uint8_t>(b.nvox);
     db.d2 = sc.get<int32_t>(b.nvox);
-    db.e2 = sc.get<int32_t>(b.nvox);
     db.tmp = sc.get<int32_t>(b.nvox);
+    db.mid = sc.get<int32_t>(b.nvox);
     db.centre = sc.get<uint64_t>(b.nwords);
-    db.reach = sc.get<uint64_t>(b.nwords);
-    db.part = sc.get<long long>(2 * kPrepBlocks);
+    db.part = sc.get<int>(seg_blocks(b, 2));
+    db.part2 = sc.get<long long>(2 * kPrepBlocks);
     uint8_t* nw_dev = sc.get<uint8_t>(b.nvox);
-    if (!db.pore || !db.d2 || !db.e2 || !db.tmp || !db.centre || !db.reach || !db.part || !nw_dev)
+    if (inlet) {
+        db.label = sc.get<int32_t>(b.nvox);
+        db.flag = sc.get<uint8_t>(b.nvox);
+        db.reach = sc.get<uint64_t>(b.nwords);
+    }
+    if (!db.pore || !db.d2 || !db.tmp || !db.mid || !db.centre || !db.part || !db.part2 ||
+        !nw_dev || (inlet && (!db.label || !db.flag || !db.reach)))
         return sc.failed("the drainage");
     HIP_TRY(hipMemcpyAsync(db.pore, pore, (size_t)b.nvox, hipMemcpyHostToDevice, s));
 
     // D^2: distance to the solid and to the wall planes of the non-periodic faces.
-    hipLaunchKernelGGL(pack_kernel<FeatureZero>, dim3(grid_for(b.nwords)), dim3(256), 0, s, b,
+    hipLaunchKernelGGL(pack_kernel<FeatureZero>, pack_grid(b), dim3(256), 0, s, b,
                        FeatureZero{db.pore}, db.centre);
     HIP_TRY(hipGetLastError());
     const int walls = inlet ? 3 : 7;
     if (lbm_status st = edt(b, db.centre, kInf, walls, db.tmp, db.d2, s)) return st;
     hipLaunchKernelGGL(pore_max_kernel, dim3(kPrepBlocks), dim3(kPrepThreads), 0, s, b.nvox,
-                       (const uint8_t*)db.pore, (const int32_t*)db.d2, db.part);
+                       (const uint8_t*)db.pore, (const int32_t*)db.d2, db.part2);
     HIP_TRY(hipGetLastError());
     std::vector<long long> h(2 * kPrepBlocks);
-    if (lbm_status st = read_parts(db.part, 2 * kPrepBlocks, h.data(), s)) return st;
+    HIP_TRY(hipMemcpyAsync(h.data(), db.part2, sizeof(long long) * h.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     long long kmax = -1, npore = 0;
     for (int i = 0; i < kPrepBlocks; ++i) {
         kmax = std::max(kmax, h[2 * i]);
@@ -666,13 +818,12 @@ lbm_status lbm_prep_relabel(int32_t nx, int32_t ny, int32_t nz, const int32_t pe
                            s));
     HIP_TRY(hipMemcpyAsync(kind, label_kind, (size_t)n_labels, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(m, nw, (size_t)b.nvox, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(pack_kernel<FeatureNonzero>, dim3(grid_for(b.nwords)), dim3(256), 0, s, b,
+    hipLaunchKernelGGL(pack_kernel<FeatureNonzero>, pack_grid(b), dim3(256), 0, s, b,
                        FeatureNonzero{m}, bits);
     HIP_TRY(hipGetLastError());
     if (lbm_status st = edt(b, bits, cap, 0, tmp, e2, s)) return st;
-    hipLaunchKernelGGL(relabel_kernel, dim3(grid_for(b.nvox)), dim3(256), 0, s, b.nvox,
-                       (const int32_t*)lab, (const int8_t*)kind, (const int32_t*)e2, within,
-                       new_label, res);
+    hipLaunchKernelGGL(relabel_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, (const int32_t*)lab,
+                       (const int8_t*)kind, (const int32_t*)e2, within, new_label, res);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(labels_out, res, sizeof(int32_t) * (size_t)b.nvox,
                            hipMemcpyDeviceToHost, s));
@@ -700,8 +851,8 @@ lbm_status lbm_prep_mixing_layer(int32_t nx, int32_t ny, int32_t nz, const int32
     HIP_TRY(hipMemcpyAsync(lab, labels, sizeof(int32_t) * (size_t)b.nvox, hipMemcpyHostToDevice,
                            s));
     HIP_TRY(hipMemcpyAsync(kind, label_kind, (size_t)n_labels, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(mixing_kernel, dim3(grid_for(b.nvox)), dim3(256), 0, s, b,
-                       (const int32_t*)lab, (const int8_t*)kind, nmix, pore_label, res);
+    hipLaunchKernelGGL(mixing_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, (const int32_t*)lab,
+                       (const int8_t*)kind, nmix, pore_label, res);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(labels_out, res, sizeof(int32_t) * (size_t)b.nvox,
                            hipMemcpyDeviceToHost, s));
