@@ -229,3 +229,34 @@ def test_row_block_numbering(rows):
         pore = old < n
         assert np.array_equal(new[pore], inv[old[pore]])
         assert np.array_equal(res["tail_phi"][new[~pore] - n], dense["tail_phi"][old[~pore] - n])
+
+
+def test_prep_calls_validate_before_touching_the_device():
+    """Argument errors of the pre-processing calls come back as LBM_ERR_ARG from host checks
+    that run before any device call (this container has no GPU)."""
+    pore = np.ones((4, 5, 6), dtype=bool)
+    with pytest.raises(lbm.LbmError, match="target_sw"):
+        lbm.prep_drain(pore, (False, False, False), 1.0)
+    with pytest.raises(lbm.LbmError, match="target_sw"):
+        lbm.prep_drain(pore, (False, False, False), -0.1)
+    with pytest.raises(lbm.LbmError, match="non-periodic z"):
+        lbm.prep_drain(pore, (False, False, True), 0.5, inlet=True)
+    with pytest.raises(lbm.LbmError, match="sizes"):
+        lbm.prep_distance(np.zeros((0, 3, 3), dtype=bool))
+    with pytest.raises(lbm.LbmError, match="wall_axes"):
+        lbm.prep_distance(pore, wall_axes=9)
+    labels = np.zeros((4, 5, 6), dtype=np.int32)
+    labels[1:3] = 1
+    kind = np.array([inputs.KIND_SOLID, inputs.KIND_PORE_INIT], np.int8)
+    with pytest.raises(lbm.LbmError, match="outside"):
+        lbm.prep_relabel(labels + 1, kind, pore, (False,) * 3, 2.0, 2)
+    with pytest.raises(lbm.LbmError, match="dist"):
+        lbm.prep_relabel(labels, kind, pore, (False,) * 3, -1.0, 2)
+    with pytest.raises(lbm.LbmError, match="new_label"):
+        lbm.prep_relabel(labels, kind, pore, (False,) * 3, 2.0, -1)
+    with pytest.raises(lbm.LbmError, match="nmix"):
+        lbm.prep_mixing_layer(labels, kind, 5, 1)
+    with pytest.raises(lbm.LbmError, match="pore label"):
+        lbm.prep_mixing_layer(labels, kind, 2, 0)
+    with pytest.raises(lbm.LbmError, match="lbm_label_kind"):
+        lbm.prep_mixing_layer(labels, np.array([0, 7], np.int8), 2, 1)
