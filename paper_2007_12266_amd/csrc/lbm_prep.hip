@@ -41,7 +41,6 @@ namespace {
 
 constexpr int32_t kInf = 0x3fffffff;
 constexpr int kMaxDim = 16384;
-constexpr int kPrepBlocks = 512;
 constexpr int kPrepThreads = 256;
 constexpr int kSumThreads = 1024;
 
@@ -125,6 +124,66 @@ __global__ void __launch_bounds__(256) pack_kernel(Box b, P pred, uint64_t* __re
     }
 }
 
+// Rows whose length is a multiple of 8: each lane reads 8 consecutive voxels with wide loads
+// (8-byte and 16-byte aligned) and the 8 lanes of a word merge their bytes by shuffles; a wave
+// covers 8 words. The predicate's byte8(v) gives bit i for voxel v + i.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint64_t w) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) m |= (((w >> (8 * i)) & 0xffull) != 0 ? 1u : 0u) << i;
+    return m;
+}
+struct Wide8Nonzero {
+    const uint8_t* m;
+    __device__ uint32_t byte8(int64_t v) const {
+        return nonzero_bytes(*reinterpret_cast<const uint64_t*>(m + v));
+    }
+};
+struct Wide8Zero {
+    const uint8_t* m;
+    __device__ uint32_t byte8(int64_t v) const {
+        return ~nonzero_bytes(*reinterpret_cast<const uint64_t*>(m + v)) & 0xffu;
+    }
+};
+struct Wide8Centre {
+    const uint8_t* pore;
+    const int32_t* d2;
+    int32_t k;
+    __device__ uint32_t byte8(int64_t v) const {
+        const uint32_t pm = nonzero_bytes(*reinterpret_cast<const uint64_t*>(pore + v));
+        const int4 a = *reinterpret_cast<const int4*>(d2 + v);
+        const int4 c = *reinterpret_cast<const int4*>(d2 + v + 4);
+        const uint32_t dm = (a.x >= k ? 1u : 0u) | (a.y >= k ? 2u : 0u) | (a.z >= k ? 4u : 0u) |
+                            (a.w >= k ? 8u : 0u) | (c.x >= k ? 16u : 0u) | (c.y >= k ? 32u : 0u) |
+                            (c.z >= k ? 64u : 0u) | (c.w >= k ? 128u : 0u);
+        return pm & dm;
+    }
+};
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename P>
+__global__ void __launch_bounds__(256) pack8_kernel(Box b, P pred, uint64_t* __restrict__ bits) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane & 7;
+    const int64_t word = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 8 + (lane >> 3);
+    uint32_t byte = 0;
+    if (word < b.nwords) {
+        const int row = (int)(word / b.W);
+        const int x = 64 * (int)(word - (int64_t)row * b.W) + 8 * g;
+        if (x < b.nx) byte = pred.byte8((int64_t)row * b.nx + x);
+    }
+    uint64_t m = (uint64_t)byte << (8 * g);
+    m |= shfl_xor_u64(m, 1);
+    m |= shfl_xor_u64(m, 2);
+    m |= shfl_xor_u64(m, 4);
+    if (g == 0 && word < b.nwords) bits[word] = m;
+}
+
 // First set bit at a position in [p, e] of a row (p <= e), or -1.
 __device__ __forceinline__ int first_set(const uint64_t* __restrict__ r, int p, int e) {
     int w = p >> 6;
@@ -158,21 +217,13 @@ __device__ __forceinline__ int last_set(const uint64_t* __restrict__ r, int s, i
 }
 
 // Row pass: out[v] = min(g^2, cap), g = distance along x to the nearest feature bit in the
-// row (wrapping when x is periodic), searched to at most `lim` voxels. The words w-1, w, w+1
-// around x are read together and settle almost every voxel; the full word-by-word search runs
-// only for a direction they leave open.
-__global__ void __launch_bounds__(256) edt_row_kernel(Box b, const uint64_t* __restrict__ bits,
-                                                      int lim, int32_t cap,
-                                                      int32_t* __restrict__ out) {
-    const VoxelIdx t = voxel_of(b);
-    if (!t.active) return;
-    const uint64_t* r = bits + (int64_t)t.row * b.W;
-    const bool per = (b.per & 1) != 0;
-    const int nx = b.nx, x = t.x;
+// row (wrapping when x is periodic), searched to at most `lim` voxels. Four consecutive voxels
+// per thread (one 16-byte store when nx is a multiple of 4). The words w-1, w, w+1 around them
+// are read together and settle almost every voxel; the full word-by-word search runs only for a
+// side they leave open and whose remainder lies within the limit.
+__device__ __forceinline__ int row_dist(const uint64_t* __restrict__ r, int W, int nx, bool per,
+                                        int lim, int x, uint64_t cur, uint64_t lo, uint64_t hi) {
     const int w = x >> 6, sh = x & 63;
-    const uint64_t cur = r[w];
-    const uint64_t lo = w > 0 ? r[w - 1] : 0ull;
-    const uint64_t hi = w + 1 < b.W ? r[w + 1] : 0ull;
     int d = kInf;
     bool right_open = false, left_open = false;
     // right: bits >= x in this word, then the next word
@@ -198,7 +249,7 @@ __global__ void __launch_bounds__(256) edt_row_kernel(Box b, const uint64_t* __r
     // search on the other side (periodic), so the result is min(d^2, cap) either way. An open
     // side is searched in full only when what lies beyond the window (a further word, or the
     // wrap through the periodic face) is within the limit and could still be nearer than d.
-    int rb = w + 1 < b.W ? 128 - sh : kInf;
+    int rb = w + 1 < W ? 128 - sh : kInf;
     int lb = w > 0 ? sh + 65 : kInf;
     if (per) {
         rb = min(rb, nx - x);
@@ -222,7 +273,36 @@ __global__ void __launch_bounds__(256) edt_row_kernel(Box b, const uint64_t* __r
             if (q >= 0) d = min(d, x + nx - q);
         }
     }
-    out[t.v] = d >= kInf ? cap : min(d * d, cap);
+    return d;
+}
+
+__global__ void __launch_bounds__(256) edt_row_kernel(Box b, const uint64_t* __restrict__ bits,
+                                                      int lim, int32_t cap,
+                                                      int32_t* __restrict__ out) {
+    const int row = (int)blockIdx.x;
+    const int x0 = 4 * ((int)blockIdx.y * (int)blockDim.x + (int)threadIdx.x);
+    if (x0 >= b.nx) return;
+    const uint64_t* r = bits + (int64_t)row * b.W;
+    const bool per = (b.per & 1) != 0;
+    const int w = x0 >> 6;   // the four voxels share this word
+    const uint64_t cur = r[w];
+    const uint64_t lo = w > 0 ? r[w - 1] : 0ull;
+    const uint64_t hi = w + 1 < b.W ? r[w + 1] : 0ull;
+    int res[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int x = x0 + j;
+        const int d = x < b.nx ? row_dist(r, b.W, b.nx, per, lim, x, cur, lo, hi) : kInf;
+        res[j] = d >= kInf ? cap : min(d * d, cap);
+    }
+    const int64_t v = (int64_t)row * b.nx + x0;
+    if ((b.nx & 3) == 0) {
+        *reinterpret_cast<int4*>(out + v) = make_int4(res[0], res[1], res[2], res[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (x0 + j < b.nx) out[v + j] = res[j];
+    }
 }
 
 // Continues min over d >= d0 of in[base + ((c + d) mod n) stride] + d^2 (offsets outside a
@@ -444,24 +524,68 @@ __global__ void __launch_bounds__(256) ccl_mark_kernel(Box b, const int32_t* __r
     if (l >= 0) flag[l] = 1;
 }
 
-// Largest d2 over pore voxels and the pore count, per block.
+// Largest d2 over pore voxels and the pore count: eight consecutive voxels per thread (wide
+// loads; the flat arrays are 256-byte aligned), per-workgroup results, then one workgroup
+// combines them.
 __global__ void __launch_bounds__(kPrepThreads) pore_max_kernel(int64_t n,
                                                                const uint8_t* __restrict__ pore,
                                                                const int32_t* __restrict__ d2,
                                                                long long* __restrict__ part) {
-    __shared__ long long smax[kPrepThreads];
-    __shared__ long long scnt[kPrepThreads];
-    long long mx = -1, cnt = 0;
-    for (int64_t v = (int64_t)blockIdx.x * kPrepThreads + threadIdx.x; v < n;
-         v += (int64_t)kPrepBlocks * kPrepThreads)
-        if (pore[v]) {
-            mx = max(mx, (long long)d2[v]);
-            ++cnt;
-        }
-    smax[threadIdx.x] = mx;
-    scnt[threadIdx.x] = cnt;
+    const int64_t v0 = 8 * ((int64_t)blockIdx.x * kPrepThreads + threadIdx.x);
+    int mx = -1, cnt = 0;
+    if (v0 + 8 <= n) {
+        const uint32_t pm = nonzero_bytes(*reinterpret_cast<const uint64_t*>(pore + v0));
+        const int4 a = *reinterpret_cast<const int4*>(d2 + v0);
+        const int4 c = *reinterpret_cast<const int4*>(d2 + v0 + 4);
+        const int dv[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if ((pm >> i) & 1u) {
+                mx = max(mx, dv[i]);
+                ++cnt;
+            }
+    } else {
+        for (int64_t v = v0; v < n; ++v)
+            if (pore[v]) {
+                mx = max(mx, d2[v]);
+                ++cnt;
+            }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = max(mx, __shfl_xor(mx, off));
+        cnt += __shfl_xor(cnt, off);
+    }
+    __shared__ int wmax[kPrepThreads / 64], wcnt[kPrepThreads / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wmax[threadIdx.x >> 6] = mx;
+        wcnt[threadIdx.x >> 6] = cnt;
+    }
     __syncthreads();
-    for (int h = kPrepThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x == 0) {
+        int m = -1, c = 0;
+        for (int i = 0; i < kPrepThreads / 64; ++i) {
+            m = max(m, wmax[i]);
+            c += wcnt[i];
+        }
+        part[2 * blockIdx.x] = m;
+        part[2 * blockIdx.x + 1] = c;
+    }
+}
+
+// Combines nblk (max, count) pairs into out[0] (max) and out[1] (total count).
+__global__ void __launch_bounds__(kSumThreads) max_count_kernel(const long long* __restrict__ part,
+                                                                int64_t nblk,
+                                                                long long* __restrict__ out) {
+    __shared__ long long smax[kSumThreads], scnt[kSumThreads];
+    long long m = -1, c = 0;
+    for (int64_t i = threadIdx.x; i < nblk; i += kSumThreads) {
+        m = max(m, part[2 * i]);
+        c += part[2 * i + 1];
+    }
+    smax[threadIdx.x] = m;
+    scnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = kSumThreads / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
             smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + h]);
             scnt[threadIdx.x] += scnt[threadIdx.x + h];
@@ -469,8 +593,8 @@ __global__ void __launch_bounds__(kPrepThreads) pore_max_kernel(int64_t n,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = smax[0];
-        part[2 * blockIdx.x + 1] = scnt[0];
+        out[0] = smax[0];
+        out[1] = scnt[0];
     }
 }
 
@@ -558,6 +682,16 @@ lbm_status check_box(int32_t nx, int32_t ny, int32_t nz, const int32_t* periodic
 
 // Grid of the per-voxel kernels (one workgroup per row and chunk of x) and of the bit packing.
 dim3 vox_grid(const Box& b) { return dim3((unsigned)(b.ny * b.nz), (unsigned)b.chunks); }
+// Row pass: four voxels per thread.
+int row_threads(const Box& b) {
+    const int quads = (b.nx + 3) / 4;
+    return std::min(kPrepThreads, 64 * ((quads + 63) / 64));
+}
+dim3 row_grid(const Box& b) {
+    const int t = 4 * row_threads(b);
+    return dim3((unsigned)(b.ny * b.nz), (unsigned)((b.nx + t - 1) / t));
+}
+dim3 pack8_grid(const Box& b) { return dim3((unsigned)((b.nwords + 31) / 32)); }
 dim3 pack_grid(const Box& b) {
     const int64_t per_block = 4 * kWordsPerWave;   // four waves of kWordsPerWave words
     return dim3((unsigned)((b.nwords + per_block - 1) / per_block));
@@ -573,6 +707,17 @@ lbm_status check_labels(const Box& b, const int32_t* labels, int32_t n_labels,
     for (int64_t v = 0; v < b.nvox; ++v)
         if (labels[v] < 0 || labels[v] >= n_labels)
             return fail(LBM_ERR_ARG, "labels[" + std::to_string(v) + "] is outside [0, n_labels)");
+    return LBM_OK;
+}
+
+// Packs a predicate into row bits, with the wide kernel when rows are a multiple of 8 long.
+template <typename P, typename P8>
+lbm_status pack(const Box& b, P pred, P8 pred8, uint64_t* bits, hipStream_t s) {
+    if ((b.nx & 7) == 0)
+        hipLaunchKernelGGL(pack8_kernel<P8>, pack8_grid(b), dim3(256), 0, s, b, pred8, bits);
+    else
+        hipLaunchKernelGGL(pack_kernel<P>, pack_grid(b), dim3(256), 0, s, b, pred, bits);
+    HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
 
@@ -597,8 +742,8 @@ int64_t seg_blocks(const Box& b, int ax) {
 // (row-pass scratch in tmp).
 lbm_status edt_xy(const Box& b, const uint64_t* bits, int32_t cap, int32_t* tmp, int32_t* mid,
                   hipStream_t s) {
-    hipLaunchKernelGGL(edt_row_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, bits, row_limit(b, cap),
-                       cap, tmp);
+    hipLaunchKernelGGL(edt_row_kernel, row_grid(b), dim3(row_threads(b)), 0, s, b, bits,
+                       row_limit(b, cap), cap, tmp);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(edt_seg_kernel<0>, seg_grid(b, 1), dim3(b.tpb), 0, s, b, 1, cap, 0,
                        (const int32_t*)tmp, mid, nullptr, nullptr, nullptr);
@@ -627,7 +772,8 @@ struct DrainBuffers {
     uint64_t* centre;
     uint64_t* reach;
     int* part;        // per-workgroup counts
-    long long* part2; // pore maximum and count per block; final sums
+    long long* part2; // final sums: count, or (max, count)
+    long long* pairs; // (max, count) per workgroup of the pore reduction
 };
 
 // Reach bits: the centres whose face-connected component touches the z = 0 plane.
@@ -655,9 +801,7 @@ lbm_status connect_to_inlet(const Box& b, const DrainBuffers& db, hipStream_t s)
 lbm_status drain_eval(const Box& b, const DrainBuffers& db, int32_t k, bool inlet,
                       uint8_t* nw_dev, int64_t* n_nw, hipStream_t s) {
     FeatureCentre fc{db.pore, db.d2, k};
-    hipLaunchKernelGGL(pack_kernel<FeatureCentre>, pack_grid(b), dim3(256), 0, s, b, fc,
-                       db.centre);
-    HIP_TRY(hipGetLastError());
+    if (lbm_status st = pack(b, fc, Wide8Centre{db.pore, db.d2, k}, db.centre, s)) return st;
     const uint64_t* feat = db.centre;
     if (inlet) {
         if (lbm_status st = connect_to_inlet(b, db, s)) return st;
@@ -697,9 +841,7 @@ lbm_status lbm_prep_distance(int32_t nx, int32_t ny, int32_t nz, const int32_t p
     int32_t* out = sc.get<int32_t>(b.nvox);
     if (!f || !bits || !tmp || !out) return sc.failed("the transform");
     HIP_TRY(hipMemcpyAsync(f, feature, (size_t)b.nvox, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(pack_kernel<FeatureNonzero>, pack_grid(b), dim3(256), 0, s, b,
-                       FeatureNonzero{f}, bits);
-    HIP_TRY(hipGetLastError());
+    if (lbm_status st = pack(b, FeatureNonzero{f}, Wide8Nonzero{f}, bits, s)) return st;
     if (lbm_status st = edt(b, bits, kInf, wall_axes, tmp, out, s)) return st;
     HIP_TRY(hipMemcpyAsync(dist_sq, out, sizeof(int32_t) * (size_t)b.nvox, hipMemcpyDeviceToHost,
                            s));
@@ -730,7 +872,8 @@ lbm_status lbm_prep_drain(int32_t nx, int32_t ny, int32_t nz, const int32_t peri
     db.mid = sc.get<int32_t>(b.nvox);
     db.centre = sc.get<uint64_t>(b.nwords);
     db.part = sc.get<int>(seg_blocks(b, 2));
-    db.part2 = sc.get<long long>(2 * kPrepBlocks);
+    db.part2 = sc.get<long long>(2);
+    db.pairs = sc.get<long long>(2 * ((b.nvox + 8 * kPrepThreads - 1) / (8 * kPrepThreads)));
     uint8_t* nw_dev = sc.get<uint8_t>(b.nvox);
     if (inlet) {
         db.label = sc.get<int32_t>(b.nvox);
@@ -738,28 +881,26 @@ lbm_status lbm_prep_drain(int32_t nx, int32_t ny, int32_t nz, const int32_t peri
         db.reach = sc.get<uint64_t>(b.nwords);
     }
     if (!db.pore || !db.d2 || !db.tmp || !db.mid || !db.centre || !db.part || !db.part2 ||
-        !nw_dev || (inlet && (!db.label || !db.flag || !db.reach)))
+        !db.pairs || !nw_dev || (inlet && (!db.label || !db.flag || !db.reach)))
         return sc.failed("the drainage");
     HIP_TRY(hipMemcpyAsync(db.pore, pore, (size_t)b.nvox, hipMemcpyHostToDevice, s));
 
     // D^2: distance to the solid and to the wall planes of the non-periodic faces.
-    hipLaunchKernelGGL(pack_kernel<FeatureZero>, pack_grid(b), dim3(256), 0, s, b,
-                       FeatureZero{db.pore}, db.centre);
-    HIP_TRY(hipGetLastError());
+    if (lbm_status st = pack(b, FeatureZero{db.pore}, Wide8Zero{db.pore}, db.centre, s))
+        return st;
     const int walls = inlet ? 3 : 7;
     if (lbm_status st = edt(b, db.centre, kInf, walls, db.tmp, db.d2, s)) return st;
-    hipLaunchKernelGGL(pore_max_kernel, dim3(kPrepBlocks), dim3(kPrepThreads), 0, s, b.nvox,
-                       (const uint8_t*)db.pore, (const int32_t*)db.d2, db.part2);
+    const int64_t nblk = (b.nvox + 8 * kPrepThreads - 1) / (8 * kPrepThreads);
+    hipLaunchKernelGGL(pore_max_kernel, dim3((unsigned)nblk), dim3(kPrepThreads), 0, s, b.nvox,
+                       (const uint8_t*)db.pore, (const int32_t*)db.d2, db.pairs);
     HIP_TRY(hipGetLastError());
-    std::vector<long long> h(2 * kPrepBlocks);
-    HIP_TRY(hipMemcpyAsync(h.data(), db.part2, sizeof(long long) * h.size(),
-                           hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(kSumThreads), 0, s,
+                       (const long long*)db.pairs, nblk, db.part2);
+    HIP_TRY(hipGetLastError());
+    long long h[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(h, db.part2, sizeof h, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    long long kmax = -1, npore = 0;
-    for (int i = 0; i < kPrepBlocks; ++i) {
-        kmax = std::max(kmax, h[2 * i]);
-        npore += h[2 * i + 1];
-    }
+    const long long kmax = h[0], npore = h[1];
     if (npore == 0) return fail(LBM_ERR_ARG, "the image has no pore voxel");
     if (kmax >= kInf) return fail(LBM_ERR_ARG, "no solid voxel and no wall: distances are unbounded");
 
@@ -818,9 +959,7 @@ lbm_status lbm_prep_relabel(int32_t nx, int32_t ny, int32_t nz, const int32_t pe
                            s));
     HIP_TRY(hipMemcpyAsync(kind, label_kind, (size_t)n_labels, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(m, nw, (size_t)b.nvox, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(pack_kernel<FeatureNonzero>, pack_grid(b), dim3(256), 0, s, b,
-                       FeatureNonzero{m}, bits);
-    HIP_TRY(hipGetLastError());
+    if (lbm_status st = pack(b, FeatureNonzero{m}, Wide8Nonzero{m}, bits, s)) return st;
     if (lbm_status st = edt(b, bits, cap, 0, tmp, e2, s)) return st;
     hipLaunchKernelGGL(relabel_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, (const int32_t*)lab,
                        (const int8_t*)kind, (const int32_t*)e2, within, new_label, res);
