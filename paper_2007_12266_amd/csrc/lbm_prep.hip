@@ -9,24 +9,24 @@
 // min over (y', z') of [g(x; y', z')^2 + (y - y')^2 + (z - z')^2], g the distance along the
 // row. The row pass finds g from the rows packed as 64-voxel bit words (find-first-set on whole
 // words); the y and z passes search outward from each voxel and stop once d^2 reaches the best
-// value so far, which is exact because every candidate at offset d costs at least d^2. The
-// first four offsets are loaded together so that the common short search is one round trip.
-// With a cap c (only distances below c matter) every value is clipped at c and the searches
-// stop at c. Squared distances are int32 with kInf = 2^30 - 1 for "none": sizes up to 16384
-// keep kInf + n^2 below 2^31.
+// value so far, which is exact because every candidate at offset d costs at least d^2. A thread
+// of those passes takes 8 positions of a line and reads the 16 values of their offsets up to 4
+// at once, so the common short search is one round trip. With a cap c (only distances below c
+// matter) every value is clipped at c and the searches stop at c. Squared distances are int32
+// with kInf = 2^30 - 1 for "none": sizes up to 16384 keep kInf + n^2 below 2^31.
 //
 // Per-voxel kernels run on a 2-D grid: blockIdx.x is the image row (y, z), blockIdx.y the
-// chunk of x, so no thread divides a 64-bit index. Bit rows are packed by one wave per 64-voxel
-// word with a ballot.
+// chunk of x, so no thread divides a 64-bit index. Bit rows are packed with wide loads and
+// shuffles when rows are a multiple of 8 long, else with a ballot per word.
 //
 // Connectivity of the sphere centres to the inlet plane: union-find labelling. Every centre
 // starts under the first voxel of its run of centres along x; runs that touch across a -y or
 // -z face (or the periodic x face) are united by linking the larger root under the smaller
-// with atomicMin, retrying from the new parent when another thread linked first. A parent index is never larger than its child,
-// so every find walks a strictly decreasing chain and ends. After the merges each label is
-// replaced by its root, the roots of the z = 0 plane are flagged, and a centre is reached when
-// its root is flagged. Counts use fixed-shape block sums and a fixed-order final sum, so every
-// result is deterministic.
+// with atomicMin, retrying from the new parent when another thread linked first. A parent
+// index is never larger than its child, so every find walks a strictly decreasing chain and
+// ends. After the merges each label is replaced by its root, the roots of the z = 0 plane are
+// flagged, and a centre is reached when its root is flagged. Counts use fixed-shape workgroup
+// sums and a fixed-order final sum, so every result is deterministic.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
