@@ -359,11 +359,34 @@ def serve_main(args):
     def done(tag):
         return lambda r: log("%s: request %d (%d pore voxels) done after %d steps, latency "
                              "%.2f s" % (tag, r.rid, r.n_pore, r.steps, r.latency))
+    def dump(tag, results):
+        if args.serve_dump:
+            with open("%s.%s.json" % (args.serve_dump, tag), "w") as fh:
+                json.dump([{"rid": r.rid, "n_pore": r.n_pore, "steps": r.steps,
+                            "arrival": r.arrival, "completed": r.completed,
+                            "latency": r.latency, "final": r.final} for r in results], fh)
+
+    if args.serve_part == "fifo":
+        base = serve.fifo_baseline(reqs, precision=lbm.FP64, chunk=1000,
+                                   on_result=done("fp64 fifo"))
+        dump("fifo", base)
+        sb = serve.latency_stats(base)
+        log("fp64 fifo: %s" % sb)
+        print(json.dumps({"part": "fifo", "requests": count, "fp64_fifo": sb}), flush=True)
+        return
     res = srv.run(reqs, realtime=True, on_result=done("served"))
     info = srv.pool.info()
     srv.close()
+    dump("served", res)
     st = serve.latency_stats(res)
     log("served: %s" % st)
+    if args.serve_part == "served":
+        lups = sum(r.n_pore * r.steps for r in res)
+        span = max(r.completed for r in res) - min(r.arrival for r in res)
+        print(json.dumps({"part": "served", "requests": count, "served": st,
+                          "aggregate_mlups": round(lups / span / 1e6, 1),
+                          "graph_replays": info["graph_replays"]}), flush=True)
+        return
     base = serve.fifo_baseline(reqs, precision=lbm.FP64, chunk=1000,
                                on_result=done("fp64 fifo"))
     sb = serve.latency_stats(base)
@@ -406,6 +429,11 @@ def main():
     ap.add_argument("--requests", type=int, default=16, help="serve: number of requests")
     ap.add_argument("--serve-lmax", type=int, default=192, help="serve: largest cube edge")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0, help="serve: HBM budget")
+    ap.add_argument("--serve-part", default="both", choices=["both", "served", "fifo"],
+                    help="serve: run only the continuous-batching server or only the FP64 "
+                         "one-at-a-time baseline (for traces too long for one run)")
+    ap.add_argument("--serve-dump", default="", metavar="PREFIX",
+                    help="serve: write per-request results to PREFIX.<part>.json")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32dev"])
