@@ -455,7 +455,7 @@ def main():
     args = ap.parse_args()
     args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
