@@ -23,7 +23,8 @@ CPP_SOURCES = ["lbm_prepass.cpp"]
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include")]
-CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I", os.path.join(ROOT, "include")]
+CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", "-I",
+             os.path.join(ROOT, "include")]
 
 
 def _run(cmd):
@@ -44,7 +45,7 @@ def build(verbose: bool = True) -> str:
             _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
         out = os.path.join(tmp, "liblbm.so")
-        _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", out])
+        _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", *objs, "-o", out])
         os.replace(out, LIB) if os.path.dirname(out) == os.path.dirname(LIB) else \
             _copy_atomic(out, LIB)
     return LIB

@@ -18,9 +18,11 @@
 //    or the solid's phi_s. Streaming treats every tail entry as a wall (bounce-back).
 #include "lbm_prepass.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <limits>
+#include <thread>
 #include <unordered_map>
 
 namespace lbm {
@@ -34,6 +36,27 @@ std::string fmt(const char* f, long long a = 0, long long b = 0) {
     char buf[256];
     std::snprintf(buf, sizeof buf, f, a, b);
     return buf;
+}
+
+// body(begin, end) over [0, n) in contiguous chunks, one per thread (up to 16 threads; when
+// the total work, n items unless stated, is small the calling thread runs it all). Chunks are
+// disjoint, so a body that writes only the entries of its own indices needs no
+// synchronisation.
+template <typename F>
+void parallel_for(int64_t n, F body, int64_t work = -1) {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if ((work < 0 ? n : work) < (1 << 16) || n < 2 || hw == 1) {
+        body((int64_t)0, n);
+        return;
+    }
+    const int64_t chunk = (n + hw - 1) / hw;
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < hw; ++t) {
+        const int64_t b = (int64_t)t * chunk, e = std::min(n, b + chunk);
+        if (b >= e) break;
+        pool.emplace_back(body, b, e);
+    }
+    for (std::thread& th : pool) th.join();
 }
 
 }  // namespace
@@ -70,37 +93,73 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
     // pore list (a block's plane instead of a whole plane apart), so they are still in the L2
     // when they are reused; every row's pore voxels stay consecutive.
     std::vector<int32_t> pidx(nvox, -1);
-    int64_t n = 0;
     const int64_t rows = std::min<int64_t>(p.order_rows > 0 ? p.order_rows : kDefaultOrderRows, ny);
-    for (int64_t y0 = 0; y0 < ny; y0 += rows)
-        for (int64_t z = 0; z < nz; ++z)
-            for (int64_t y = y0; y < std::min(y0 + rows, ny); ++y)
+    const int64_t nblk = (ny + rows - 1) / rows;
+    // Unit u = (block u / nz, plane u % nz): count its pore voxels, then number them from the
+    // prefix sum of the counts, so the numbering is the one of a single pass in unit order.
+    std::vector<int64_t> ucount(nblk * nz + 1, 0);
+    auto unit_rows = [&](int64_t u, int64_t& y0, int64_t& y1, int64_t& z) {
+        z = u % nz;
+        y0 = (u / nz) * rows;
+        y1 = std::min(y0 + rows, ny);
+    };
+    parallel_for(nblk * nz, [&](int64_t u0, int64_t u1) {
+        for (int64_t u = u0; u < u1; ++u) {
+            int64_t y0, y1, z, c = 0;
+            unit_rows(u, y0, y1, z);
+            for (int64_t y = y0; y < y1; ++y)
+                for (int64_t x = 0; x < nx; ++x)
+                    c += label_kind[labels[x + nx * (y + ny * z)]] != LBM_LABEL_SOLID;
+            ucount[u + 1] = c;
+        }
+    }, nvox);
+    for (int64_t u = 0; u < nblk * nz; ++u) ucount[u + 1] += ucount[u];
+    const int64_t n = ucount[nblk * nz];
+    if (n >= (int64_t)std::numeric_limits<int32_t>::max() / 2)
+        return "too many pore voxels for int32 indexing";
+    parallel_for(nblk * nz, [&](int64_t u0, int64_t u1) {
+        for (int64_t u = u0; u < u1; ++u) {
+            int64_t y0, y1, z, k = ucount[u];
+            unit_rows(u, y0, y1, z);
+            for (int64_t y = y0; y < y1; ++y)
                 for (int64_t x = 0; x < nx; ++x) {
                     const int64_t v = x + nx * (y + ny * z);
-                    if (label_kind[labels[v]] == LBM_LABEL_SOLID) continue;
-                    if (n >= (int64_t)std::numeric_limits<int32_t>::max() / 2)
-                        return "too many pore voxels for int32 indexing";
-                    pidx[v] = (int32_t)n++;
+                    if (label_kind[labels[v]] != LBM_LABEL_SOLID) pidx[v] = (int32_t)k++;
                 }
+        }
+    }, nvox);
     if (n == 0) return "the image has no pore voxel";
     out = Prepass();
     out.n_pore = n;
     out.ld = (n + 63) / 64 * 64;
     out.pore_voxel.resize(n);
     out.phi0.resize(n);
-    for (int64_t v = 0; v < nvox; ++v) {
-        const int32_t i = pidx[v];
-        if (i < 0) continue;
-        out.pore_voxel[i] = v;
-        const int k = label_kind[labels[v]];
-        double ph = k == LBM_LABEL_FLUID_A ? 1.0 : (k == LBM_LABEL_FLUID_B ? -1.0 : 0.0);
-        if (k == LBM_LABEL_PORE_INIT) {
+    // Errors are reported for the first offending voxel in dense order, as a single pass would.
+    std::vector<int64_t> bad(nvox > 0 ? 17 : 1, nvox);
+    const int64_t vchunk = (nvox + 15) / 16;
+    parallel_for(16, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c)
+            for (int64_t v = c * vchunk; v < std::min(nvox, (c + 1) * vchunk); ++v) {
+                const int32_t i = pidx[v];
+                if (i < 0) continue;
+                out.pore_voxel[i] = v;
+                const int k = label_kind[labels[v]];
+                double ph = k == LBM_LABEL_FLUID_A ? 1.0 : (k == LBM_LABEL_FLUID_B ? -1.0 : 0.0);
+                if (k == LBM_LABEL_PORE_INIT) {
+                    ph = init_phi ? init_phi[v] : 0.0;
+                    if (!init_phi || !(ph >= -1.0 && ph <= 1.0)) {
+                        bad[c] = v;
+                        break;
+                    }
+                }
+                out.phi0[i] = ph;
+            }
+    }, nvox);
+    for (int c = 0; c < 16; ++c)
+        if (bad[c] < nvox) {
             if (!init_phi) return "init_phi is required for LBM_LABEL_PORE_INIT labels";
-            ph = init_phi[v];
-            if (!(ph >= -1.0 && ph <= 1.0)) return fmt("init_phi[%lld] is outside [-1, 1]", v);
+            return fmt("init_phi[%lld] is outside [-1, 1]", bad[c]);
         }
-        out.phi0[i] = ph;
-    }
 
     // Tail: entry 0 is the wall; then every solid voxel that is a D3Q19 neighbour of a pore
     // voxel, in dense order (so its tail index is a rank); z-face ghosts are appended on use.
@@ -108,84 +167,130 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
     auto solid_phi = [&](int64_t v) -> double {
         return voxel_affinity ? voxel_affinity[v] : label_affinity[labels[v]];
     };
-    std::vector<int32_t> tidx(nvox, 0);         // tail index of each tail solid (0: none)
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t v = out.pore_voxel[i];
-        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / (nx * ny));
-        for (int q = 1; q < 19; ++q) {
-            int c[3] = {x + CX[q], y + CY[q], z + CZ[q]};
-            bool outside = false;
-            for (int a = 0; a < 3; ++a)
-                if (c[a] < 0 || c[a] >= dims[a]) {
-                    if (p.periodic[a]) c[a] = (c[a] + dims[a]) % dims[a];
-                    else outside = true;
-                }
-            if (outside) continue;
-            const int64_t w = (int64_t)c[0] + nx * ((int64_t)c[1] + ny * (int64_t)c[2]);
-            if (pidx[w] < 0) tidx[w] = 1;
-        }
-    }
-    out.tail_phi.push_back(p.wall_affinity);
-    for (int64_t v = 0; v < nvox; ++v) {
-        if (!tidx[v]) continue;
-        const double ps = solid_phi(v);
-        if (!(ps >= -1.0 && ps <= 1.0)) return fmt("affinity of solid voxel %lld is outside [-1, 1]", v);
-        tidx[v] = (int32_t)out.tail_phi.size();
-        out.tail_phi.push_back(ps);
-    }
-    std::unordered_map<int64_t, int32_t> ghost_of;     // dense voxel mirrored -> tail index
-    out.nbr.assign((size_t)18 * out.ld, (int32_t)n);  // padding lanes point at the wall
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t v = out.pore_voxel[i];
-        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / (nx * ny));
-        for (int q = 1; q < 19; ++q) {
-            int c[3] = {x + CX[q], y + CY[q], z + CZ[q]};
-            bool outside = false, outside_z_only = false;
-            for (int a = 0; a < 3; ++a) {
-                if (c[a] < 0 || c[a] >= dims[a]) {
-                    if (p.periodic[a]) {
-                        c[a] = (c[a] + dims[a]) % dims[a];
-                    } else {
-                        outside = true;
+    // Marks of the solid neighbours, set from all threads (every writer stores 1).
+    std::vector<uint8_t> mark(nvox, 0);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t v = out.pore_voxel[i];
+            const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / (nx * ny));
+            for (int q = 1; q < 19; ++q) {
+                int c[3] = {x + CX[q], y + CY[q], z + CZ[q]};
+                bool outside = false;
+                for (int a = 0; a < 3; ++a)
+                    if (c[a] < 0 || c[a] >= dims[a]) {
+                        if (p.periodic[a]) c[a] = (c[a] + dims[a]) % dims[a];
+                        else outside = true;
                     }
-                }
-            }
-            int32_t entry;
-            if (outside) {
-                // Outside a wall face; with pressure faces an exit through z alone mirrors.
-                outside_z_only = p.bc_z == 1 && (c[2] < 0 || c[2] >= dims[2]) &&
-                                 c[0] >= 0 && c[0] < dims[0] && c[1] >= 0 && c[1] < dims[1];
-                if (!outside_z_only) {
-                    entry = (int32_t)n;  // tail 0: the wall
-                } else {
-                    const int64_t m = (int64_t)c[0] + nx * ((int64_t)c[1] + ny * (int64_t)z);
-                    auto it = ghost_of.find(m);
-                    int32_t t;
-                    if (it != ghost_of.end()) {
-                        t = it->second;
-                    } else {
-                        t = (int32_t)out.tail_phi.size();
-                        ghost_of.emplace(m, t);
-                        if (pidx[m] >= 0) {
-                            out.tail_phi.push_back(out.phi0[pidx[m]]);
-                            out.ghost_tail.push_back(t);
-                            out.ghost_src.push_back(pidx[m]);
-                        } else {
-                            // The in-plane mirror is itself a neighbour, so it is a tail solid.
-                            out.tail_phi.push_back(out.tail_phi[tidx[m]]);
-                        }
-                    }
-                    entry = (int32_t)(n + t);
-                }
-            } else {
+                if (outside) continue;
                 const int64_t w = (int64_t)c[0] + nx * ((int64_t)c[1] + ny * (int64_t)c[2]);
-                entry = pidx[w] >= 0 ? pidx[w] : (int32_t)(n + tidx[w]);
+                if (pidx[w] < 0) __atomic_store_n(&mark[w], (uint8_t)1, __ATOMIC_RELAXED);
             }
-            out.nbr[(size_t)(q - 1) * out.ld + i] = entry;
         }
-        if (p.bc_z == 1) {
+    });
+    // Tail indices in dense order: marks counted per chunk, then numbered from the prefix sum.
+    std::vector<int32_t> tidx(nvox, 0);         // tail index of each tail solid (0: none)
+    std::vector<int64_t> tcount(17, 0);
+    std::fill(bad.begin(), bad.end(), nvox);
+    parallel_for(16, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            int64_t k = 0;
+            for (int64_t v = c * vchunk; v < std::min(nvox, (c + 1) * vchunk); ++v) {
+                if (!mark[v]) continue;
+                const double ps = solid_phi(v);
+                if (!(ps >= -1.0 && ps <= 1.0)) {
+                    bad[c] = v;
+                    break;
+                }
+                ++k;
+            }
+            tcount[c + 1] = k;
+        }
+    }, nvox);
+    for (int c = 0; c < 16; ++c)
+        if (bad[c] < nvox) return fmt("affinity of solid voxel %lld is outside [-1, 1]", bad[c]);
+    for (int c = 0; c < 16; ++c) tcount[c + 1] += tcount[c];
+    out.tail_phi.assign((size_t)(1 + tcount[16]), p.wall_affinity);
+    parallel_for(16, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            int64_t t = 1 + tcount[c];
+            for (int64_t v = c * vchunk; v < std::min(nvox, (c + 1) * vchunk); ++v) {
+                if (!mark[v]) continue;
+                tidx[v] = (int32_t)t;
+                out.tail_phi[(size_t)t++] = solid_phi(v);
+            }
+        }
+    }, nvox);
+    // Neighbour table, in parallel over the pore voxels. An exit through a pressure face (z
+    // alone) needs a ghost tail entry, numbered in order of first use; those entries are
+    // filled afterwards by one thread in pore order, so the tail is the same for any thread
+    // count.
+    out.nbr.assign((size_t)18 * out.ld, (int32_t)n);  // padding lanes point at the wall
+    auto neighbour = [&](int x, int y, int z, int q, bool& ghost, int64_t& mirror) -> int32_t {
+        int c[3] = {x + CX[q], y + CY[q], z + CZ[q]};
+        bool outside = false;
+        for (int a = 0; a < 3; ++a) {
+            if (c[a] < 0 || c[a] >= dims[a]) {
+                if (p.periodic[a]) {
+                    c[a] = (c[a] + dims[a]) % dims[a];
+                } else {
+                    outside = true;
+                }
+            }
+        }
+        ghost = false;
+        if (outside) {
+            // Outside a wall face; with pressure faces an exit through z alone mirrors.
+            ghost = p.bc_z == 1 && (c[2] < 0 || c[2] >= dims[2]) && c[0] >= 0 &&
+                    c[0] < dims[0] && c[1] >= 0 && c[1] < dims[1];
+            if (ghost) mirror = (int64_t)c[0] + nx * ((int64_t)c[1] + ny * (int64_t)z);
+            return (int32_t)n;   // tail 0: the wall (a ghost entry is replaced below)
+        }
+        const int64_t w = (int64_t)c[0] + nx * ((int64_t)c[1] + ny * (int64_t)c[2]);
+        return pidx[w] >= 0 ? pidx[w] : (int32_t)(n + tidx[w]);
+    };
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t v = out.pore_voxel[i];
+            const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / (nx * ny));
+            for (int q = 1; q < 19; ++q) {
+                bool ghost;
+                int64_t mirror;
+                out.nbr[(size_t)(q - 1) * out.ld + i] = neighbour(x, y, z, q, ghost, mirror);
+            }
+        }
+    });
+    if (p.bc_z == 1) {
+        std::unordered_map<int64_t, int32_t> ghost_of;   // dense voxel mirrored -> tail index
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t v = out.pore_voxel[i];
+            const int z = (int)(v / (nx * ny));
+            if (z != 0 && z != nz - 1) continue;
             if (z == 0) out.inlet.push_back((int32_t)i);
-            if (z == p.nz - 1) out.outlet.push_back((int32_t)i);
+            if (z == nz - 1) out.outlet.push_back((int32_t)i);
+            const int x = (int)(v % nx), y = (int)((v / nx) % ny);
+            for (int q = 1; q < 19; ++q) {
+                bool ghost;
+                int64_t m = 0;
+                neighbour(x, y, z, q, ghost, m);
+                if (!ghost) continue;
+                auto it = ghost_of.find(m);
+                int32_t t;
+                if (it != ghost_of.end()) {
+                    t = it->second;
+                } else {
+                    t = (int32_t)out.tail_phi.size();
+                    ghost_of.emplace(m, t);
+                    if (pidx[m] >= 0) {
+                        out.tail_phi.push_back(out.phi0[pidx[m]]);
+                        out.ghost_tail.push_back(t);
+                        out.ghost_src.push_back(pidx[m]);
+                    } else {
+                        // The in-plane mirror is itself a neighbour, so it is a tail solid.
+                        out.tail_phi.push_back(out.tail_phi[tidx[m]]);
+                    }
+                }
+                out.nbr[(size_t)(q - 1) * out.ld + i] = (int32_t)(n + t);
+            }
         }
     }
     out.n_tail = (int64_t)out.tail_phi.size();
@@ -199,31 +304,47 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
         // A segment's pore voxels are consecutive in the pore list (rows stay whole in every
         // numbering) and its tail solids consecutive in the tail (dense order), so each base is
         // the index of the segment's first one.
-        int32_t next_tail = 1;
-        for (int64_t r = 0; r < ny * nz; ++r)
-            for (int64_t w = 0; w < W; ++w) {
-                RowWord& rw = out.words[(size_t)(r * W + w)];
-                rw.tail_base = next_tail;
-                bool first = true;
-                for (int b = 0; b < 64 && 64 * w + b < nx; ++b) {
-                    const int64_t v = r * nx + 64 * w + b;
-                    if (pidx[v] >= 0) {
-                        if (first) rw.pore_base = pidx[v];
-                        first = false;
-                        rw.pore |= 1ull << b;
-                    } else if (tidx[v]) {
-                        rw.tail |= 1ull << b;
-                        ++next_tail;
+        // Tail solids of each row, then each row's records from the prefix sum of those counts.
+        const int64_t nrows = ny * nz;
+        std::vector<int64_t> rtail(nrows + 1, 0);
+        parallel_for(nrows, [&](int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r) {
+                int64_t c = 0;
+                for (int64_t x = 0; x < nx; ++x) c += (pidx[r * nx + x] < 0 && tidx[r * nx + x]);
+                rtail[r + 1] = c;
+            }
+        }, nvox);
+        for (int64_t r = 0; r < nrows; ++r) rtail[r + 1] += rtail[r];
+        parallel_for(nrows, [&](int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r) {
+                int32_t next_tail = (int32_t)(1 + rtail[r]);
+                for (int64_t w = 0; w < W; ++w) {
+                    RowWord& rw = out.words[(size_t)(r * W + w)];
+                    rw.tail_base = next_tail;
+                    bool first = true;
+                    for (int b = 0; b < 64 && 64 * w + b < nx; ++b) {
+                        const int64_t v = r * nx + 64 * w + b;
+                        if (pidx[v] >= 0) {
+                            if (first) rw.pore_base = pidx[v];
+                            first = false;
+                            rw.pore |= 1ull << b;
+                        } else if (tidx[v]) {
+                            rw.tail |= 1ull << b;
+                            ++next_tail;
+                        }
                     }
                 }
             }
+        }, nvox);
         out.coord.assign((size_t)out.ld, 0u);
-        for (int64_t i = 0; i < n; ++i) {
-            const int64_t v = out.pore_voxel[i];
-            const uint32_t x = (uint32_t)(v % nx), y = (uint32_t)((v / nx) % ny);
-            const uint32_t z = (uint32_t)(v / (nx * ny));
-            out.coord[i] = x | (y << kCoordXBits) | (z << (kCoordXBits + kCoordYBits));
-        }
+        parallel_for(n, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const int64_t v = out.pore_voxel[i];
+                const uint32_t x = (uint32_t)(v % nx), y = (uint32_t)((v / nx) % ny);
+                const uint32_t z = (uint32_t)(v / (nx * ny));
+                out.coord[i] = x | (y << kCoordXBits) | (z << (kCoordXBits + kCoordYBits));
+            }
+        });
     }
     if (n + out.n_tail >= (int64_t)std::numeric_limits<int32_t>::max())
         return "pore voxels plus solid tail exceed int32 indexing";
