@@ -260,3 +260,73 @@ def test_prep_calls_validate_before_touching_the_device():
         lbm.prep_mixing_layer(labels, kind, 2, 0)
     with pytest.raises(lbm.LbmError, match="lbm_label_kind"):
         lbm.prep_mixing_layer(labels, np.array([0, 7], np.int8), 2, 1)
+
+
+@pytest.mark.parametrize("bc_z", [0, 1])
+def test_prepass_large_image_layout(bc_z):
+    """An image large enough that the pre-pass runs its loops on several threads: the pore
+    order (blocks of 16 rows, plane by plane), the tail of solid neighbours (dense order), every
+    neighbour-table entry and the pressure-face ghosts (numbered in order of first use) match a
+    NumPy construction of the same layout."""
+    shape = (40, 48, 56)
+    periodic = (True, True, bc_z == 0)
+    prob = _random_problem(shape, periodic, seed=21, frac=0.3)
+    prob.bc_z = bc_z
+    res = lbm.prepass_query(prob)
+    nz, ny, nx = shape
+    solid = prob.solid_mask().astype(bool)
+    z, y, x = np.nonzero(~solid)
+    order = np.lexsort((x, y, z, y // 16))
+    pv = (x + nx * (y + ny * z))[order]
+    assert np.array_equal(res["pore_voxel"], pv)
+    n = len(pv)
+    assert n >= 1 << 16
+    index = -np.ones(solid.size, np.int64)
+    index[pv] = np.arange(n)
+    px, py, pz = pv % nx, (pv // nx) % ny, pv // (nx * ny)
+    # tail: solid neighbours of pore voxels inside the domain, in dense order
+    mark = np.zeros(solid.size, bool)
+    cand = []
+    for q in range(1, 19):
+        c = [px + XI[q][0], py + XI[q][1], pz + XI[q][2]]
+        inside = np.ones(n, bool)
+        for a, dim in enumerate((nx, ny, nz)):
+            if periodic[a]:
+                c[a] = c[a] % dim
+            else:
+                inside &= (c[a] >= 0) & (c[a] < dim)
+        w = np.where(inside, c[0] + nx * (c[1] + ny * c[2]), -1)
+        cand.append((w, inside))
+        ws = w[inside]
+        mark[ws[solid.ravel()[ws]]] = True
+    tidx = np.zeros(solid.size, np.int64)
+    tidx[mark] = np.arange(1, mark.sum() + 1)
+    phis = prob.solid_affinity().ravel()
+    tail = res["tail_phi"]
+    assert np.array_equal(tail[1:1 + mark.sum()], phis[mark])
+    for q in range(1, 19):
+        w, inside = cand[q - 1]
+        want = np.full(n, n, np.int64)
+        wi = w[inside]
+        want[inside] = np.where(solid.ravel()[wi], n + tidx[wi], index[wi])
+        got = res["nbr"][q - 1, :n].astype(np.int64)
+        if bc_z:
+            ghost = ~inside
+            want[ghost] = got[ghost]          # checked below
+        assert np.array_equal(got, want), q
+    if bc_z:
+        phi0 = prob.phase0().ravel()
+        seen = {}
+        nxt = 1 + mark.sum()
+        for i in np.flatnonzero((pz == 0) | (pz == nz - 1)):
+            for q in range(1, 19):
+                if 0 <= pz[i] + XI[q][2] < nz:
+                    continue
+                m = (px[i] + XI[q][0]) % nx + nx * ((py[i] + XI[q][1]) % ny + ny * pz[i])
+                if m not in seen:
+                    seen[m] = nxt
+                    nxt += 1
+                e = res["nbr"][q - 1, i]
+                assert e == n + seen[m]
+                assert tail[seen[m]] == (phi0[m] if not solid.ravel()[m] else phis[m])
+        assert len(tail) == nxt
