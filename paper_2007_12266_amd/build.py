@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["lbm_kernels.hip", "lbm_runtime.hip", "lbm_pool.hip", "lbm_morph.hip",
-               "lbm_prep.hip"]
+               "lbm_prep.hip", "lbm_transfer.hip"]
 CPP_SOURCES = ["lbm_prepass.cpp"]
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -91,4 +91,10 @@ hipError_t launch_reduce_batched(const BatchArgs& b, int prec, bool odd, int nsl
 hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int block,
                         hipStream_t s);
 
+// Host <-> device copies of large caller buffers (lbm_transfer.hip): staged through pinned
+// memory by several host threads while the previous chunk's DMA runs. Ordered on stream s after
+// its earlier work; they return once the copy is complete (the stream is synchronised).
+hipError_t copy_to_device(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 }  // namespace lbm

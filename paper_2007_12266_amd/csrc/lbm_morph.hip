@@ -219,9 +219,8 @@ lbm_status ensure_buffers(lbm_domain* d) {
         d->morph_label = nullptr;   // the partial allocations stay with the domain
         return fail(LBM_ERR_OOM, "no device memory for the morphological work buffers");
     }
-    HIP_TRY(hipMemcpyAsync(d->morph_vox, d->pre.pore_voxel.data(), sizeof(int64_t) * (size_t)n,
-                           hipMemcpyHostToDevice, d->stream));
-    HIP_TRY(hipStreamSynchronize(d->stream));   // the host vector must outlive the copy
+    HIP_TRY(copy_to_device(d->morph_vox, d->pre.pore_voxel.data(), sizeof(int64_t) * (size_t)n,
+                           d->stream));
     return LBM_OK;
 }
 

@@ -840,12 +840,10 @@ lbm_status lbm_prep_distance(int32_t nx, int32_t ny, int32_t nz, const int32_t p
     int32_t* tmp = sc.get<int32_t>(b.nvox);
     int32_t* out = sc.get<int32_t>(b.nvox);
     if (!f || !bits || !tmp || !out) return sc.failed("the transform");
-    HIP_TRY(hipMemcpyAsync(f, feature, (size_t)b.nvox, hipMemcpyHostToDevice, s));
+    HIP_TRY(copy_to_device(f, feature, (size_t)b.nvox, s));
     if (lbm_status st = pack(b, FeatureNonzero{f}, Wide8Nonzero{f}, bits, s)) return st;
     if (lbm_status st = edt(b, bits, kInf, wall_axes, tmp, out, s)) return st;
-    HIP_TRY(hipMemcpyAsync(dist_sq, out, sizeof(int32_t) * (size_t)b.nvox, hipMemcpyDeviceToHost,
-                           s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(copy_to_host(dist_sq, out, sizeof(int32_t) * (size_t)b.nvox, s));
     for (int64_t v = 0; v < b.nvox; ++v)
         if (dist_sq[v] >= kInf) dist_sq[v] = -1;
     return LBM_OK;
@@ -883,7 +881,7 @@ lbm_status lbm_prep_drain(int32_t nx, int32_t ny, int32_t nz, const int32_t peri
     if (!db.pore || !db.d2 || !db.tmp || !db.mid || !db.centre || !db.part || !db.part2 ||
         !db.pairs || !nw_dev || (inlet && (!db.label || !db.flag || !db.reach)))
         return sc.failed("the drainage");
-    HIP_TRY(hipMemcpyAsync(db.pore, pore, (size_t)b.nvox, hipMemcpyHostToDevice, s));
+    HIP_TRY(copy_to_device(db.pore, pore, (size_t)b.nvox, s));
 
     // D^2: distance to the solid and to the wall planes of the non-periodic faces.
     if (lbm_status st = pack(b, FeatureZero{db.pore}, Wide8Zero{db.pore}, db.centre, s))
@@ -924,8 +922,7 @@ lbm_status lbm_prep_drain(int32_t nx, int32_t ny, int32_t nz, const int32_t peri
     if (lbm_status st = drain_eval(b, db, r.radius_sq, inlet, nw_dev, &r.n_nw, s)) return st;
     ++r.evaluations;
     r.sw = sw_of(r.n_nw);
-    HIP_TRY(hipMemcpyAsync(nw, nw_dev, (size_t)b.nvox, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(copy_to_host(nw, nw_dev, (size_t)b.nvox, s));
     *out = r;
     return LBM_OK;
 }
@@ -955,18 +952,15 @@ lbm_status lbm_prep_relabel(int32_t nx, int32_t ny, int32_t nz, const int32_t pe
     int32_t* tmp = sc.get<int32_t>(b.nvox);
     if (!lab || !res || !kind || !m || !bits || !e2 || !tmp)
         return sc.failed("the relabelling");
-    HIP_TRY(hipMemcpyAsync(lab, labels, sizeof(int32_t) * (size_t)b.nvox, hipMemcpyHostToDevice,
-                           s));
+    HIP_TRY(copy_to_device(lab, labels, sizeof(int32_t) * (size_t)b.nvox, s));
     HIP_TRY(hipMemcpyAsync(kind, label_kind, (size_t)n_labels, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(m, nw, (size_t)b.nvox, hipMemcpyHostToDevice, s));
+    HIP_TRY(copy_to_device(m, nw, (size_t)b.nvox, s));
     if (lbm_status st = pack(b, FeatureNonzero{m}, Wide8Nonzero{m}, bits, s)) return st;
     if (lbm_status st = edt(b, bits, cap, 0, tmp, e2, s)) return st;
     hipLaunchKernelGGL(relabel_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, (const int32_t*)lab,
                        (const int8_t*)kind, (const int32_t*)e2, within, new_label, res);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(labels_out, res, sizeof(int32_t) * (size_t)b.nvox,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(copy_to_host(labels_out, res, sizeof(int32_t) * (size_t)b.nvox, s));
     return LBM_OK;
 }
 
@@ -987,14 +981,11 @@ lbm_status lbm_prep_mixing_layer(int32_t nx, int32_t ny, int32_t nz, const int32
     int32_t* res = sc.get<int32_t>(b.nvox);
     int8_t* kind = sc.get<int8_t>(n_labels);
     if (!lab || !res || !kind) return sc.failed("the mixing layer");
-    HIP_TRY(hipMemcpyAsync(lab, labels, sizeof(int32_t) * (size_t)b.nvox, hipMemcpyHostToDevice,
-                           s));
+    HIP_TRY(copy_to_device(lab, labels, sizeof(int32_t) * (size_t)b.nvox, s));
     HIP_TRY(hipMemcpyAsync(kind, label_kind, (size_t)n_labels, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(mixing_kernel, vox_grid(b), dim3(b.tpb), 0, s, b, (const int32_t*)lab,
                        (const int8_t*)kind, nmix, pore_label, res);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(labels_out, res, sizeof(int32_t) * (size_t)b.nvox,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(copy_to_host(labels_out, res, sizeof(int32_t) * (size_t)b.nvox, s));
     return LBM_OK;
 }

@@ -311,8 +311,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         return fail(LBM_ERR_OOM, "device allocation failed");
     }
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, d->stream)
-                     : hipSuccess;
+        return copy_to_device(dst, src, bytes, d->stream);
     };
     lbm_status st = LBM_OK;
     auto guard = [&](hipError_t e, const char* what) {
@@ -389,9 +388,7 @@ lbm_status lbm_read_pore_field(lbm_domain* d, int32_t field, double* host_pore) 
     if (!host_pore) return fail(LBM_ERR_ARG, "host_pore must be non-null");
     const StepArgs a = d->args();
     HIP_TRY(launch_field(a, (d->step & 1) != 0, field, d->stage, d->block, d->stream));
-    HIP_TRY(hipMemcpyAsync(host_pore, d->stage, sizeof(double) * d->pre.n_pore,
-                           hipMemcpyDeviceToHost, d->stream));
-    HIP_TRY(hipStreamSynchronize(d->stream));
+    HIP_TRY(copy_to_host(host_pore, d->stage, sizeof(double) * d->pre.n_pore, d->stream));
     return LBM_OK;
 }
 
@@ -535,12 +532,10 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
     std::memcpy(host_buf, &h, sizeof h);
     char* dst = (char*)host_buf + sizeof h;
     // f: 19 rows of n values and M: 4 rows of n value pairs (pitch ld on the device).
-    HIP_TRY(hipMemcpy2DAsync(dst, eb * n, d->f, eb * ld, eb * n, 19, hipMemcpyDeviceToHost,
-                             d->stream));
-    dst += eb * n * 19;
-    HIP_TRY(hipMemcpy2DAsync(dst, 2 * eb * n, d->M, 2 * eb * ld, 2 * eb * n, 4,
-                             hipMemcpyDeviceToHost, d->stream));
-    HIP_TRY(hipStreamSynchronize(d->stream));
+    for (int q = 0; q < 19; ++q, dst += eb * n)
+        HIP_TRY(copy_to_host(dst, (const char*)d->f + eb * ld * q, eb * n, d->stream));
+    for (int k = 0; k < 4; ++k, dst += 2 * eb * n)
+        HIP_TRY(copy_to_host(dst, (const char*)d->M + 2 * eb * ld * k, 2 * eb * n, d->stream));
     *nbytes = need;
     return LBM_OK;
 }
@@ -559,11 +554,10 @@ lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes) {
         nbytes != sizeof h + eb * kStateRows * n)
         return fail(LBM_ERR_STATE, "state does not match this domain");
     const char* src = (const char*)host_buf + sizeof h;
-    HIP_TRY(hipMemcpy2DAsync(d->f, eb * ld, src, eb * n, eb * n, 19, hipMemcpyHostToDevice,
-                             d->stream));
-    src += eb * n * 19;
-    HIP_TRY(hipMemcpy2DAsync(d->M, 2 * eb * ld, src, 2 * eb * n, 2 * eb * n, 4,
-                             hipMemcpyHostToDevice, d->stream));
+    for (int q = 0; q < 19; ++q, src += eb * n)
+        HIP_TRY(copy_to_device((char*)d->f + eb * ld * q, src, eb * n, d->stream));
+    for (int k = 0; k < 4; ++k, src += 2 * eb * n)
+        HIP_TRY(copy_to_device((char*)d->M + 2 * eb * ld * k, src, 2 * eb * n, d->stream));
     d->one = h.fresh ? 1 : 0;                // a state at rest (initial, or after lbm_morph)
     HIP_TRY(hipMemcpyAsync(d->fresh, &d->one, sizeof(int32_t), hipMemcpyHostToDevice,
                            d->stream));
