@@ -414,13 +414,19 @@ class Domain:
         L = load_library()
         n = ctypes.c_size_t()
         _check(L.lbm_state_save(self.handle, None, ctypes.byref(n)))
-        buf = ctypes.create_string_buffer(n.value)
-        _check(L.lbm_state_save(self.handle, buf, ctypes.byref(n)))
-        return buf.raw
+        buf = np.empty(n.value, dtype=np.uint8)        # no zero fill before the library writes
+        _check(L.lbm_state_save(self.handle, _ptr(buf), ctypes.byref(n)))
+        return buf.tobytes()
 
-    def load(self, blob: bytes):
-        buf = ctypes.create_string_buffer(blob, len(blob))
-        _check(load_library().lbm_state_load(self.handle, buf, len(blob)))
+    def load(self, blob):
+        """Restore a state from lbm_state_save's bytes (bytes, bytearray or a uint8 array); the
+        library reads the caller's buffer in place."""
+        if isinstance(blob, bytes):
+            ptr = ctypes.cast(ctypes.c_char_p(blob), ctypes.c_void_p)
+        else:
+            arr = np.frombuffer(blob, dtype=np.uint8)
+            ptr = ctypes.c_void_p(arr.ctypes.data)
+        _check(load_library().lbm_state_load(self.handle, ptr, len(blob)))
         return self
 
     def autotune(self, trial_steps: int = 10) -> dict:
