@@ -38,7 +38,8 @@
  * tension and profile, the Laplace law, contact angles, symmetries, pressure-driven slit flow and
  * an independent brute-force implementation; the unlisted equilibria are pinned to the published
  * D3Q19 equilibria of d'Humieres et al. (2002). One reading has no value to pin it: the
- * composition imposed at the pressure faces beyond "a enters, b leaves" -- parity unpinned there.
+ * composition imposed at the pressure faces beyond fluid a entering and fluid b leaving -- parity
+ * unpinned there.
  *
  * State layout: f[q * nvox + v], A[q * nvox + v], B[q * nvox + v], v = x + nx*(y + ny*z).
  * Entries of solid voxels are never read and are left as they are.
