@@ -247,8 +247,9 @@ lbm_status lbm_run_steady(lbm_domain* d, const lbm_steady_params* sp, lbm_steady
  * nothing across the boundary within the radius keep their phase), and the densities restart
  * at rest with N_a = N (1 + phi')/2, N_b = N (1 - phi')/2 and the voxel's current N. The flow
  * populations, the step counter and the history are kept. The first call allocates work
- * buffers (about 1.1 nx*ny*nz bytes plus 17 bytes per pore voxel) that stay with the domain. Errors:
- * LBM_ERR_ARG (parameters), LBM_ERR_STATE (pooled domain), LBM_ERR_OOM. Synchronises. */
+ * buffers (about 4.3 nx*ny*nz bytes plus 17 bytes per pore voxel) that stay with the domain.
+ * Errors: LBM_ERR_ARG (parameters; also an image of 2^31 voxels or more, or an edge above
+ * 16384), LBM_ERR_STATE (pooled domain), LBM_ERR_OOM. Synchronises. */
 typedef struct {
     double delta;          /* growth distance in voxels; |delta| <= radius - 2; unused when
                             * target_ratio > 0                                               */

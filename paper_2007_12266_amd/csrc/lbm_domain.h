@@ -74,6 +74,10 @@ struct lbm_domain {
     // Work buffers of the morphological growth step, allocated on its first use.
     uint8_t* morph_label = nullptr;  // [nx*ny*nz] 1 where a pore voxel has phi > 0
     uint64_t* morph_bits = nullptr;  // [nz][ny][ceil(nx/64)] the same labels as row bits
+    uint64_t* morph_other = nullptr; // their complement within each row
+    uint8_t* morph_to_a = nullptr;   // [nx*ny*nz] squared distance to fluid a, clipped
+    uint8_t* morph_to_b = nullptr;   // [nx*ny*nz] squared distance to the rest, clipped
+    uint8_t* morph_tmp = nullptr;    // [nx*ny*nz] transform scratch
     int64_t* morph_vox = nullptr;    // [N] dense index of each pore voxel
     double* morph_dist = nullptr;    // [N] signed distance map Phi_a
     int8_t* morph_far = nullptr;     // [N] 1: no voxel across the boundary within the radius

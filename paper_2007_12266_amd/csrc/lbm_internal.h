@@ -97,4 +97,13 @@ hipError_t launch_field(const StepArgs& a, bool odd, int field, double* out, int
 hipError_t copy_to_device(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// Squared distances between voxel centres for the morphological step (lbm_prep.hip), clipped
+// at cap (<= 255): to_a[v] to the nearest voxel whose bit is set in label_bits (rows packed as
+// 64-voxel words), to_other[v] to the nearest voxel whose bit is clear or beyond a non-periodic
+// face (periodic: bit a for axis a). other_bits receives the complement bits; tmp, to_a and
+// to_other hold nx*ny*nz bytes each.
+lbm_status morph_distance(int nx, int ny, int nz, int periodic, const uint64_t* label_bits,
+                          uint64_t* other_bits, int32_t cap, uint8_t* tmp, uint8_t* to_a,
+                          uint8_t* to_other, hipStream_t s);
+
 }  // namespace lbm

@@ -13,6 +13,11 @@
 // and keeps its phase. The new phase is phi' = 2 e / (1 + e) - 1, e = exp(-2 beta (Phi_a -
 // delta)); N_a = N (1 + phi')/2, N_b = N (1 - phi')/2 with the voxel's current N; the D3Q7
 // populations restart at rest (the fresh state), the D3Q19 populations are kept.
+//
+// The far-field distances come from two exact separable distance transforms of the dense
+// fluid-a bits (shared with the image pre-processing), clipped at radius^2 + 1 and stored as
+// bytes: the distance to fluid a, for the voxels outside it, and the distance to the rest
+// (with the planes beyond non-periodic faces), for the voxels inside it.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -49,51 +54,13 @@ __global__ void __launch_bounds__(256) morph_pack_kernel(int64_t nrows, int nx, 
     bits[k] = m;
 }
 
-// Smallest |dx| <= radius such that the label at x + dx in row `row` differs from `own`
-// (radius + 1 if none). Outside a non-periodic x face the label is 0 (not fluid a).
-__device__ __forceinline__ int row_nearest(const uint64_t* __restrict__ bits, int64_t row, int x,
-                                           int nx, int words, bool xper, int own, int radius) {
-    const uint64_t* r = bits + row * words;
-    if (x - radius >= 0 && x + radius < nx) {
-        // Window of 2 radius + 1 bits starting at x - radius (radius <= 12: within two words).
-        const int lo = x - radius;
-        const int w = lo >> 6, sh = lo & 63;
-        uint64_t win = r[w] >> sh;
-        if (sh && w + 1 < words) win |= r[w + 1] << (64 - sh);
-        const int width = 2 * radius + 1;
-        uint64_t opp = own ? ~win : win;
-        opp &= (width == 64 ? ~0ull : ((1ull << width) - 1ull));
-        int best = radius + 1;
-        const uint64_t right = opp >> radius;              // dx >= 0
-        if (right) best = __ffsll((long long)right) - 1;
-        const uint64_t left = opp & ((1ull << radius) - 1ull);   // dx < 0
-        if (left) best = min(best, radius - (63 - __clzll((long long)left)));
-        return best;
-    }
-    for (int dx = 0; dx <= radius; ++dx)
-        for (int sgn = 0; sgn < 2; ++sgn) {
-            if (dx == 0 && sgn) continue;
-            int xx = sgn ? x - dx : x + dx;
-            int lab;
-            if (xx < 0 || xx >= nx) {
-                if (!xper) {
-                    lab = 0;
-                } else {
-                    xx = xx < 0 ? xx + nx : xx - nx;
-                    lab = (int)((r[xx >> 6] >> (xx & 63)) & 1ull);
-                }
-            } else {
-                lab = (int)((r[xx >> 6] >> (xx & 63)) & 1ull);
-            }
-            if (lab != own) return dx;
-        }
-    return radius + 1;
-}
-
+// Phi_a of every pore voxel: the closed form in the band; elsewhere -/+(d - 1/2) with d^2 the
+// squared distance to the nearest voxel across the boundary of fluid a (to_b for a voxel of
+// fluid a, to_a for any other), both clipped at radius^2 + 1, which marks a far voxel.
 template <typename S>
 __global__ void __launch_bounds__(256) morph_distance_kernel(
-    int n, int nx, int ny, int nz, int periodic, const int64_t* __restrict__ vox,
-    const S* __restrict__ phi, const uint64_t* __restrict__ bits, int words, double beta,
+    int n, const int64_t* __restrict__ vox, const S* __restrict__ phi,
+    const uint8_t* __restrict__ to_a, const uint8_t* __restrict__ to_b, double beta,
     double phi_band, int radius, double* __restrict__ dist, int8_t* __restrict__ far) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -104,38 +71,9 @@ __global__ void __launch_bounds__(256) morph_distance_kernel(
         return;
     }
     const int64_t v = vox[i];
-    const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
     const int own = ph > 0.0 ? 1 : 0;
-    const int r2max = radius * radius;
-    int best = r2max + 1;
-    for (int dz = -radius; dz <= radius; ++dz) {
-        const int z2 = dz * dz;
-        if (z2 >= best) continue;
-        int zz = z + dz;
-        bool zin = zz >= 0 && zz < nz;
-        if (!zin && (periodic & 4)) {
-            zz = zz < 0 ? zz + nz : zz - nz;
-            zin = true;
-        }
-        for (int dy = -radius; dy <= radius; ++dy) {
-            const int zy2 = z2 + dy * dy;
-            if (zy2 >= best) continue;
-            int yy = y + dy;
-            bool yin = yy >= 0 && yy < ny;
-            if (!yin && (periodic & 2)) {
-                yy = yy < 0 ? yy + ny : yy - ny;
-                yin = true;
-            }
-            int dx;
-            if (!zin || !yin)
-                dx = own ? 0 : radius + 1;   // a row outside the domain is not fluid a
-            else
-                dx = row_nearest(bits, (int64_t)yy + (int64_t)ny * zz, x, nx, words,
-                                 (periodic & 1) != 0, own, radius);
-            if (dx <= radius) best = min(best, zy2 + dx * dx);
-        }
-    }
-    if (best > r2max) {
+    const int best = own ? (int)to_b[v] : (int)to_a[v];
+    if (best > radius * radius) {
         far[i] = 1;
         dist[i] = own ? -(radius + 0.5) : (radius + 0.5);
     } else {
@@ -214,8 +152,13 @@ lbm_status ensure_buffers(lbm_domain* d) {
     d->morph_count = (long long*)d->dalloc(sizeof(long long) * kMorphBlocks);
     const int64_t words = (int64_t)d->p.ny * d->p.nz * ((d->p.nx + 63) / 64);
     d->morph_bits = (uint64_t*)d->dalloc(sizeof(uint64_t) * (size_t)words);
+    d->morph_other = (uint64_t*)d->dalloc(sizeof(uint64_t) * (size_t)words);
+    d->morph_to_a = (uint8_t*)d->dalloc((size_t)nvox);
+    d->morph_to_b = (uint8_t*)d->dalloc((size_t)nvox);
+    d->morph_tmp = (uint8_t*)d->dalloc((size_t)nvox);
     if (!d->morph_label || !d->morph_vox || !d->morph_dist || !d->morph_far ||
-        !d->morph_count || !d->morph_bits) {
+        !d->morph_count || !d->morph_bits || !d->morph_other || !d->morph_to_a ||
+        !d->morph_to_b || !d->morph_tmp) {
         d->morph_label = nullptr;   // the partial allocations stay with the domain
         return fail(LBM_ERR_OOM, "no device memory for the morphological work buffers");
     }
@@ -278,9 +221,13 @@ lbm_status distance_map(lbm_domain* d, const lbm_morph_params& mp) {
     hipLaunchKernelGGL(morph_pack_kernel, dim3(blocks_for(nrows * words)), dim3(256), 0,
                        d->stream, nrows, d->p.nx, words, d->morph_label, d->morph_bits);
     HIP_TRY(hipGetLastError());
+    if (lbm_status st = morph_distance(d->p.nx, d->p.ny, d->p.nz, periodic, d->morph_bits,
+                                       d->morph_other, mp.radius * mp.radius + 1, d->morph_tmp,
+                                       d->morph_to_a, d->morph_to_b, d->stream))
+        return st;
     hipLaunchKernelGGL(morph_distance_kernel<S>, dim3(blocks_for(n)), dim3(256), 0, d->stream,
-                       n, d->p.nx, d->p.ny, d->p.nz, periodic, d->morph_vox, (const S*)d->phi,
-                       d->morph_bits, words, d->p.beta, std::tanh(mp.band * d->p.beta),
+                       n, d->morph_vox, (const S*)d->phi, (const uint8_t*)d->morph_to_a,
+                       (const uint8_t*)d->morph_to_b, d->p.beta, std::tanh(mp.band * d->p.beta),
                        mp.radius, d->morph_dist, d->morph_far);
     HIP_TRY(hipGetLastError());
     return LBM_OK;

@@ -184,6 +184,17 @@ __global__ void __launch_bounds__(256) pack8_kernel(Box b, P pred, uint64_t* __r
     if (g == 0 && word < b.nwords) bits[word] = m;
 }
 
+// Complement of row bits within each row (bits past nx stay clear).
+__global__ void __launch_bounds__(256) invert_bits_kernel(Box b, const uint64_t* __restrict__ in,
+                                                          uint64_t* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.nwords) return;
+    const int w = (int)(k % b.W);
+    const int tail = b.nx & 63;
+    const uint64_t valid = (w == b.W - 1 && tail) ? ((1ull << tail) - 1ull) : ~0ull;
+    out[k] = ~in[k] & valid;
+}
+
 // First set bit at a position in [p, e] of a row (p <= e), or -1.
 __device__ __forceinline__ int first_set(const uint64_t* __restrict__ r, int p, int e) {
     int w = p >> 6;
@@ -276,9 +287,10 @@ __device__ __forceinline__ int row_dist(const uint64_t* __restrict__ r, int W, i
     return d;
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256) edt_row_kernel(Box b, const uint64_t* __restrict__ bits,
                                                       int lim, int32_t cap,
-                                                      int32_t* __restrict__ out) {
+                                                      T* __restrict__ out) {
     const int row = (int)blockIdx.x;
     const int x0 = 4 * ((int)blockIdx.y * (int)blockDim.x + (int)threadIdx.x);
     if (x0 >= b.nx) return;
@@ -297,17 +309,23 @@ __global__ void __launch_bounds__(256) edt_row_kernel(Box b, const uint64_t* __r
     }
     const int64_t v = (int64_t)row * b.nx + x0;
     if ((b.nx & 3) == 0) {
-        *reinterpret_cast<int4*>(out + v) = make_int4(res[0], res[1], res[2], res[3]);
+        if constexpr (sizeof(T) == 4)
+            *reinterpret_cast<int4*>(out + v) = make_int4(res[0], res[1], res[2], res[3]);
+        else
+            *reinterpret_cast<uchar4*>(out + v) =
+                make_uchar4((unsigned char)res[0], (unsigned char)res[1], (unsigned char)res[2],
+                            (unsigned char)res[3]);
     } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (x0 + j < b.nx) out[v + j] = res[j];
+            if (x0 + j < b.nx) out[v + j] = (T)res[j];
     }
 }
 
 // Continues min over d >= d0 of in[base + ((c + d) mod n) stride] + d^2 (offsets outside a
 // non-periodic line are skipped) from `best`, stopping once d^2 reaches best.
-__device__ __forceinline__ int line_min_from(const int32_t* __restrict__ in, int64_t base,
+template <typename T>
+__device__ __forceinline__ int line_min_from(const T* __restrict__ in, int64_t base,
                                              int64_t stride, int c, int n, bool per, int best,
                                              int d0) {
     const int lim = per ? n / 2 : max(c, n - 1 - c);
@@ -317,8 +335,8 @@ __device__ __forceinline__ int line_min_from(const int32_t* __restrict__ in, int
         int a = c + d, e = c - d;
         if (a >= n) a = per ? a - n : -1;
         if (e < 0) e = per ? e + n : -1;
-        if (a >= 0) best = min(best, in[base + (int64_t)a * stride] + d2);
-        if (e >= 0) best = min(best, in[base + (int64_t)e * stride] + d2);
+        if (a >= 0) best = min(best, (int)in[base + (int64_t)a * stride] + d2);
+        if (e >= 0) best = min(best, (int)in[base + (int64_t)e * stride] + d2);
     }
     return best;
 }
@@ -346,10 +364,10 @@ __device__ __forceinline__ int wall_min(const Box& b, int walls, int x, int y, i
 //           (kPrepThreads threads).
 constexpr int kSeg = 8;
 
-template <int MODE>
+template <int MODE, typename T>
 __global__ void __launch_bounds__(256) edt_seg_kernel(Box b, int ax, int32_t cap, int walls,
-                                                      const int32_t* __restrict__ in,
-                                                      int32_t* __restrict__ out,
+                                                      const T* __restrict__ in,
+                                                      T* __restrict__ out,
                                                       const uint8_t* __restrict__ pore,
                                                       uint8_t* __restrict__ nw,
                                                       int* __restrict__ part) {
@@ -370,7 +388,7 @@ __global__ void __launch_bounds__(256) edt_seg_kernel(Box b, int ax, int32_t cap
         for (int j = 0; j < kSeg + 8; ++j) {
             int c = c0 - 4 + j;
             if (c < 0 || c >= n) c = per ? ((c % n) + n) % n : -1;
-            win[j] = c >= 0 ? in[base + (int64_t)c * stride] : kInf;
+            win[j] = c >= 0 ? (int)in[base + (int64_t)c * stride] : kInf;
         }
 #pragma unroll
         for (int i = 0; i < kSeg; ++i) {
@@ -388,7 +406,7 @@ __global__ void __launch_bounds__(256) edt_seg_kernel(Box b, int ax, int32_t cap
                 best = min(best, min(win[i + 4 + d], win[i + 4 - d]) + d * d);
             if (best > 25) best = line_min_from(in, base, stride, c, n, per, best, 5);
             if (MODE == 0) {
-                out[v] = min(best, cap);
+                out[v] = (T)min(best, cap);
             } else {
                 const bool f = best < cap;
                 cnt += f ? 1 : 0;
@@ -739,25 +757,27 @@ int64_t seg_blocks(const Box& b, int ax) {
 }
 
 // Row and y passes of the transform of the feature bits: leaves the y-pass result in mid
-// (row-pass scratch in tmp).
-lbm_status edt_xy(const Box& b, const uint64_t* bits, int32_t cap, int32_t* tmp, int32_t* mid,
+// (row-pass scratch in tmp). T holds values up to cap (int32_t, or uint8_t for caps <= 255).
+template <typename T>
+lbm_status edt_xy(const Box& b, const uint64_t* bits, int32_t cap, T* tmp, T* mid,
                   hipStream_t s) {
-    hipLaunchKernelGGL(edt_row_kernel, row_grid(b), dim3(row_threads(b)), 0, s, b, bits,
+    hipLaunchKernelGGL(edt_row_kernel<T>, row_grid(b), dim3(row_threads(b)), 0, s, b, bits,
                        row_limit(b, cap), cap, tmp);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(edt_seg_kernel<0>, seg_grid(b, 1), dim3(b.tpb), 0, s, b, 1, cap, 0,
-                       (const int32_t*)tmp, mid, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((edt_seg_kernel<0, T>), seg_grid(b, 1), dim3(b.tpb), 0, s, b, 1, cap, 0,
+                       (const T*)tmp, mid, nullptr, nullptr, nullptr);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
 
 // Full squared distance transform of the feature bits into out (tmp: a second buffer of nvox);
 // values at or above cap are clipped to cap.
-lbm_status edt(const Box& b, const uint64_t* bits, int32_t cap, int walls, int32_t* tmp,
-               int32_t* out, hipStream_t s) {
-    if (lbm_status st = edt_xy(b, bits, cap, out, tmp, s)) return st;
-    hipLaunchKernelGGL(edt_seg_kernel<0>, seg_grid(b, 2), dim3(b.tpb), 0, s, b, 2, cap, walls,
-                       (const int32_t*)tmp, out, nullptr, nullptr, nullptr);
+template <typename T>
+lbm_status edt(const Box& b, const uint64_t* bits, int32_t cap, int walls, T* tmp, T* out,
+               hipStream_t s) {
+    if (lbm_status st = edt_xy<T>(b, bits, cap, out, tmp, s)) return st;
+    hipLaunchKernelGGL((edt_seg_kernel<0, T>), seg_grid(b, 2), dim3(b.tpb), 0, s, b, 2, cap,
+                       walls, (const T*)tmp, out, nullptr, nullptr, nullptr);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
@@ -810,7 +830,7 @@ lbm_status drain_eval(const Box& b, const DrainBuffers& db, int32_t k, bool inle
     if (lbm_status st = edt_xy(b, feat, k, db.tmp, db.mid, s)) return st;
     // kPrepThreads per workgroup (its block sum needs them all): whenever b.tpb is smaller,
     // there is one chunk per row, which 256 threads cover as well.
-    hipLaunchKernelGGL(edt_seg_kernel<1>, seg_grid(b, 2), dim3(kPrepThreads), 0, s, b, 2, k, 0,
+    hipLaunchKernelGGL((edt_seg_kernel<1, int32_t>), seg_grid(b, 2), dim3(kPrepThreads), 0, s, b, 2, k, 0,
                        (const int32_t*)db.mid, nullptr, (const uint8_t*)db.pore, nw_dev, db.part);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kSumThreads), 0, s, (const int*)db.part,
@@ -824,6 +844,24 @@ lbm_status drain_eval(const Box& b, const DrainBuffers& db, int32_t k, bool inle
 }
 
 }  // namespace
+
+namespace lbm {
+
+lbm_status morph_distance(int nx, int ny, int nz, int periodic, const uint64_t* label_bits,
+                          uint64_t* other_bits, int32_t cap, uint8_t* tmp, uint8_t* to_a,
+                          uint8_t* to_other, hipStream_t s) {
+    if (cap < 1 || cap > 255) return fail(LBM_ERR_ARG, "internal: distance cap outside [1, 255]");
+    const int32_t per[3] = {periodic & 1, (periodic >> 1) & 1, (periodic >> 2) & 1};
+    Box b{};
+    if (lbm_status st = check_box(nx, ny, nz, per, &b)) return st;
+    if (lbm_status st = edt<uint8_t>(b, label_bits, cap, 0, tmp, to_a, s)) return st;
+    hipLaunchKernelGGL(invert_bits_kernel, dim3((unsigned)((b.nwords + 255) / 256)), dim3(256), 0,
+                       s, b, label_bits, other_bits);
+    HIP_TRY(hipGetLastError());
+    return edt<uint8_t>(b, other_bits, cap, 7, tmp, to_other, s);
+}
+
+}  // namespace lbm
 
 lbm_status lbm_prep_distance(int32_t nx, int32_t ny, int32_t nz, const int32_t periodic[3],
                              int32_t wall_axes, const uint8_t* feature, int32_t* dist_sq,
