@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <limits>
+#include <system_error>
 #include <thread>
 #include <unordered_map>
 
@@ -54,7 +55,11 @@ void parallel_for(int64_t n, F body, int64_t work = -1) {
     for (unsigned t = 0; t < hw; ++t) {
         const int64_t b = (int64_t)t * chunk, e = std::min(n, b + chunk);
         if (b >= e) break;
-        pool.emplace_back(body, b, e);
+        try {
+            pool.emplace_back(body, b, e);
+        } catch (const std::system_error&) {
+            body(b, e);   // no thread to be had: this chunk runs here
+        }
     }
     for (std::thread& th : pool) th.join();
 }

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -56,7 +57,11 @@ void copy_threads(void* dst, const void* src, size_t n) {
         const size_t b = t * slice;
         if (b >= n) break;
         const size_t len = std::min(slice, n - b);
-        pool.emplace_back([=] { std::memcpy((char*)dst + b, (const char*)src + b, len); });
+        try {
+            pool.emplace_back([=] { std::memcpy((char*)dst + b, (const char*)src + b, len); });
+        } catch (const std::system_error&) {
+            std::memcpy((char*)dst + b, (const char*)src + b, len);   // no thread: copy here
+        }
     }
     for (std::thread& th : pool) th.join();
 }
