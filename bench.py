@@ -151,6 +151,56 @@ def prep_study(prob, lbm) -> dict:
             "relabelled": int((relab == new_label).sum())}
 
 
+def steady_study(prob, args, lbm, plain_ms: float) -> dict:
+    """One steady-state point under the paper's flow control (lbm_run_steady) on the workload:
+    1000 relaxation steps, one force rescaling towards 1.5x the measured capillary number
+    (capped at 2x), then 500-step blocks until |dCa|/Ca < 1e-3 or 10000 steps. Reports the
+    decision and the cost per step against plain stepping."""
+    P = lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV
+    dom = lbm.Domain(prob, precision=P, allocator="hip")
+    dom.step(200)
+    ca0 = dom.reduce()["ca"]
+    t0 = time.perf_counter()
+    r = dom.run_steady(ca_target=1.5 * ca0, relax_steps=1000, interval=500, tol=1e-3,
+                       max_steps=10000)
+    wall = time.perf_counter() - t0
+    dom.close()
+    ms = wall * 1e3 / max(r["steps"], 1)
+    return {"steps": r["steps"], "converged": r["converged"], "rescales": r["rescales"],
+            "factor": r["factor"], "ca_start": ca0, "ca_target": 1.5 * ca0, "ca_end": r["ca"],
+            "delta_ca": r["delta_ca"], "wall_s": round(wall, 3), "ms_per_step": round(ms, 5),
+            "overhead_vs_plain": round(ms / plain_ms - 1.0, 4)}
+
+
+def flux_study(prob, args, lbm) -> dict:
+    """The flux inlet on a pressure-face workload: the same geometry stepped with the imposed
+    inlet density and with the imposed total flow rate (inlet_mode 1, flux = the flow rate the
+    density inlet carries after 200 steps); per-step device time of the boundary kernels
+    (inlet density + pressure faces) and of the whole step from HIP events."""
+    import dataclasses
+    P = lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV
+    out = {}
+    dom = lbm.Domain(prob, precision=P, allocator="hip")
+    dom.step(200)
+    uz = dom.pore_field("uz")
+    pv = dom.pore_index()
+    plane = prob.shape[1] * prob.shape[2]
+    flux = float(uz[pv < plane].sum())
+    t = dom.step_timed(100)
+    out["density_inlet"] = {"bc_ms": round(t["bc_ms"], 5), "step_ms": round(t["step_ms"], 5)}
+    dom.close()
+    fprob = dataclasses.replace(prob, inlet_mode=1, flux_in=flux)
+    dom = lbm.Domain(fprob, precision=P, allocator="hip")
+    dom.step(200)
+    t = dom.step_timed(100)
+    uz = dom.pore_field("uz")
+    out["flux_inlet"] = {"flux_in": flux, "bc_ms": round(t["bc_ms"], 5),
+                         "step_ms": round(t["step_ms"], 5),
+                         "inlet_flux_after": float(uz[pv < plane].sum())}
+    dom.close()
+    return out
+
+
 def precision_study(prob, steps: int, every: int, torch, lbm) -> dict:
     """FP32-deviation against FP64 on the same problem: both advance side by side and every
     `every` steps the saturation, the Darcy flux and the front position are compared."""
@@ -446,6 +496,12 @@ def main():
     ap.add_argument("--morph-study", action="store_true",
                     help="also time the morphological growth step (dilation by 0.5 voxel) "
                          "and the phase-volume count on the same workload")
+    ap.add_argument("--steady-study", action="store_true",
+                    help="also run one steady-state point under the flow control "
+                         "(lbm_run_steady) and report its cost per step")
+    ap.add_argument("--flux-study", action="store_true",
+                    help="pressure-face workloads: also time the flux inlet against the "
+                         "density inlet")
     ap.add_argument("--prep-study", action="store_true",
                     help="also time the image pre-processing calls (drainage, distance "
                          "transform, relabelling, mixing layer) on the workload's image")
@@ -565,6 +621,10 @@ def main():
         out["morph"] = morph_study(prob, args, torch, lbm)
     if args.prep_study:
         out["prep"] = prep_study(prob, lbm)
+    if args.steady_study:
+        out["steady"] = steady_study(prob, args, lbm, ms_per_step)
+    if args.flux_study:
+        out["flux_inlet"] = flux_study(prob, args, lbm)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         sample = prob if wl["n"] <= 256 else make_problem(wl, n=256)

@@ -74,9 +74,11 @@ hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* f
                               int32_t n_in, int32_t n_out, double rho_in, double rho_out,
                               const double* rho_in_dev, hipStream_t s);
 // Flux inlet: the inlet density for which the flow velocity summed over the n_in inlet voxels
-// (faces[0..n_in)) equals flux, written to *rho_in_dev (one workgroup, fixed order).
+// (faces[0..n_in)) equals flux, written to *rho_in_dev (fixed grid and order; partial holds at
+// least 256 doubles of scratch).
 hipError_t launch_inlet_density(const StepArgs& a, bool next_odd, const int32_t* faces,
-                                int32_t n_in, double flux, double* rho_in_dev, hipStream_t s);
+                                int32_t n_in, double flux, double* rho_in_dev, double* partial,
+                                hipStream_t s);
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,
                          hipStream_t s);
 // lookup: LBM_NBR_TABLE or LBM_NBR_RANK when every member uses that neighbour lookup, else

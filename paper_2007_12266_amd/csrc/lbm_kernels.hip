@@ -795,20 +795,22 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
 
 // Flux inlet: sum over the inlet voxels of s0 + 2 sout (the known part of each voxel's
 // j_z = rho - s0 - 2 sout under the pressure condition), then the density that makes the summed
-// flow velocity u_z = j_z + F_z/2 equal the imposed flux. One workgroup of kInletThreads
-// threads with a fixed stride and a fixed tree order.
-constexpr int kInletThreads = 1024;
+// flow velocity u_z = j_z + F_z/2 equal the imposed flux. A fixed grid of kInletBlocks
+// workgroups of kInletThreads threads with a fixed stride writes one partial sum per workgroup;
+// one workgroup adds them in a fixed tree order, so the result does not depend on timing.
+constexpr int kInletBlocks = 256;
+constexpr int kInletThreads = 256;
 
 template <int PREC, bool ODD>
-__global__ void __launch_bounds__(kInletThreads) inlet_density_kernel(
-    StepArgs a, const int32_t* __restrict__ faces, int n_in, double flux,
-    double* __restrict__ rho_in_dev) {
+__global__ void __launch_bounds__(kInletThreads) inlet_partial_kernel(
+    StepArgs a, const int32_t* __restrict__ faces, int n_in, double* __restrict__ partial) {
     using P = Prec<PREC>;
     using S = typename P::S;
     __shared__ double acc[kInletThreads];
     const S* f = (const S*)a.f;
     double s = 0.0;
-    for (int k = threadIdx.x; k < n_in; k += kInletThreads) {
+    for (int k = blockIdx.x * kInletThreads + threadIdx.x; k < n_in;
+         k += kInletBlocks * kInletThreads) {
         const int i = faces[k];
         int r[19];
         r[0] = i;
@@ -830,8 +832,21 @@ __global__ void __launch_bounds__(kInletThreads) inlet_density_kernel(
         if ((int)threadIdx.x < h) acc[threadIdx.x] += acc[threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
+}
+
+__global__ void __launch_bounds__(kInletBlocks) inlet_finish_kernel(
+    const double* __restrict__ partial, int n_in, double flux, double fz,
+    double* __restrict__ rho_in_dev) {
+    __shared__ double acc[kInletBlocks];
+    acc[threadIdx.x] = partial[threadIdx.x];
+    __syncthreads();
+    for (int h = kInletBlocks / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) acc[threadIdx.x] += acc[threadIdx.x + h];
+        __syncthreads();
+    }
     if (threadIdx.x == 0)
-        rho_in_dev[0] = (flux - (double)n_in * 0.5 * a.F[2] + acc[0]) / (double)n_in;
+        rho_in_dev[0] = (flux - (double)n_in * 0.5 * fz + acc[0]) / (double)n_in;
 }
 
 int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
@@ -1019,11 +1034,15 @@ hipError_t launch_pressure_bc(const StepArgs& a, bool next_odd, const int32_t* f
 }
 
 hipError_t launch_inlet_density(const StepArgs& a, bool next_odd, const int32_t* faces,
-                                int32_t n_in, double flux, double* rho_in_dev, hipStream_t s) {
+                                int32_t n_in, double flux, double* rho_in_dev, double* partial,
+                                hipStream_t s) {
     if (n_in <= 0) return hipSuccess;
     const bool odd = next_odd;
-    LBM_DISPATCH(inlet_density_kernel, dim3(1), dim3(kInletThreads), a, faces, n_in, flux,
-                 rho_in_dev);
+    LBM_DISPATCH(inlet_partial_kernel, dim3(kInletBlocks), dim3(kInletThreads), a, faces, n_in,
+                 partial);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(inlet_finish_kernel, dim3(1), dim3(kInletBlocks), 0, s,
+                       (const double*)partial, n_in, flux, a.F[2], rho_in_dev);
     return hipGetLastError();
 }
 

@@ -121,9 +121,11 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
         if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
         if (d->p.bc_z == 1) {
             if (timing) { sp.kind = 2; HIP_TRY(mark(&sp.a)); }
+            // The reduction partials are free between reductions: scratch for the inlet sum.
             if (d->inlet_rho)
                 HIP_TRY(launch_inlet_density(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
-                                             d->p.flux_in, d->inlet_rho, d->stream));
+                                             d->p.flux_in, d->inlet_rho, d->red_partials,
+                                             d->stream));
             HIP_TRY(launch_pressure_bc(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
                                        (int32_t)d->pre.outlet.size(), d->p.rho_in,
                                        d->p.rho_out, d->inlet_rho, d->stream));
