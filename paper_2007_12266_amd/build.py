@@ -33,17 +33,18 @@ def _run(cmd):
 
 
 def build(verbose: bool = True) -> str:
-    """Compile every source and link liblbm.so atomically; returns its path."""
+    """Compile every source (up to four compilers at a time) and link liblbm.so atomically;
+    returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     with tempfile.TemporaryDirectory(prefix="lbm_build_") as tmp:
-        objs = []
-        for src in CPP_SOURCES:
-            obj = os.path.join(tmp, src + ".o")
-            _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-            objs.append(obj)
-        for src in HIP_SOURCES:
-            obj = os.path.join(tmp, src + ".o")
-            _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-            objs.append(obj)
+        jobs = [["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o",
+                 os.path.join(tmp, src + ".o")] for src in CPP_SOURCES]
+        jobs += [[HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o",
+                  os.path.join(tmp, src + ".o")] for src in HIP_SOURCES]
+        objs = [cmd[-1] for cmd in jobs]
+        with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as pool:
+            for _ in pool.map(_run, jobs):   # re-raises the first failed compile
+                pass
         out = os.path.join(tmp, "liblbm.so")
         _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", *objs, "-o", out])
         os.replace(out, LIB) if os.path.dirname(out) == os.path.dirname(LIB) else \
