@@ -352,10 +352,12 @@ lbm_status lbm_domain_destroy(lbm_domain* d);
  * A pool steps every member domain with one launch per kernel per time step (a persistent grid
  * striding over the tiles of all members), in chunks captured once as a HIP graph and replayed.
  * Members keep their own state and parameters; a member's results are bitwise the same as
- * stepping it alone. Members must share the pool's precision, have bc_z == 0, and have the same
- * step parity as the pool (a fresh domain joins a pool whose step count is even). While a domain
- * is a member it runs on the pool's stream and lbm_step on it returns LBM_ERR_STATE; its fields,
- * reductions and state can still be read. The pool never frees member domains. */
+ * stepping it alone. A member with pressure faces (bc_z == 1) also gets its own boundary
+ * launches (inlet density, face conditions) after the batched ones, so its admission or
+ * retirement rebuilds the captured graph. Members must share the pool's precision and have the
+ * same step parity as the pool (a fresh domain joins a pool whose step count is even). While a
+ * domain is a member it runs on the pool's stream and lbm_step on it returns LBM_ERR_STATE; its
+ * fields, reductions and state can still be read. The pool never frees member domains. */
 
 /* Create a pool for up to max_slots members whose device memory (lbm_domain_info.device_bytes)
  * sums to at most hbm_budget_bytes. chunk_steps (even, >= 2) is the length of the captured step
@@ -364,7 +366,7 @@ lbm_status lbm_pool_create(int64_t hbm_budget_bytes, int32_t precision, int32_t 
                            int32_t chunk_steps, void* hip_stream, lbm_pool** out);
 
 /* Add a domain; *slot receives its slot index. LBM_ERR_OOM if the budget or the slots are
- * exhausted; LBM_ERR_STATE for a precision, boundary or parity mismatch or a pooled domain. */
+ * exhausted; LBM_ERR_STATE for a precision or parity mismatch or a pooled domain. */
 lbm_status lbm_pool_admit(lbm_pool* pool, lbm_domain* d, int32_t* slot);
 
 /* Remove the member of `slot` (it keeps its state and returns to its own stream). */

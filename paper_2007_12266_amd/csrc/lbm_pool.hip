@@ -125,14 +125,41 @@ lbm_status upload_tables(lbm_pool* p) {
     return LBM_OK;
 }
 
+// A member with pressure faces gets the boundary work of its single-domain step between and
+// after the batched launches, in the same order: the ghost phi entries after the phase kernel,
+// then (flux inlet) the inlet density and the pressure faces after the collide kernel.
+lbm_status launch_face_work(lbm_pool* p, bool odd, bool after_collide) {
+    for (lbm_domain* d : p->slots) {
+        if (!d || d->p.bc_z != 1) continue;
+        const StepArgs a = d->args();
+        if (!after_collide) {
+            if (!d->rank && !d->pre.ghost_tail.empty())
+                HIP_TRY(launch_ghosts(a, d->ghost_tail, d->ghost_src,
+                                      (int32_t)d->pre.ghost_tail.size(), p->stream));
+            continue;
+        }
+        // The member's reduction partials are free between reductions: scratch for the inlet.
+        if (d->inlet_rho)
+            HIP_TRY(launch_inlet_density(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
+                                         d->p.flux_in, d->inlet_rho, d->red_partials,
+                                         p->stream));
+        HIP_TRY(launch_pressure_bc(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
+                                   (int32_t)d->pre.outlet.size(), d->p.rho_in, d->p.rho_out,
+                                   d->inlet_rho, p->stream));
+    }
+    return LBM_OK;
+}
+
 lbm_status launch_steps(lbm_pool* p, int64_t first_step, int64_t n) {
     const BatchArgs b = p->batch();
     for (int64_t k = 0; k < n; ++k) {
         const bool odd = ((first_step + k) & 1) != 0;
         HIP_TRY(launch_phase_batched(b, p->precision, odd, p->lookup, p->launch_grid(),
                                      kPoolBlock, p->stream));
+        if (lbm_status st = launch_face_work(p, odd, false)) return st;
         HIP_TRY(launch_collide_batched(b, p->precision, odd, p->lookup, p->launch_grid(),
                                        kPoolBlock, p->stream));
+        if (lbm_status st = launch_face_work(p, odd, true)) return st;
     }
     return LBM_OK;
 }
@@ -216,7 +243,6 @@ lbm_status lbm_pool_admit(lbm_pool* p, lbm_domain* d, int32_t* slot) {
     if (!p || !d || !slot) return fail(LBM_ERR_ARG, "null argument");
     if (d->pool) return fail(LBM_ERR_STATE, "the domain already belongs to a pool");
     if (d->p.precision != p->precision) return fail(LBM_ERR_STATE, "precision differs from the pool's");
-    if (d->p.bc_z != 0) return fail(LBM_ERR_STATE, "pools take domains without pressure faces");
     if ((d->step & 1) != (p->step & 1))
         return fail(LBM_ERR_STATE, "step parity differs from the pool's");
     if (d->unstable) return fail(LBM_ERR_UNSTABLE, "the domain is unstable");
@@ -226,6 +252,11 @@ lbm_status lbm_pool_admit(lbm_pool* p, lbm_domain* d, int32_t* slot) {
         if (!p->slots[k]) s = k;
     if (s < 0) return fail(LBM_ERR_OOM, "no free slot");
     HIP_TRY(hipStreamSynchronize(d->stream));
+    if (d->p.bc_z == 1) {
+        // The captured chunk holds the face work of every member with pressure faces.
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        p->drop_graph();
+    }
     d->own_stream_saved = d->stream;
     d->stream = p->stream;
     d->pool = p;
@@ -241,6 +272,7 @@ lbm_status lbm_pool_retire(lbm_pool* p, int32_t slot) {
         return fail(LBM_ERR_ARG, "no member in that slot");
     lbm_domain* d = p->slots[slot];
     HIP_TRY(hipStreamSynchronize(p->stream));
+    if (d->p.bc_z == 1) p->drop_graph();
     d->stream = d->own_stream_saved;
     d->own_stream_saved = nullptr;
     d->pool = nullptr;

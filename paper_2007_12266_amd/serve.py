@@ -1,6 +1,8 @@
-"""Continuous-batching solve server for steady-state colour-LBM solves on one GPU.
+"""Continuous-batching solve server for colour-LBM solves on one GPU.
 
-Requests (a rock sub-volume and its fluid parameters) arrive over time. The server
+Requests (a rock sub-volume and its fluid parameters: a steady-state solve with periodic
+boundaries and a body force, or a displacement solve driven by pressure or flux faces at z)
+arrive over time. The server
   * computes each request's exact device footprint on a CPU worker (host pre-pass) and builds
     its domain there once the footprint fits the HBM budget (requests are taken in arrival
     order; a request that does not fit waits, and so do the ones behind it);
@@ -14,7 +16,9 @@ Requests (a rock sub-volume and its fluid parameters) arrive over time. The serv
 Every member's arithmetic is that of a solo run (pool members are bitwise identical to solo
 domains), so a request's result does not depend on what else is being served. The flow control
 is the paper's steady-state loop (analysis at an interval, convergence over an interval, step
-ceiling) with the saturation change in place of the capillary-number change.
+ceiling) with the saturation change in place of the capillary-number change; a displacement
+solve usually runs to its step ceiling (its injection length), or stops early once the
+saturation no longer changes.
 """
 from __future__ import annotations
 

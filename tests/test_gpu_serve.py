@@ -1,4 +1,5 @@
-"""Serving: continuous batching over a pool; each result is the same alone and in the mix."""
+"""Serving: continuous batching over a pool of steady-state and displacement solves; each result
+is the same alone and in the mix."""
 import numpy as np
 import pytest
 
@@ -17,10 +18,16 @@ def mods():
     return lbm, serve
 
 
-def _requests(serve, n=5, tol=1e-4):
+def _requests(serve, n=5, tol=1e-4, displacement=()):
+    """Steady-state solves, and displacement solves (pressure faces at z) at the indices in
+    `displacement`."""
     reqs = []
     for k in range(n):
-        p = inputs.serving_problem(k, seed0=300, edge=(16, 28))
+        if k in displacement:
+            p = inputs.displacement_problem(shape=(20 + 3 * k, 14, 12), seed_geom=400 + k,
+                                            porosity_target=0.35, reservoir=3)
+        else:
+            p = inputs.serving_problem(k, seed0=300, edge=(16, 28))
         reqs.append(serve.Request(k, 0.02 * k, p, max_steps=1200, check_every=400, tol=tol))
     return reqs
 
@@ -29,7 +36,7 @@ def _requests(serve, n=5, tol=1e-4):
 def test_served_results_equal_solo_results(mods, precision):
     lbm, serve = mods
     prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
-    reqs = _requests(serve)
+    reqs = _requests(serve, displacement=(1, 4))
     sizes = [lbm.footprint(r.problem, prec) for r in reqs]
     budget = sorted(sizes)[-1] + sorted(sizes)[-2]   # at most about two at a time
     srv = serve.Server(budget, precision=prec, chunk=200, graph_chunk=100, max_slots=4,
@@ -48,7 +55,7 @@ def test_served_results_equal_solo_results(mods, precision):
 
 def test_realtime_trace_reports_latency(mods):
     lbm, serve = mods
-    reqs = _requests(serve, n=6, tol=1e-3)
+    reqs = _requests(serve, n=6, tol=1e-3, displacement=(2,))
     srv = serve.Server(1 << 33, precision=lbm.FP32_DEV, chunk=200, max_slots=8, workers=2)
     got = srv.run(reqs, realtime=True)
     srv.close()
