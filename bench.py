@@ -389,15 +389,23 @@ def serve_main(args):
     periodic GRF cube of edge L ~ U{64..L_max} with porosity, affinity and Sw drawn as for the
     batched volumes, run until |Sw(t) - Sw(t-1000)| < 1e-5 or 20000 steps. FP32-deviation
     storage, FP64 reductions, admission by HBM budget, continuous batching in one pool; the
-    baseline is the plain FP64 path serving the same trace one request at a time."""
+    baseline is the plain FP64 path serving the same trace one request at a time. With
+    --serve-displacement F, a seeded fraction F of the requests are displacement solves instead
+    (same cube edges and draws, rock between reservoirs, pressure faces at z, same stop rule)."""
     import torch
     from paper_2007_12266_amd import inputs, lbm, serve
 
     count = args.requests
     lmax = args.serve_lmax
     t0 = time.perf_counter()
+    # Request kinds come from their own seeded stream, so the steady-state requests of a mixed
+    # trace are those of the plain trace at the same indices.
+    kinds = np.random.Generator(np.random.PCG64(201)).random(count) < args.serve_displacement
     def make(k):
-        prob = inputs.serving_problem(k, seed0=200, edge=(64, lmax))
+        if kinds[k]:
+            prob = inputs.serving_displacement_problem(k, seed0=200, edge=(64, lmax))
+        else:
+            prob = inputs.serving_problem(k, seed0=200, edge=(64, lmax))
         log("request %d: %s" % (k, prob.name))
         return prob
     reqs = serve.poisson_trace(count, 2.0, 200, make)
@@ -453,8 +461,11 @@ def serve_main(args):
         "config": {"workload": "serving: Poisson arrivals 2/s (seed 200), %d requests, periodic "
                                "GRF cubes L~U{64..%d}, porosity U[0.15,0.35], affinity "
                                "U[-0.9,0.9], Sw U[0.2,0.8], Fz=1e-5, stop at |dSw|<1e-5 per 1000 "
-                               "steps or 20000 steps; HBM budget %.0f GiB"
-                               % (count, lmax, args.serve_budget_gb),
+                               "steps or 20000 steps; HBM budget %.0f GiB%s"
+                               % (count, lmax, args.serve_budget_gb,
+                                  "; %d of them displacement solves (reservoirs, pressure "
+                                  "faces 1.03/0.97 at z)" % int(kinds.sum())
+                                  if kinds.any() else ""),
                    "chunk_steps": 200, "graph_replays": info["graph_replays"]},
         "latency_p50_s": round(st["p50_s"], 3), "latency_p99_s": round(st["p99_s"], 3),
         "converged": st["converged"], "pore_lups_total": lups,
@@ -463,6 +474,15 @@ def serve_main(args):
                       "latency_p50_s": round(sb["p50_s"], 3),
                       "latency_p99_s": round(sb["p99_s"], 3), "converged": sb["converged"]},
         "solves_per_s_ratio_vs_fp64_fifo": round(st["solves_per_s"] / sb["solves_per_s"], 3),
+        "by_kind": ({kind: {"count": int(sum(kinds[r.rid] == want for r in res)),
+                            "served_p50_s": round(float(np.percentile(
+                                [r.latency for r in res if kinds[r.rid] == want], 50)), 3),
+                            "fifo_p50_s": round(float(np.percentile(
+                                [r.latency for r in base if kinds[r.rid] == want], 50)), 3),
+                            "served_converged": int(sum(r.converged for r in res
+                                                        if kinds[r.rid] == want))}
+                     for kind, want in (("steady", False), ("displacement", True))}
+                    if kinds.any() and not kinds.all() else None),
         "fp32_vs_fp64_final_sw_rel_max": max(abs(a.final["sw"] - b.final["sw"]) / b.final["sw"]
                                              for a, b in zip(res, base)),
     }
@@ -482,6 +502,9 @@ def main():
     ap.add_argument("--serve-part", default="both", choices=["both", "served", "fifo"],
                     help="serve: run only the continuous-batching server or only the FP64 "
                          "one-at-a-time baseline (for traces too long for one run)")
+    ap.add_argument("--serve-displacement", type=float, default=0.0, metavar="FRACTION",
+                    help="serve: fraction of requests that are displacement solves (GRF rock "
+                         "between reservoirs, pressure faces at z, same stop rule)")
     ap.add_argument("--serve-dump", default="", metavar="PREFIX",
                     help="serve: write per-request results to PREFIX.<part>.json")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -254,7 +254,8 @@ def grf_problem(n: int = 256, seed_geom: int = 3, seed_aff: int = 4, seed_phase:
 
 def displacement_problem(n: int = 512, shape=None, seed_geom: int = 5, porosity_target: float = 0.2,
                          corr: float = 4.0, affinity: float = -0.7, reservoir: int = 4,
-                         rho_in: float = 1.03, rho_out: float = 0.97) -> Problem:
+                         rho_in: float = 1.03, rho_out: float = 0.97,
+                         max_redraws: int = 8) -> Problem:
     """Unsteady displacement: fluid a is injected at z = 0 by a pressure face into rock filled
     with b. GRF rock (as ``grf_rock``) between two solid-free reservoirs of ``reservoir`` planes;
     x and y periodic, z bounded by the pressure faces (rho_in at z = 0, rho_out at z = nz-1).
@@ -262,7 +263,8 @@ def displacement_problem(n: int = 512, shape=None, seed_geom: int = 5, porosity_
     phase: +1 in the inlet reservoir, -1 elsewhere."""
     shape = tuple(shape) if shape is not None else (n, n, n)
     nz, ny, nx = shape
-    rock, _ = grf_rock((nz - 2 * reservoir, ny, nx), corr, porosity_target, seed_geom)
+    rock, _ = grf_rock((nz - 2 * reservoir, ny, nx), corr, porosity_target, seed_geom,
+                       max_redraws=max_redraws)
     solid = np.zeros(shape, np.uint8)
     solid[reservoir:nz - reservoir] = rock
     labels = np.where(solid > 0, 0, 1).astype(np.int32)
@@ -274,6 +276,30 @@ def displacement_problem(n: int = 512, shape=None, seed_geom: int = 5, porosity_
                    periodic=(True, True, False), force=(0.0, 0.0, 0.0),
                    wall_affinity=affinity, bc_z=1, rho_in=rho_in, rho_out=rho_out,
                    name="displacement-%dx%dx%d" % (nx, ny, nz))
+
+
+def serving_displacement_problem(k: int, seed0: int = 200, edge=(64, 384),
+                                 porosity=(0.15, 0.35), affinity=(-0.9, 0.9),
+                                 corr: float = 4.0, reservoir: int = 4) -> Problem:
+    """Displacement solve request k: a cube of edge L ~ U{edge} (seed seed0 + k) holding GRF rock
+    of the drawn porosity between two `reservoir`-plane reservoirs, filled with b and invaded
+    by a through the pressure face at z = 0 (``displacement_problem``), wall affinity drawn as
+    for the batched volumes. The porosity is raised in steps of 0.02 until the rock has a
+    z-spanning pore cluster."""
+    seed = seed0 + k
+    rng = _rng(seed)
+    L = int(rng.integers(edge[0], edge[1] + 1))
+    por = float(rng.uniform(*porosity))
+    aff = float(rng.uniform(*affinity))
+    while True:
+        try:
+            prob = displacement_problem(shape=(L, L, L), seed_geom=seed, porosity_target=por,
+                                        corr=corr, affinity=aff, reservoir=reservoir,
+                                        max_redraws=3)
+            break
+        except RuntimeError:
+            por += 0.02
+    return dataclasses.replace(prob, name="disp%d-L%d-por%.3f-aff%+.2f" % (k, L, por, aff))
 
 
 def batch_volumes(count: int = 64, seed0: int = 100, edge=(48, 160), porosity=(0.15, 0.35),

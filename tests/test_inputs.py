@@ -40,3 +40,20 @@ def test_problem_views():
     phi0 = p.phase0()
     assert np.all(np.abs(phi0[solid == 0]) == 1) and np.all(phi0[solid == 1] == 0)
     assert np.all(p.solid_affinity()[solid == 1] == 0.5)
+
+
+def test_serving_requests_of_both_kinds():
+    """A displacement request has the cube edge, porosity and affinity draws of the steady
+    request with the same index; its rock sits between solid-free reservoirs and percolates
+    from the inlet plane to the outlet plane."""
+    steady = inputs.serving_problem(5, seed0=300, edge=(30, 44))
+    disp = inputs.serving_displacement_problem(5, seed0=300, edge=(30, 44), reservoir=3)
+    assert disp.labels.shape == steady.labels.shape
+    assert disp.bc_z == 1 and disp.periodic == (True, True, False)
+    pore = disp.solid_mask() == 0
+    assert pore[:3].all() and pore[-3:].all() and not pore[3:-3].all()
+    assert disp.label_affinity[0] == steady.label_affinity[0] == disp.wall_affinity
+    phi0 = disp.phase0()
+    assert (phi0[:3] == 1).all() and (phi0[3:][pore[3:]] == -1).all()
+    again = inputs.serving_displacement_problem(5, seed0=300, edge=(30, 44), reservoir=3)
+    assert np.array_equal(again.labels, disp.labels) and again.name == disp.name
