@@ -177,9 +177,10 @@ def test_pressure_face_members_match_solo_runs_bitwise(lbm, precision):
 
 
 def test_pool_autotune_restores_members(lbm):
-    """The pool autotuner times grids in both tile orders on the members themselves and then
-    restores every member: later results equal solo runs bitwise."""
-    probs = _mix()[:3]
+    """The pool autotuner times grids in both tile orders on the members themselves (one with
+    flux-driven pressure faces) and then restores every member: later results equal solo runs
+    bitwise."""
+    probs = _mix()[:2] + [_displacement(9, (22, 12, 14), flux=0.01)]
     pool = lbm.Pool(1 << 34, precision=lbm.FP32_DEV, max_slots=4, chunk_steps=10)
     doms = [lbm.Domain(p, precision=lbm.FP32_DEV) for p in probs]
     for d in doms:
