@@ -385,9 +385,21 @@ typedef struct {
     int32_t max_slots, members, chunk_steps, grid;  /* grid: workgroups of the batched launch */
     int64_t step, used_bytes, budget_bytes, tiles;
     int64_t graph_replays, eager_steps;
-    int32_t order, pad_;      /* tile order of the batched launch (see lbm_pool_set_order)  */
+    int32_t order;            /* tile order of the batched launch (see lbm_pool_set_order)  */
+    int32_t groups;           /* cache groups of the captured chunk (0: none; -1: not yet
+                                 computed since the last membership change)                  */
 } lbm_pool_info;
 lbm_status lbm_pool_get_info(lbm_pool* pool, lbm_pool_info* out);
+
+/* Cache groups: with group_bytes > 0 the captured chunk runs the members in groups, each a run
+ * of consecutive members (slot order) whose lbm_domain_info.device_bytes sum to at most
+ * group_bytes (a larger member forms a group of its own), and each group takes all chunk_steps
+ * steps before the next group starts, so that a group sized to the last-level cache keeps its
+ * state there across its steps. Eager steps (counts that are not whole chunks) still step all
+ * members together. Members are independent, so results are bitwise the same for any
+ * group_bytes; 0 (the default) turns grouping off. Takes effect at the next lbm_pool_step;
+ * a change of the grouping rebuilds the captured graph. LBM_ERR_ARG for group_bytes < 0. */
+lbm_status lbm_pool_set_group_bytes(lbm_pool* pool, int64_t group_bytes);
 
 /* Set the number of workgroups of the batched step kernels (e.g. from an autotuner);
  * 0 restores the default. Invalidates the captured graph. */

@@ -29,6 +29,7 @@ struct lbm_pool {
     double* d_red = nullptr;
     std::vector<StepArgs> h_doms;
     std::vector<int32_t> h_tile_first, h_tile_dom;
+    std::vector<int32_t> h_group_first, h_group_ntiles;
     int32_t h_ntiles = 0;
     int32_t lookup = LBM_NBR_TABLE;   // the members' common neighbour lookup, else AUTO (mixed)
     bool dirty = true;
@@ -37,8 +38,32 @@ struct lbm_pool {
     hipGraphExec_t exec = nullptr;
     int64_t replays = 0, eager = 0;
 
+    // Cache groups of the captured chunk (group_bytes > 0): consecutive members whose device
+    // footprints sum to at most group_bytes run the whole chunk before the next group starts,
+    // so a group's state can stay in the last-level cache across its steps. Group g covers
+    // tiles [first, first + ntiles) of the tile table; its launches see that range through
+    // d_group_ntiles[g] and a tile_first table relative to its first tile (d_group_first,
+    // max_slots entries per group).
+    struct Group {
+        int32_t first = 0, ntiles = 0;
+        std::vector<int32_t> members, offsets;   // slots, and their first tiles - first
+        bool operator==(const Group& o) const {
+            return first == o.first && ntiles == o.ntiles && members == o.members &&
+                   offsets == o.offsets;
+        }
+    };
+    int64_t group_bytes = 0;
+    std::vector<Group> groups;
+    int32_t* d_group_first = nullptr;
+    int32_t* d_group_ntiles = nullptr;
+    size_t group_cap = 0;             // groups the two device arrays hold
+
     BatchArgs batch() const {
         return BatchArgs{d_doms, d_tile_dom, d_tile_first, d_ntiles, order};
+    }
+    BatchArgs group_batch(size_t g) const {
+        return BatchArgs{d_doms, d_tile_dom + groups[g].first,
+                         d_group_first + g * (size_t)max_slots, d_group_ntiles + g, order};
     }
     // Workgroups of the batched launch: the XCD-aware order needs whole runs on every XCD.
     int32_t launch_grid() const {
@@ -67,6 +92,63 @@ int32_t highest_slot(const lbm_pool* p) {
     for (int32_t s = 0; s < p->max_slots; ++s)
         if (p->slots[s]) n = s + 1;
     return n;
+}
+
+// Cache groups (see lbm_pool::Group): members in slot order, a new group whenever the next
+// member would take the group past group_bytes. A change of the grouping invalidates the
+// captured chunk. Uploads are asynchronous on the pool's stream; the caller synchronises.
+lbm_status upload_groups(lbm_pool* p) {
+    std::vector<lbm_pool::Group> groups;
+    if (p->group_bytes > 0) {
+        int64_t bytes = 0;
+        for (int32_t s = 0; s < p->max_slots; ++s) {
+            lbm_domain* d = p->slots[s];
+            if (!d) continue;
+            const int32_t nt = (int32_t)((d->pre.n_pore + kPoolBlock - 1) / kPoolBlock);
+            if (groups.empty() || bytes + d->device_bytes > p->group_bytes) {
+                groups.emplace_back();
+                groups.back().first = p->h_tile_first[s];
+                bytes = 0;
+            }
+            groups.back().ntiles += nt;
+            groups.back().members.push_back(s);
+            groups.back().offsets.push_back(p->h_tile_first[s] - groups.back().first);
+            bytes += d->device_bytes;
+        }
+    }
+    if (groups == p->groups && (groups.empty() || p->group_cap >= groups.size())) return LBM_OK;
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->drop_graph();
+    if (groups.size() > p->group_cap) {
+        const size_t cap = std::max(groups.size(), 2 * p->group_cap);
+        int32_t *first = nullptr, *nt = nullptr;
+        if (hipMalloc(&first, sizeof(int32_t) * cap * p->max_slots) != hipSuccess ||
+            hipMalloc(&nt, sizeof(int32_t) * cap) != hipSuccess) {
+            if (first) (void)hipFree(first);
+            return fail(LBM_ERR_OOM, "device allocation failed (pool groups)");
+        }
+        if (p->d_group_first) (void)hipFree(p->d_group_first);
+        if (p->d_group_ntiles) (void)hipFree(p->d_group_ntiles);
+        p->d_group_first = first;
+        p->d_group_ntiles = nt;
+        p->group_cap = cap;
+    }
+    p->groups = groups;
+    if (groups.empty()) return LBM_OK;
+    p->h_group_first.assign(groups.size() * (size_t)p->max_slots, 0);
+    p->h_group_ntiles.assign(groups.size(), 0);
+    for (size_t g = 0; g < groups.size(); ++g) {
+        p->h_group_ntiles[g] = groups[g].ntiles;
+        for (size_t k = 0; k < groups[g].members.size(); ++k)
+            p->h_group_first[g * p->max_slots + groups[g].members[k]] = groups[g].offsets[k];
+    }
+    HIP_TRY(hipMemcpyAsync(p->d_group_first, p->h_group_first.data(),
+                           sizeof(int32_t) * p->h_group_first.size(), hipMemcpyHostToDevice,
+                           p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_group_ntiles, p->h_group_ntiles.data(),
+                           sizeof(int32_t) * p->h_group_ntiles.size(), hipMemcpyHostToDevice,
+                           p->stream));
+    return LBM_OK;
 }
 
 // Rebuild and upload the per-slot arguments and the tile table after a membership change.
@@ -118,6 +200,7 @@ lbm_status upload_tables(lbm_pool* p) {
                                sizeof(int32_t) * p->h_ntiles, hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_ntiles, &p->h_ntiles, sizeof(int32_t), hipMemcpyHostToDevice,
                            p->stream));
+    if (lbm_status st = upload_groups(p)) return st;
     // The host vectors stay alive and unchanged until the next upload, which first waits for
     // the stream, so the asynchronous copies never read a buffer being rewritten.
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -128,8 +211,10 @@ lbm_status upload_tables(lbm_pool* p) {
 // A member with pressure faces gets the boundary work of its single-domain step between and
 // after the batched launches, in the same order: the ghost phi entries after the phase kernel,
 // then (flux inlet) the inlet density and the pressure faces after the collide kernel.
-lbm_status launch_face_work(lbm_pool* p, bool odd, bool after_collide) {
-    for (lbm_domain* d : p->slots) {
+lbm_status launch_face_work(lbm_pool* p, const std::vector<int32_t>& members, bool odd,
+                            bool after_collide) {
+    for (int32_t s : members) {
+        lbm_domain* d = p->slots[s];
         if (!d || d->p.bc_z != 1) continue;
         const StepArgs a = d->args();
         if (!after_collide) {
@@ -150,24 +235,45 @@ lbm_status launch_face_work(lbm_pool* p, bool odd, bool after_collide) {
     return LBM_OK;
 }
 
-lbm_status launch_steps(lbm_pool* p, int64_t first_step, int64_t n) {
-    const BatchArgs b = p->batch();
+// n steps of the members in `members` over the tiles that b covers.
+lbm_status launch_steps_of(lbm_pool* p, const BatchArgs& b, const std::vector<int32_t>& members,
+                           int64_t first_step, int64_t n) {
     for (int64_t k = 0; k < n; ++k) {
         const bool odd = ((first_step + k) & 1) != 0;
         HIP_TRY(launch_phase_batched(b, p->precision, odd, p->lookup, p->launch_grid(),
                                      kPoolBlock, p->stream));
-        if (lbm_status st = launch_face_work(p, odd, false)) return st;
+        if (lbm_status st = launch_face_work(p, members, odd, false)) return st;
         HIP_TRY(launch_collide_batched(b, p->precision, odd, p->lookup, p->launch_grid(),
                                        kPoolBlock, p->stream));
-        if (lbm_status st = launch_face_work(p, odd, true)) return st;
+        if (lbm_status st = launch_face_work(p, members, odd, true)) return st;
     }
     return LBM_OK;
+}
+
+std::vector<int32_t> all_members(const lbm_pool* p) {
+    std::vector<int32_t> m;
+    for (int32_t s = 0; s < p->max_slots; ++s)
+        if (p->slots[s]) m.push_back(s);
+    return m;
+}
+
+// n steps of every member, each step one batched launch per kernel over all tiles.
+lbm_status launch_steps(lbm_pool* p, int64_t first_step, int64_t n) {
+    return launch_steps_of(p, p->batch(), all_members(p), first_step, n);
 }
 
 lbm_status capture(lbm_pool* p) {
     p->drop_graph();
     HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-    lbm_status st = launch_steps(p, 0, p->chunk);   // chunks start on even steps
+    // Chunks start on even steps. With cache groups, each group takes the whole chunk in turn
+    // (members are independent, so only the order of their launches changes).
+    lbm_status st = LBM_OK;
+    if (p->groups.empty()) {
+        st = launch_steps(p, 0, p->chunk);
+    } else {
+        for (size_t g = 0; g < p->groups.size() && st == LBM_OK; ++g)
+            st = launch_steps_of(p, p->group_batch(g), p->groups[g].members, 0, p->chunk);
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->stream, &g);
     if (st != LBM_OK) {
@@ -351,6 +457,7 @@ lbm_status lbm_pool_get_info(lbm_pool* p, lbm_pool_info* out) {
     out->graph_replays = p->replays;
     out->eager_steps = p->eager;
     out->order = p->order;
+    out->groups = p->dirty ? -1 : (int32_t)p->groups.size();
     return LBM_OK;
 }
 
@@ -359,6 +466,13 @@ lbm_status lbm_pool_set_order(lbm_pool* p, int32_t order) {
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->order = order;
     p->drop_graph();
+    return LBM_OK;
+}
+
+lbm_status lbm_pool_set_group_bytes(lbm_pool* p, int64_t group_bytes) {
+    if (!p || group_bytes < 0) return fail(LBM_ERR_ARG, "group_bytes must be >= 0");
+    p->group_bytes = group_bytes;
+    p->dirty = true;
     return LBM_OK;
 }
 
@@ -465,7 +579,7 @@ lbm_status lbm_pool_destroy(lbm_pool* p) {
         if (p->slots[s]) (void)lbm_pool_retire(p, s);
     p->drop_graph();
     void* bufs[] = {p->d_doms, p->d_tile_first, p->d_tile_dom, p->d_ntiles, p->d_partials,
-                    p->d_red};
+                    p->d_red, p->d_group_first, p->d_group_ntiles};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);

@@ -28,7 +28,8 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_prepass_query", "lbm_domain_footprint", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
            "lbm_pool_create", "lbm_pool_admit", "lbm_pool_retire", "lbm_pool_step",
            "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
-           "lbm_pool_destroy", "lbm_pool_set_order", "lbm_set_force", "lbm_run_steady",
+           "lbm_pool_destroy", "lbm_pool_set_order", "lbm_pool_set_group_bytes",
+           "lbm_set_force", "lbm_run_steady",
            "lbm_morph", "lbm_phase_volume", "lbm_shell_aggregate",
            "lbm_prep_distance", "lbm_prep_drain", "lbm_prep_relabel", "lbm_prep_mixing_layer",
            "lbm_last_error", "lbm_version")
@@ -157,7 +158,7 @@ class PoolInfo(ctypes.Structure):
                 ("step", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
                 ("budget_bytes", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("graph_replays", ctypes.c_int64), ("eager_steps", ctypes.c_int64),
-                ("order", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("groups", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -215,6 +216,7 @@ def load_library(path: str = LIB_PATH):
     L.lbm_pool_get_info.argtypes = [vp, ctypes.POINTER(PoolInfo)]
     L.lbm_pool_set_grid.argtypes = [vp, i32]
     L.lbm_pool_set_order.argtypes = [vp, i32]
+    L.lbm_pool_set_group_bytes.argtypes = [vp, i64]
     L.lbm_pool_destroy.argtypes = [vp]
     L.lbm_pool_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
     i32p = ctypes.POINTER(i32)
@@ -549,6 +551,12 @@ class Pool:
     def set_order(self, order: int):
         """0: tiles in launch order; 1: XCD-aware runs of tiles."""
         _check(load_library().lbm_pool_set_order(self.handle, int(order)))
+        return self
+
+    def set_group_bytes(self, group_bytes: int):
+        """Captured chunks run the members in cache groups of at most group_bytes of device
+        memory each, one group after the other (0: all members together)."""
+        _check(load_library().lbm_pool_set_group_bytes(self.handle, int(group_bytes)))
         return self
 
     def close(self):

@@ -200,3 +200,39 @@ def test_pool_autotune_restores_members(lbm):
     pool.close()
     for d in doms:
         d.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32dev", "fp64"])
+def test_cache_groups_keep_results(lbm, precision):
+    """Captured chunks that run the members in cache groups (each group all chunk steps, one
+    group after the other) leave every member bitwise equal to its solo run, through eager
+    steps, a change of grouping and membership changes; a member larger than the group size
+    forms a group of its own."""
+    prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
+    probs = _mix() + [_displacement(10, (24, 12, 16), flux=0.015)]
+    doms = [lbm.Domain(p, precision=prec) for p in probs]
+    sizes = [d.info()["device_bytes"] for d in doms]
+    pool = lbm.Pool(1 << 34, precision=prec, max_slots=8, chunk_steps=10)
+    pool.set_group_bytes(sorted(sizes)[-2] + sorted(sizes)[0])
+    slots = [pool.admit(d) for d in doms[:5]]
+    pool.step(28)                                   # 2 replays + 8 eager steps
+    assert 2 <= pool.info()["groups"] <= 5
+    pool.set_group_bytes(1)                         # every member alone
+    pool.step(20)
+    assert pool.info()["groups"] == 5
+    pool.retire(slots[1])
+    slots[1] = pool.admit(doms[5])                  # joins at pool step 48, own step 0
+    pool.step(22)
+    info = pool.info()
+    assert info["graph_replays"] == 6 and info["groups"] == 5
+    members = [0, 5, 2, 3, 4]
+    for k, n in zip(members, [70, 22, 70, 70, 70]):
+        solo = lbm.Domain(probs[k], precision=prec)
+        solo.step(n)
+        assert doms[k].info()["step"] == n, k
+        assert doms[k].save() == solo.save(), k
+        solo.close()
+    assert doms[1].info()["step"] == 48
+    pool.close()
+    for d in doms:
+        d.close()
