@@ -305,7 +305,8 @@ def batch_main(args):
     """64 independent sub-volumes (edges U{48..160}, porosity U[0.15,0.35], affinity
     U[-0.9,0.9], Sw U[0.2,0.8], periodic, F_z = 1e-5), 3000 steps each: FP32-deviation storage in
     one pool (one batched launch per kernel per step, 100-step chunks replayed from a captured
-    HIP graph, FP64 reductions after every chunk) against the plain FP64 path run one volume at
+    HIP graph, members in autotuned cache groups within a chunk, FP64 reductions after every
+    chunk) against the plain FP64 path run one volume at
     a time with reductions every 100 steps. Domain creation (pre-pass and upload) is outside both
     timed regions."""
     import torch
@@ -372,6 +373,7 @@ def batch_main(args):
                                "Fz=1e-5, FP32-deviation storage, FP64 reductions every 100 steps",
                    "n_pore_total": n_tot, "chunk_steps": chunk, "pool_grid": grid,
                    "pool_order": "xcd" if info["order"] else "linear",
+                   "pool_cache_groups": info["groups"],
                    "graph_replays": info["graph_replays"]},
         "aggregate_mlups": round(n_tot * steps / t_pool / 1e6, 1),
         "fp64_one_at_a_time": {"seconds": round(t_base, 3), "solves_per_s": round(64 / t_base, 4),

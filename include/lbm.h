@@ -412,10 +412,13 @@ lbm_status lbm_pool_set_grid(lbm_pool* pool, int32_t grid);
 lbm_status lbm_pool_set_order(lbm_pool* pool, int32_t order);
 
 /* Autotuner for the batched launch: times each candidate workgroup count (multiples of the
- * compute-unit count) in both tile orders over trial_steps >= 2 steps of the current members,
- * applies the fastest pair and writes the workgroup count to *grid (nullable; the order is in
- * lbm_pool_info). Every member's state and step counter are restored, so later results are
- * unchanged. Needs device memory for one copy of the members' populations. */
+ * compute-unit count) in both tile orders over trial_steps >= 2 steps of the current members
+ * and applies the fastest pair; then, if the pool is at an even step, times one replay of the
+ * captured chunk for each cache-group size (lbm_pool_set_group_bytes: 0, 128, 192, 256, 320 and
+ * 384 MiB) and applies the fastest. Writes the workgroup count to *grid (nullable; the order
+ * and the group count are in lbm_pool_info). Every member's state and step counter are
+ * restored, so later results are unchanged. Needs device memory for one copy of the members'
+ * populations. */
 lbm_status lbm_pool_autotune(lbm_pool* pool, int32_t trial_steps, int32_t* grid);
 
 /* Retire every member and free the pool. NULL is accepted. */

@@ -543,6 +543,39 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
             best_order = p->order;
         }
     }
+    // Cache groups: with the chosen grid and order, one warm-up and one timed replay of the
+    // captured chunk per candidate group size (needs the pool at an even step, like any chunk).
+    const int64_t keep_group = p->group_bytes;
+    int64_t best_group = keep_group;
+    if (st == LBM_OK) {
+        p->grid = best;
+        p->order = best_order;
+        p->drop_graph();
+    }
+    if (st == LBM_OK && (p->step & 1) == 0 && p->h_ntiles > 0) {
+        const int64_t MiB = 1 << 20;
+        const int64_t cand[6] = {0, 128 * MiB, 192 * MiB, 256 * MiB, 320 * MiB, 384 * MiB};
+        double best_chunk = 1e30;
+        for (int c = 0; c < 6 && st == LBM_OK; ++c) {
+            p->group_bytes = cand[c];
+            if ((st = upload_groups(p)) != LBM_OK) break;
+            if (hipStreamSynchronize(p->stream) != hipSuccess) { st = fail(LBM_ERR_DEVICE, "sync"); break; }
+            if (!p->exec && (st = capture(p)) != LBM_OK) break;
+            float ms = 0.f;
+            if (hipGraphLaunch(p->exec, p->stream) != hipSuccess ||
+                hipEventRecord(e0, p->stream) != hipSuccess ||
+                hipGraphLaunch(p->exec, p->stream) != hipSuccess ||
+                hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = fail(LBM_ERR_DEVICE, "chunk timing failed");
+                break;
+            }
+            if (ms < best_chunk) {
+                best_chunk = ms;
+                best_group = cand[c];
+            }
+        }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     // Restore states; the trial steps came in even numbers, so parities are unchanged.
@@ -567,7 +600,9 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
     for (const Snap& sn : snaps) (void)hipFree(sn.buf);
     p->grid = st == LBM_OK ? best : keep;
     p->order = st == LBM_OK ? best_order : keep_order;
+    p->group_bytes = st == LBM_OK ? best_group : keep_group;
     p->drop_graph();
+    p->dirty = true;                  // regroup at the next step
     if (st == LBM_OK && grid) *grid = p->grid;
     return st;
 }

@@ -67,7 +67,7 @@ def _check_due(steps: int, check_every: int) -> bool:
 class Server:
     def __init__(self, hbm_budget: int, precision: int = lbm.FP32_DEV, chunk: int = 200,
                  graph_chunk: int = 100, max_slots: int = 64, workers: int = 4,
-                 keep_state: bool = False, stream=None):
+                 keep_state: bool = False, stream=None, group_bytes: int = 256 << 20):
         if chunk % graph_chunk or graph_chunk % 2:
             raise ValueError("chunk must be a multiple of an even graph_chunk")
         self.budget = int(hbm_budget)
@@ -75,6 +75,9 @@ class Server:
         self.chunk = chunk
         self.pool = lbm.Pool(self.budget, precision=precision, max_slots=max_slots,
                              chunk_steps=graph_chunk, stream=stream)
+        # Members run in cache groups of about the last-level cache (256 MB Infinity Cache on
+        # MI355X) inside each captured chunk; results do not depend on it.
+        self.pool.set_group_bytes(group_bytes)
         self.workers = cf.ThreadPoolExecutor(max_workers=workers)
         self.keep_state = keep_state
 

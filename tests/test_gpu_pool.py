@@ -192,6 +192,7 @@ def test_pool_autotune_restores_members(lbm):
     assert grid > 0 and info["grid"] == grid and info["order"] in (0, 1) and info["step"] == 10
     assert [d.save() for d in doms] == before
     pool.step(20)
+    assert pool.info()["groups"] >= 0                # cache grouping chosen by the tuner
     for p, d in zip(probs, doms):
         solo = lbm.Domain(p, precision=lbm.FP32_DEV)
         solo.step(30)
