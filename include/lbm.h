@@ -398,7 +398,9 @@ lbm_status lbm_pool_get_info(lbm_pool* pool, lbm_pool_info* out);
  * state there across its steps. Eager steps (counts that are not whole chunks) still step all
  * members together. Members are independent, so results are bitwise the same for any
  * group_bytes; 0 (the default) turns grouping off. Takes effect at the next lbm_pool_step;
- * a change of the grouping rebuilds the captured graph. LBM_ERR_ARG for group_bytes < 0. */
+ * a change of the grouping rebuilds the captured graph. The pool keeps 4 * (max_slots + 1)
+ * bytes of device memory per group for the group tables (LBM_ERR_OOM from lbm_pool_step if
+ * they cannot be allocated). LBM_ERR_ARG for group_bytes < 0. */
 lbm_status lbm_pool_set_group_bytes(lbm_pool* pool, int64_t group_bytes);
 
 /* Set the number of workgroups of the batched step kernels (e.g. from an autotuner);
