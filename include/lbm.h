@@ -404,13 +404,13 @@ lbm_status lbm_pool_get_info(lbm_pool* pool, lbm_pool_info* out);
 lbm_status lbm_pool_set_group_bytes(lbm_pool* pool, int64_t group_bytes);
 
 /* Set the number of workgroups of the batched step kernels (e.g. from an autotuner);
- * 0 restores the default. Invalidates the captured graph. */
+ * 0 restores the default (32 per compute unit). Invalidates the captured graph. */
 lbm_status lbm_pool_set_grid(lbm_pool* pool, int32_t grid);
 
 /* Tile order of the batched step kernels: 0 = tiles in launch order, 1 = XCD-aware order (each
  * of the 8 XCDs takes runs of 16 consecutive tiles, the runs interleaved; the launch is rounded
- * up to whole runs). Results do not depend on it (bitwise). Invalidates the captured graph.
- * LBM_ERR_ARG for another value. */
+ * up to whole runs; the default). Results do not depend on it (bitwise). Invalidates the
+ * captured graph. LBM_ERR_ARG for another value. */
 lbm_status lbm_pool_set_order(lbm_pool* pool, int32_t order);
 
 /* Autotuner for the batched launch: times each candidate workgroup count (multiples of the

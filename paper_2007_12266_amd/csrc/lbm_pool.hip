@@ -16,8 +16,8 @@ struct lbm_pool {
     bool own_stream = false;
     std::vector<lbm_domain*> slots;
     int64_t step = 0;
-    int32_t grid = 0, default_grid = 0;
-    int32_t order = 0;                // 0: linear tile order, 1: XCD-aware runs
+    int32_t grid = 0, default_grid = 0, cus = 1;
+    int32_t order = 1;                // 0: linear tile order, 1: XCD-aware runs
 
     // Device tables of the batched kernels (fixed addresses, so captured graphs stay valid).
     StepArgs* d_doms = nullptr;
@@ -327,7 +327,10 @@ lbm_status lbm_pool_create(int64_t hbm_budget_bytes, int32_t precision, int32_t 
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return bail(LBM_ERR_DEVICE, "device query failed");
-    p->default_grid = p->grid = std::max(1, cus) * 8;
+    // Defaults: 32 workgroups per compute unit in the XCD-aware order, what the autotuner picks
+    // for uneven batches of 48..160-voxel volumes.
+    p->cus = std::max(1, cus);
+    p->default_grid = p->grid = p->cus * 32;
     p->tile_cap = 1 << 16;
     if (hipMalloc(&p->d_doms, sizeof(StepArgs) * max_slots) != hipSuccess ||
         hipMalloc(&p->d_tile_first, sizeof(int32_t) * max_slots) != hipSuccess ||
@@ -524,7 +527,7 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
         st = fail(LBM_ERR_DEVICE, "event creation failed");
     const int mult[5] = {2, 4, 8, 16, 32};
     for (int c = 0; c < 10 && st == LBM_OK && p->h_ntiles > 0; ++c) {
-        p->grid = std::max(1, p->default_grid / 8) * mult[c % 5];
+        p->grid = p->cus * mult[c % 5];
         p->order = c / 5;
         st = launch_steps(p, p->step, 2);                      // warm-up
         if (st != LBM_OK) break;
