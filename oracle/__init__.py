@@ -33,7 +33,7 @@ class OraParams(ctypes.Structure):
                 ("force", ctypes.c_double * 3), ("wall_affinity", ctypes.c_double),
                 ("bc_z", ctypes.c_int32), ("inlet_mode", ctypes.c_int32),
                 ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
-                ("flux_in", ctypes.c_double)]
+                ("flux_in", ctypes.c_double), ("c_min", ctypes.c_double)]
 
 
 def build(force: bool = False) -> str:
@@ -81,7 +81,7 @@ def _d(a):
 
 def make_params(shape, periodic=(True, True, True), tau_a=0.7, tau_b=0.7, alpha=0.005,
                 beta=0.95, force=(0.0, 0.0, 0.0), wall_affinity=0.0, bc_z=0, rho_in=1.0,
-                rho_out=1.0, inlet_mode=0, flux_in=0.0) -> OraParams:
+                rho_out=1.0, inlet_mode=0, flux_in=0.0, c_min=1e-10) -> OraParams:
     nz, ny, nx = shape
     p = OraParams()
     p.nx, p.ny, p.nz = nx, ny, nz
@@ -93,6 +93,7 @@ def make_params(shape, periodic=(True, True, True), tau_a=0.7, tau_b=0.7, alpha=
     p.bc_z = bc_z
     p.rho_in, p.rho_out = rho_in, rho_out
     p.inlet_mode, p.flux_in = inlet_mode, float(flux_in)
+    p.c_min = float(c_min)
     return p
 
 

@@ -16,7 +16,8 @@
  *   - colour gradient stencil: C = sum_q c_q xi_q phi(x + xi_q) with c_q = 1 on the six axis
  *     links and 1/2 on the twelve diagonals (this makes the flat-interface tension exactly
  *     6 alpha, the stated sigma_ab = 6 alpha);
- *   - n = C/|C| when |C| > 1e-10, else C is taken as zero (n = 0, alpha|C| = 0): below that
+ *   - n = C/|C| when |C| > c_min (a parameter, 1e-10 by default; 0 gives the literal
+ *     "n = C/|C| wherever C != 0"), else C is taken as zero (n = 0, alpha|C| = 0): below that
  *     size the gradient is unresolved, a cancellation of O(1) neighbour values whose rounding
  *     residue would otherwise set the direction of the recolouring;
  *   - unlisted equilibria follow d'Humieres et al. 2002 (w_eps = 3, w_epsj = -11/2,
@@ -50,8 +51,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORA_C_MIN 1e-10
-
 typedef struct {
     int32_t nx, ny, nz;
     int32_t periodic[3];
@@ -63,6 +62,7 @@ typedef struct {
     int32_t inlet_mode;    /* with bc_z == 1: 0 = inlet density rho_in; 1 = inlet flux flux_in */
     double rho_in, rho_out;
     double flux_in;        /* inlet_mode 1: sum of u_z over the inlet plane's pore voxels */
+    double c_min;          /* a colour gradient with |C| <= c_min counts as zero (n = 0)     */
 } ora_params;
 
 /* D3Q19 velocity set of the d3q19 equation, grouped as rest, axes, then three diagonal planes. */
@@ -180,11 +180,11 @@ void ora_collide(const ora_params* p, const double* f, double Na, double Nb, con
 
     /* Phase indicator and interface normal. */
     const double phi = (Na - Nb) / (Na + Nb);
-    /* A gradient no larger than ORA_C_MIN is unresolved (its size is then set by rounding
-     * of cancelling neighbour values, and n would point anywhere): it is taken as zero. */
+    /* A gradient no larger than c_min is unresolved (its size is then set by rounding of
+     * cancelling neighbour values, and n would point anywhere): it is taken as zero. */
     double cmag = sqrt(C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
     double nx = 0.0, ny = 0.0, nz = 0.0;
-    if (cmag > ORA_C_MIN) {
+    if (cmag > p->c_min) {
         nx = C[0] / cmag;
         ny = C[1] / cmag;
         nz = C[2] / cmag;

@@ -501,3 +501,109 @@ def test_equilibrium_moments_are_the_published_ones():
                 want = (c[0] * rho + c[1] * jj + c[2] * j[0] + c[3] * j[1] + c[4] * j[2]
                         + c[5] * (3 * j[0] ** 2 - jj) + c[6] * (j[1] ** 2 - j[2] ** 2))
             assert abs(m[k] - want) <= 1e-14, (r[0], m[k], want)
+
+
+# ---------------------------------------------------------------------------------------------
+# Readings R3 (unresolved gradient) and R9 (pressure faces): what fixes them
+# ---------------------------------------------------------------------------------------------
+
+def test_gradient_threshold_changes_nothing_on_the_sphere_pack():
+    """Reading R3 takes |C| <= 1e-10 as no gradient (n = 0). On the 32^3 sphere-pack parity case
+    the oracle with that threshold and with the literal rule (n = C/|C| wherever C != 0) give
+    bitwise the same state after 200 steps: no voxel of that run has 0 < |C| <= 1e-10, so the
+    reading does not move the parity case at all."""
+    prob = inputs.sphere_problem()
+    pore = prob.solid_mask() == 0
+    out = {}
+    for c_min in (1e-10, 0.0):
+        p = O.params_of(prob)
+        p.c_min = c_min
+        st = O.State(p, prob.solid_mask(), prob.solid_affinity()).init(prob.phase0()).run(200)
+        out[c_min] = st.fields()
+    for k in ("Na", "Nb", "phi", "rho", "ux", "uy", "uz"):
+        assert np.array_equal(out[1e-10][k][pore], out[0.0][k][pore]), k
+
+
+def _pressure_slit(H=8, L=20, nx=6, seed=3):
+    """Two-phase slit between solid planes y = 0 and y = H+1 with random wall affinity, x
+    periodic, pressure faces at z (rho 1.02 in, 0.98 out), body force with x and z parts."""
+    rng = np.random.default_rng(seed)
+    shape = (L, H + 2, nx)
+    solid = np.zeros(shape, np.uint8)
+    solid[:, 0, :] = solid[:, H + 1, :] = 1
+    phi_s = rng.uniform(-0.9, 0.9, shape)
+    phi0 = np.where(rng.random(shape) < 0.5, 1.0, -1.0)
+    p = O.make_params(shape, (True, False, False), 0.8, 0.65, 0.01, 0.9, (1e-6, 0, 2e-6), 0.3,
+                      bc_z=1, rho_in=1.02, rho_out=0.98)
+    return O.State(p, solid, phi_s).init(phi0), solid
+
+
+def test_pressure_faces_impose_pure_equilibria_and_balance_species():
+    """Reading R9 at the faces, checked through the paper's mass LBEs rather than the oracle's
+    code. (i) After a step the inlet plane holds pure fluid a at unit density in equilibrium with
+    the face's own flow velocity, A_q = w_q (1 + u.xi_q / cs^2) with cs^2 = 2/9 and u the read-out
+    velocity, and B = 0 (the outlet: the same for b). (ii) What the inlet sends into the rock in
+    the next step is the recoloured population of that pure voxel, A_5(z=1) = (1 + 4.5 u_z(z=0))/9,
+    with no b. (iii) Species balance: the change of the mass of a in the planes between the faces
+    equals what crosses the two bounding planes in that step -- the D3Q7 links are the only
+    carriers, each outgoing pair of a voxel sums to 2 w N_a, so the crossing populations follow
+    from the two stored states -- to round-off, so the faces create or destroy a only by their
+    imposed composition."""
+    st, solid = _pressure_slit()
+    st.run(40)
+    X = st.fields()
+    st.run(1)
+    Y = st.fields()
+    A1, B1 = st.A, st.B
+    pore = solid == 0
+    xi, _, w, _ = _d3q19()
+    u = np.stack([Y["ux"], Y["uy"], Y["uz"]])
+    for q in range(7):
+        eu_in = (xi[q][:, None, None] * u[:, 0]).sum(0)
+        eu_out = (xi[q][:, None, None] * u[:, -1]).sum(0)
+        assert np.abs(A1[q, 0] - w[q] * (1 + 4.5 * eu_in))[pore[0]].max() < 1e-16
+        assert np.abs(B1[q, -1] - w[q] * (1 + 4.5 * eu_out))[pore[-1]].max() < 1e-16
+        assert not B1[q, 0][pore[0]].any() and not A1[q, -1][pore[-1]].any()
+    m_in, m_out = pore[0] & pore[1], pore[-1] & pore[-2]
+    assert np.abs(A1[5, 1] - (1 + 4.5 * X["uz"][0]) / 9)[m_in].max() < 1e-16
+    assert not B1[5, 1][m_in].any()
+    assert np.abs(B1[6, -2] - (1 - 4.5 * X["uz"][-1]) / 9)[m_out].max() < 1e-16
+    assert not A1[6, -2][m_out].any()
+    # (iii) planes 1..nz-2; every voxel of those planes off the walls is pore.
+    inner = slice(1, solid.shape[0] - 1)
+    d_mass = np.nansum(Y["Na"][inner][pore[inner]]) - np.nansum(X["Na"][inner][pore[inner]])
+    into = A1[5, 1][m_in].sum() - ((2 / 9) * X["Na"][1] - A1[5, 2])[m_in].sum()
+    out_of = ((2 / 9) * X["Na"][-2] - A1[6, -3])[m_out].sum() - A1[6, -2][m_out].sum()
+    gross = A1[5, 1][m_in].sum() + A1[6, -3][m_out].sum()
+    assert abs(d_mass - (into - out_of)) <= 1e-13 * gross, (d_mass, into - out_of)
+
+
+def test_pressure_face_gradient_mirrors_the_face_plane():
+    """Reading R9's gradient across a pressure face: phi beyond the face is the face plane's own
+    (zero normal derivative). Checked by construction: one step of a domain with pressure faces
+    equals, on every plane but the faces, one step of the same domain extended below the inlet
+    by a copy of its first plane (state, solids and affinities), where the inlet voxels see that
+    copy as ordinary neighbours. Bitwise, from a mixed initial phase (so recolouring at the face
+    depends on the gradient) and after 30 steps (face planes pure)."""
+    rng = np.random.default_rng(5)
+    shape = (9, 8, 7)
+    solid = (rng.random(shape) < 0.25).astype(np.uint8)
+    phi_s = rng.uniform(-0.9, 0.9, shape)
+    phi0 = rng.uniform(-1.0, 1.0, shape)
+    kw = dict(periodic=(True, True, False), tau_a=0.8, tau_b=0.65, alpha=0.01, beta=0.9,
+              force=(1e-6, -2e-6, 3e-6), wall_affinity=0.4, bc_z=1, rho_in=1.02,
+              rho_out=0.98)
+
+    def ext(a, ax):
+        return np.ascontiguousarray(np.concatenate([np.take(a, [0], axis=ax), a], axis=ax))
+
+    pore = solid == 0
+    for warm in (0, 30):
+        st = O.State(O.make_params(shape, **kw), solid, phi_s).init(phi0).run(warm)
+        big = O.State(O.make_params((shape[0] + 1,) + shape[1:], **kw), ext(solid, 0),
+                      ext(phi_s, 0))
+        big.f[:], big.A[:], big.B[:] = ext(st.f, 1), ext(st.A, 1), ext(st.B, 1)
+        st.run(1)
+        big.run(1)
+        for a, b in ((st.f, big.f), (st.A, big.A), (st.B, big.B)):
+            assert np.array_equal(a[:, 1:-1][:, pore[1:-1]], b[:, 2:-1][:, pore[1:-1]]), warm
