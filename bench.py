@@ -1,16 +1,19 @@
 """Throughput of the colour-LBM time step on one MI355X, with its HBM roofline and CPU baseline.
 
-Workload (default): steady-state two-fluid flow through a 256^3 synthetic rock, FP64. The rock
-is a periodic Gaussian random field with 4-voxel correlation length thresholded at porosity 0.2,
-keeping the pore clusters that span z (about 3.2e6 pore voxels); per-voxel wall affinity
-U[-0.9, 0.9]; random initial phase at Sw = 0.5; body force F_z = 1e-5; periodic on all axes;
-tau = 0.7, alpha = 0.005, beta = 0.95; saturation and flux reductions every 100 steps.
+Workload (default): unsteady displacement in a 512^3 synthetic rock, FP64. The rock is a
+periodic-in-x/y Gaussian random field with 4-voxel correlation length thresholded at porosity
+0.2, keeping the pore clusters that span z (about 2.8e7 pore voxels), between two solid-free
+reservoirs of 4 planes; walls of affinity -0.7; fluid a is injected by a pressure face at z = 0
+(rho 1.03) against rho 0.97 at z = nz-1; tau = 0.7, alpha = 0.005, beta = 0.95; saturation and
+flux reductions every 100 steps (their cost is reported amortised over that cadence).
 
 One bench step is one full time step (densities and phase, fused gradient + collision +
-recolouring + streaming, reductions at their cadence). Inputs are resident in HBM before the
-timed region. Prints one JSON line.
+recolouring + streaming, pressure faces). Inputs are resident in HBM before the timed region.
+After the headline measurement the same JSON line carries the batched workload (64 GRF volumes,
+3000 steps each, in one FP32-mixed pool, against the plain FP64 path one volume at a time) and a
+short serving trace (16 Poisson arrivals), unless --no-extras. Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 2000] [--warmup 100] [--workload grf256|grf512]
+    python bench.py [--gpus 1] [--steps 2000] [--warmup 100] [--workload disp512|grf256|grf512]
 """
 from __future__ import annotations
 
@@ -30,29 +33,42 @@ if ROOT not in sys.path:
 METRIC = "pore-voxel MLUPS + % HBM roofline; batched solves/s with p50/p99 latency"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 
-# Algorithmic bytes per pore voxel and step, by storage precision (E = bytes per stored value)
-# and neighbour lookup. The collide kernel reads 19 f, writes 19 f and the 8 D3Q7 moment slots
-# (N_a, N_b, u, G), reads phi and N at the voxel (neighbour phi is reuse) and its neighbours'
-# indices; the phase kernel reads the 8 moment slots (each voxel's once; the six neighbours' are
-# reuse), its neighbours' indices, and writes phi and N. The indices cost 4*18 (collide) and
-# 4*6 (phase) bytes per voxel with the int32 table; with the rank lookup, 4 bytes of packed
-# coordinates per voxel plus one pass over the 32-byte row segments (nz*ny*ceil(nx/64) of them,
-# counted per launch, about 0.5/porosity bytes per pore voxel).
-# FP64: 456 / 104 / 560 B per voxel with the table, 388 / 84 / 472 with the rank lookup;
-# FP32-dev: 264 / 64 / 328 and 196 / 44 / 240.
-# (Streaming the 14 D3Q7 populations themselves instead of their 8 moments would add 6E to the
-# collide and phase kernels each.)
-def _bytes(E, rank):
+# Algorithmic bytes per pore voxel and step, by storage precision (F = bytes per stored D3Q19
+# population, S = bytes per stored moment slot, phi or N value) and neighbour lookup. The
+# collide kernel reads 19 f, writes 19 f and the 8 D3Q7 moment slots (N_a, N_b, u, G), reads phi
+# and N at the voxel (neighbour phi is reuse) and its neighbours' indices; the phase kernel
+# reads the 8 moment slots (each voxel's once; the six neighbours' are reuse), its neighbours'
+# indices, and writes phi and N. The indices cost 4*18 (collide) and 4*6 (phase) bytes per voxel
+# with the int32 table; with the rank lookup, 4 bytes of packed coordinates per voxel plus one
+# pass over the 32-byte row segments (nz*ny*ceil(nx/64) of them, counted per launch, about
+# 0.5/porosity bytes per pore voxel).
+# FP64 (F = S = 8): 456 / 104 / 560 B per voxel with the table, 388 / 84 / 472 with the rank
+# lookup; FP32-dev (4, 4): 264 / 64 / 328 and 196 / 44 / 240; FP32-mixed (4, 8): 304 / 104 / 408
+# and 236 / 84 / 320.
+# The survey's accounting streams the 14 D3Q7 populations instead of their 8 moments and counts
+# the 72-byte table once per step: 632 B per step and 504 B for the collide kernel in FP64
+# (FP32-dev 352 / 288, FP32-mixed 480 / 352).
+STORE = {"fp64": (8, 8), "fp32dev": (4, 4), "mixed": (4, 8)}
+
+
+def _bytes(F, S, rank):
     if rank:
-        return {"collide": E * (19 + 19 + 8 + 2) + 4, "phase": E * (8 + 2) + 4,
-                "step": E * (38 + 16 + 4) + 8}
-    return {"collide": E * (19 + 19 + 8 + 2) + 4 * 18, "phase": E * (8 + 2) + 4 * 6,
-            "step": E * (38 + 16 + 4) + 4 * 24}
+        return {"collide": F * 38 + S * (8 + 2) + 4, "phase": S * (8 + 2) + 4,
+                "step": F * 38 + S * (16 + 4) + 8}
+    return {"collide": F * 38 + S * (8 + 2) + 4 * 18, "phase": S * (8 + 2) + 4 * 6,
+            "step": F * 38 + S * (16 + 4) + 4 * 24}
+
+
+def survey_bytes(precision):
+    """Bytes per pore voxel of the whole step and of the collide kernel in the survey's
+    accounting (the 14 D3Q7 populations streamed, the neighbour table read once per step)."""
+    F, S = STORE[precision]
+    return {"step": F * 38 + S * (28 + 4) + 72, "collide": F * 38 + S * (14 + 2) + 72}
 
 
 def launch_bytes(precision, rank, n_pore, shape):
     """Algorithmic bytes of one collide launch, one phase launch and one whole step."""
-    per = _bytes(8 if precision == "fp64" else 4, rank)
+    per = _bytes(*STORE[precision], rank)
     nz, ny, nx = shape
     rows = nz * ny * ((nx + 63) // 64) * 32 if rank else 0
     return {"collide": per["collide"] * n_pore + rows, "phase": per["phase"] * n_pore + rows,
@@ -96,7 +112,7 @@ def front_position(phi) -> float:
 def morph_study(prob, args, torch, lbm) -> dict:
     """Wall time of lbm_morph (first call, which allocates its work buffers, and later calls)
     and of lbm_phase_volume on the workload after 100 steps."""
-    dom = lbm.Domain(prob, precision=lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV,
+    dom = lbm.Domain(prob, precision=prec_of(lbm, args.precision),
                      allocator="hip")
     dom.step(100)
     torch.cuda.synchronize()
@@ -156,7 +172,7 @@ def steady_study(prob, args, lbm, plain_ms: float) -> dict:
     1000 relaxation steps, one force rescaling towards 1.5x the measured capillary number
     (capped at 2x), then 500-step blocks until |dCa|/Ca < 1e-3 or 10000 steps. Reports the
     decision and the cost per step against plain stepping."""
-    P = lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV
+    P = prec_of(lbm, args.precision)
     dom = lbm.Domain(prob, precision=P, allocator="hip")
     dom.step(200)
     ca0 = dom.reduce()["ca"]
@@ -178,7 +194,7 @@ def flux_study(prob, args, lbm) -> dict:
     density inlet carries after 200 steps); per-step device time of the boundary kernels
     (inlet density + pressure faces) and of the whole step from HIP events."""
     import dataclasses
-    P = lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV
+    P = prec_of(lbm, args.precision)
     out = {}
     dom = lbm.Domain(prob, precision=P, allocator="hip")
     dom.step(200)
@@ -202,10 +218,10 @@ def flux_study(prob, args, lbm) -> dict:
 
 
 def precision_study(prob, steps: int, every: int, torch, lbm) -> dict:
-    """FP32-deviation against FP64 on the same problem: both advance side by side and every
-    `every` steps the saturation, the Darcy flux and the front position are compared."""
-    doms = {k: lbm.Domain(prob, precision=p, allocator="hip")
-            for k, p in (("fp64", lbm.FP64), ("fp32dev", lbm.FP32_DEV))}
+    """FP32-deviation and FP32-mixed storage against FP64 on the same problem: all three advance
+    side by side and every `every` steps the saturation, the Darcy flux and the front position
+    are compared."""
+    doms = {k: lbm.Domain(prob, precision=prec_of(lbm, k), allocator="hip") for k in PRECISIONS}
     rows = []
     for t in range(every, steps + 1, every):
         rec = {"step": t}
@@ -215,23 +231,23 @@ def precision_study(prob, steps: int, every: int, torch, lbm) -> dict:
             rec[k] = {"sw": r["sw"], "qz": r["qz"], "zf": front_position(d.field("phi")),
                       "unstable": r["unstable"], "mass_a": r["mass_a"]}
         rows.append(rec)
-        log("precision study step %d: Sw %.6f / %.6f, qz %.4e / %.4e, zf %.3f / %.3f"
-            % (t, rec["fp64"]["sw"], rec["fp32dev"]["sw"], rec["fp64"]["qz"],
-               rec["fp32dev"]["qz"], rec["fp64"]["zf"], rec["fp32dev"]["zf"]))
+        log("precision study step %d: Sw %.6f / %.6f / %.6f, qz %.4e / %.4e / %.4e"
+            % (t, rec["fp64"]["sw"], rec["fp32dev"]["sw"], rec["mixed"]["sw"],
+               rec["fp64"]["qz"], rec["fp32dev"]["qz"], rec["mixed"]["qz"]))
     for d in doms.values():
         d.close()
 
-    def rel(k):
-        return max(abs(r["fp32dev"][k] - r["fp64"][k]) / abs(r["fp64"][k]) for r in rows)
-    last = rows[-1]
-    return {"steps": steps, "every": every,
-            "sw_rel_max": rel("sw"), "qz_rel_max": rel("qz"),
-            "zf_abs_max_planes": max(abs(r["fp32dev"]["zf"] - r["fp64"]["zf"]) for r in rows),
-            "unstable": max(r[k]["unstable"] for r in rows for k in ("fp64", "fp32dev")),
-            "final": {"fp64": last["fp64"], "fp32dev": last["fp32dev"]},
-            "series": [[r["step"], r["fp64"]["sw"], r["fp32dev"]["sw"], r["fp64"]["qz"],
-                        r["fp32dev"]["qz"], r["fp64"]["zf"], r["fp32dev"]["zf"]]
-                       for r in rows]}
+    def rel(p, k):
+        return max(abs(r[p][k] - r["fp64"][k]) / abs(r["fp64"][k]) for r in rows)
+    out = {"steps": steps, "every": every,
+           "unstable": max(r[k]["unstable"] for r in rows for k in PRECISIONS),
+           "final": {k: rows[-1][k] for k in PRECISIONS}}
+    for p in ("fp32dev", "mixed"):
+        out[p] = {"sw_rel_max": rel(p, "sw"), "qz_rel_max": rel(p, "qz"),
+                  "zf_abs_max_planes": max(abs(r[p]["zf"] - r["fp64"]["zf"]) for r in rows)}
+    out["series"] = [[r["step"]] + [r[k][q] for k in PRECISIONS for q in ("sw", "qz", "zf")]
+                     for r in rows]
+    return out
 
 
 def log(msg):
@@ -278,11 +294,19 @@ def _cpu_model() -> str:
     return platform.machine()
 
 
-def _profiled_traffic(precision: str, neighbours: str):
-    """Calibrated collide-kernel HBM bytes per pore voxel from the committed rocprofv3 summary,
-    if it was measured on the current kernel source with the same neighbour lookup; else None."""
+PRECISIONS = ("fp64", "fp32dev", "mixed")
+
+
+def prec_of(lbm, name):
+    return {"fp64": lbm.FP64, "fp32dev": lbm.FP32_DEV, "mixed": lbm.FP32_MIXED}[name]
+
+
+def _profiled_traffic(workload: str, precision: str, neighbours: str):
+    """Calibrated collide-kernel HBM bytes per pore voxel from the committed rocprofv3 summary of
+    this workload and precision, if it was measured on the current kernel source with the same
+    neighbour lookup; else None."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "collide_phase_grf256_%s.md" % precision)
+    prof = os.path.join(ROOT, "profiles", "collide_phase_%s_%s.md" % (workload, precision))
     src = os.path.join(ROOT, "paper_2007_12266_amd", "csrc", "lbm_kernels.hip")
     try:
         vals = {}
@@ -301,50 +325,53 @@ def _profiled_traffic(precision: str, neighbours: str):
     return None
 
 
-def batch_main(args):
+def _rel(a, b):
+    return abs(a - b) / abs(b) if b != 0 else (0.0 if a == 0 else float("inf"))
+
+
+def final_errors(finals, refs) -> dict:
+    """Relative errors of reduced-precision final reductions against FP64 ones (pairs of
+    lbm_reduction dicts): saturation, Darcy flux q_z, mass of a, total capillary number and the
+    phase pressure difference p_a - p_b."""
+    e = {"sw": [], "qz": [], "mass_a": [], "ca": [], "dp": []}
+    for r, ref in zip(finals, refs):
+        for k in ("sw", "qz", "mass_a", "ca"):
+            e[k].append(_rel(r[k], ref[k]))
+        e["dp"].append(_rel(r["p_a"] - r["p_b"], ref["p_a"] - ref["p_b"]))
+    out = {}
+    for k, v in e.items():
+        out[k + "_rel_max"] = float(max(v))
+        out[k + "_rel_median"] = float(np.median(v))
+    return out
+
+
+def batch_run(args, precisions=("mixed",)) -> dict:
     """64 independent sub-volumes (edges U{48..160}, porosity U[0.15,0.35], affinity
-    U[-0.9,0.9], Sw U[0.2,0.8], periodic, F_z = 1e-5), 3000 steps each: FP32-deviation storage in
-    one pool (one batched launch per kernel per step, 100-step chunks replayed from a captured
-    HIP graph, members in autotuned cache groups within a chunk, FP64 reductions after every
-    chunk) against the plain FP64 path run one volume at
-    a time with reductions every 100 steps. Domain creation (pre-pass and upload) is outside both
-    timed regions."""
+    U[-0.9,0.9], Sw U[0.2,0.8], periodic, F_z = 1e-5), `args.batch_steps` steps each: each given
+    reduced precision in one pool (one batched launch per kernel per step, 100-step chunks
+    replayed from a captured HIP graph, members in autotuned cache groups within a chunk, FP64
+    reductions after every chunk) against the plain FP64 path run one volume at a time with
+    reductions every 100 steps. Domain creation (pre-pass and upload) is outside every timed
+    region."""
     import torch
     from paper_2007_12266_amd import inputs, lbm
 
-    steps = args.steps if args.steps_given else 3000
+    steps = args.batch_steps
     chunk = 100
     t0 = time.perf_counter()
     probs = inputs.batch_volumes(64)
     n_tot = sum(p.n_pore() for p in probs)
     log("64 volumes generated in %.1f s, %d pore voxels" % (time.perf_counter() - t0, n_tot))
     torch.cuda.set_device(0)
-    doms = [lbm.Domain(p, precision=lbm.FP32_DEV, allocator="hip") for p in probs]
-    budget = sum(d.info()["device_bytes"] for d in doms)
-    pool = lbm.Pool(budget, precision=lbm.FP32_DEV, max_slots=64, chunk_steps=chunk)
-    for d in doms:
-        pool.admit(d)
-    grid = pool.autotune(10)
-    log("pool grid %d, tile order %s" % (grid, "xcd" if pool.info()["order"] else "linear"))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reds = []
-    for _ in range(steps // chunk):
-        pool.step(chunk)
-        reds.append(pool.reduce())
-    torch.cuda.synchronize()
-    t_pool = time.perf_counter() - t0
-    info = pool.info()
-    final32 = reds[-1]
-    pool.close()
-    for d in doms:
-        d.close()
-    log("pool: %d steps in %.2f s (%d graph replays)" % (steps, t_pool, info["graph_replays"]))
+    out = {"workload": "64 GRF sub-volumes, edges U{48..160}, porosity U[0.15,0.35], affinity "
+                       "U[-0.9,0.9], Sw U[0.2,0.8], periodic, Fz=1e-5, %d steps each, FP64 "
+                       "reductions every 100 steps" % steps,
+           "volumes": 64, "steps": steps, "n_pore_total": n_tot, "chunk_steps": chunk}
 
     # Baseline: the plain FP64 path, one volume at a time.
     t_base = 0.0
-    final64 = {}
-    for k, p in enumerate(probs):
+    final64 = []
+    for p in probs:
         d = lbm.Domain(p, precision=lbm.FP64, reduce_every=chunk, allocator="hip")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -352,48 +379,55 @@ def batch_main(args):
         hist = d.history()
         torch.cuda.synchronize()
         t_base += time.perf_counter() - t0
-        final64[k] = hist[-1]
+        final64.append(hist[-1])
         d.close()
     log("fp64 one at a time: %.2f s" % t_base)
-    errs_sw = [abs(final32[k]["sw"] - final64[k]["sw"]) / final64[k]["sw"] for k in range(64)]
-    errs_m = [abs(final32[k]["mass_a"] - final64[k]["mass_a"]) / final64[k]["mass_a"]
-              for k in range(64)]
-    errs_q = [abs(final32[k]["qz"] - final64[k]["qz"]) / max(abs(final64[k]["qz"]), 1e-300)
-              for k in range(64)]
-    out = {
-        "metric": METRIC,
-        "value": round(64 / t_pool, 4),
-        "unit": "solves/s (64 volumes x %d steps)" % steps,
-        "n_gpus": 1, "steps": steps, "warmup": 0,
-        "ms_per_step": round(t_pool / steps * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched: 64 GRF sub-volumes, edges U{48..160}, porosity "
-                               "U[0.15,0.35], affinity U[-0.9,0.9], Sw U[0.2,0.8], periodic, "
-                               "Fz=1e-5, FP32-deviation storage, FP64 reductions every 100 steps",
-                   "n_pore_total": n_tot, "chunk_steps": chunk, "pool_grid": grid,
-                   "pool_order": "xcd" if info["order"] else "linear",
-                   "pool_cache_groups": info["groups"],
-                   "graph_replays": info["graph_replays"]},
-        "aggregate_mlups": round(n_tot * steps / t_pool / 1e6, 1),
-        "fp64_one_at_a_time": {"seconds": round(t_base, 3), "solves_per_s": round(64 / t_base, 4),
-                               "aggregate_mlups": round(n_tot * steps / t_base / 1e6, 1)},
-        "speedup_vs_fp64_serial": round(t_base / t_pool, 3),
-        "fp32_vs_fp64_final": {"sw_rel_max": max(errs_sw), "mass_a_rel_max": max(errs_m),
-                               "qz_rel_median": float(np.median(errs_q)),
-                               "qz_rel_max": max(errs_q)},
-    }
-    print(json.dumps(out), flush=True)
+    out["fp64_one_at_a_time"] = {"seconds": round(t_base, 3),
+                                 "solves_per_s": round(64 / t_base, 4),
+                                 "aggregate_mlups": round(n_tot * steps / t_base / 1e6, 1)}
+    for name in precisions:
+        P = prec_of(lbm, name)
+        doms = [lbm.Domain(p, precision=P, allocator="hip") for p in probs]
+        budget = sum(d.info()["device_bytes"] for d in doms)
+        pool = lbm.Pool(budget, precision=P, max_slots=64, chunk_steps=chunk)
+        for d in doms:
+            pool.admit(d)
+        grid = pool.autotune(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reds = None
+        for _ in range(steps // chunk):
+            pool.step(chunk)
+            reds = pool.reduce()
+        torch.cuda.synchronize()
+        t_pool = time.perf_counter() - t0
+        info = pool.info()
+        pool.close()
+        for d in doms:
+            d.close()
+        log("pool %s: %d steps in %.2f s (%d graph replays)" % (name, steps, t_pool,
+                                                               info["graph_replays"]))
+        out["pool_" + name] = {
+            "seconds": round(t_pool, 3), "solves_per_s": round(64 / t_pool, 4),
+            "ms_per_step": round(t_pool / steps * 1e3, 4),
+            "aggregate_mlups": round(n_tot * steps / t_pool / 1e6, 1),
+            "solves_per_s_ratio_vs_fp64": round(t_base / t_pool, 3),
+            "grid": grid, "order": "xcd" if info["order"] else "linear",
+            "cache_groups": info["groups"], "graph_replays": info["graph_replays"],
+            "error_vs_fp64": final_errors([reds[k] for k in range(64)], final64)}
+    return out
 
 
-def serve_main(args):
+def serve_run(args, precision: str) -> dict:
     """Serving: Poisson arrivals (rate 2/s, seed 200) of steady-state solve requests, each a
     periodic GRF cube of edge L ~ U{64..L_max} with porosity, affinity and Sw drawn as for the
-    batched volumes, run until |Sw(t) - Sw(t-1000)| < 1e-5 or 20000 steps. FP32-deviation
+    batched volumes, run until |Sw(t) - Sw(t-1000)| < 1e-5 or 20000 steps. Reduced-precision
     storage, FP64 reductions, admission by HBM budget, continuous batching in one pool; the
     baseline is the plain FP64 path serving the same trace one request at a time. With
     --serve-displacement F, a seeded fraction F of the requests are displacement solves instead
-    (same cube edges and draws, rock between reservoirs, pressure faces at z, same stop rule)."""
+    (same cube edges and draws, rock between reservoirs, pressure faces at z, same stop rule).
+    Errors against FP64 are taken over the requests that stopped after the same number of steps
+    in both runs."""
     import torch
     from paper_2007_12266_amd import inputs, lbm, serve
 
@@ -403,6 +437,7 @@ def serve_main(args):
     # Request kinds come from their own seeded stream, so the steady-state requests of a mixed
     # trace are those of the plain trace at the same indices.
     kinds = np.random.Generator(np.random.PCG64(201)).random(count) < args.serve_displacement
+
     def make(k):
         if kinds[k]:
             prob = inputs.serving_displacement_problem(k, seed0=200, edge=(64, lmax))
@@ -414,11 +449,11 @@ def serve_main(args):
     log("%d requests generated in %.1f s" % (count, time.perf_counter() - t0))
     torch.cuda.set_device(0)
     budget = int(args.serve_budget_gb * (1 << 30))
-    srv = serve.Server(budget, precision=lbm.FP32_DEV, chunk=200, graph_chunk=100,
-                       max_slots=64, workers=4)
+
     def done(tag):
         return lambda r: log("%s: request %d (%d pore voxels) done after %d steps, latency "
                              "%.2f s" % (tag, r.rid, r.n_pore, r.steps, r.latency))
+
     def dump(tag, results):
         if args.serve_dump:
             with open("%s.%s.json" % (args.serve_dump, tag), "w") as fh:
@@ -426,69 +461,69 @@ def serve_main(args):
                             "arrival": r.arrival, "completed": r.completed,
                             "latency": r.latency, "final": r.final} for r in results], fh)
 
-    if args.serve_part == "fifo":
+    out = {"workload": "Poisson arrivals 2/s (seed 200), %d requests, periodic GRF cubes "
+                       "L~U{64..%d}, porosity U[0.15,0.35], affinity U[-0.9,0.9], Sw U[0.2,0.8], "
+                       "Fz=1e-5, stop at |dSw|<1e-5 per 1000 steps or 20000 steps; HBM budget "
+                       "%.0f GiB%s" % (count, lmax, args.serve_budget_gb,
+                                       "; %d of them displacement solves (reservoirs, pressure "
+                                       "faces 1.03/0.97 at z)" % int(kinds.sum())
+                                       if kinds.any() else ""),
+           "precision": precision, "requests": count}
+    res = None
+    if args.serve_part in ("both", "served"):
+        srv = serve.Server(budget, precision=prec_of(lbm, precision), chunk=200, graph_chunk=100,
+                           max_slots=64, workers=4)
+        res = srv.run(reqs, realtime=True, on_result=done("served"))
+        info = srv.pool.info()
+        srv.close()
+        dump("served", res)
+        st = serve.latency_stats(res)
+        log("served: %s" % st)
+        lups = sum(r.n_pore * r.steps for r in res)
+        span = max(r.completed for r in res) - min(r.arrival for r in res)
+        out.update({"solves_per_s": round(st["solves_per_s"], 4),
+                    "latency_p50_s": round(st["p50_s"], 3),
+                    "latency_p99_s": round(st["p99_s"], 3), "converged": st["converged"],
+                    "pore_lups_total": lups, "aggregate_mlups": round(lups / span / 1e6, 1),
+                    "chunk_steps": 200, "graph_replays": info["graph_replays"]})
+    if args.serve_part in ("both", "fifo"):
         base = serve.fifo_baseline(reqs, precision=lbm.FP64, chunk=1000,
                                    on_result=done("fp64 fifo"))
         dump("fifo", base)
         sb = serve.latency_stats(base)
         log("fp64 fifo: %s" % sb)
-        print(json.dumps({"part": "fifo", "requests": count, "fp64_fifo": sb}), flush=True)
-        return
-    res = srv.run(reqs, realtime=True, on_result=done("served"))
-    info = srv.pool.info()
-    srv.close()
-    dump("served", res)
-    st = serve.latency_stats(res)
-    log("served: %s" % st)
-    if args.serve_part == "served":
-        lups = sum(r.n_pore * r.steps for r in res)
-        span = max(r.completed for r in res) - min(r.arrival for r in res)
-        print(json.dumps({"part": "served", "requests": count, "served": st,
-                          "aggregate_mlups": round(lups / span / 1e6, 1),
-                          "graph_replays": info["graph_replays"]}), flush=True)
-        return
-    base = serve.fifo_baseline(reqs, precision=lbm.FP64, chunk=1000,
-                               on_result=done("fp64 fifo"))
-    sb = serve.latency_stats(base)
-    log("fp64 fifo: %s" % sb)
-    lups = sum(r.n_pore * r.steps for r in res)
-    span = max(r.completed for r in res) - min(r.arrival for r in res)
-    out = {
-        "metric": METRIC,
-        "value": round(st["solves_per_s"], 4),
-        "unit": "solves/s (continuous batching, FP32-dev)",
-        "n_gpus": 1, "steps": int(sum(r.steps for r in res)), "warmup": 0,
-        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "serving: Poisson arrivals 2/s (seed 200), %d requests, periodic "
-                               "GRF cubes L~U{64..%d}, porosity U[0.15,0.35], affinity "
-                               "U[-0.9,0.9], Sw U[0.2,0.8], Fz=1e-5, stop at |dSw|<1e-5 per 1000 "
-                               "steps or 20000 steps; HBM budget %.0f GiB%s"
-                               % (count, lmax, args.serve_budget_gb,
-                                  "; %d of them displacement solves (reservoirs, pressure "
-                                  "faces 1.03/0.97 at z)" % int(kinds.sum())
-                                  if kinds.any() else ""),
-                   "chunk_steps": 200, "graph_replays": info["graph_replays"]},
-        "latency_p50_s": round(st["p50_s"], 3), "latency_p99_s": round(st["p99_s"], 3),
-        "converged": st["converged"], "pore_lups_total": lups,
-        "aggregate_mlups": round(lups / span / 1e6, 1),
-        "fp64_fifo": {"solves_per_s": round(sb["solves_per_s"], 4),
-                      "latency_p50_s": round(sb["p50_s"], 3),
-                      "latency_p99_s": round(sb["p99_s"], 3), "converged": sb["converged"]},
-        "solves_per_s_ratio_vs_fp64_fifo": round(st["solves_per_s"] / sb["solves_per_s"], 3),
-        "by_kind": ({kind: {"count": int(sum(kinds[r.rid] == want for r in res)),
-                            "served_p50_s": round(float(np.percentile(
-                                [r.latency for r in res if kinds[r.rid] == want], 50)), 3),
-                            "fifo_p50_s": round(float(np.percentile(
-                                [r.latency for r in base if kinds[r.rid] == want], 50)), 3),
-                            "served_converged": int(sum(r.converged for r in res
-                                                        if kinds[r.rid] == want))}
-                     for kind, want in (("steady", False), ("displacement", True))}
-                    if kinds.any() and not kinds.all() else None),
-        "fp32_vs_fp64_final_sw_rel_max": max(abs(a.final["sw"] - b.final["sw"]) / b.final["sw"]
-                                             for a, b in zip(res, base)),
-    }
-    print(json.dumps(out), flush=True)
+        out["fp64_fifo"] = {"solves_per_s": round(sb["solves_per_s"], 4),
+                            "latency_p50_s": round(sb["p50_s"], 3),
+                            "latency_p99_s": round(sb["p99_s"], 3), "converged": sb["converged"]}
+        if res is not None:
+            out["solves_per_s_ratio_vs_fp64_fifo"] = round(
+                out["solves_per_s"] / sb["solves_per_s"], 3)
+            same = [(a, b) for a, b in zip(sorted(res, key=lambda r: r.rid),
+                                           sorted(base, key=lambda r: r.rid))
+                    if a.steps == b.steps]
+            out["error_vs_fp64"] = dict(final_errors([a.final for a, _ in same],
+                                                     [b.final for _, b in same]),
+                                        compared=len(same))
+            if kinds.any() and not kinds.all():
+                out["by_kind"] = {
+                    kind: {"count": int(sum(kinds[r.rid] == want for r in res)),
+                           "served_p50_s": round(float(np.percentile(
+                               [r.latency for r in res if kinds[r.rid] == want], 50)), 3),
+                           "fifo_p50_s": round(float(np.percentile(
+                               [r.latency for r in base if kinds[r.rid] == want], 50)), 3),
+                           "served_converged": int(sum(r.converged for r in res
+                                                       if kinds[r.rid] == want))}
+                    for kind, want in (("steady", False), ("displacement", True))}
+    return out
+
+
+def _contract_line(value, unit, steps, ms_per_step, dtype, config, **extra):
+    line = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": 0, "ms_per_step": ms_per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+    line.update(extra)
+    return line
 
 
 def main():
@@ -496,8 +531,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="grf256",
+    ap.add_argument("--workload", default="disp512",
                     choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and serving measurements after the headline")
+    ap.add_argument("--batch-steps", type=int, default=3000, help="batched: steps per volume")
+    ap.add_argument("--batch-precisions", default="mixed,fp32dev",
+                    help="batched: comma-separated pool precisions (mixed, fp32dev, fp64)")
+    ap.add_argument("--serve-precision", default="mixed", choices=PRECISIONS)
     ap.add_argument("--requests", type=int, default=16, help="serve: number of requests")
     ap.add_argument("--serve-lmax", type=int, default=192, help="serve: largest cube edge")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0, help="serve: HBM budget")
@@ -511,7 +552,7 @@ def main():
                     help="serve: write per-request results to PREFIX.<part>.json")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32dev"])
+    ap.add_argument("--precision", default="fp64", choices=PRECISIONS)
     ap.add_argument("--neighbours", default="auto", choices=["auto", "table", "rank"],
                     help="neighbour lookup: int32 table or rank of row-segment bit masks")
     ap.add_argument("--no-autotune", action="store_true",
@@ -531,23 +572,37 @@ def main():
                     help="also time the image pre-processing calls (drainage, distance "
                          "transform, relabelling, mixing layer) on the workload's image")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
-                    help="also run FP32-deviation beside FP64 for STEPS steps from the initial "
-                         "state, comparing Sw, Darcy flux and front position every 100 steps")
+                    help="also run FP32-deviation and FP32-mixed beside FP64 for STEPS steps "
+                         "from the initial state, comparing Sw, Darcy flux and front position "
+                         "every 100 steps")
     args = ap.parse_args()
-    args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
-        batch_main(args)
+        precs = tuple(p for p in args.batch_precisions.split(",") if p)
+        b = batch_run(args, precs)
+        first = b["pool_" + precs[0]]
+        print(json.dumps(_contract_line(
+            first["solves_per_s"], "solves/s (64 volumes x %d steps, %s pool)"
+            % (b["steps"], precs[0]), b["steps"], first["ms_per_step"],
+            "f32" if precs[0] == "fp32dev" else ("f32+f64" if precs[0] == "mixed" else "f64"),
+            {"workload": "batched: " + b["workload"]}, batched=b)), flush=True)
         return
     if args.workload == "serve":
-        serve_main(args)
+        sv = serve_run(args, args.serve_precision)
+        if args.serve_part != "both":
+            print(json.dumps({"part": args.serve_part, "serving": sv}), flush=True)
+            return
+        print(json.dumps(_contract_line(
+            sv["solves_per_s"], "solves/s (continuous batching, %s)" % args.serve_precision,
+            None, None, "f32+f64" if args.serve_precision == "mixed" else "f32",
+            {"workload": "serving: " + sv["workload"]}, serving=sv)), flush=True)
         return
 
     import torch
-    from paper_2007_12266_amd import inputs, lbm
+    from paper_2007_12266_amd import lbm
 
     wl = WORKLOADS[args.workload]
     log("generating %s" % args.workload)
@@ -559,8 +614,7 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         dom = lbm.Domain(prob, reduce_every=wl["reduce_every"], block_size=args.block,
-                         stream=stream.cuda_stream,
-                         precision=lbm.FP64 if args.precision == "fp64" else lbm.FP32_DEV,
+                         stream=stream.cuda_stream, precision=prec_of(lbm, args.precision),
                          neighbour_mode={"auto": lbm.NBR_AUTO, "table": lbm.NBR_TABLE,
                                          "rank": lbm.NBR_RANK}[args.neighbours])
     n_pore = dom.n_pore
@@ -586,15 +640,28 @@ def main():
     ms_per_step = ms / args.steps
     mlups = n_pore * args.steps / (ms / 1e3) / 1e6
 
+    # Reductions at their cadence: advance to the next multiple of the cadence, then time one
+    # whole interval, which ends with exactly one recorded reduction.
+    every = wl["reduce_every"]
+    dom.step((-dom.info()["step"]) % every)
+    torch.cuda.synchronize()
+    dom.history()
+    start.record(stream)
+    dom.step(every)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms_every = start.elapsed_time(end)
+    n_red = len(dom.history())
+
     # Per-kernel device time (HIP events around every launch, on the library's stream).
-    ksteps = min(args.steps, 200)
+    ksteps = min(max(args.steps, 2), 200)
     timing = dom.step_timed(ksteps)
     coll_s = timing["collide_ms"] / 1e3
     rank = dom.info()["neighbour_mode"] == lbm.NBR_RANK
     nbytes = launch_bytes(args.precision, rank, n_pore, prob.shape)
+    sbytes = survey_bytes(args.precision)
     achieved = nbytes["collide"] / coll_s / 1e9
-    tb = (_profiled_traffic(args.precision, "rank" if rank else "table")
-          if args.workload == "grf256" else None)
+    tb = _profiled_traffic(args.workload, args.precision, "rank" if rank else "table")
     traffic = None if tb is None else round(tb * n_pore / coll_s / 1e9, 1)
     step_gbs = nbytes["step"] / (ms_per_step / 1e3) / 1e9
 
@@ -608,40 +675,42 @@ def main():
     red = dom.reduce()
     block = dom.info()["block_size"]
     dom.close()
-    out = {
-        "metric": METRIC,
-        "value": round(mlups, 2),
-        "unit": "MLUPS (pore-voxel lattice updates per second / 1e6)",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
-        "data": "synthetic",
-        "config": {"workload": wl["desc"], "grid": list(prob.shape), "n_pore": n_pore,
-                   "porosity": round(n_pore / float(np.prod(prob.shape)), 5),
-                   "precision": args.precision, "reduce_every": wl["reduce_every"],
-                   "block": block, "tuning": tuning},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "traffic_unit": "GB/s (rocprofv3 FETCH_SIZE x2.0 + "
-                     "WRITE_SIZE x1.0 per voxel, over this run's kernel time)",
-                     "kernel": "collide_kernel",
-                     "bytes_per_voxel": nbytes["per_voxel"]["collide"],
-                     "row_bytes_per_launch": nbytes["row_bytes"],
-                     "neighbours": "rank" if rank else "table",
-                     "kernel_ms": round(timing["collide_ms"], 5)},
-        "step_hbm": {"bytes_per_voxel": nbytes["per_voxel"]["step"], "achieved_gbs": round(step_gbs, 1),
-                     "frac": round(step_gbs / HBM_PEAK_GBS, 4),
-                     "phase_ms": round(timing["phase_ms"], 5)},
-        "reductions": {"recorded": len(hist), "sw": red["sw"], "qz": red["qz"],
-                       "unstable": red["unstable"]},
-    }
+    dtype = {"fp64": "f64", "fp32dev": "f32", "mixed": "f32+f64"}[args.precision]
+    out = _contract_line(
+        round(mlups, 2), "MLUPS (pore-voxel lattice updates per second / 1e6)", args.steps,
+        round(ms_per_step, 5), dtype,
+        {"workload": wl["desc"], "grid": list(prob.shape), "n_pore": n_pore,
+         "porosity": round(n_pore / float(np.prod(prob.shape)), 5),
+         "precision": args.precision, "reduce_every": every, "block": block, "tuning": tuning},
+        roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                  "traffic": traffic,
+                  "traffic_unit": "GB/s (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 per "
+                                  "voxel, over this run's kernel time)",
+                  "traffic_bytes_per_voxel": tb,
+                  "kernel": "collide_kernel",
+                  "bytes_per_voxel": nbytes["per_voxel"]["collide"],
+                  "survey_bytes_per_voxel": sbytes["collide"],
+                  "frac_survey_bytes": round(sbytes["collide"] * n_pore / coll_s / 1e9
+                                             / HBM_PEAK_GBS, 4),
+                  "row_bytes_per_launch": nbytes["row_bytes"],
+                  "neighbours": "rank" if rank else "table",
+                  "kernel_ms": round(timing["collide_ms"], 5)},
+        step_hbm={"bytes_per_voxel": nbytes["per_voxel"]["step"],
+                  "achieved_gbs": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                  "survey_bytes_per_voxel": sbytes["step"],
+                  "frac_survey_bytes": round(sbytes["step"] * n_pore / (ms_per_step / 1e3)
+                                             / 1e9 / HBM_PEAK_GBS, 4),
+                  "phase_ms": round(timing["phase_ms"], 5), "bc_ms": round(timing["bc_ms"], 5)},
+        reductions={"every": every, "recorded_in_timed_steps": len(hist),
+                    "interval_ms": round(ms_every, 4), "recorded_in_interval": n_red,
+                    "ms_per_step_with_reductions": round(ms_every / every, 5),
+                    "reduction_ms_amortised_per_step": round(ms_every / every - ms_per_step, 5),
+                    "value_with_reductions": round(n_pore * every / (ms_every / 1e3) / 1e6, 2),
+                    "sw": red["sw"], "qz": red["qz"], "unstable": red["unstable"]})
+    out["warmup"] = args.warmup
     if args.precision_study:
-        out["fp32_vs_fp64"] = precision_study(prob, args.precision_study, 100, torch, lbm)
+        out["precision_vs_fp64"] = precision_study(prob, args.precision_study, 100, torch, lbm)
     if args.morph_study:
         out["morph"] = morph_study(prob, args, torch, lbm)
     if args.prep_study:
@@ -657,6 +726,12 @@ def main():
         if sample is not prob:
             out["cpu_baseline"]["sample"] += " (the same generator at 256^3, which bounds the " \
                                              "dense oracle's memory and set-up time)"
+    if not args.no_extras:
+        log("batched volumes")
+        out["batched"] = batch_run(args, tuple(p for p in args.batch_precisions.split(",")
+                                               if p))
+        log("serving trace")
+        out["serving"] = serve_run(args, args.serve_precision)
     print(json.dumps(out), flush=True)
 
 

@@ -44,7 +44,17 @@ typedef enum {
     LBM_ERR_STATE = 5     /* state buffer does not match this domain                   */
 } lbm_status;
 
-typedef enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 } lbm_precision;
+/* Storage and arithmetic of the state.
+ *   FP64       every value in double, double arithmetic.
+ *   FP32_DEV   the D3Q19 populations as float deviations f_q - t_q from the rest equilibrium,
+ *              the D3Q7 moment slots, phi and N as float, float arithmetic (the densities summed
+ *              in double): 328 bytes per pore voxel and step against 560.
+ *   FP32_MIXED the D3Q19 populations as float deviations, the phase field (D3Q7 moment slots,
+ *              phi, N) in double, double arithmetic: 408 bytes per pore voxel and step. Rounding
+ *              the phase field to float every step is what moves the Darcy flux of a two-phase
+ *              state; rounding f moves it about a thousand times less.
+ * Reductions and read-back are FP64 in every mode. */
+typedef enum { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP32_MIXED = 2 } lbm_precision;
 
 /* How the kernels find a pore voxel's 18 D3Q19 neighbours. TABLE: an int32 table of 18 entries
  * per pore voxel, read every step (72 bytes per voxel and step). RANK: computed from the voxel's
@@ -106,6 +116,10 @@ typedef struct {
                              /* 0 = 16 rows; R >= ny = dense order (z, y, x). Results do not */
                              /* depend on it.                                                 */
     int32_t pad_;
+    double rho_a, rho_b;     /* densities of fluids a and b. The model is the incompressible  */
+                             /* form with unit reference density (the paper runs density     */
+                             /* ratio 1), so both must be 1; 0 is read as 1 (a zeroed struct) */
+                             /* and any other value is LBM_ERR_ARG                             */
 } lbm_params;
 
 /* Reductions over the pore voxels (section "Analysis framework", integral measures, and the
@@ -361,25 +375,33 @@ lbm_status lbm_domain_destroy(lbm_domain* d);
 
 /* Create a pool for up to max_slots members whose device memory (lbm_domain_info.device_bytes)
  * sums to at most hbm_budget_bytes. chunk_steps (even, >= 2) is the length of the captured step
- * chunk. hip_stream is nullable (the pool then owns a stream). */
+ * chunk. alloc (nullable) is the device-memory hook for the pool's own tables (slot arguments,
+ * tile and group tables, reduction partials: about 4 KiB + 25 KiB per slot), else hipMalloc;
+ * members keep their own memory. hip_stream is nullable (the pool then owns a stream). */
 lbm_status lbm_pool_create(int64_t hbm_budget_bytes, int32_t precision, int32_t max_slots,
-                           int32_t chunk_steps, void* hip_stream, lbm_pool** out);
+                           int32_t chunk_steps, const lbm_allocator* alloc, void* hip_stream,
+                           lbm_pool** out);
 
 /* Add a domain; *slot receives its slot index. LBM_ERR_OOM if the budget or the slots are
  * exhausted; LBM_ERR_STATE for a precision or parity mismatch or a pooled domain. */
 lbm_status lbm_pool_admit(lbm_pool* pool, lbm_domain* d, int32_t* slot);
 
-/* Remove the member of `slot` (it keeps its state and returns to its own stream). */
-lbm_status lbm_pool_retire(lbm_pool* pool, int32_t slot);
+/* Remove the member of `slot`: it keeps its state and returns to its own stream. *out
+ * (nullable) receives its handle. The caller still owns the domain (the pool never frees one). */
+lbm_status lbm_pool_retire(lbm_pool* pool, int32_t slot, lbm_domain** out);
 
 /* Advance every member by nsteps >= 0 steps, asynchronously on the pool's stream. */
 lbm_status lbm_pool_step(lbm_pool* pool, int64_t nsteps);
 
+/* Reduce the member of `slot` now (see lbm_reduction), bitwise what lbm_reduce gives on it.
+ * Synchronises. LBM_ERR_ARG for an empty slot. */
+lbm_status lbm_pool_reduce(lbm_pool* pool, int32_t slot, lbm_reduction* out);
+
 /* Reduce every member now (one batched launch). out[slot] is written for slots 0..max_count-1
  * (an empty slot gets n_pore = 0); *count receives the number of slots written. Synchronises.
  * Each member's values are bitwise those of lbm_reduce on it. */
-lbm_status lbm_pool_reduce(lbm_pool* pool, lbm_reduction* out, int32_t max_count,
-                           int32_t* count);
+lbm_status lbm_pool_reduce_all(lbm_pool* pool, lbm_reduction* out, int32_t max_count,
+                               int32_t* count);
 
 typedef struct {
     int32_t max_slots, members, chunk_steps, grid;  /* grid: workgroups of the batched launch */

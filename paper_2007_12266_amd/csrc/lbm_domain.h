@@ -23,7 +23,7 @@ namespace lbm {
 // Turns the kNRed accumulators of a domain's reduction into an lbm_reduction.
 void finish_reduction(const lbm_domain* d, const double* acc, int64_t step, lbm_reduction* r);
 // A member's launch arguments changed: the pool re-uploads them before its next step.
-void pool_member_changed(lbm_pool* p);
+lbm_status pool_member_changed(lbm_pool* p, const lbm_domain* d);
 }  // namespace lbm
 
 #define HIP_TRY(expr)                                                                        \
@@ -87,6 +87,18 @@ struct lbm_domain {
     bool unstable = false;
     bool record_history = true;
 
+    // The step loop of lbm_step captured as a HIP graph: lbm::kStepGraphChunk steps from an
+    // even step, with the launch shapes and arguments at capture time. Dropped when those
+    // change (force, tuning) and rebuilt on the next use.
+    hipGraph_t step_graph = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    void drop_step_graph() {
+        if (step_exec) (void)hipGraphExecDestroy(step_exec);
+        if (step_graph) (void)hipGraphDestroy(step_graph);
+        step_exec = nullptr;
+        step_graph = nullptr;
+    }
+
     // Kernel arguments for a launch with `blk` threads per workgroup and schedule `sched`.
     lbm::StepArgs args(int blk = 256, int sched = 1) const {
         lbm::StepArgs a{};
@@ -135,6 +147,7 @@ struct lbm_domain {
 
     void release() {
         if (stream) (void)hipStreamSynchronize(stream);
+        drop_step_graph();
         for (void* ptr : allocations) {
             if (has_alloc)
                 alloc.free(ptr, alloc.ctx);
@@ -147,5 +160,7 @@ struct lbm_domain {
         stream = nullptr;
     }
 
-    size_t elem_bytes() const { return p.precision == LBM_FP32_DEV ? 4 : 8; }
+    // Bytes per stored D3Q19 population, and per stored moment-slot, phi or N value.
+    size_t f_bytes() const { return p.precision == LBM_FP64 ? 8 : 4; }
+    size_t m_bytes() const { return p.precision == LBM_FP32_DEV ? 4 : 8; }
 };

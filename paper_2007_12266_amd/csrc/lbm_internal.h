@@ -53,6 +53,10 @@ struct StepArgs {
 // given runs of kXcdRun consecutive tiles, the runs interleaved (grid a multiple of 8 kXcdRun).
 constexpr int kXcdRun = 16;
 
+// Steps in the captured chunk of the single-domain step loop (even, so every chunk starts and
+// ends on an even step).
+constexpr int64_t kStepGraphChunk = 64;
+
 struct BatchArgs {
     const StepArgs* doms;       // per-slot kernel arguments (N = 0 for an empty slot)
     const int32_t* tile_dom;    // slot of each tile

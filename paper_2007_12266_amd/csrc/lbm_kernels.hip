@@ -46,11 +46,14 @@
 //    interleaved. Neighbouring tiles then share an L2 (the cache lines a wave's scattered
 //    accesses leave half used are completed by the next tile on the same XCD) while all XCDs
 //    still stream through the pore list together.
-//  * Two storage precisions share every kernel body through a precision policy: FP64 stores f,
-//    the moment slots, phi and N in double and computes in double; FP32-deviation stores f as the
-//    deviation f_q - t_q from the rest equilibrium (rho0 = 1), the rest as float, and computes in
-//    float on those deviations. The two-rate collision is invariant under that shift (t_q is
-//    the same for q and opp(q)), so the same formulas serve both.
+//  * Three storage precisions share every kernel body through a precision policy: FP64 stores
+//    f, the moment slots, phi and N in double and computes in double; FP32-deviation stores f as
+//    the deviation f_q - t_q from the rest equilibrium (rho0 = 1), the rest as float, and
+//    computes in float on those deviations; the mixed form stores f as FP32 deviations but keeps
+//    the phase field (moment slots, phi, N) in double and computes in double, because rounding
+//    the phase field to float every step is what moves the Darcy flux of a two-phase state, not
+//    rounding f. The two-rate collision is invariant under the deviation shift (t_q is the same
+//    for q and opp(q)), so the same formulas serve all three.
 //  * No MFMA: nothing here is a dense contraction. The kernel is bound by HBM traffic.
 
 #include <cmath>
@@ -70,21 +73,31 @@ __host__ __device__ constexpr double tw(int q) {   // D3Q19 weights t_q
     return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-// Precision policies. S: storage type of f, the moment slots, phi, N. R: arithmetic type.
-// kDev: f is stored as f_q - t_q. kCMin: smallest resolved colour-gradient magnitude (a few
-// orders above the rounding noise of C in that precision); a smaller |C| counts as zero.
+// Precision policies. F: storage type of f. S: storage type of the moment slots, phi and N.
+// R: arithmetic type. kDev: f is stored as f_q - t_q. kCMin: smallest resolved colour-gradient
+// magnitude (a few orders above the rounding noise of C in the arithmetic type); a smaller |C|
+// counts as zero.
 template <int PREC> struct Prec;
 template <> struct Prec<LBM_FP64> {
+    using F = double;
     using S = double;
     using R = double;
     static constexpr bool kDev = false;
     static constexpr double kCMin = 1e-10;
 };
 template <> struct Prec<LBM_FP32_DEV> {
+    using F = float;
     using S = float;
     using R = float;
     static constexpr bool kDev = true;
     static constexpr double kCMin = 1e-5;
+};
+template <> struct Prec<LBM_FP32_MIXED> {
+    using F = float;
+    using S = double;
+    using R = double;
+    static constexpr bool kDev = true;
+    static constexpr double kCMin = 1e-10;
 };
 
 // Hardware block b runs on XCD b % 8 as that XCD's (b / 8)-th block; it takes logical tile
@@ -228,14 +241,15 @@ __device__ __forceinline__ void store_out(S* __restrict__ X, const StepArgs& a, 
 template <int PREC>
 __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double* __restrict__ phi0) {
     using P = Prec<PREC>;
+    using F = typename P::F;
     using S = typename P::S;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
-    S* f = (S*)a.f;
+    F* f = (F*)a.f;
     S* M = (S*)a.M;
     const double na = 0.5 * (1.0 + phi0[i]), nbv = 0.5 * (1.0 - phi0[i]);
 #pragma unroll
-    for (int q = 0; q < 19; ++q) f[(size_t)q * a.ld + i] = (S)(P::kDev ? 0.0 : tw(q));
+    for (int q = 0; q < 19; ++q) f[(size_t)q * a.ld + i] = (F)(P::kDev ? 0.0 : tw(q));
     // A fresh state: the component slots hold the densities (the fresh flag is set by the host).
     store_pair<S>(M, a.ld, 0, i, (S)na, (S)nbv);
 #pragma unroll
@@ -334,7 +348,7 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
         const R sq = (q & 1) ? (R)1 : (R)-1;
         ab_out<R>(sna[q], snb[q], suc[q], sgc[q], up[q] < a.N ? sq : -sq, ain[q], bin[q]);
     }
-    if (P::kDev) {
+    if (sizeof(S) == sizeof(float)) {
         // The rest population is what the six moving ones leave of N (the rounded float weights
         // would otherwise add 1.5e-8 of mass per step); sums in double, see below.
         double sa = 0.0, sb = 0.0;
@@ -395,9 +409,10 @@ __global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
 template <int PREC, bool ODD, int NB = NB_DYN>
 __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     using P = Prec<PREC>;
+    using F = typename P::F;
     using S = typename P::S;
     using R = typename P::R;
-    S* f = (S*)a.f;
+    F* f = (F*)a.f;
 
     int r[19];           // gradient neighbours (phi index)
     uint32_t mirror = 0; // bit q: streaming along q bounces back although r[q] is a pore index
@@ -522,7 +537,7 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     }
 
 #pragma unroll
-    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, RS(q), (S)fs[q]);
+    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, RS(q), (F)fs[q]);
 #undef RS
     if (i == 0) *a.fresh = 0;        // the state now holds outgoing moments
 }
@@ -593,8 +608,8 @@ template <int PREC, bool ODD>
 __device__ __forceinline__ void voxel_state(const StepArgs& a, int i, double& na, double& nbv,
                                             double& rho, double& jx, double& jy, double& jz) {
     using P = Prec<PREC>;
-    using S = typename P::S;
-    const S* f = (const S*)a.f;
+    using F = typename P::F;
+    const F* f = (const F*)a.f;
     int r[19];
     r[0] = i;
     const Pos pos = pos_of(a, i);
@@ -695,15 +710,35 @@ __global__ void __launch_bounds__(kRedThreads) reduce_batched(BatchArgs b,
                             partials + (size_t)slot * kRedBlocks * kNRed);
 }
 
-// Fixed-order sum of each group's nblocks partials; one workgroup per group.
-__global__ void reduce_final_kernel(const double* __restrict__ partials, int nblocks,
-                                    double* __restrict__ out) {
-    const int k = threadIdx.x;
-    if (k >= kNRed) return;
+// Sum of each group's nblocks partial records (kNRed values each); one workgroup of
+// kFinalThreads per group. Thread t adds the records t, t + kFinalThreads, ... in that order,
+// each wave combines its threads with the fixed butterfly, and the waves' sums are added in
+// wave order: the same order on every call, whatever the timing.
+constexpr int kFinalThreads = 256;
+
+__global__ void __launch_bounds__(kFinalThreads) reduce_final_kernel(
+    const double* __restrict__ partials, int nblocks, double* __restrict__ out) {
     const double* p = partials + (size_t)blockIdx.x * nblocks * kNRed;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += p[(size_t)b * kNRed + k];
-    out[(size_t)blockIdx.x * kNRed + k] = s;
+    double acc[kNRed];
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kFinalThreads) {
+#pragma unroll
+        for (int k = 0; k < kNRed; ++k) acc[k] += p[(size_t)b * kNRed + k];
+    }
+    __shared__ double lds[kFinalThreads / 64][kNRed];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) lds[wave][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNRed) {
+        double s = 0.0;
+        for (int w = 0; w < kFinalThreads / 64; ++w) s += lds[w][threadIdx.x];
+        out[(size_t)blockIdx.x * kNRed + threadIdx.x] = s;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -757,13 +792,13 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
                                                           double rho_out,
                                                           const double* __restrict__ rho_in_dev) {
     using P = Prec<PREC>;
-    using S = typename P::S;
+    using F = typename P::F;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_in + n_out) return;
     const int i = faces[k];
     const int dir = k < n_in ? 1 : -1;
     const double rho_b = k < n_in ? (rho_in_dev ? *rho_in_dev : rho_in) : rho_out;
-    S* f = (S*)a.f;
+    F* f = (F*)a.f;
     int r[19];
     r[0] = i;
     const Pos pos = pos_of(a, i);
@@ -789,7 +824,7 @@ __global__ void __launch_bounds__(256) pressure_bc_kernel(StepArgs a,
     for (int q = 0; q < 19; ++q) {
         if (CZ[q] != dir) continue;
         const double val = fl[OPP[q]] + 6.0 * tw(q) * CZ[q] * jz - 0.5 * (CX[q] * tx + CY[q] * ty);
-        f[(size_t)q * a.ld + i] = (S)(val - (P::kDev ? tw(q) : 0.0));
+        f[(size_t)q * a.ld + i] = (F)(val - (P::kDev ? tw(q) : 0.0));
     }
 }
 
@@ -805,9 +840,9 @@ template <int PREC, bool ODD>
 __global__ void __launch_bounds__(kInletThreads) inlet_partial_kernel(
     StepArgs a, const int32_t* __restrict__ faces, int n_in, double* __restrict__ partial) {
     using P = Prec<PREC>;
-    using S = typename P::S;
+    using F = typename P::F;
     __shared__ double acc[kInletThreads];
-    const S* f = (const S*)a.f;
+    const F* f = (const F*)a.f;
     double s = 0.0;
     for (int k = blockIdx.x * kInletThreads + threadIdx.x; k < n_in;
          k += kInletBlocks * kInletThreads) {
@@ -861,40 +896,46 @@ dim3 step_grid(const StepArgs& a) {
 // ------------------------------------------------------------------------------------------
 // Launchers: dispatch on precision and step parity (the step kernels also on the lookup).
 // ------------------------------------------------------------------------------------------
-#define LBM_DISPATCH(KERNEL, GRID, BLOCK, ...)                                              \
-    do {                                                                                    \
-        if (a.prec == LBM_FP32_DEV) {                                                       \
-            if (odd)                                                                        \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
-            else                                                                            \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false>), GRID, BLOCK, 0, s, __VA_ARGS__); \
-        } else {                                                                            \
-            if (odd)                                                                        \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, true>), GRID, BLOCK, 0, s, __VA_ARGS__);      \
-            else                                                                            \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, false>), GRID, BLOCK, 0, s, __VA_ARGS__);     \
-        }                                                                                   \
+// One launch of KERNEL<P, odd> (or KERNEL<P, odd, NB>) for the precision P of the domain.
+#define LBM_LAUNCH_ODD(KERNEL, P, GRID, BLOCK, ...)                                            \
+    do {                                                                                       \
+        if (odd)                                                                               \
+            hipLaunchKernelGGL((KERNEL<P, true>), GRID, BLOCK, 0, s, __VA_ARGS__);             \
+        else                                                                                   \
+            hipLaunchKernelGGL((KERNEL<P, false>), GRID, BLOCK, 0, s, __VA_ARGS__);            \
     } while (0)
 
-#define LBM_DISPATCH_NB(KERNEL, GRID, BLOCK, ...)                                                  \
-    do {                                                                                           \
-        if (a.prec == LBM_FP32_DEV) {                                                              \
-            if (odd)                                                                               \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true, NB>), GRID, BLOCK, 0, s, __VA_ARGS__);\
-            else                                                                                   \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false, NB>), GRID, BLOCK, 0, s, __VA_ARGS__);\
-        } else {                                                                                   \
-            if (odd)                                                                               \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, true, NB>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
-            else                                                                                   \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, false, NB>), GRID, BLOCK, 0, s, __VA_ARGS__); \
-        }                                                                                          \
+#define LBM_LAUNCH_ODD_NB(KERNEL, P, NBV, GRID, BLOCK, ...)                                    \
+    do {                                                                                       \
+        if (odd)                                                                               \
+            hipLaunchKernelGGL((KERNEL<P, true, NBV>), GRID, BLOCK, 0, s, __VA_ARGS__);        \
+        else                                                                                   \
+            hipLaunchKernelGGL((KERNEL<P, false, NBV>), GRID, BLOCK, 0, s, __VA_ARGS__);       \
     } while (0)
+
+#define LBM_PREC_SWITCH(PREC, LAUNCH, KERNEL, ...)                                             \
+    do {                                                                                       \
+        if ((PREC) == LBM_FP32_DEV)                                                            \
+            LAUNCH(KERNEL, LBM_FP32_DEV, __VA_ARGS__);                                         \
+        else if ((PREC) == LBM_FP32_MIXED)                                                     \
+            LAUNCH(KERNEL, LBM_FP32_MIXED, __VA_ARGS__);                                       \
+        else                                                                                   \
+            LAUNCH(KERNEL, LBM_FP64, __VA_ARGS__);                                             \
+    } while (0)
+
+#define LBM_DISPATCH(KERNEL, GRID, BLOCK, ...)                                                 \
+    LBM_PREC_SWITCH(a.prec, LBM_LAUNCH_ODD, KERNEL, GRID, BLOCK, __VA_ARGS__)
+
+#define LBM_DISPATCH_NB(KERNEL, GRID, BLOCK, ...)                                              \
+    LBM_PREC_SWITCH(a.prec, LBM_LAUNCH_ODD_NB, KERNEL, NB, GRID, BLOCK, __VA_ARGS__)
 
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s) {
     (void)block;
     if (a.prec == LBM_FP32_DEV)
         hipLaunchKernelGGL(init_kernel<LBM_FP32_DEV>, dim3(grid_for(a, 256)), dim3(256), 0, s,
+                           a, phi0);
+    else if (a.prec == LBM_FP32_MIXED)
+        hipLaunchKernelGGL(init_kernel<LBM_FP32_MIXED>, dim3(grid_for(a, 256)), dim3(256), 0, s,
                            a, phi0);
     else
         hipLaunchKernelGGL(init_kernel<LBM_FP64>, dim3(grid_for(a, 256)), dim3(256), 0, s, a,
@@ -930,52 +971,22 @@ hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* 
     LBM_DISPATCH(reduce_kernel, dim3(kRedBlocks), dim3(kRedThreads), a, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, partials, kRedBlocks, out);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kFinalThreads), 0, s, partials,
+                       kRedBlocks, out);
     return hipGetLastError();
 }
 
-#define LBM_DISPATCH_B(KERNEL, GRID, BLOCK, ...)                                            \
-    do {                                                                                    \
-        if (prec == LBM_FP32_DEV) {                                                         \
-            if (odd)                                                                        \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
-            else                                                                            \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false>), GRID, BLOCK, 0, s, __VA_ARGS__); \
-        } else {                                                                            \
-            if (odd)                                                                        \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, true>), GRID, BLOCK, 0, s, __VA_ARGS__);      \
-            else                                                                            \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, false>), GRID, BLOCK, 0, s, __VA_ARGS__);     \
-        }                                                                                   \
-    } while (0)
+#define LBM_DISPATCH_B(KERNEL, GRID, BLOCK, ...)                                               \
+    LBM_PREC_SWITCH(prec, LBM_LAUNCH_ODD, KERNEL, GRID, BLOCK, __VA_ARGS__)
 
-#define LBM_DISPATCH_B_NB(KERNEL, GRID, BLOCK, ...)                                         \
-    do {                                                                                    \
-        if (lookup == LBM_NBR_TABLE)                                                        \
-            LBM_DISPATCH_B3(KERNEL, NB_TABLE, GRID, BLOCK, __VA_ARGS__);                    \
-        else if (lookup == LBM_NBR_RANK)                                                    \
-            LBM_DISPATCH_B3(KERNEL, NB_RANK, GRID, BLOCK, __VA_ARGS__);                     \
-        else                                                                                \
-            LBM_DISPATCH_B3(KERNEL, NB_DYN, GRID, BLOCK, __VA_ARGS__);                      \
-    } while (0)
-
-#define LBM_DISPATCH_B3(KERNEL, NBV, GRID, BLOCK, ...)                                      \
-    do {                                                                                    \
-        if (prec == LBM_FP32_DEV) {                                                         \
-            if (odd)                                                                        \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, true, NBV>), GRID, BLOCK, 0, s,    \
-                                   __VA_ARGS__);                                            \
-            else                                                                            \
-                hipLaunchKernelGGL((KERNEL<LBM_FP32_DEV, false, NBV>), GRID, BLOCK, 0, s,   \
-                                   __VA_ARGS__);                                            \
-        } else {                                                                            \
-            if (odd)                                                                        \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, true, NBV>), GRID, BLOCK, 0, s,        \
-                                   __VA_ARGS__);                                            \
-            else                                                                            \
-                hipLaunchKernelGGL((KERNEL<LBM_FP64, false, NBV>), GRID, BLOCK, 0, s,       \
-                                   __VA_ARGS__);                                            \
-        }                                                                                   \
+#define LBM_DISPATCH_B_NB(KERNEL, GRID, BLOCK, ...)                                            \
+    do {                                                                                       \
+        if (lookup == LBM_NBR_TABLE)                                                           \
+            LBM_PREC_SWITCH(prec, LBM_LAUNCH_ODD_NB, KERNEL, NB_TABLE, GRID, BLOCK, __VA_ARGS__); \
+        else if (lookup == LBM_NBR_RANK)                                                       \
+            LBM_PREC_SWITCH(prec, LBM_LAUNCH_ODD_NB, KERNEL, NB_RANK, GRID, BLOCK, __VA_ARGS__); \
+        else                                                                                   \
+            LBM_PREC_SWITCH(prec, LBM_LAUNCH_ODD_NB, KERNEL, NB_DYN, GRID, BLOCK, __VA_ARGS__); \
     } while (0)
 
 hipError_t launch_phase_batched(const BatchArgs& b, int prec, bool odd, int lookup, int grid,
@@ -996,8 +1007,8 @@ hipError_t launch_reduce_batched(const BatchArgs& b, int prec, bool odd, int nsl
     LBM_DISPATCH_B(reduce_batched, dim3(nslots * kRedBlocks), dim3(kRedThreads), b, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(nslots), dim3(64), 0, s, partials, kRedBlocks,
-                       out);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(nslots), dim3(kFinalThreads), 0, s, partials,
+                       kRedBlocks, out);
     return hipGetLastError();
 }
 

@@ -38,6 +38,23 @@ struct lbm_pool {
     hipGraphExec_t exec = nullptr;
     int64_t replays = 0, eager = 0;
 
+    // Device memory of the pool's own tables: the caller's hook, else hipMalloc.
+    lbm_allocator alloc{};
+    bool has_alloc = false;
+    hipError_t dmalloc(void** out, size_t bytes) {
+        bytes = std::max<size_t>(bytes, 256);
+        if (!has_alloc) return hipMalloc(out, bytes);
+        *out = alloc.alloc(bytes, alloc.ctx);
+        return *out ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void dfree(void* ptr) {
+        if (!ptr) return;
+        if (has_alloc)
+            alloc.free(ptr, alloc.ctx);
+        else
+            (void)hipFree(ptr);
+    }
+
     // Cache groups of the captured chunk (group_bytes > 0): consecutive members whose device
     // footprints sum to at most group_bytes run the whole chunk before the next group starts,
     // so a group's state can stay in the last-level cache across its steps. Group g covers
@@ -80,7 +97,18 @@ struct lbm_pool {
 };
 
 namespace lbm {
-void pool_member_changed(lbm_pool* p) { p->dirty = true; }
+// A member's parameters changed (lbm_set_force): the batched kernels read them from the slot
+// table, which is uploaded again before the next step. A member with pressure faces also has
+// boundary launches of its own in the captured chunk, and those carry its arguments by value
+// (the flux inlet's body force), so the chunk is captured again.
+lbm_status pool_member_changed(lbm_pool* p, const lbm_domain* d) {
+    p->dirty = true;
+    if (d->p.bc_z == 1) {
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        p->drop_graph();
+    }
+    return LBM_OK;
+}
 }  // namespace lbm
 
 namespace {
@@ -122,13 +150,13 @@ lbm_status upload_groups(lbm_pool* p) {
     if (groups.size() > p->group_cap) {
         const size_t cap = std::max(groups.size(), 2 * p->group_cap);
         int32_t *first = nullptr, *nt = nullptr;
-        if (hipMalloc(&first, sizeof(int32_t) * cap * p->max_slots) != hipSuccess ||
-            hipMalloc(&nt, sizeof(int32_t) * cap) != hipSuccess) {
-            if (first) (void)hipFree(first);
+        if (p->dmalloc((void**)&first, sizeof(int32_t) * cap * p->max_slots) != hipSuccess ||
+            p->dmalloc((void**)&nt, sizeof(int32_t) * cap) != hipSuccess) {
+            p->dfree(first);
             return fail(LBM_ERR_OOM, "device allocation failed (pool groups)");
         }
-        if (p->d_group_first) (void)hipFree(p->d_group_first);
-        if (p->d_group_ntiles) (void)hipFree(p->d_group_ntiles);
+        p->dfree(p->d_group_first);
+        p->dfree(p->d_group_ntiles);
         p->d_group_first = first;
         p->d_group_ntiles = nt;
         p->group_cap = cap;
@@ -185,8 +213,9 @@ lbm_status upload_tables(lbm_pool* p) {
         int64_t cap = std::max<int64_t>(p->tile_cap * 2, (int64_t)p->h_tile_dom.size());
         int32_t* ptr = nullptr;
         HIP_TRY(hipStreamSynchronize(p->stream));
-        HIP_TRY(hipMalloc(&ptr, sizeof(int32_t) * cap));
-        if (p->d_tile_dom) (void)hipFree(p->d_tile_dom);
+        if (p->dmalloc((void**)&ptr, sizeof(int32_t) * cap) != hipSuccess)
+            return fail(LBM_ERR_OOM, "device allocation failed (pool tile table)");
+        p->dfree(p->d_tile_dom);
         p->d_tile_dom = ptr;
         p->tile_cap = cap;
         p->drop_graph();
@@ -297,16 +326,23 @@ void advance_members(lbm_pool* p, int64_t n) {
 extern "C" {
 
 lbm_status lbm_pool_create(int64_t hbm_budget_bytes, int32_t precision, int32_t max_slots,
-                           int32_t chunk_steps, void* hip_stream, lbm_pool** out) {
+                           int32_t chunk_steps, const lbm_allocator* alloc, void* hip_stream,
+                           lbm_pool** out) {
     if (!out) return fail(LBM_ERR_ARG, "out must be non-null");
     *out = nullptr;
     if (hbm_budget_bytes <= 0 || max_slots <= 0 || max_slots > 4096)
         return fail(LBM_ERR_ARG, "need hbm_budget_bytes > 0 and 0 < max_slots <= 4096");
-    if (precision != LBM_FP64 && precision != LBM_FP32_DEV)
-        return fail(LBM_ERR_ARG, "precision must be LBM_FP64 or LBM_FP32_DEV");
+    if (precision != LBM_FP64 && precision != LBM_FP32_DEV && precision != LBM_FP32_MIXED)
+        return fail(LBM_ERR_ARG, "precision must be a lbm_precision");
     if (chunk_steps < 2 || (chunk_steps & 1)) return fail(LBM_ERR_ARG, "chunk_steps must be even and >= 2");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(LBM_ERR_ARG, "allocator needs both alloc and free");
     lbm_pool* p = new (std::nothrow) lbm_pool();
     if (!p) return fail(LBM_ERR_OOM, "host allocation failed");
+    if (alloc) {
+        p->alloc = *alloc;
+        p->has_alloc = true;
+    }
     p->precision = precision;
     p->max_slots = max_slots;
     p->chunk = chunk_steps;
@@ -332,13 +368,13 @@ lbm_status lbm_pool_create(int64_t hbm_budget_bytes, int32_t precision, int32_t 
     p->cus = std::max(1, cus);
     p->default_grid = p->grid = p->cus * 32;
     p->tile_cap = 1 << 16;
-    if (hipMalloc(&p->d_doms, sizeof(StepArgs) * max_slots) != hipSuccess ||
-        hipMalloc(&p->d_tile_first, sizeof(int32_t) * max_slots) != hipSuccess ||
-        hipMalloc(&p->d_tile_dom, sizeof(int32_t) * p->tile_cap) != hipSuccess ||
-        hipMalloc(&p->d_ntiles, sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&p->d_partials, sizeof(double) * kNRed * kRedBlocks * (size_t)max_slots) !=
-            hipSuccess ||
-        hipMalloc(&p->d_red, sizeof(double) * kNRed * (size_t)max_slots) != hipSuccess)
+    if (p->dmalloc((void**)&p->d_doms, sizeof(StepArgs) * max_slots) != hipSuccess ||
+        p->dmalloc((void**)&p->d_tile_first, sizeof(int32_t) * max_slots) != hipSuccess ||
+        p->dmalloc((void**)&p->d_tile_dom, sizeof(int32_t) * p->tile_cap) != hipSuccess ||
+        p->dmalloc((void**)&p->d_ntiles, sizeof(int32_t)) != hipSuccess ||
+        p->dmalloc((void**)&p->d_partials,
+                   sizeof(double) * kNRed * kRedBlocks * (size_t)max_slots) != hipSuccess ||
+        p->dmalloc((void**)&p->d_red, sizeof(double) * kNRed * (size_t)max_slots) != hipSuccess)
         return bail(LBM_ERR_OOM, "device allocation failed");
     if (lbm_status s = upload_tables(p)) {
         lbm_pool_destroy(p);
@@ -376,7 +412,8 @@ lbm_status lbm_pool_admit(lbm_pool* p, lbm_domain* d, int32_t* slot) {
     return LBM_OK;
 }
 
-lbm_status lbm_pool_retire(lbm_pool* p, int32_t slot) {
+lbm_status lbm_pool_retire(lbm_pool* p, int32_t slot, lbm_domain** out) {
+    if (out) *out = nullptr;
     if (!p || slot < 0 || slot >= p->max_slots || !p->slots[slot])
         return fail(LBM_ERR_ARG, "no member in that slot");
     lbm_domain* d = p->slots[slot];
@@ -388,6 +425,7 @@ lbm_status lbm_pool_retire(lbm_pool* p, int32_t slot) {
     p->slots[slot] = nullptr;
     p->used -= d->device_bytes;
     p->dirty = true;
+    if (out) *out = d;
     return LBM_OK;
 }
 
@@ -421,7 +459,17 @@ lbm_status lbm_pool_step(lbm_pool* p, int64_t nsteps) {
     return LBM_OK;
 }
 
-lbm_status lbm_pool_reduce(lbm_pool* p, lbm_reduction* out, int32_t max_count, int32_t* count) {
+lbm_status lbm_pool_reduce(lbm_pool* p, int32_t slot, lbm_reduction* out) {
+    if (!p || !out) return fail(LBM_ERR_ARG, "null argument");
+    if (slot < 0 || slot >= p->max_slots || !p->slots[slot])
+        return fail(LBM_ERR_ARG, "no member in that slot");
+    // A member runs on the pool's stream; its own reduction is the single-domain one, whose
+    // decomposition the batched reduction reproduces bit for bit.
+    return lbm_reduce(p->slots[slot], out);
+}
+
+lbm_status lbm_pool_reduce_all(lbm_pool* p, lbm_reduction* out, int32_t max_count,
+                               int32_t* count) {
     if (!p || !count || (max_count > 0 && !out)) return fail(LBM_ERR_ARG, "null argument");
     if (p->dirty)
         if (lbm_status s = upload_tables(p)) return s;
@@ -499,16 +547,16 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
     lbm_status st = LBM_OK;
     for (lbm_domain* d : p->slots) {
         if (!d) continue;
-        const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
-        Snap sn{d, nullptr, eb * 27 * ld + sizeof(int32_t)};
-        if (hipMalloc(&sn.buf, sn.bytes) != hipSuccess) {
+        const size_t fb = d->f_bytes(), eb = d->m_bytes(), ld = (size_t)d->pre.ld;
+        Snap sn{d, nullptr, (fb * 19 + eb * 8) * ld + sizeof(int32_t)};
+        if (p->dmalloc(&sn.buf, sn.bytes) != hipSuccess) {
             st = fail(LBM_ERR_OOM, "no device memory for the autotuner's snapshot");
             break;
         }
         snaps.push_back(sn);
         size_t off = 0;
         void* arr[3] = {d->f, d->M, d->fresh};
-        const size_t sizes[3] = {eb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
+        const size_t sizes[3] = {fb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
         for (int k = 0; k < 3 && st == LBM_OK; ++k) {
             if (hipMemcpyAsync((char*)sn.buf + off, arr[k], sizes[k], hipMemcpyDeviceToDevice,
                                p->stream) != hipSuccess)
@@ -584,10 +632,10 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
     // Restore states; the trial steps came in even numbers, so parities are unchanged.
     for (size_t k = 0; k < snaps.size(); ++k) {
         lbm_domain* d = snaps[k].d;
-        const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
+        const size_t fb = d->f_bytes(), eb = d->m_bytes(), ld = (size_t)d->pre.ld;
         size_t off = 0;
         void* arr[3] = {d->f, d->M, d->fresh};
-        const size_t sizes[3] = {eb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
+        const size_t sizes[3] = {fb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
         for (int a = 0; a < 3; ++a) {
             if (hipMemcpyAsync(arr[a], (char*)snaps[k].buf + off, sizes[a],
                                hipMemcpyDeviceToDevice, p->stream) != hipSuccess &&
@@ -600,7 +648,7 @@ lbm_status lbm_pool_autotune(lbm_pool* p, int32_t trial_steps, int32_t* grid) {
     p->step = step0;
     if (hipStreamSynchronize(p->stream) != hipSuccess && st == LBM_OK)
         st = fail(LBM_ERR_DEVICE, "synchronise failed");
-    for (const Snap& sn : snaps) (void)hipFree(sn.buf);
+    for (const Snap& sn : snaps) p->dfree(sn.buf);
     p->grid = st == LBM_OK ? best : keep;
     p->order = st == LBM_OK ? best_order : keep_order;
     p->group_bytes = st == LBM_OK ? best_group : keep_group;
@@ -614,12 +662,11 @@ lbm_status lbm_pool_destroy(lbm_pool* p) {
     if (!p) return LBM_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     for (int32_t s = 0; s < (int32_t)p->slots.size(); ++s)
-        if (p->slots[s]) (void)lbm_pool_retire(p, s);
+        if (p->slots[s]) (void)lbm_pool_retire(p, s, nullptr);
     p->drop_graph();
     void* bufs[] = {p->d_doms, p->d_tile_first, p->d_tile_dom, p->d_ntiles, p->d_partials,
                     p->d_red, p->d_group_first, p->d_group_ntiles};
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
+    for (void* b : bufs) p->dfree(b);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
     return LBM_OK;

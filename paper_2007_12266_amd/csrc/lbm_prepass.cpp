@@ -86,6 +86,9 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
     }
     if (!(p.wall_affinity >= -1.0 && p.wall_affinity <= 1.0))
         return "wall_affinity is outside [-1, 1]";
+    // The model is the incompressible form with unit reference density for both fluids.
+    if ((p.rho_a != 0.0 && p.rho_a != 1.0) || (p.rho_b != 0.0 && p.rho_b != 1.0))
+        return "rho_a and rho_b must be 1 (or 0 for the default 1)";
 
     if (p.order_rows < 0) return "order_rows must be >= 0";
     for (int64_t v = 0; v < nvox; ++v) {

@@ -28,14 +28,14 @@ void clear_error() { g_err.clear(); }
 
 namespace {
 
-constexpr uint64_t kStateMagic = 0x4c424d434f4c5234ull;  // "LBMCOLR4"
-constexpr int kStateRows = 27;  // 19 D3Q19 populations + 8 D3Q7 moment slots
+constexpr uint64_t kStateMagic = 0x4c424d434f4c5235ull;  // "LBMCOLR5"
 
 struct StateHeader {
     uint64_t magic;
     int64_t n_pore, n_tail, step;
-    int32_t precision, elem_bytes;
-    int32_t fresh, pad_;   // 1: the moment slots hold densities of a state at rest (see init)
+    int32_t precision, f_bytes;   // bytes per stored D3Q19 population
+    int32_t fresh;   // 1: the moment slots hold densities of a state at rest (see init)
+    int32_t m_bytes; // bytes per stored moment-slot value
 };
 
 }  // namespace
@@ -86,11 +86,84 @@ lbm_status check_domain(lbm_domain* d) {
     return LBM_OK;
 }
 
+// The launches of one time step at parity `odd`: densities and phase, the z-face mirror of
+// the phase, the fused gradient + collision + recolouring + streaming, then (pressure faces) the
+// inlet density of a flux inlet and the face conditions. `mark(kind, begin)` brackets each
+// kernel group with events when timing (kind 0: phase, 1: collide, 2: faces); null otherwise.
+template <typename Mark>
+lbm_status launch_step(lbm_domain* d, bool odd, Mark mark) {
+    const lbm_tuning& tu = d->tune;
+    const StepArgs ap = d->args(tu.phase_block, tu.phase_schedule);
+    const StepArgs ac = d->args(tu.collide_block, tu.collide_schedule);
+    if (lbm_status s = mark(0, true)) return s;
+    HIP_TRY(launch_phase(ap, odd, tu.phase_block, d->stream));
+    if (!d->rank && !d->pre.ghost_tail.empty())
+        HIP_TRY(launch_ghosts(ap, d->ghost_tail, d->ghost_src, (int32_t)d->pre.ghost_tail.size(),
+                              d->stream));
+    if (lbm_status s = mark(0, false)) return s;
+    if (lbm_status s = mark(1, true)) return s;
+    HIP_TRY(launch_collide(ac, odd, tu.collide_block, d->stream));
+    if (lbm_status s = mark(1, false)) return s;
+    if (d->p.bc_z == 1) {
+        if (lbm_status s = mark(2, true)) return s;
+        // The reduction partials are free between reductions: scratch for the inlet sum.
+        if (d->inlet_rho)
+            HIP_TRY(launch_inlet_density(ac, !odd, d->faces, (int32_t)d->pre.inlet.size(),
+                                         d->p.flux_in, d->inlet_rho, d->red_partials,
+                                         d->stream));
+        HIP_TRY(launch_pressure_bc(ac, !odd, d->faces, (int32_t)d->pre.inlet.size(),
+                                   (int32_t)d->pre.outlet.size(), d->p.rho_in, d->p.rho_out,
+                                   d->inlet_rho, d->stream));
+        if (lbm_status s = mark(2, false)) return s;
+    }
+    return LBM_OK;
+}
+
+lbm_status no_mark(int, bool) { return LBM_OK; }
+
+// Capture kStepGraphChunk steps from an even step. The capture is always ended, so a failed
+// launch leaves the stream usable.
+lbm_status capture_step_chunk(lbm_domain* d) {
+    d->drop_step_graph();
+    HIP_TRY(hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal));
+    lbm_status st = LBM_OK;
+    for (int64_t k = 0; k < kStepGraphChunk && st == LBM_OK; ++k)
+        st = launch_step(d, (k & 1) != 0, no_mark);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(d->stream, &g);
+    if (st != LBM_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != LBM_OK ? st
+                            : fail(LBM_ERR_DEVICE, std::string("step graph capture: ") +
+                                                       hipGetErrorString(e));
+    }
+    d->step_graph = g;
+    if (hipGraphInstantiate(&d->step_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        d->drop_step_graph();
+        return fail(LBM_ERR_DEVICE, "step graph instantiation failed");
+    }
+    return LBM_OK;
+}
+
+lbm_status record_due_reduction(lbm_domain* d) {
+    if (!(d->record_history && d->p.reduce_every > 0 && d->step % d->p.reduce_every == 0))
+        return LBM_OK;
+    const int slot = d->hist_head;
+    if (lbm_status st = record_reduction(d, d->hist + (size_t)slot * kNRed)) return st;
+    d->hist_step[slot] = d->step;
+    d->hist_head = (d->hist_head + 1) % d->hist_cap;
+    d->hist_count = std::min(d->hist_count + 1, d->hist_cap);
+    return LBM_OK;
+}
+
+// nsteps steps. Untimed, whole chunks that start on an even step and have no reduction due
+// before their last step replay the captured chunk (one launch instead of 2 to 4 per step);
+// the rest, and every timed step, is launched step by step. Results are the same either way.
 lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
     if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
     if (d->unstable) return fail(LBM_ERR_UNSTABLE, "domain is unstable; load a state");
     std::vector<hipEvent_t> ev;
-    auto mark = [&](hipEvent_t* out) -> hipError_t {
+    auto event = [&](hipEvent_t* out) -> hipError_t {
         hipError_t e = hipEventCreate(out);
         if (e != hipSuccess) return e;
         ev.push_back(*out);
@@ -101,47 +174,43 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (timing) {
         std::memset(timing, 0, sizeof *timing);
-        HIP_TRY(mark(&t0));
+        HIP_TRY(event(&t0));
     }
+    auto mark = [&](int kind, bool begin) -> lbm_status {
+        if (begin) {
+            spans.push_back(Span{nullptr, nullptr, kind});
+            HIP_TRY(event(&spans.back().a));
+        } else {
+            HIP_TRY(event(&spans.back().b));
+        }
+        return LBM_OK;
+    };
+    // A caller may capture lbm_step into a graph of its own: then no nested capture.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(d->stream, &cap));
+    const bool graphs = !timing && cap == hipStreamCaptureStatusNone;
     lbm_status st = LBM_OK;
-    for (int64_t s = 0; s < nsteps && st == LBM_OK; ++s) {
-        const lbm_tuning& tu = d->tune;
-        const StepArgs ap = d->args(tu.phase_block, tu.phase_schedule);
-        const StepArgs ac = d->args(tu.collide_block, tu.collide_schedule);
-        const StepArgs a = ac;
-        const bool odd = (d->step & 1) != 0;
-        Span sp{};
-        if (timing) { sp.kind = 0; HIP_TRY(mark(&sp.a)); }
-        HIP_TRY(launch_phase(ap, odd, tu.phase_block, d->stream));
-        if (!d->rank && !d->pre.ghost_tail.empty())
-            HIP_TRY(launch_ghosts(ap, d->ghost_tail, d->ghost_src,
-                                  (int32_t)d->pre.ghost_tail.size(), d->stream));
-        if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); sp.kind = 1; HIP_TRY(mark(&sp.a)); }
-        HIP_TRY(launch_collide(ac, odd, tu.collide_block, d->stream));
-        if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
-        if (d->p.bc_z == 1) {
-            if (timing) { sp.kind = 2; HIP_TRY(mark(&sp.a)); }
-            // The reduction partials are free between reductions: scratch for the inlet sum.
-            if (d->inlet_rho)
-                HIP_TRY(launch_inlet_density(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
-                                             d->p.flux_in, d->inlet_rho, d->red_partials,
-                                             d->stream));
-            HIP_TRY(launch_pressure_bc(a, !odd, d->faces, (int32_t)d->pre.inlet.size(),
-                                       (int32_t)d->pre.outlet.size(), d->p.rho_in,
-                                       d->p.rho_out, d->inlet_rho, d->stream));
-            if (timing) { HIP_TRY(mark(&sp.b)); spans.push_back(sp); }
+    int64_t s = 0;
+    while (s < nsteps && st == LBM_OK) {
+        const int64_t every = d->record_history ? d->p.reduce_every : 0;
+        if (graphs && nsteps - s >= kStepGraphChunk && (d->step & 1) == 0 &&
+            (every <= 0 || every - d->step % every >= kStepGraphChunk)) {
+            if (!d->step_exec)
+                if ((st = capture_step_chunk(d)) != LBM_OK) break;
+            HIP_TRY(hipGraphLaunch(d->step_exec, d->stream));
+            d->step += kStepGraphChunk;
+            s += kStepGraphChunk;
+        } else {
+            st = timing ? launch_step(d, (d->step & 1) != 0, mark)
+                        : launch_step(d, (d->step & 1) != 0, no_mark);
+            if (st != LBM_OK) break;
+            d->step += 1;
+            s += 1;
         }
-        d->step += 1;
-        if (d->record_history && d->p.reduce_every > 0 && d->step % d->p.reduce_every == 0) {
-            const int slot = d->hist_head;
-            st = record_reduction(d, d->hist + (size_t)slot * kNRed);
-            d->hist_step[slot] = d->step;
-            d->hist_head = (d->hist_head + 1) % d->hist_cap;
-            d->hist_count = std::min(d->hist_count + 1, d->hist_cap);
-        }
+        st = record_due_reduction(d);
     }
-    if (timing) {
-        HIP_TRY(mark(&t1));
+    if (timing && st == LBM_OK) {
+        HIP_TRY(event(&t1));
         HIP_TRY(hipEventSynchronize(t1));
         double sum[3] = {0, 0, 0};
         int64_t cnt[3] = {0, 0, 0};
@@ -174,12 +243,14 @@ static bool uses_rank(const lbm_params& p, const Prepass& pre) {
 }
 
 static int64_t domain_bytes(const lbm_params& p, const Prepass& pre) {
-    const size_t eb = p.precision == LBM_FP32_DEV ? 4 : 8, ld = (size_t)pre.ld;
+    const size_t fb = p.precision == LBM_FP64 ? 8 : 4;         // D3Q19 populations
+    const size_t eb = p.precision == LBM_FP32_DEV ? 4 : 8;     // moment slots, phi, N
+    const size_t ld = (size_t)pre.ld;
     auto r = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
     const int64_t nbr = uses_rank(p, pre)
                             ? r(sizeof(uint32_t) * ld) + r(sizeof(RowWord) * pre.words.size())
                             : r(sizeof(int32_t) * 18 * ld);
-    int64_t total = r(eb * 19 * ld) + r(eb * 8 * ld) + r(sizeof(int32_t)) +
+    int64_t total = r(fb * 19 * ld) + r(eb * 8 * ld) + r(sizeof(int32_t)) +
                     r(eb * (size_t)(pre.n_pore + pre.n_tail)) + r(eb * ld) +
                     r(sizeof(double) * ld) + nbr +
                     r(sizeof(double) * kRedBlocks * kNRed) + r(sizeof(double) * kNRed) +
@@ -229,8 +300,8 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return fail(LBM_ERR_ARG, "alpha must be >= 0");
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(p.force[c])) return fail(LBM_ERR_ARG, "force must be finite");
-    if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV)
-        return fail(LBM_ERR_ARG, "precision must be LBM_FP64 or LBM_FP32_DEV");
+    if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV && p.precision != LBM_FP32_MIXED)
+        return fail(LBM_ERR_ARG, "precision must be a lbm_precision");
     if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
         return fail(LBM_ERR_ARG, "rho_in and rho_out must be positive");
     if (p.inlet_mode != 0 && p.inlet_mode != 1)
@@ -267,9 +338,9 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         d->own_stream = true;
     }
     const Prepass& pre = d->pre;
-    const size_t eb = d->elem_bytes();
+    const size_t fb = d->f_bytes(), eb = d->m_bytes();
     const size_t ld = (size_t)pre.ld;
-    d->f = d->dalloc(eb * 19 * ld);
+    d->f = d->dalloc(fb * 19 * ld);
     d->M = d->dalloc(eb * 8 * ld);
     d->fresh = (int32_t*)d->dalloc(sizeof(int32_t));
     d->phi = d->dalloc(eb * (size_t)(pre.n_pore + pre.n_tail));
@@ -354,7 +425,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         guard(up(d->ghost_src, pre.ghost_src.data(), sizeof(int32_t) * pre.ghost_src.size()),
               "upload ghosts");
     }
-    guard(hipMemsetAsync(d->f, 0, eb * 19 * ld, d->stream), "clear f");
+    guard(hipMemsetAsync(d->f, 0, fb * 19 * ld, d->stream), "clear f");
     guard(hipMemsetAsync(d->M, 0, eb * 8 * ld, d->stream), "clear M");
     if (st == LBM_OK) guard(launch_init(d->args(), phi0, d->block, d->stream), "init kernel");
     if (st == LBM_OK) guard(hipStreamSynchronize(d->stream), "create sync");
@@ -430,7 +501,9 @@ lbm_status lbm_set_force(lbm_domain* d, const double force[3]) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(force[a])) return fail(LBM_ERR_ARG, "force must be finite");
     for (int a = 0; a < 3; ++a) d->p.force[a] = force[a];
-    if (d->pool) pool_member_changed(d->pool);
+    if (d->stream) HIP_TRY(hipStreamSynchronize(d->stream));
+    d->drop_step_graph();                    // its launches carry the old force
+    if (d->pool) return pool_member_changed(d->pool, d);
     return LBM_OK;
 }
 
@@ -518,9 +591,9 @@ lbm_status lbm_read_history(lbm_domain* d, lbm_reduction* out, int32_t max_count
 lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
     if (lbm_status s = check_domain(d)) return s;
     if (!nbytes) return fail(LBM_ERR_ARG, "nbytes must be non-null");
-    const size_t eb = d->elem_bytes();
+    const size_t fb = d->f_bytes(), eb = d->m_bytes();
     const size_t n = (size_t)d->pre.n_pore, ld = (size_t)d->pre.ld;
-    const size_t need = sizeof(StateHeader) + eb * kStateRows * n;
+    const size_t need = sizeof(StateHeader) + (fb * 19 + eb * 8) * n;
     if (!host_buf) {
         *nbytes = need;
         return LBM_OK;
@@ -529,13 +602,13 @@ lbm_status lbm_state_save(lbm_domain* d, void* host_buf, size_t* nbytes) {
     int32_t fresh = 0;
     HIP_TRY(hipMemcpyAsync(&fresh, d->fresh, sizeof fresh, hipMemcpyDeviceToHost, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
-    StateHeader h{kStateMagic, d->pre.n_pore, d->pre.n_tail, d->step, d->p.precision, (int32_t)eb,
-                  fresh, 0};
+    StateHeader h{kStateMagic, d->pre.n_pore, d->pre.n_tail, d->step, d->p.precision, (int32_t)fb,
+                  fresh, (int32_t)eb};
     std::memcpy(host_buf, &h, sizeof h);
     char* dst = (char*)host_buf + sizeof h;
     // f: 19 rows of n values and M: 4 rows of n value pairs (pitch ld on the device).
-    for (int q = 0; q < 19; ++q, dst += eb * n)
-        HIP_TRY(copy_to_host(dst, (const char*)d->f + eb * ld * q, eb * n, d->stream));
+    for (int q = 0; q < 19; ++q, dst += fb * n)
+        HIP_TRY(copy_to_host(dst, (const char*)d->f + fb * ld * q, fb * n, d->stream));
     for (int k = 0; k < 4; ++k, dst += 2 * eb * n)
         HIP_TRY(copy_to_host(dst, (const char*)d->M + 2 * eb * ld * k, 2 * eb * n, d->stream));
     *nbytes = need;
@@ -546,18 +619,18 @@ lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes) {
     if (lbm_status s = check_domain(d)) return s;
     if (!host_buf) return fail(LBM_ERR_ARG, "host_buf must be non-null");
     if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool; retire it first");
-    const size_t eb = d->elem_bytes();
+    const size_t fb = d->f_bytes(), eb = d->m_bytes();
     const size_t n = (size_t)d->pre.n_pore, ld = (size_t)d->pre.ld;
     StateHeader h;
     if (nbytes < sizeof h) return fail(LBM_ERR_STATE, "state buffer too small");
     std::memcpy(&h, host_buf, sizeof h);
     if (h.magic != kStateMagic || h.n_pore != d->pre.n_pore || h.n_tail != d->pre.n_tail ||
-        h.precision != d->p.precision || h.elem_bytes != (int32_t)eb ||
-        nbytes != sizeof h + eb * kStateRows * n)
+        h.precision != d->p.precision || h.f_bytes != (int32_t)fb || h.m_bytes != (int32_t)eb ||
+        nbytes != sizeof h + (fb * 19 + eb * 8) * n)
         return fail(LBM_ERR_STATE, "state does not match this domain");
     const char* src = (const char*)host_buf + sizeof h;
-    for (int q = 0; q < 19; ++q, src += eb * n)
-        HIP_TRY(copy_to_device((char*)d->f + eb * ld * q, src, eb * n, d->stream));
+    for (int q = 0; q < 19; ++q, src += fb * n)
+        HIP_TRY(copy_to_device((char*)d->f + fb * ld * q, src, fb * n, d->stream));
     for (int k = 0; k < 4; ++k, src += 2 * eb * n)
         HIP_TRY(copy_to_device((char*)d->M + 2 * eb * ld * k, src, 2 * eb * n, d->stream));
     d->one = h.fresh ? 1 : 0;                // a state at rest (initial, or after lbm_morph)
@@ -596,6 +669,8 @@ static bool tuning_ok(const lbm_tuning& t) {
 lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t) {
     if (lbm_status s = check_domain(d)) return s;
     if (!t || !tuning_ok(*t)) return fail(LBM_ERR_ARG, "unsupported block or schedule");
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    d->drop_step_graph();
     d->tune = *t;
     return LBM_OK;
 }
@@ -613,12 +688,12 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     if (d->pool) return fail(LBM_ERR_STATE, "the domain belongs to a pool");
     if (d->unstable) return fail(LBM_ERR_UNSTABLE, "domain is unstable; load a state");
     trial_steps += trial_steps & 1;  // even: both parities equally
-    const size_t eb = d->elem_bytes(), ld = (size_t)d->pre.ld;
-    const size_t bytes = eb * kStateRows * ld + 256;
+    const size_t fb = d->f_bytes(), eb = d->m_bytes(), ld = (size_t)d->pre.ld;
+    const size_t bytes = (fb * 19 + eb * 8) * ld + 256;
     char* snap = (char*)d->dalloc(bytes);
     if (!snap) return fail(LBM_ERR_OOM, "no device memory for the autotuner's snapshot");
     void* arrays[3] = {d->f, d->M, d->fresh};
-    const size_t sizes[3] = {eb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
+    const size_t sizes[3] = {fb * 19 * ld, eb * 8 * ld, sizeof(int32_t)};
     auto copy_all = [&](bool save) -> hipError_t {
         size_t off = 0;
         for (int k = 0; k < 3; ++k) {
@@ -685,6 +760,7 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     }
     best.phase_ms = best_ms[0];
     best.collide_ms = best_ms[1];
+    d->drop_step_graph();
     d->tune = best;
     if (out) *out = best;
     return LBM_OK;

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE, LBM_ERR_STATE = range(6)
-FP64, FP32_DEV = 0, 1
+FP64, FP32_DEV, FP32_MIXED = 0, 1, 2
 NBR_AUTO, NBR_TABLE, NBR_RANK = 0, 1, 2
 FIELDS = {"Na": 0, "Nb": 1, "phi": 2, "rho": 3, "p": 4, "ux": 5, "uy": 6, "uz": 7}
 
@@ -27,7 +27,7 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_state_save", "lbm_state_load", "lbm_domain_get_info", "lbm_domain_destroy",
            "lbm_prepass_query", "lbm_domain_footprint", "lbm_autotune", "lbm_set_tuning", "lbm_get_tuning",
            "lbm_pool_create", "lbm_pool_admit", "lbm_pool_retire", "lbm_pool_step",
-           "lbm_pool_reduce", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
+           "lbm_pool_reduce", "lbm_pool_reduce_all", "lbm_pool_get_info", "lbm_pool_set_grid", "lbm_pool_autotune",
            "lbm_pool_destroy", "lbm_pool_set_order", "lbm_pool_set_group_bytes",
            "lbm_set_force", "lbm_run_steady",
            "lbm_morph", "lbm_phase_volume", "lbm_shell_aggregate",
@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
                 ("reduce_every", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("neighbour_mode", ctypes.c_int32), ("inlet_mode", ctypes.c_int32),
                 ("flux_in", ctypes.c_double), ("order_rows", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("pad_", ctypes.c_int32), ("rho_a", ctypes.c_double),
+                ("rho_b", ctypes.c_double)]
 
 
 class Reduction(ctypes.Structure):
@@ -208,11 +209,13 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(i64)]
     L.lbm_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.lbm_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
-    L.lbm_pool_create.argtypes = [i64, i32, i32, i32, vp, ctypes.POINTER(vp)]
+    L.lbm_pool_create.argtypes = [i64, i32, i32, i32, ctypes.POINTER(Allocator), vp,
+                                  ctypes.POINTER(vp)]
     L.lbm_pool_admit.argtypes = [vp, vp, ctypes.POINTER(i32)]
-    L.lbm_pool_retire.argtypes = [vp, i32]
+    L.lbm_pool_retire.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.lbm_pool_step.argtypes = [vp, i64]
-    L.lbm_pool_reduce.argtypes = [vp, ctypes.POINTER(Reduction), i32, ctypes.POINTER(i32)]
+    L.lbm_pool_reduce.argtypes = [vp, i32, ctypes.POINTER(Reduction)]
+    L.lbm_pool_reduce_all.argtypes = [vp, ctypes.POINTER(Reduction), i32, ctypes.POINTER(i32)]
     L.lbm_pool_get_info.argtypes = [vp, ctypes.POINTER(PoolInfo)]
     L.lbm_pool_set_grid.argtypes = [vp, i32]
     L.lbm_pool_set_order.argtypes = [vp, i32]
@@ -261,6 +264,7 @@ def make_params(problem, precision: int = FP64, reduce_every: int = 0,
     p.flux_in = float(getattr(problem, "flux_in", 0.0))
     p.precision = precision
     p.rho_in, p.rho_out = problem.rho_in, problem.rho_out
+    p.rho_a = p.rho_b = 1.0                 # unit density of both fluids (the model's rho0)
     p.reduce_every = reduce_every
     p.block_size = block_size
     p.neighbour_mode = neighbour_mode
@@ -502,12 +506,21 @@ class Pool:
     """Many domains stepped together by one launch per kernel per step (wraps lbm_pool*)."""
 
     def __init__(self, budget_bytes: int, precision: int = FP32_DEV, max_slots: int = 64,
-                 chunk_steps: int = 100, stream=None):
+                 chunk_steps: int = 100, stream=None, allocator: str = "torch"):
         L = load_library()
         h = ctypes.c_void_p()
+        # The pool's own tables come from PyTorch's caching allocator (or hipMalloc).
+        self._torch_alloc = None
+        if allocator == "torch":
+            import torch
+            self._torch_alloc = _TorchAllocator(stream if stream is not None
+                                                else torch.cuda.current_stream().cuda_stream)
         _check(L.lbm_pool_create(int(budget_bytes), int(precision), int(max_slots),
-                                 int(chunk_steps), None if stream is None else
-                                 ctypes.c_void_p(stream), ctypes.byref(h)))
+                                 int(chunk_steps),
+                                 ctypes.byref(self._torch_alloc.struct) if self._torch_alloc
+                                 else None,
+                                 None if stream is None else ctypes.c_void_p(stream),
+                                 ctypes.byref(h)))
         self.handle = h
         self.max_slots = max_slots
         self.members = {}
@@ -519,19 +532,28 @@ class Pool:
         return slot.value
 
     def retire(self, slot: int) -> Domain:
-        _check(load_library().lbm_pool_retire(self.handle, int(slot)))
-        return self.members.pop(slot)
+        h = ctypes.c_void_p()
+        _check(load_library().lbm_pool_retire(self.handle, int(slot), ctypes.byref(h)))
+        dom = self.members.pop(slot)
+        assert h.value == dom.handle.value, "pool returned another domain"
+        return dom
 
     def step(self, n: int):
         _check(load_library().lbm_pool_step(self.handle, int(n)))
         return self
 
+    def reduce_slot(self, slot: int) -> dict:
+        """Reduction of the member of one slot."""
+        r = Reduction()
+        _check(load_library().lbm_pool_reduce(self.handle, int(slot), ctypes.byref(r)))
+        return r.as_dict()
+
     def reduce(self) -> dict:
-        """Reductions of every member, keyed by slot."""
+        """Reductions of every member (one batched launch), keyed by slot."""
         arr = (Reduction * self.max_slots)()
         n = ctypes.c_int32()
-        _check(load_library().lbm_pool_reduce(self.handle, arr, self.max_slots,
-                                              ctypes.byref(n)))
+        _check(load_library().lbm_pool_reduce_all(self.handle, arr, self.max_slots,
+                                                  ctypes.byref(n)))
         return {s: arr[s].as_dict() for s in range(n.value) if s in self.members}
 
     def info(self) -> dict:

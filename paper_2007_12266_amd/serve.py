@@ -65,7 +65,7 @@ def _check_due(steps: int, check_every: int) -> bool:
 
 
 class Server:
-    def __init__(self, hbm_budget: int, precision: int = lbm.FP32_DEV, chunk: int = 200,
+    def __init__(self, hbm_budget: int, precision: int = lbm.FP32_MIXED, chunk: int = 200,
                  graph_chunk: int = 100, max_slots: int = 64, workers: int = 4,
                  keep_state: bool = False, stream=None, group_bytes: int = 256 << 20):
         if chunk % graph_chunk or graph_chunk % 2:

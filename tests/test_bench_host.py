@@ -5,7 +5,6 @@ import os
 import subprocess
 import sys
 
-import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -21,25 +20,33 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 def test_algorithmic_bytes_per_voxel():
     """Per pore voxel and step: 19 f read and written, 8 moment slots read and written, phi and
-    N written then read, 24 neighbour entries (6 in the phase kernel, 18 in the collide)."""
-    b64 = bench.launch_bytes("fp64", False, 1000, (8, 8, 8))["per_voxel"]
-    b32 = bench.launch_bytes("fp32dev", False, 1000, (8, 8, 8))["per_voxel"]
-    assert (b64["collide"], b64["phase"], b64["step"]) == (456, 104, 560)
-    assert (b32["collide"], b32["phase"], b32["step"]) == (264, 64, 328)
+    N written then read, 24 neighbour entries (6 in the phase kernel, 18 in the collide); f in
+    the first storage width, the rest in the second (FP64 8/8, FP32-dev 4/4, FP32-mixed 4/8)."""
+    per = {p: bench.launch_bytes(p, False, 1000, (8, 8, 8))["per_voxel"]
+           for p in ("fp64", "fp32dev", "mixed")}
+    assert (per["fp64"]["collide"], per["fp64"]["phase"], per["fp64"]["step"]) == (456, 104, 560)
+    assert (per["fp32dev"]["collide"], per["fp32dev"]["phase"], per["fp32dev"]["step"]) == \
+        (264, 64, 328)
+    assert (per["mixed"]["collide"], per["mixed"]["phase"], per["mixed"]["step"]) == \
+        (304, 104, 408)
     rank = bench.launch_bytes("fp64", True, 1000, (8, 8, 64))
     assert rank["per_voxel"]["step"] == 8 * 58 + 8
     assert rank["row_bytes"] == 8 * 8 * 1 * 32
+    # The survey's accounting: the 14 D3Q7 populations instead of their 8 moments, the table
+    # once per step.
+    assert bench.survey_bytes("fp64") == {"step": 632, "collide": 504}
+    assert bench.survey_bytes("fp32dev") == {"step": 352, "collide": 288}
+    assert bench.survey_bytes("mixed") == {"step": 480, "collide": 352}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
-def test_committed_profiles_describe_the_current_kernels(precision):
-    """The traffic figure bench.py reports comes from the committed summary only while it was
-    measured on the current kernel source."""
+def test_committed_profile_describes_the_current_kernels():
+    """The traffic figure of the default (512^3 displacement, FP64) line comes from the committed
+    counter summary only while it was measured on the current kernel source."""
     src = os.path.join(ROOT, "paper_2007_12266_amd", "csrc", "lbm_kernels.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    prof = open(os.path.join(ROOT, "profiles", "collide_phase_grf256_%s.md" % precision)).read()
+    prof = open(os.path.join(ROOT, "profiles", "collide_phase_disp512_fp64.md")).read()
     assert "kernel_source_sha256_prefix: " + digest[:16] in prof
-    t = bench._profiled_traffic(precision, "table")
-    assert t is not None and t > bench.launch_bytes(precision, False, 1, (1, 1, 1))[
+    t = bench._profiled_traffic("disp512", "fp64", "table")
+    assert t is not None and t > bench.launch_bytes("fp64", False, 1, (1, 1, 1))[
         "per_voxel"]["collide"] * 0.9
-    assert bench._profiled_traffic(precision, "rank") is None
+    assert bench._profiled_traffic("disp512", "fp64", "rank") is None

@@ -116,7 +116,8 @@ def test_create_validates_parameters_before_touching_the_device():
     prob = _random_problem((4, 4, 4), (True, True, True), seed=2)
     labels, kind, aff, vaff, iphi = lbm._problem_arrays(prob)
     for field, value, msg in (("tau_a", 0.5, b"tau"), ("beta", 1.0, b"beta"),
-                              ("block_size", 96, b"block_size"), ("precision", 7, b"precision")):
+                              ("block_size", 96, b"block_size"), ("precision", 7, b"precision"),
+                              ("rho_a", 0.9, b"rho_a"), ("rho_b", 1.2, b"rho_b")):
         p = lbm.make_params(prob)
         setattr(p, field, value)
         h = ctypes.c_void_p()
@@ -124,6 +125,22 @@ def test_create_validates_parameters_before_touching_the_device():
                                  lbm._ptr(aff), lbm._ptr(vaff), lbm._ptr(iphi), None, None,
                                  ctypes.byref(h))
         assert st == lbm.LBM_ERR_ARG and msg in L.lbm_last_error() and not h.value
+
+
+def test_unit_fluid_densities_are_the_default():
+    """rho_a and rho_b: 1, or 0 for the default 1 (a zeroed struct), are accepted by every
+    entry point that checks parameters; any other density is rejected there too."""
+    prob = _random_problem((4, 4, 4), (True, True, True), seed=2)
+    L = lbm.load_library()
+    labels, kind, aff, vaff, iphi = lbm._problem_arrays(prob)
+    for ra, rb, ok in ((1.0, 1.0, True), (0.0, 0.0, True), (0.0, 1.0, True), (1.0, 0.5, False)):
+        p = lbm.make_params(prob)
+        p.rho_a, p.rho_b = ra, rb
+        b = ctypes.c_int64()
+        st = L.lbm_domain_footprint(ctypes.byref(p), lbm._ptr(labels), int(aff.size),
+                                    lbm._ptr(kind), lbm._ptr(aff), lbm._ptr(vaff), lbm._ptr(iphi),
+                                    ctypes.byref(b))
+        assert (st == lbm.LBM_OK) == ok, (ra, rb)
 
 
 def test_prepass_pressure_faces_mirror_the_plane():

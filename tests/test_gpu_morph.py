@@ -24,12 +24,19 @@ def lbm():
     return mod
 
 
+# Velocities here stay below 1e-3, where 1e-12 relative is below the few ulp of rho that two
+# correct FP64 evaluations in different order can agree to (u is a difference of O(rho/18)
+# populations): they are held to 1e-15 absolute (4.5 ulp of rho = 1) where that is looser.
+U_ABS = 1e-15
+
+
 def _compare(gpu, ref, pore, tol=1e-12):
     for k in FIELDS:
         g, r = gpu[k][pore], ref[k][pore]
-        scale = max(np.abs(r).max(), 1e-3 if k[0] == "u" else 0.0)
-        err = np.abs(g - r).max() / scale
-        assert err <= tol, (k, err)
+        d = np.abs(g - r).max()
+        if k[0] == "u" and d <= U_ABS:
+            continue
+        assert d <= tol * np.abs(r).max(), (k, d, np.abs(r).max())
 
 
 def _problem():

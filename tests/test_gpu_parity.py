@@ -27,18 +27,20 @@ def lbm():
     return mod
 
 
-def _compare(gpu: dict, ref: dict, pore, tol=TOL, fields=FIELDS, vel_floor=0.0):
-    """Normwise relative error per field. ``vel_floor`` bounds the velocity scale from below:
-    u is a difference of O(rho/18) populations, so two correct FP64 evaluations in different
-    order differ by ~10 ulp of rho in u; where |u| << 1e-3 that floor, not 1e-12 |u|, is the
-    attainable agreement (two independent CPU implementations show the same)."""
+def _compare(gpu: dict, ref: dict, pore, tol=TOL, fields=FIELDS, u_abs=0.0):
+    """Normwise relative error per field, max |gpu - oracle| / max |oracle| <= tol. A velocity
+    component may instead meet the absolute bound ``u_abs`` when a test states one: u is a
+    difference of O(rho/18) populations, so two correct FP64 evaluations in different order
+    agree in u only to a few ulp of rho (2.2e-16 at rho = 1), whatever the size of u. Tests
+    whose velocities are far below 1e-3 state that bound; the others use none."""
     errs = {}
     for k in fields:
         g, r = gpu[k][pore], ref[k][pore]
         scale = np.abs(r).max()
-        if k in ("ux", "uy", "uz"):
-            scale = max(scale, vel_floor)
-        errs[k] = np.abs(g - r).max() / (scale if scale > 0 else 1.0)
+        d = np.abs(g - r).max()
+        errs[k] = d / (scale if scale > 0 else 1.0)
+        if k in ("ux", "uy", "uz") and d <= u_abs:
+            errs[k] = 0.0
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, (bad, errs)
     return errs
@@ -109,6 +111,60 @@ def test_block_size_and_launch_shape_do_not_change_results(lbm):
         outs.append(dom.save())
         dom.close()
     assert outs[0] == outs[1] == outs[2]
+
+
+@pytest.mark.parametrize("mode", ["rank", "table"])
+def test_results_do_not_depend_on_the_pore_numbering(lbm, spheres32, mode):
+    """The pore numbering (blocks of order_rows rows of y, each block plane by plane; ny rows
+    is the dense z, y, x order) only decides where a voxel's values live in memory: dense
+    fields after 61 steps are bitwise the same for blocks of 8 and 16 rows and for the dense
+    order, on the sphere pack (walls in z) and on a displacement with pressure faces. The
+    reductions sum in pore order, so they agree to rounding: 1e-14 relative, the flux
+    relative to the sum of |u_z| over the box."""
+    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    disp = inputs.displacement_problem(shape=(40, 20, 18), seed_geom=8, porosity_target=0.3)
+    for prob in (spheres32, disp):
+        ny = prob.shape[1]
+        runs = []
+        for rows in (16, 8, ny):
+            dom = lbm.Domain(prob, neighbour_mode=nm, order_rows=rows)
+            dom.step(61)
+            runs.append((dom.fields(), dom.reduce()))
+            dom.close()
+        f0, r0 = runs[0]
+        pore = prob.solid_mask() == 0
+        uz_scale = np.abs(f0["uz"][pore]).sum() / pore.size
+        for f, r in runs[1:]:
+            for k in FIELDS:
+                assert np.array_equal(f[k][pore], f0[k][pore]), (prob.name, k)
+            for k in ("mass_a", "mass_b", "sw", "sw_count", "p_a", "p_b", "ca"):
+                assert abs(r[k] - r0[k]) <= 1e-14 * abs(r0[k]), (prob.name, k, r[k], r0[k])
+            assert abs(r["qz"] - r0["qz"]) <= 1e-14 * uz_scale, (prob.name, r["qz"], r0["qz"])
+
+
+def test_captured_step_chunks_equal_step_by_step_launches(lbm, spheres32):
+    """lbm_step replays a captured chunk of 64 steps wherever one fits (from an even step, no
+    reduction due before its last step); lbm_step_timed launches every step. The two give the
+    same state bitwise and the same reductions, with an odd start, reductions every 100 steps
+    or none, and across a force change (which must reach the captured launches)."""
+    for every in (100, 0):
+        a = lbm.Domain(spheres32, reduce_every=every)
+        b = lbm.Domain(spheres32, reduce_every=every)
+        a.step(1)
+        b.step_timed(1)
+        a.step(250)
+        b.step_timed(250)
+        assert a.save() == b.save(), every
+        assert a.history() == b.history(), every
+        force = (0.0, 2e-6, 2e-5)
+        a.set_force(force)
+        b.set_force(force)
+        a.step(130)
+        b.step_timed(130)
+        assert a.save() == b.save(), every
+        assert a.history() == b.history(), every
+        a.close()
+        b.close()
 
 
 def test_reductions_match_oracle(lbm):
@@ -256,7 +312,10 @@ def test_degenerate_domains(lbm):
         dom.step(11)
         gpu = dom.fields()
         ref = O.state_for(prob).run(11).fields()
-        _compare(gpu, ref, prob.solid_mask() == 0, vel_floor=1e-3)
+        # |u| stays near F/2 = 5e-5 in these one-voxel and one-row domains, where 1e-12
+        # relative would ask for 5e-17, a quarter of an ulp of rho: the velocities are held to
+        # 1e-15 absolute instead (4.5 ulp of rho = 1).
+        _compare(gpu, ref, prob.solid_mask() == 0, u_abs=1e-15)
         dom.close()
 
 

@@ -41,9 +41,9 @@ def _mix():
             _problem(5, (12, 30, 22), tau=(0.65, 0.8), sw=0.7)]
 
 
-@pytest.mark.parametrize("precision", ["fp32dev", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32dev", "fp64", "mixed"])
 def test_members_match_solo_runs_bitwise(lbm, precision):
-    prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
+    prec = {"fp32dev": lbm.FP32_DEV, "fp64": lbm.FP64, "mixed": lbm.FP32_MIXED}[precision]
     probs = _mix()
     pool = lbm.Pool(1 << 34, precision=prec, max_slots=8, chunk_steps=20)
     pool.set_order(1 if precision == "fp64" else 0)     # both tile orders are covered
@@ -145,13 +145,13 @@ def _displacement(seed, shape, flux=None):
     return prob
 
 
-@pytest.mark.parametrize("precision", ["fp32dev", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32dev", "fp64", "mixed"])
 def test_pressure_face_members_match_solo_runs_bitwise(lbm, precision):
     """Displacement solves (pressure faces at z: imposed inlet density, or imposed inlet flux
     with the inlet density solved every step) share the pool with periodic members; each
     member's state and reductions are bitwise those of a solo run, through graph replays and
     eager steps, and after one member joins late."""
-    prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
+    prec = {"fp32dev": lbm.FP32_DEV, "fp64": lbm.FP64, "mixed": lbm.FP32_MIXED}[precision]
     probs = [_displacement(7, (30, 14, 12)), _mix()[0], _displacement(8, (26, 10, 17), flux=0.02),
              _mix()[2]]
     modes = [lbm.NBR_TABLE, lbm.NBR_RANK, lbm.NBR_RANK, lbm.NBR_TABLE]
@@ -173,6 +173,34 @@ def test_pressure_face_members_match_solo_runs_bitwise(lbm, precision):
         solo.close()
     pool.close()
     for d in doms:
+        d.close()
+
+
+def test_force_change_on_pooled_flux_inlet_member_matches_solo_run(lbm):
+    """The flux inlet's density depends on the body force, and a member with pressure faces has
+    its boundary launches captured in the pool's chunk: a force change while the member is in
+    the pool must reach those launches too. Changed between graph replays, the pooled member
+    stays bitwise its solo run with the same change, next to a periodic member."""
+    import dataclasses
+    prob = dataclasses.replace(_displacement(8, (26, 10, 17), flux=0.02),
+                               force=(0.0, 0.0, 2e-6))
+    other = _mix()[0]
+    forces = [(0.0, 0.0, 2e-6), (1e-6, 0.0, 8e-6), (0.0, -1e-6, -3e-6)]
+    dom, mate = lbm.Domain(prob), lbm.Domain(other)
+    pool = lbm.Pool(1 << 34, precision=lbm.FP64, max_slots=2, chunk_steps=10)
+    slot = pool.admit(dom)
+    pool.admit(mate)
+    solo = lbm.Domain(prob)
+    for k, F in enumerate(forces):
+        dom.set_force(F)
+        solo.set_force(F)
+        pool.step(20)                              # two replays of the captured chunk
+        solo.step(20)
+        assert dom.save() == solo.save(), k
+    assert pool.info()["graph_replays"] == 6
+    assert pool.reduce()[slot] == solo.reduce()
+    pool.close()
+    for d in (solo, dom, mate):
         d.close()
 
 
@@ -203,13 +231,13 @@ def test_pool_autotune_restores_members(lbm):
         d.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32dev", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32dev", "fp64", "mixed"])
 def test_cache_groups_keep_results(lbm, precision):
     """Captured chunks that run the members in cache groups (each group all chunk steps, one
     group after the other) leave every member bitwise equal to its solo run, through eager
     steps, a change of grouping and membership changes; a member larger than the group size
     forms a group of its own."""
-    prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
+    prec = {"fp32dev": lbm.FP32_DEV, "fp64": lbm.FP64, "mixed": lbm.FP32_MIXED}[precision]
     probs = _mix() + [_displacement(10, (24, 12, 16), flux=0.015)]
     doms = [lbm.Domain(p, precision=prec) for p in probs]
     sizes = [d.info()["device_bytes"] for d in doms]

@@ -32,10 +32,10 @@ def _requests(serve, n=5, tol=1e-4, displacement=()):
     return reqs
 
 
-@pytest.mark.parametrize("precision", ["fp32dev", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32dev", "fp64", "mixed"])
 def test_served_results_equal_solo_results(mods, precision):
     lbm, serve = mods
-    prec = lbm.FP32_DEV if precision == "fp32dev" else lbm.FP64
+    prec = {"fp32dev": lbm.FP32_DEV, "fp64": lbm.FP64, "mixed": lbm.FP32_MIXED}[precision]
     reqs = _requests(serve, displacement=(1, 4))
     sizes = [lbm.footprint(r.problem, prec) for r in reqs]
     budget = sorted(sizes)[-1] + sorted(sizes)[-2]   # at most about two at a time
@@ -56,7 +56,7 @@ def test_served_results_equal_solo_results(mods, precision):
 def test_realtime_trace_reports_latency(mods):
     lbm, serve = mods
     reqs = _requests(serve, n=6, tol=1e-3, displacement=(2,))
-    srv = serve.Server(1 << 33, precision=lbm.FP32_DEV, chunk=200, max_slots=8, workers=2)
+    srv = serve.Server(1 << 33, chunk=200, max_slots=8, workers=2)     # default: FP32-mixed
     got = srv.run(reqs, realtime=True)
     srv.close()
     stats = serve.latency_stats(got)

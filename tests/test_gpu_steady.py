@@ -51,11 +51,19 @@ def oracle_steady(prob, ca_target, relax, interval, tol, max_steps, max_factor=2
     return st, t, converged, factor, dcas
 
 
+# Velocities here stay below 1e-3, where 1e-12 relative is below the few ulp of rho that two
+# correct FP64 evaluations in different order can agree to (u is a difference of O(rho/18)
+# populations): they are held to 1e-15 absolute (4.5 ulp of rho = 1) where that is looser.
+U_ABS = 1e-15
+
+
 def _check_fields(gpu, ref, pore, tol=1e-12):
     for k in FIELDS:
         g, r = gpu[k][pore], ref[k][pore]
-        err = np.abs(g - r).max() / max(np.abs(r).max(), 1e-3 if k[0] == "u" else 0.0)
-        assert err <= tol, (k, err)
+        d = np.abs(g - r).max()
+        if k[0] == "u" and d <= U_ABS:
+            continue
+        assert d <= tol * np.abs(r).max(), (k, d, np.abs(r).max())
 
 
 def test_force_adaptation_and_steady_test_match_the_protocol_on_the_oracle(lbm):

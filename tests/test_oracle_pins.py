@@ -285,7 +285,44 @@ def test_laplace_law_cylinders():
     assert dps[0] > dps[1] > dps[2] > 0
 
 
+@pytest.mark.slow
+def test_laplace_law_spherical_drops():
+    """Spherical drops of b in a periodic 40^3 box of a (tau 1, alpha 0.005, beta 0.95, 1500
+    steps): p_in - p_out is linear in 1/R (R^2 > 0.999, R_eff from the drop volume), and the
+    tension sigma(R) = (p_in - p_out) R_eff / 2 of each drop approaches 6 alpha from above with
+    a correction in 1/R^2 (the diffuse interface's finite width): extrapolated to a flat
+    interface it is 6 alpha within 2%, the stated sigma_ab = 6 alpha."""
+    alpha, L = 0.005, 40
+    r_eff, dps = [], []
+    z, y, x = np.mgrid[0:L, 0:L, 0:L] + 0.5
+    d = np.sqrt((x - L / 2) ** 2 + (y - L / 2) ** 2 + (z - L / 2) ** 2)
+    for R in (6, 8, 10):
+        shape = (L, L, L)
+        phi0 = np.where(d < R, -1.0, 1.0)
+        p = O.make_params(shape, (True, True, True), 1.0, 1.0, alpha, 0.95, (0, 0, 0), 0.0)
+        st = O.State(p, np.zeros(shape, np.uint8), np.zeros(shape)).init(phi0).run(1500)
+        fl = st.fields()
+        ph, pr = fl["phi"], fl["p"]
+        dps.append(pr[ph < -0.99].mean() - pr[ph > 0.99].mean())
+        r_eff.append((3 * ((1 - ph) / 2).sum() / (4 * np.pi)) ** (1 / 3))
+        assert st.reduce()["unstable"] == 0
+    r_eff, dps = np.array(r_eff), np.array(dps)
+    assert dps[0] > dps[1] > dps[2] > 0
+    A = np.vstack([1 / r_eff, np.ones(3)]).T
+    c = np.linalg.lstsq(A, dps, rcond=None)[0]
+    r2 = 1 - ((dps - A @ c) ** 2).sum() / ((dps - dps.mean()) ** 2).sum()
+    assert r2 > 0.999, r2
+    sig = dps * r_eff / 2
+    assert sig[0] > sig[1] > sig[2] > 6 * alpha, sig
+    B = np.vstack([np.ones(3), 1 / r_eff ** 2]).T
+    sig_flat = np.linalg.lstsq(B, sig, rcond=None)[0][0]
+    assert abs(sig_flat / (6 * alpha) - 1) < 0.02, (sig, sig_flat)
+
+
 def _contact_angle(phi_s, nx=96, ny=48, steps=10000):
+    """Equilibrium angle of a cap of a on a flat wall of affinity phi_s (solid plane y = 0, wall
+    at the half link y = 1/2), from a circle fitted to the phi = 0 contour above the wall's
+    diffuse layer."""
     shape = (1, ny, nx)
     solid = np.zeros(shape, np.uint8)
     solid[0, 0, :] = 1
@@ -315,15 +352,53 @@ def _contact_angle(phi_s, nx=96, ny=48, steps=10000):
     return np.degrees(np.arccos(np.clip((0.5 - yc) / R, -1, 1)))   # wall at the half link
 
 
-def test_contact_angle_follows_affinity():
-    """A cap of a on a wall with affinity phi_s: cos(theta) = phi_s in the wetting section. The
-    discrete model at beta = 0.95 reproduces it to about 10 degrees, symmetric about 90."""
-    th = {s: _contact_angle(s) for s in (-0.5, 0.0, 0.5)}
+def _meniscus_angle(phi_s, H=32, L=128, steps=20000, alpha=0.005):
+    """Equilibrium angle from the Laplace pressure of the two menisci of a slug of b in a
+    between parallel walls of affinity phi_s (solid rows y = 0 and y = H+1, so the channel width
+    between the half-link walls is H; periodic x): p_b - p_a = sigma / R with R = H / (2 cos
+    theta) in 2-D and sigma = 6 alpha, so cos theta = (p_b - p_a) H / (12 alpha). Independent of
+    any contour fit."""
+    shape = (1, H + 2, L)
+    solid = np.zeros(shape, np.uint8)
+    solid[0, 0, :] = solid[0, H + 1, :] = 1
+    x = np.broadcast_to(np.arange(L), shape)
+    phi0 = np.where((x >= L // 4) & (x < 3 * L // 4), -1.0, 1.0)
+    p = O.make_params(shape, (True, True, True), 0.7, 0.7, alpha, 0.95, (0, 0, 0), 0.0)
+    st = O.State(p, solid, np.full(shape, phi_s)).init(phi0).run(steps)
+    fl = st.fields()
+    ph, pr = fl["phi"][0], fl["p"][0]
+    pore = solid[0] == 0
+    dp = pr[pore & (ph < -0.99)].mean() - pr[pore & (ph > 0.99)].mean()
+    return dp * H / (12 * alpha)
+
+
+@pytest.fixture(scope="module")
+def cap_angles():
+    return {s: _contact_angle(s) for s in (-0.5, 0.0, 0.5)}
+
+
+def test_contact_angle_follows_affinity(cap_angles):
+    """A cap of a on a wall with affinity phi_s: the wetting section states cos(theta) = phi_s.
+    The discrete model keeps the ordering, the symmetry about 90 degrees and 90 degrees at
+    phi_s = 0, and meets the stated relation to within 11 degrees at phi_s = +-0.5: it gives
+    cos(theta) = 1.30 phi_s (130.4 / 50.5 degrees), the same with caps of radius 18, 27 and 36
+    (within 0.5 degree) and from the meniscus pressure below, so the gap is the wetting rule
+    on the lattice (phi_s entering the colour gradient), not resolution or the fit."""
+    th = cap_angles
     assert abs(th[0.0] - 90) < 3
     assert th[-0.5] > th[0.0] > th[0.5]
     assert abs((th[-0.5] - 90) - (90 - th[0.5])) < 1.5
     for s, v in th.items():
-        assert abs(v - np.degrees(np.arccos(s))) < 12, th
+        assert abs(v - np.degrees(np.arccos(s))) < 11, th
+
+
+def test_meniscus_pressure_gives_the_cap_angle(cap_angles):
+    """A second measurement of the same angle that fits no contour: the Laplace pressure of a
+    meniscus between two walls. It agrees with the cap to 1.5 degrees, and a neutral wall
+    (phi_s = 0) gives a flat meniscus, no pressure jump at all (90 degrees exactly)."""
+    cos_t = _meniscus_angle(0.5)
+    assert abs(np.degrees(np.arccos(cos_t)) - cap_angles[0.5]) < 1.5, (cos_t, cap_angles)
+    assert abs(_meniscus_angle(0.0, steps=4000)) < 1e-9
 
 
 def _small_problem(seed=0, n=(10, 9, 8), periodic=(True, False, True)):
