@@ -36,11 +36,12 @@
  *
  * Pins (tests, independent of these formulas) cover the moment basis, isotropy, fixed points,
  * conservation, the colour perturbation, recolouring, Poiseuille flow, the flat-interface
- * tension and profile, the Laplace law, contact angles, symmetries, pressure-driven slit flow and
- * an independent brute-force implementation; the unlisted equilibria are pinned to the published
- * D3Q19 equilibria of d'Humieres et al. (2002). One reading has no value to pin it: the
- * composition imposed at the pressure faces beyond fluid a entering and fluid b leaving -- parity
- * unpinned there.
+ * tension and profile, the Laplace law (cylinders and spheres), contact angles (cap fit and
+ * meniscus pressure), symmetries, the gradient threshold, pressure-driven slit flow, the
+ * pressure faces' composition, inflow and species balance, the gradient mirror across a face,
+ * and an independent brute-force implementation; the unlisted equilibria are pinned to the
+ * published D3Q19 equilibria of d'Humieres et al. (2002). That the inlet takes pure a at N = 1
+ * is a reading (the paper says only that fluid a is injected); its consequences are pinned.
  *
  * State layout: f[q * nvox + v], A[q * nvox + v], B[q * nvox + v], v = x + nx*(y + ny*z).
  * Entries of solid voxels are never read and are left as they are.
