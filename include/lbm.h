@@ -466,6 +466,21 @@ lbm_status lbm_prep_distance(int32_t nx, int32_t ny, int32_t nz, const int32_t p
                              int32_t wall_axes, const uint8_t* feature, int32_t* dist_sq,
                              void* hip_stream);
 
+/* Allocation-free form of lbm_prep_distance, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * transform of the same arguments, but feature_dev[nx*ny*nz] and dist_sq_dev[nx*ny*nz] are
+ * DEVICE pointers owned by the caller (dist_sq_dev 4-byte aligned), the call is asynchronous on
+ * hip_stream (nullable: the null stream) and it allocates nothing: its work buffers live in a
+ * fixed 16 MiB device array of the library, one per GPU, held until the process ends. The image
+ * must fit that array: 8 bytes per 64-voxel row word (ny*nz*ceil(nx/64) words) plus 4 bytes per
+ * voxel, e.g. up to about 3.9M voxels (a 157^3 image); LBM_ERR_ARG otherwise, before anything is
+ * launched. Every call on one GPU uses the same array, so calls on that GPU must not overlap
+ * (use one stream, or synchronise between calls). Errors as lbm_prep_distance, and
+ * LBM_ERR_DEVICE if a launch fails. */
+lbm_status lbm_prep_distance_noalloc(int32_t nx, int32_t ny, int32_t nz, const int32_t periodic[3],
+                                     int32_t wall_axes, const uint8_t* feature_dev,
+                                     int32_t* dist_sq_dev, void* hip_stream);
+
 typedef struct {
     double target_sw;   /* water (wetting-fluid) saturation to reach, in [0, 1)              */
     int32_t inlet;      /* 1: only sphere centres connected through face-adjacent centres to */

@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -843,6 +844,42 @@ lbm_status drain_eval(const Box& b, const DrainBuffers& db, int32_t k, bool inle
     return LBM_OK;
 }
 
+// ---- Scratch of the allocation-free distance transform -------------------------------------
+// lbm_prep_distance_noalloc keeps its work buffers (row words, one int32 transform pass) in this
+// file-scope device array: one copy per GPU, held until the process ends, shared by every call on
+// that GPU. Host code never passes the array's name to a kernel: its device address is taken once
+// per device with hipGetSymbolAddress, with that device current.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+lbm_status noalloc_scratch_of_current_device(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBM_ERR_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return LBM_OK;
+}
+
+// No feature within reach: kInf -> -1, as the host side of lbm_prep_distance does.
+__global__ void __launch_bounds__(256) none_to_minus_one_kernel(int32_t* __restrict__ d,
+                                                                int64_t n) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && d[v] >= kInf) d[v] = -1;
+}
+
 }  // namespace
 
 namespace lbm {
@@ -884,6 +921,43 @@ lbm_status lbm_prep_distance(int32_t nx, int32_t ny, int32_t nz, const int32_t p
     HIP_TRY(copy_to_host(dist_sq, out, sizeof(int32_t) * (size_t)b.nvox, s));
     for (int64_t v = 0; v < b.nvox; ++v)
         if (dist_sq[v] >= kInf) dist_sq[v] = -1;
+    return LBM_OK;
+}
+
+lbm_status lbm_prep_distance_noalloc(int32_t nx, int32_t ny, int32_t nz, const int32_t periodic[3],
+                                     int32_t wall_axes, const uint8_t* feature_dev,
+                                     int32_t* dist_sq_dev, void* hip_stream) {
+    clear_error();
+    Box b{};
+    if (lbm_status st = check_box(nx, ny, nz, periodic, &b)) return st;
+    if (!feature_dev || !dist_sq_dev) return fail(LBM_ERR_ARG, "null argument");
+    if (wall_axes < 0 || wall_axes > 7) return fail(LBM_ERR_ARG, "wall_axes must lie in [0, 7]");
+    if (((uintptr_t)dist_sq_dev & 3) != 0)
+        return fail(LBM_ERR_ARG, "dist_sq_dev must be 4-byte aligned");
+    const size_t words_bytes = ((size_t)8 * (size_t)b.nwords + 255) / 256 * 256;
+    const size_t need = words_bytes + sizeof(int32_t) * (size_t)b.nvox;
+    if (need > kNoAllocScratchBytes)
+        return fail(LBM_ERR_ARG, "image too large for the allocation-free transform: it needs " +
+                                     std::to_string(need) + " bytes of scratch (8 per 64-voxel "
+                                     "row word + 4 per voxel), the limit is " +
+                                     std::to_string(kNoAllocScratchBytes));
+    void* base = nullptr;
+    if (lbm_status st = noalloc_scratch_of_current_device(&base)) return st;
+    uint64_t* bits = (uint64_t*)base;
+    int32_t* tmp = (int32_t*)((char*)base + words_bytes);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // Wide packing reads 8 voxels per 8-byte load: rows of whole bytes and an aligned image.
+    if ((b.nx & 7) == 0 && ((uintptr_t)feature_dev & 7) == 0)
+        hipLaunchKernelGGL(pack8_kernel<Wide8Nonzero>, pack8_grid(b), dim3(256), 0, s, b,
+                           Wide8Nonzero{feature_dev}, bits);
+    else
+        hipLaunchKernelGGL(pack_kernel<FeatureNonzero>, pack_grid(b), dim3(256), 0, s, b,
+                           FeatureNonzero{feature_dev}, bits);
+    HIP_TRY(hipGetLastError());
+    if (lbm_status st = edt(b, bits, kInf, wall_axes, tmp, dist_sq_dev, s)) return st;
+    hipLaunchKernelGGL(none_to_minus_one_kernel, dim3((unsigned)((b.nvox + 255) / 256)),
+                       dim3(256), 0, s, dist_sq_dev, b.nvox);
+    HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTS = ("lbm_domain_create", "lbm_step", "lbm_step_timed", "lbm_read_field",
            "lbm_pool_destroy", "lbm_pool_set_order", "lbm_pool_set_group_bytes",
            "lbm_set_force", "lbm_run_steady",
            "lbm_morph", "lbm_phase_volume", "lbm_shell_aggregate",
-           "lbm_prep_distance", "lbm_prep_drain", "lbm_prep_relabel", "lbm_prep_mixing_layer",
+           "lbm_prep_distance", "lbm_prep_distance_noalloc", "lbm_prep_drain", "lbm_prep_relabel", "lbm_prep_mixing_layer",
            "lbm_last_error", "lbm_version")
 
 
@@ -224,6 +224,7 @@ def load_library(path: str = LIB_PATH):
     L.lbm_pool_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
     i32p = ctypes.POINTER(i32)
     L.lbm_prep_distance.argtypes = [i32, i32, i32, i32p, i32, vp, vp, vp]
+    L.lbm_prep_distance_noalloc.argtypes = [i32, i32, i32, i32p, i32, vp, vp, vp]
     L.lbm_prep_drain.argtypes = [i32, i32, i32, i32p, vp, ctypes.POINTER(DrainParams), vp,
                                  ctypes.POINTER(DrainResult), vp]
     L.lbm_prep_relabel.argtypes = [i32, i32, i32, i32p, vp, i32, vp, vp, ctypes.c_double, i32,
@@ -613,6 +614,19 @@ def prep_distance(feature: np.ndarray, periodic=(False, False, False), wall_axes
     out = np.empty(f.shape, dtype=np.int32)
     _check(load_library().lbm_prep_distance(nx, ny, nz, _periodic3(periodic), int(wall_axes),
                                             _ptr(f), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def prep_distance_noalloc(feature, out, periodic=(False, False, False), wall_axes: int = 0,
+                          stream=None):
+    """The allocation-free transform on device tensors: feature (uint8, [nz, ny, nx], on the
+    GPU) in, out (int32, same shape, on the GPU) written asynchronously on `stream` (a
+    hipStream_t handle; None: the null stream)."""
+    nz, ny, nx = feature.shape
+    assert tuple(out.shape) == (nz, ny, nx) and feature.is_contiguous() and out.is_contiguous()
+    _check(load_library().lbm_prep_distance_noalloc(
+        nx, ny, nz, _periodic3(periodic), int(wall_axes), ctypes.c_void_p(feature.data_ptr()),
+        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 
