@@ -763,6 +763,12 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     d->drop_step_graph();
     d->tune = best;
     if (out) *out = best;
+    // Record the step chunk for the chosen launch shapes now (recording runs nothing), so its
+    // one-time capture cost is not paid by the first lbm_step that replays it.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(d->stream, &cap));
+    if (cap == hipStreamCaptureStatusNone)
+        if (lbm_status s = capture_step_chunk(d)) return s;
     return LBM_OK;
 }
 
