@@ -41,22 +41,49 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 # indices, and writes phi and N. The indices cost 4*18 (collide) and 4*6 (phase) bytes per voxel
 # with the int32 table; with the rank lookup, 4 bytes of packed coordinates per voxel plus one
 # pass over the 32-byte row segments (nz*ny*ceil(nx/64) of them, counted per launch, about
-# 0.5/porosity bytes per pore voxel).
+# 0.5/porosity bytes per pore voxel); with the compact lookup, the 16-byte axis record (phase) or
+# all 40 bytes of records (collide) per voxel, plus the wave bases each kernel reads (13 or 37
+# ints per 64 voxels), the voxels of exception waves reading int32 entries (24 or 72 bytes)
+# instead of records.
 # FP64 (F = S = 8): 456 / 104 / 560 B per voxel with the table, 388 / 84 / 472 with the rank
-# lookup; FP32-dev (4, 4): 264 / 64 / 328 and 196 / 44 / 240; FP32-mixed (4, 8): 304 / 104 / 408
-# and 236 / 84 / 320.
+# lookup, 426.3 / 96.8 / 523.1 with the compact one (no exception waves); FP32-dev (4, 4):
+# 264 / 64 / 328, 196 / 44 / 240 and 234.3 / 56.8 / 291.1; FP32-mixed (4, 8): 304 / 104 / 408,
+# 236 / 84 / 320 and 274.3 / 96.8 / 371.1.
 # The survey's accounting streams the 14 D3Q7 populations instead of their 8 moments and counts
 # the 72-byte table once per step: 632 B per step and 504 B for the collide kernel in FP64
 # (FP32-dev 352 / 288, FP32-mixed 480 / 352).
 STORE = {"fp64": (8, 8), "fp32dev": (4, 4), "mixed": (4, 8)}
 
 
-def _bytes(F, S, rank):
-    if rank:
-        return {"collide": F * 38 + S * (8 + 2) + 4, "phase": S * (8 + 2) + 4,
-                "step": F * 38 + S * (16 + 4) + 8}
-    return {"collide": F * 38 + S * (8 + 2) + 4 * 18, "phase": S * (8 + 2) + 4 * 6,
-            "step": F * 38 + S * (16 + 4) + 4 * 24}
+def _index_bytes(neighbours, n_pore, ex_waves):
+    """Neighbour-lookup bytes per pore voxel read by one collide and one phase launch (the rank
+    lookup's row segments are counted per launch by launch_bytes)."""
+    if neighbours == "rank":
+        return 4.0, 4.0
+    if neighbours == "table":
+        return 72.0, 24.0
+    waves = -(-n_pore // 64)
+    ex = min(ex_waves * 64, n_pore)
+    reg = n_pore - ex
+    coll = (reg * 40 + ex * 72 + waves * 37 * 4) / n_pore
+    phase = (reg * 16 + ex * 24 + waves * 13 * 4) / n_pore
+    return coll, phase
+
+
+def launch_bytes(precision, neighbours, n_pore, shape, ex_waves=0):
+    """Algorithmic bytes of one collide launch, one phase launch and one whole step."""
+    F, S = STORE[precision]
+    ic, ip = _index_bytes(neighbours, n_pore, ex_waves)
+    per = {"collide": F * 38 + S * (8 + 2) + ic, "phase": S * (8 + 2) + ip}
+    per["step"] = per["collide"] + per["phase"]
+    nz, ny, nx = shape
+    rows = nz * ny * ((nx + 63) // 64) * 32 if neighbours == "rank" else 0
+    out = {"collide": round(per["collide"] * n_pore) + rows,
+           "phase": round(per["phase"] * n_pore) + rows,
+           "step": round(per["step"] * n_pore) + 2 * rows, "row_bytes": rows}
+    out["per_voxel"] = {k: (int(v) if float(v).is_integer() else round(v, 2))
+                        for k, v in per.items()}
+    return out
 
 
 def survey_bytes(precision):
@@ -64,15 +91,6 @@ def survey_bytes(precision):
     accounting (the 14 D3Q7 populations streamed, the neighbour table read once per step)."""
     F, S = STORE[precision]
     return {"step": F * 38 + S * (28 + 4) + 72, "collide": F * 38 + S * (14 + 2) + 72}
-
-
-def launch_bytes(precision, rank, n_pore, shape):
-    """Algorithmic bytes of one collide launch, one phase launch and one whole step."""
-    per = _bytes(*STORE[precision], rank)
-    nz, ny, nx = shape
-    rows = nz * ny * ((nx + 63) // 64) * 32 if rank else 0
-    return {"collide": per["collide"] * n_pore + rows, "phase": per["phase"] * n_pore + rows,
-            "step": per["step"] * n_pore + 2 * rows, "per_voxel": per, "row_bytes": rows}
 
 
 WORKLOADS = {
@@ -553,8 +571,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=PRECISIONS)
-    ap.add_argument("--neighbours", default="auto", choices=["auto", "table", "rank"],
-                    help="neighbour lookup: int32 table or rank of row-segment bit masks")
+    ap.add_argument("--order-rows", type=int, default=0,
+                    help="rows of y per block of the pore numbering (0: the library's 16)")
+    ap.add_argument("--neighbours", default="auto", choices=["auto", "table", "rank", "compact"],
+                    help="neighbour lookup: int32 table, rank of row-segment bit masks or "
+                         "16-bit codes above per-wave bases")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch shape PHASE_BLOCK,PHASE_SCHEDULE,COLLIDE_BLOCK,"
+                         "COLLIDE_SCHEDULE instead of the autotuner (profiled runs)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of autotuning them")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -616,12 +640,23 @@ def main():
         dom = lbm.Domain(prob, reduce_every=wl["reduce_every"], block_size=args.block,
                          stream=stream.cuda_stream, precision=prec_of(lbm, args.precision),
                          neighbour_mode={"auto": lbm.NBR_AUTO, "table": lbm.NBR_TABLE,
-                                         "rank": lbm.NBR_RANK}[args.neighbours])
+                                         "rank": lbm.NBR_RANK,
+                                         "compact": lbm.NBR_COMPACT}[args.neighbours],
+                         order_rows=args.order_rows)
     n_pore = dom.n_pore
-    log("domain: N=%d, device bytes %.2f GB" % (n_pore, dom.info()["device_bytes"] / 1e9))
+    log("domain: N=%d, device bytes %.2f GB, compact exception waves %d"
+        % (n_pore, dom.info()["device_bytes"] / 1e9, dom.info()["compact_ex_waves"]))
 
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        pb, ps, cb, cs = (int(v) for v in args.tuning.split(","))
+        dom.set_tuning(phase_block=pb, phase_schedule=ps, collide_block=cb, collide_schedule=cs)
+        tuning = {"phase_block": pb, "phase_schedule": ps, "collide_block": cb,
+                  "collide_schedule": cs, "fixed": True}
+        log("tuning: %s" % tuning)
+        # Capture the step graph outside the timed window, as the autotuner does.
+        dom.step(64)
+    elif not args.no_autotune:
         tuning = dom.autotune(10)
         log("autotune: %s" % tuning)
     dom.step(args.warmup)
@@ -657,11 +692,14 @@ def main():
     ksteps = min(max(args.steps, 2), 200)
     timing = dom.step_timed(ksteps)
     coll_s = timing["collide_ms"] / 1e3
-    rank = dom.info()["neighbour_mode"] == lbm.NBR_RANK
-    nbytes = launch_bytes(args.precision, rank, n_pore, prob.shape)
+    dinfo = dom.info()
+    nb_name = {lbm.NBR_TABLE: "table", lbm.NBR_RANK: "rank",
+               lbm.NBR_COMPACT: "compact"}[dinfo["neighbour_mode"]]
+    nbytes = launch_bytes(args.precision, nb_name, n_pore, prob.shape,
+                          dinfo["compact_ex_waves"])
     sbytes = survey_bytes(args.precision)
     achieved = nbytes["collide"] / coll_s / 1e9
-    tb = _profiled_traffic(args.workload, args.precision, "rank" if rank else "table")
+    tb = _profiled_traffic(args.workload, args.precision, nb_name)
     traffic = None if tb is None else round(tb * n_pore / coll_s / 1e9, 1)
     step_gbs = nbytes["step"] / (ms_per_step / 1e3) / 1e9
 
@@ -681,7 +719,8 @@ def main():
         round(ms_per_step, 5), dtype,
         {"workload": wl["desc"], "grid": list(prob.shape), "n_pore": n_pore,
          "porosity": round(n_pore / float(np.prod(prob.shape)), 5),
-         "precision": args.precision, "reduce_every": every, "block": block, "tuning": tuning},
+         "precision": args.precision, "reduce_every": every, "block": block, "tuning": tuning,
+         "order_rows": args.order_rows or 16},
         roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                   "traffic": traffic,
@@ -694,7 +733,8 @@ def main():
                   "frac_survey_bytes": round(sbytes["collide"] * n_pore / coll_s / 1e9
                                              / HBM_PEAK_GBS, 4),
                   "row_bytes_per_launch": nbytes["row_bytes"],
-                  "neighbours": "rank" if rank else "table",
+                  "neighbours": nb_name,
+                  "compact_ex_waves": dinfo["compact_ex_waves"],
                   "kernel_ms": round(timing["collide_ms"], 5)},
         step_hbm={"bytes_per_voxel": nbytes["per_voxel"]["step"],
                   "achieved_gbs": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),

@@ -61,9 +61,16 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_DEV = 1, LBM_FP32_MIXED = 2 } lbm_precisio
  * packed coordinate and a per-64-voxel record of the image (pore and solid bitmasks with running
  * indices: about 0.5 byte per image voxel, read through the caches), 4 bytes per voxel and step
  * and 68 bytes less device memory per pore voxel, but slower on MI355X (the lookup adds a
- * dependent load to every gather); needs nx <= 1024 and ny, nz <= 2048. AUTO takes TABLE.
+ * dependent load to every gather); needs nx <= 1024 and ny, nz <= 2048. COMPACT: the table's
+ * entries as 16-bit codes above per-wave bases (64 consecutive pore voxels share a base per
+ * direction) with an 18-bit solid mask: 40 bytes per voxel plus 160 bytes per 64 voxels, the
+ * few waves whose targets spread beyond 16 bits keeping int32 entries: about 37 bytes per
+ * voxel and step less to read than TABLE, and the fastest of the three on MI355X. AUTO takes
+ * COMPACT.
  * Results are bitwise identical. */
-typedef enum { LBM_NBR_AUTO = 0, LBM_NBR_TABLE = 1, LBM_NBR_RANK = 2 } lbm_neighbour_mode;
+typedef enum {
+    LBM_NBR_AUTO = 0, LBM_NBR_TABLE = 1, LBM_NBR_RANK = 2, LBM_NBR_COMPACT = 3
+} lbm_neighbour_mode;
 
 /* Label kinds (section "Initial conditions and wetting maps": every voxel carries an integer
  * label naming its material). */
@@ -155,7 +162,9 @@ typedef struct {
 /* Launch configuration of the two step kernels. block: threads per workgroup (64, 128 or 256);
  * schedule: 1 = workgroups take consecutive tiles of the pore list in launch order, 2 = XCD-aware
  * order: each of the 8 XCDs takes runs of 16 consecutive tiles, the runs interleaved, so that
- * neighbouring tiles share an L2. Results do not depend on the configuration (bitwise). */
+ * neighbouring tiles share an L2; 3 = the XCD-aware order run from the end of the pore list, so
+ * that a kernel following one in forward order starts where that one ended (on lines that may
+ * still be cached). Results do not depend on the configuration (bitwise). */
 typedef struct {
     int32_t phase_block, phase_schedule;
     int32_t collide_block, collide_schedule;
@@ -170,8 +179,8 @@ typedef struct {
     int64_t step;             /* completed steps                                             */
     int32_t precision;        /* lbm_precision                                               */
     int32_t block_size;       /* threads per workgroup in use                                */
-    int32_t neighbour_mode;   /* LBM_NBR_TABLE or LBM_NBR_RANK                               */
-    int32_t pad_;
+    int32_t neighbour_mode;   /* LBM_NBR_TABLE, LBM_NBR_RANK or LBM_NBR_COMPACT              */
+    int32_t compact_ex_waves; /* COMPACT: waves of 64 voxels kept as int32 entries; else 0    */
 } lbm_domain_info;
 
 /* Create a domain from a labelled image (sections "Initial conditions and wetting maps" and

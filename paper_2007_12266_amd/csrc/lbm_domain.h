@@ -59,6 +59,13 @@ struct lbm_domain {
     uint32_t* coord = nullptr;     // [ld] packed coordinates (rank mode)
     lbm::RowWord* words = nullptr; // row segments (rank mode)
     bool rank = false;
+    // Compact lookup (compact mode; layout in lbm_prepass.h)
+    uint4* cax = nullptr;
+    uint4* cdg4 = nullptr;
+    uint2* cdg2 = nullptr;
+    int32_t* cwave = nullptr;
+    int32_t* cex = nullptr;
+    bool compact = false;
     double* red_partials = nullptr;
     double* red_out = nullptr;
     double* hist = nullptr;
@@ -117,9 +124,15 @@ struct lbm_domain {
         a.alpha = p.alpha;
         a.beta = p.beta;
         for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
-        a.xcd_remap = sched == 2 ? 1 : 0;
+        a.xcd_remap = sched >= 2 ? 1 : 0;
+        a.reverse = sched == 3 ? 1 : 0;
         a.coord = rank ? coord : nullptr;
         a.words = rank ? words : nullptr;
+        a.cax = compact ? cax : nullptr;
+        a.cdg4 = compact ? cdg4 : nullptr;
+        a.cdg2 = compact ? cdg2 : nullptr;
+        a.cwave = compact ? cwave : nullptr;
+        a.cex = compact ? cex : nullptr;
         a.nx = p.nx;
         a.ny = p.ny;
         a.nz = p.nz;

@@ -39,10 +39,17 @@ struct StepArgs {
     double alpha, beta;
     double F[3];
     int32_t xcd_remap;  // 1: XCD-aware order (runs of consecutive tiles per XCD)
+    int32_t reverse;    // 1: the tile order runs from the end of the pore list
     int32_t prec;       // lbm_precision
     // Rank lookup of neighbours (used instead of nbr when words != null):
     const uint32_t* coord;   // [ld] packed (x, y, z) of each pore voxel
     const RowWord* words;    // [nz][ny][W] 64-voxel row segments
+    // Compact lookup (used instead of nbr when cax != null; layout in lbm_prepass.h):
+    const uint4* cax;        // [ld] mask and codes of q = 1..6
+    const uint4* cdg4;       // [ld] codes of q = 7..14
+    const uint2* cdg2;       // [ld] codes of q = 15..18
+    const int32_t* cwave;    // [ld / 64][kCompactWaveInts] bases and exception row
+    const int32_t* cex;      // [exception waves][18][64] int32 targets
     int32_t nx, ny, nz, W;
     int32_t periodic;        // bit a set: axis a is periodic
     int32_t bc_z;            // 1: z neighbours beyond the faces mirror the plane

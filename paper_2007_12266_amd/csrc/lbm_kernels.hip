@@ -108,8 +108,12 @@ __device__ __forceinline__ int xcd_run_tile(int b) {
     return ((j / kXcdRun) * 8 + x) * kXcdRun + (j % kXcdRun);
 }
 
+// Tile of this workgroup. With `reverse` the order runs from the end of the (padded) grid, so a
+// kernel launched after one in forward order starts on the tiles the other finished last, whose
+// lines may still be in the caches; on a padded grid the tiles beyond the pore list still exit.
 __device__ __forceinline__ int logical_block(const StepArgs& a) {
-    return a.xcd_remap ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
+    const int t = a.xcd_remap ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
+    return a.reverse ? (int)gridDim.x - 1 - t : t;
 }
 
 // The D3Q7 moment slots of a voxel are stored as four pairs, one row of 2*ld values per pair:
@@ -119,41 +123,123 @@ template <typename S> struct PairOf;
 template <> struct PairOf<double> { using T = double2; };
 template <> struct PairOf<float> { using T = float2; };
 
+// Streaming accesses. Per launch the step touches most of its data once: the populations of the
+// even step (read and written in place), the neighbour table, the moment slots and phi written
+// for the next kernel. Marking those accesses non-temporal lets the L2 give their lines up
+// first, which keeps resident the lines that neighbouring voxels re-read within the launch
+// (phi in the collide kernel, the moment slots in the phase kernel). The odd step's populations
+// stay ordinary accesses: they land one neighbour away, so a cache line is shared between
+// adjacent waves and must be merged in the L2.
+template <typename T>
+__device__ __forceinline__ T load_stream(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_stream(T v, T* p) {
+    __builtin_nontemporal_store(v, p);
+}
+
 template <typename S>
 __device__ __forceinline__ typename PairOf<S>::T load_pair(const S* __restrict__ M, size_t ld,
                                                           int k, int y) {
     return reinterpret_cast<const typename PairOf<S>::T*>(M)[(size_t)k * ld + y];
 }
 
+// One 16-byte (FP64) or 8-byte (FP32) streaming store of a pair of slots.
 template <typename S>
 __device__ __forceinline__ void store_pair(S* __restrict__ M, size_t ld, int k, int i, S x, S y) {
-    typename PairOf<S>::T v;
+    typedef S Vec2 __attribute__((ext_vector_type(2)));
+    Vec2 v;
     v.x = x;
     v.y = y;
-    reinterpret_cast<typename PairOf<S>::T*>(M)[(size_t)k * ld + i] = v;
+    store_stream(v, reinterpret_cast<Vec2*>(M) + ((size_t)k * ld + i));
 }
 
 // Neighbour lookup, fixed at compile time for the single-domain step kernels and chosen per
-// domain at run time (words != null selects the rank lookup) where domains of either kind meet.
-enum { NB_DYN = 0, NB_TABLE = 1, NB_RANK = 2 };
+// domain at run time (words != null selects the rank lookup, cax != null the compact one) where
+// domains of several kinds meet.
+enum { NB_DYN = 0, NB_TABLE = 1, NB_RANK = 2, NB_COMPACT = 3 };
+
+template <int NB>
+__device__ __forceinline__ bool use_compact(const StepArgs& a) {
+    return NB == NB_COMPACT || (NB == NB_DYN && a.cax);
+}
 
 template <int NB>
 __device__ __forceinline__ bool use_table(const StepArgs& a) {
-    return NB == NB_TABLE || (NB == NB_DYN && !a.words);
+    return NB == NB_TABLE || (NB == NB_DYN && !a.words && !a.cax);
 }
 
-// Coordinates of pore voxel i (rank lookup only).
+template <int NB>
+__device__ __forceinline__ bool use_rank(const StepArgs& a) {
+    return NB == NB_RANK || (NB == NB_DYN && a.words);
+}
+
+// Memory that no thread writes during a launch, read through the constant address space: where
+// the address is the same for every lane of a wave the compiler can use scalar loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
+// What a voxel's neighbour lookups share: its coordinates (rank lookup) or its 18 decoded
+// neighbours (compact lookup).
 struct Pos {
     int x, y, z;
+    int cn[18];
 };
 
-template <int NB = NB_DYN>
+// Compact lookup of all 18 neighbours of pore voxel i: a 16-bit code above the wave's pore or
+// tail base for each direction (bit q of the mask chooses), or the int32 entries of an exception
+// wave. The wave record is read once per voxel; with WAVE, the caller's waves hold 64 consecutive
+// pore voxels (tiles of a multiple of 64 starting at a multiple of 64), so the record's address
+// is wave-uniform: it is read with scalar loads and the exception test is one scalar branch.
+// Directions a kernel never asks for are dead code (the phase kernel reads only the axis record).
+template <bool WAVE>
+__device__ __forceinline__ void compact_all(const StepArgs& a, int i, int (&cn)[18]) {
+    const int w = WAVE ? __builtin_amdgcn_readfirstlane(i >> 6) : (i >> 6);
+    const auto* rec = as_const(a.cwave) + (size_t)w * kCompactWaveInts;
+    const int32_t row = rec[kCompactExRow];
+    if (row >= 0) {
+        const int32_t* ex = a.cex + (size_t)row * 18 * 64 + (i & 63);
+#pragma unroll
+        for (int q = 1; q < 19; ++q) cn[q - 1] = load_stream(ex + (q - 1) * 64);
+        return;
+    }
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t U2 __attribute__((ext_vector_type(2)));
+    const U4 ax = load_stream(reinterpret_cast<const U4*>(a.cax) + i);
+    const U4 d4 = load_stream(reinterpret_cast<const U4*>(a.cdg4) + i);
+    const U2 d2 = load_stream(reinterpret_cast<const U2*>(a.cdg2) + i);
+    const uint32_t words[9] = {ax.y, ax.z, ax.w, d4.x, d4.y, d4.z, d4.w, d2.x, d2.y};
+#pragma unroll
+    for (int q = 1; q < 19; ++q) {
+        const uint32_t word = words[(q - 1) >> 1];
+        const uint32_t code = (q & 1) ? (word & 0xffffu) : (word >> 16);
+        // Both bases as wave-uniform values, then a per-lane select (a select of the two
+        // addresses would turn the scalar loads into vector ones).
+        const int32_t pb = WAVE ? __builtin_amdgcn_readfirstlane(rec[q - 1]) : rec[q - 1];
+        const int32_t tb = WAVE ? __builtin_amdgcn_readfirstlane(rec[18 + q - 1]) : rec[18 + q - 1];
+        cn[q - 1] = (((ax.x >> q) & 1u) ? tb : pb) + (int)code;
+    }
+}
+
+// Per-voxel lookup state of pore voxel i (see Pos).
+template <int NB = NB_DYN, bool WAVE = false>
 __device__ __forceinline__ Pos pos_of(const StepArgs& a, int i) {
-    if (use_table<NB>(a)) return Pos{0, 0, 0};
+    Pos p;
+    p.x = p.y = p.z = 0;
+    if (use_compact<NB>(a)) {
+        compact_all<WAVE>(a, i, p.cn);
+        return p;
+    }
+    if (!use_rank<NB>(a)) return p;
     const uint32_t c = a.coord[i];
-    return Pos{(int)(c & ((1u << kCoordXBits) - 1)),
-               (int)((c >> kCoordXBits) & ((1u << kCoordYBits) - 1)),
-               (int)(c >> (kCoordXBits + kCoordYBits))};
+    p.x = (int)(c & ((1u << kCoordXBits) - 1));
+    p.y = (int)((c >> kCoordXBits) & ((1u << kCoordYBits) - 1));
+    p.z = (int)(c >> (kCoordXBits + kCoordYBits));
+    return p;
 }
 
 // Pore index, or N + tail index for a solid, of the in-domain voxel (x, y, z): the segment's
@@ -176,9 +262,11 @@ __device__ __forceinline__ int nb(const StepArgs& a, int q, int i, Pos p, bool& 
     mirror = false;
     if (use_table<NB>(a)) {
         // Opposite directions (q, q + 1 for odd q) share one 8-byte entry.
-        const int2 e = reinterpret_cast<const int2*>(a.nbr)[(size_t)((q - 1) >> 1) * a.ld + i];
-        return (q & 1) ? e.x : e.y;
+        const int64_t e =
+            load_stream(reinterpret_cast<const int64_t*>(a.nbr) + ((size_t)((q - 1) >> 1) * a.ld + i));
+        return (q & 1) ? (int)(uint32_t)e : (int)(e >> 32);
     }
+    if (use_compact<NB>(a)) return p.cn[q - 1];
     int cx = p.x + CX[q], cy = p.y + CY[q], cz = p.z + CZ[q];
     if (CX[q] && (cx < 0 || cx >= a.nx)) {
         if (!(a.periodic & 1)) return a.N;
@@ -213,7 +301,8 @@ __device__ __forceinline__ int nb_stream(const StepArgs& a, int q, int i, Pos p)
 template <bool ODD, typename S>
 __device__ __forceinline__ S load_in(const S* __restrict__ X, const StepArgs& a, int q, int i,
                                      int r_up) {
-    if (!ODD || q == 0) return X[(size_t)q * a.ld + i];
+    if (!ODD) return load_stream(&X[(size_t)q * a.ld + i]);
+    if (q == 0) return X[i];
     // r_up: neighbour along opp(q), i.e. the upstream voxel i - xi_q.
     return r_up < a.N ? X[(size_t)OPP[q] * a.ld + r_up] : X[(size_t)q * a.ld + i];
 }
@@ -222,10 +311,10 @@ __device__ __forceinline__ S load_in(const S* __restrict__ X, const StepArgs& a,
 template <bool ODD, typename S>
 __device__ __forceinline__ void store_out(S* __restrict__ X, const StepArgs& a, int q, int i,
                                           int r_down, S v) {
-    if (q == 0) {
+    if (!ODD) {
+        store_stream(v, &X[(size_t)OPP[q] * a.ld + i]);
+    } else if (q == 0) {
         X[i] = v;
-    } else if (!ODD) {
-        X[(size_t)OPP[q] * a.ld + i] = v;
     } else {
         // r_down: neighbour along q, the downstream voxel i + xi_q; a wall sends the population
         // back into the voxel's own opposite slot. One store to the selected address.
@@ -319,7 +408,7 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
         }
         return;
     }
-    const Pos pos = pos_of<NB>(a, i);
+    const Pos pos = pos_of<NB, true>(a, i);
     int up[7];
 #pragma unroll
     for (int q = 1; q < 7; ++q) up[q] = nb_stream<NB>(a, OPP[q], i, pos);  // voxel i - xi_q
@@ -392,8 +481,8 @@ __device__ __forceinline__ void phase_voxel(const StepArgs& a, int i, bool fresh
     double na, nbv;
     densities<PREC, NB>(a, i, fresh, na, nbv);
     const double nt = na + nbv;
-    ((S*)a.phi)[i] = (S)((na - nbv) / nt);
-    ((S*)a.ntot)[i] = (S)nt;
+    store_stream((S)((na - nbv) / nt), (S*)a.phi + i);
+    store_stream((S)nt, (S*)a.ntot + i);
 }
 
 template <int PREC, bool ODD, int NB>
@@ -418,7 +507,7 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     uint32_t mirror = 0; // bit q: streaming along q bounces back although r[q] is a pore index
     r[0] = i;
     {
-        const Pos pos = pos_of<NB>(a, i);
+        const Pos pos = pos_of<NB, true>(a, i);
 #pragma unroll
         for (int q = 1; q < 19; ++q) {
             bool m;
@@ -557,12 +646,8 @@ __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
 // is bitwise the same alone and in the mix.
 // ------------------------------------------------------------------------------------------
 // The tile table and the per-slot arguments are read-only during a launch and every index into
-// them is uniform over the workgroup: reading them through the constant address space lets the
-// compiler use scalar loads, so a slot's arguments live in scalar registers.
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
-    return (const __attribute__((address_space(4))) T*)p;
-}
+// them is uniform over the workgroup: reading them through the constant address space (as_const)
+// lets the compiler use scalar loads, so a slot's arguments live in scalar registers.
 
 // A whole record through the constant address space, one 32-bit word at a time (the compiler
 // merges the words into wide scalar loads).
@@ -958,11 +1043,13 @@ hipError_t launch_collide_nb(const StepArgs& a, bool odd, int block, hipStream_t
 
 hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s) {
     return a.words ? launch_phase_nb<NB_RANK>(a, odd, block, s)
+           : a.cax ? launch_phase_nb<NB_COMPACT>(a, odd, block, s)
                    : launch_phase_nb<NB_TABLE>(a, odd, block, s);
 }
 
 hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s) {
     return a.words ? launch_collide_nb<NB_RANK>(a, odd, block, s)
+           : a.cax ? launch_collide_nb<NB_COMPACT>(a, odd, block, s)
                    : launch_collide_nb<NB_TABLE>(a, odd, block, s);
 }
 
@@ -983,6 +1070,9 @@ hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* 
     do {                                                                                       \
         if (lookup == LBM_NBR_TABLE)                                                           \
             LBM_PREC_SWITCH(prec, LBM_LAUNCH_ODD_NB, KERNEL, NB_TABLE, GRID, BLOCK, __VA_ARGS__); \
+        else if (lookup == LBM_NBR_COMPACT)                                                    \
+            LBM_PREC_SWITCH(prec, LBM_LAUNCH_ODD_NB, KERNEL, NB_COMPACT, GRID, BLOCK,          \
+                            __VA_ARGS__);                                                      \
         else if (lookup == LBM_NBR_RANK)                                                       \
             LBM_PREC_SWITCH(prec, LBM_LAUNCH_ODD_NB, KERNEL, NB_RANK, GRID, BLOCK, __VA_ARGS__); \
         else                                                                                   \

@@ -195,14 +195,16 @@ lbm_status upload_tables(lbm_pool* p) {
     p->h_ntiles = (int32_t)p->h_tile_dom.size();
     // The step kernels are specialised on the neighbour lookup when all members share it; a
     // change of that choice invalidates the captured graph.
-    int n_rank = 0, n_members = 0;
+    int n_rank = 0, n_compact = 0, n_members = 0;
     for (lbm_domain* d : p->slots)
         if (d) {
             ++n_members;
             n_rank += d->rank ? 1 : 0;
+            n_compact += d->compact ? 1 : 0;
         }
-    const int32_t lookup = n_rank == 0 ? LBM_NBR_TABLE
-                           : n_rank == n_members ? LBM_NBR_RANK : LBM_NBR_AUTO;
+    const int32_t lookup = n_rank == n_members && n_members ? LBM_NBR_RANK
+                           : n_compact == n_members && n_members ? LBM_NBR_COMPACT
+                           : n_rank == 0 && n_compact == 0 ? LBM_NBR_TABLE : LBM_NBR_AUTO;
     if (lookup != p->lookup) {
         HIP_TRY(hipStreamSynchronize(p->stream));
         p->drop_graph();

@@ -19,6 +19,7 @@
 #include "lbm_prepass.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <limits>
@@ -356,6 +357,100 @@ std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels
     }
     if (n + out.n_tail >= (int64_t)std::numeric_limits<int32_t>::max())
         return "pore voxels plus solid tail exceed int32 indexing";
+    return "";
+}
+
+std::string build_compact_lookup(Prepass& pre) {
+    CompactNbr& c = pre.compact;
+    const int64_t ld = pre.ld, n = pre.n_pore, nw = ld / 64;
+    c.ax.assign((size_t)ld * 4, 0u);
+    c.dg4.assign((size_t)ld * 4, 0u);
+    c.dg2.assign((size_t)ld * 2, 0u);
+    c.wave.assign((size_t)nw * kCompactWaveInts, 0);
+    auto target = [&](int q, int64_t i) -> int64_t { return pre.nbr[(size_t)(q - 1) * ld + i]; };
+    // Bases per wave and direction; waves that do not fit 16-bit codes become exceptions.
+    std::vector<uint8_t> is_ex((size_t)nw, 0);
+    parallel_for(nw, [&](int64_t w0, int64_t w1) {
+        for (int64_t w = w0; w < w1; ++w) {
+            int32_t* rec = &c.wave[(size_t)w * kCompactWaveInts];
+            bool fits = true;
+            for (int q = 1; q < 19 && fits; ++q) {
+                int64_t plo = INT64_MAX, phi = -1, tlo = INT64_MAX, thi = -1;
+                for (int64_t i = 64 * w; i < 64 * w + 64; ++i) {
+                    const int64_t t = target(q, i);
+                    if (t < n) { plo = std::min(plo, t); phi = std::max(phi, t); }
+                    else { tlo = std::min(tlo, t); thi = std::max(thi, t); }
+                }
+                if ((phi >= 0 && phi - plo > 0xffff) || (thi >= 0 && thi - tlo > 0xffff)) fits = false;
+                rec[q - 1] = phi >= 0 ? (int32_t)plo : 0;
+                rec[18 + q - 1] = thi >= 0 ? (int32_t)tlo : (int32_t)n;
+            }
+            is_ex[(size_t)w] = fits ? 0 : 1;
+        }
+    }, nw * 64 * 18);
+    c.n_ex = 0;
+    for (int64_t w = 0; w < nw; ++w) {
+        int32_t* rec = &c.wave[(size_t)w * kCompactWaveInts];
+        rec[kCompactExRow] = is_ex[(size_t)w] ? (int32_t)c.n_ex++ : -1;
+    }
+    c.ex.assign((size_t)c.n_ex * 18 * 64, 0);
+    parallel_for(nw, [&](int64_t w0, int64_t w1) {
+        for (int64_t w = w0; w < w1; ++w) {
+            const int32_t* rec = &c.wave[(size_t)w * kCompactWaveInts];
+            const int32_t row = rec[kCompactExRow];
+            for (int64_t i = 64 * w; i < 64 * w + 64; ++i) {
+                uint32_t mask = 0;
+                uint16_t code[19] = {0};
+                for (int q = 1; q < 19; ++q) {
+                    const int64_t t = target(q, i);
+                    if (row >= 0) {
+                        c.ex[((size_t)row * 18 + (q - 1)) * 64 + (size_t)(i & 63)] = (int32_t)t;
+                        continue;
+                    }
+                    const bool tail = t >= n;
+                    if (tail) mask |= 1u << q;
+                    code[q] = (uint16_t)(t - (tail ? rec[18 + q - 1] : rec[q - 1]));
+                }
+                c.ax[(size_t)i * 4 + 0] = mask;
+                for (int k = 0; k < 3; ++k)
+                    c.ax[(size_t)i * 4 + 1 + k] = code[1 + 2 * k] | (uint32_t)code[2 + 2 * k] << 16;
+                for (int k = 0; k < 4; ++k)
+                    c.dg4[(size_t)i * 4 + k] = code[7 + 2 * k] | (uint32_t)code[8 + 2 * k] << 16;
+                for (int k = 0; k < 2; ++k)
+                    c.dg2[(size_t)i * 2 + k] = code[15 + 2 * k] | (uint32_t)code[16 + 2 * k] << 16;
+            }
+        }
+    }, ld * 18);
+    // Decode every entry as the kernels do and compare it with the table.
+    std::vector<int64_t> bad((size_t)nw, -1);
+    parallel_for(nw, [&](int64_t w0, int64_t w1) {
+        for (int64_t w = w0; w < w1; ++w) {
+            const int32_t* rec = &c.wave[(size_t)w * kCompactWaveInts];
+            for (int64_t i = 64 * w; i < 64 * w + 64 && bad[(size_t)w] < 0; ++i)
+                for (int q = 1; q < 19; ++q) {
+                    int64_t got;
+                    if (rec[kCompactExRow] >= 0) {
+                        got = c.ex[((size_t)rec[kCompactExRow] * 18 + (q - 1)) * 64 +
+                                   (size_t)(i & 63)];
+                    } else {
+                        uint32_t word;
+                        if (q <= 6) word = c.ax[(size_t)i * 4 + 1 + (q - 1) / 2];
+                        else if (q <= 14) word = c.dg4[(size_t)i * 4 + (q - 7) / 2];
+                        else word = c.dg2[(size_t)i * 2 + (q - 15) / 2];
+                        const uint32_t code = (q & 1) ? (word & 0xffffu) : (word >> 16);
+                        const bool tail = (c.ax[(size_t)i * 4] >> q) & 1u;
+                        got = (int64_t)(tail ? rec[18 + q - 1] : rec[q - 1]) + code;
+                    }
+                    if (got != target(q, i)) {
+                        bad[(size_t)w] = i;
+                        break;
+                    }
+                }
+        }
+    }, ld * 18);
+    for (int64_t w = 0; w < nw; ++w)
+        if (bad[(size_t)w] >= 0)
+            return fmt("compact lookup differs from the table at pore %lld", bad[(size_t)w]);
     return "";
 }
 

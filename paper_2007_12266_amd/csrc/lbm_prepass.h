@@ -27,6 +27,26 @@ struct alignas(32) RowWord {
 // Packed voxel coordinate: x | y << 10 | z << 21 (nx <= 1024, ny <= 2048, nz <= 2048).
 constexpr int kCoordXBits = 10, kCoordYBits = 11, kCoordZBits = 11;
 
+// Compact neighbour lookup. The pore list is cut into waves of 64 consecutive voxels. For each
+// wave and direction q the targets of its voxels (pore index, or N + tail index) lie close
+// together, so each is stored as a 16-bit code above one of two per-wave bases, the pore base or
+// the tail base; bit q of the voxel's mask says which. Per voxel: an axis record of 16 bytes
+// (mask, codes of q = 1..6, all the densities need) and diagonal records of 16 + 8 bytes (codes
+// of q = 7..14 and 15..18). Per wave: kCompactWaveInts ints: pore bases of q = 1..18, tail bases
+// of q = 1..18, then the wave's exception row or -1. A wave whose targets spread beyond 16 bits
+// (where the pore list jumps between blocks of rows) keeps its 18 x 64 targets as int32 in
+// exception row r: cex[(r * 18 + q - 1) * 64 + lane].
+constexpr int kCompactWaveInts = 40;
+constexpr int kCompactExRow = 36;
+struct CompactNbr {
+    std::vector<uint32_t> ax;     // [ld][4]: mask (bit q = tail target), codes 1|2, 3|4, 5|6
+    std::vector<uint32_t> dg4;    // [ld][4]: codes 7|8, 9|10, 11|12, 13|14
+    std::vector<uint32_t> dg2;    // [ld][2]: codes 15|16, 17|18
+    std::vector<int32_t> wave;    // [ld / 64][kCompactWaveInts]
+    std::vector<int32_t> ex;      // [exception waves][18][64]
+    int64_t n_ex = 0;             // exception waves
+};
+
 struct Prepass {
     int64_t n_pore = 0;                 // N
     int64_t n_tail = 0;                 // entries of the solid/wall tail of the phi array
@@ -45,12 +65,17 @@ struct Prepass {
     int32_t words_per_row = 0;          // ceil(nx / 64)
     std::vector<RowWord> words;         // [nz][ny][words_per_row]
     std::vector<uint32_t> coord;        // [ld] packed coordinate of each pore voxel
+    CompactNbr compact;                 // compact lookup (built from nbr, checked against it)
 };
 
 // Validates the inputs and builds `out`. Returns "" on success, else an error message.
 std::string prepass(const lbm_params& p, const int32_t* labels, int32_t n_labels,
                     const int8_t* label_kind, const double* label_affinity,
                     const double* voxel_affinity, const double* init_phi, Prepass& out);
+
+// Builds the compact lookup of `pre` from its table, then decodes every entry (padding lanes
+// included) the way the kernels do and compares it with the table. Returns "" when they agree.
+std::string build_compact_lookup(Prepass& pre);
 
 // Replays the rank lookup for every pore voxel and direction and compares it with the table
 // (table ghosts stand for z-face mirrors and are compared by the mirrored voxel). Returns ""

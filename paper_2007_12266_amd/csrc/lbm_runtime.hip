@@ -242,6 +242,20 @@ static bool uses_rank(const lbm_params& p, const Prepass& pre) {
     return pre.rank_ok && p.neighbour_mode == LBM_NBR_RANK;
 }
 
+// AUTO takes the compact lookup: the fastest of the three on MI355X in every precision.
+static bool uses_compact(const lbm_params& p) {
+    return p.neighbour_mode == LBM_NBR_COMPACT || p.neighbour_mode == LBM_NBR_AUTO;
+}
+
+// Device bytes of the compact lookup (built by build_compact_lookup).
+static int64_t compact_bytes(const Prepass& pre) {
+    auto r = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
+    const CompactNbr& c = pre.compact;
+    return r(sizeof(uint32_t) * c.ax.size()) + r(sizeof(uint32_t) * c.dg4.size()) +
+           r(sizeof(uint32_t) * c.dg2.size()) + r(sizeof(int32_t) * c.wave.size()) +
+           r(sizeof(int32_t) * c.ex.size());
+}
+
 static int64_t domain_bytes(const lbm_params& p, const Prepass& pre) {
     const size_t fb = p.precision == LBM_FP64 ? 8 : 4;         // D3Q19 populations
     const size_t eb = p.precision == LBM_FP32_DEV ? 4 : 8;     // moment slots, phi, N
@@ -249,7 +263,8 @@ static int64_t domain_bytes(const lbm_params& p, const Prepass& pre) {
     auto r = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
     const int64_t nbr = uses_rank(p, pre)
                             ? r(sizeof(uint32_t) * ld) + r(sizeof(RowWord) * pre.words.size())
-                            : r(sizeof(int32_t) * 18 * ld);
+                            : uses_compact(p) ? compact_bytes(pre)
+                                              : r(sizeof(int32_t) * 18 * ld);
     int64_t total = r(fb * 19 * ld) + r(eb * 8 * ld) + r(sizeof(int32_t)) +
                     r(eb * (size_t)(pre.n_pore + pre.n_tail)) + r(eb * ld) +
                     r(sizeof(double) * ld) + nbr +
@@ -281,6 +296,10 @@ lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
     if (!err.empty()) return fail(LBM_ERR_ARG, err);
     if (params->neighbour_mode == LBM_NBR_RANK && !pre.rank_ok)
         return fail(LBM_ERR_ARG, kRankLimits);
+    if (uses_compact(*params)) {
+        err = build_compact_lookup(pre);
+        if (!err.empty()) return fail(LBM_ERR_STATE, "internal: " + err);
+    }
     *bytes = domain_bytes(*params, pre);
     return LBM_OK;
 }
@@ -309,7 +328,7 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (p.inlet_mode == 1 && (p.bc_z != 1 || !std::isfinite(p.flux_in)))
         return fail(LBM_ERR_ARG, "a flux inlet needs bc_z == 1 and a finite flux_in");
     if (p.reduce_every < 0) return fail(LBM_ERR_ARG, "reduce_every must be >= 0");
-    if (p.neighbour_mode < LBM_NBR_AUTO || p.neighbour_mode > LBM_NBR_RANK)
+    if (p.neighbour_mode < LBM_NBR_AUTO || p.neighbour_mode > LBM_NBR_COMPACT)
         return fail(LBM_ERR_ARG, "neighbour_mode must be a lbm_neighbour_mode");
     int block = p.block_size == 0 ? 256 : p.block_size;
     if (block != 64 && block != 128 && block != 256)
@@ -327,6 +346,11 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (p.neighbour_mode == LBM_NBR_RANK && !d->pre.rank_ok)
         return fail(LBM_ERR_ARG, kRankLimits);
     d->rank = uses_rank(p, d->pre);
+    d->compact = uses_compact(p);
+    if (d->compact) {
+        err = build_compact_lookup(d->pre);
+        if (!err.empty()) return fail(LBM_ERR_STATE, "internal: " + err);
+    }
     if (alloc) {
         d->alloc = *alloc;
         d->has_alloc = true;
@@ -346,9 +370,16 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     d->phi = d->dalloc(eb * (size_t)(pre.n_pore + pre.n_tail));
     d->ntot = d->dalloc(eb * ld);
     d->stage = (double*)d->dalloc(sizeof(double) * ld);
+    const CompactNbr& cn = pre.compact;
     if (d->rank) {
         d->coord = (uint32_t*)d->dalloc(sizeof(uint32_t) * ld);
         d->words = (RowWord*)d->dalloc(sizeof(RowWord) * pre.words.size());
+    } else if (d->compact) {
+        d->cax = (uint4*)d->dalloc(sizeof(uint32_t) * cn.ax.size());
+        d->cdg4 = (uint4*)d->dalloc(sizeof(uint32_t) * cn.dg4.size());
+        d->cdg2 = (uint2*)d->dalloc(sizeof(uint32_t) * cn.dg2.size());
+        d->cwave = (int32_t*)d->dalloc(sizeof(int32_t) * cn.wave.size());
+        d->cex = (int32_t*)d->dalloc(sizeof(int32_t) * cn.ex.size());
     } else {
         d->nbr = (int32_t*)d->dalloc(sizeof(int32_t) * 18 * ld);
     }
@@ -357,7 +388,9 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     d->hist = (double*)d->dalloc(sizeof(double) * (size_t)d->hist_cap * kNRed);
     double* phi0 = d->stage;
     if (!d->f || !d->M || !d->fresh || !d->phi || !d->ntot || !d->stage ||
-        (d->rank ? (!d->coord || !d->words) : !d->nbr) ||
+        (d->rank ? (!d->coord || !d->words)
+                 : d->compact ? (!d->cax || !d->cdg4 || !d->cdg2 || !d->cwave || !d->cex)
+                              : !d->nbr) ||
         !d->red_partials || !d->red_out || !d->hist) {
         d->release();
         return fail(LBM_ERR_OOM, "device allocation failed");
@@ -397,6 +430,13 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (d->rank) {
         guard(up(d->coord, pre.coord.data(), sizeof(uint32_t) * pre.coord.size()), "upload coord");
         guard(up(d->words, pre.words.data(), sizeof(RowWord) * pre.words.size()), "upload words");
+    } else if (d->compact) {
+        guard(up(d->cax, cn.ax.data(), sizeof(uint32_t) * cn.ax.size()), "upload compact");
+        guard(up(d->cdg4, cn.dg4.data(), sizeof(uint32_t) * cn.dg4.size()), "upload compact");
+        guard(up(d->cdg2, cn.dg2.data(), sizeof(uint32_t) * cn.dg2.size()), "upload compact");
+        guard(up(d->cwave, cn.wave.data(), sizeof(int32_t) * cn.wave.size()), "upload compact");
+        if (!cn.ex.empty())
+            guard(up(d->cex, cn.ex.data(), sizeof(int32_t) * cn.ex.size()), "upload compact");
     } else {
         const size_t ld = (size_t)pre.ld;
         nbr2.resize(18 * ld);
@@ -654,14 +694,14 @@ lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out) {
     out->step = d->step;
     out->precision = d->p.precision;
     out->block_size = d->tune.collide_block;
-    out->neighbour_mode = d->rank ? LBM_NBR_RANK : LBM_NBR_TABLE;
-    out->pad_ = 0;
+    out->neighbour_mode = d->rank ? LBM_NBR_RANK : d->compact ? LBM_NBR_COMPACT : LBM_NBR_TABLE;
+    out->compact_ex_waves = d->compact ? (int32_t)d->pre.compact.n_ex : 0;
     return LBM_OK;
 }
 
 static bool tuning_ok(const lbm_tuning& t) {
     auto blk = [](int b) { return b == 64 || b == 128 || b == 256; };
-    auto sch = [](int v) { return v == 1 || v == 2; };
+    auto sch = [](int v) { return v >= 1 && v <= 3; };
     return blk(t.phase_block) && blk(t.collide_block) && sch(t.phase_schedule) &&
            sch(t.collide_schedule);
 }
@@ -717,7 +757,7 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     const int blocks[3] = {64, 128, 256};
     for (int kernel = 0; kernel < 2 && st == LBM_OK && he == hipSuccess; ++kernel) {
         for (int bi = 0; bi < 3 && st == LBM_OK; ++bi) {
-            for (int sched = 1; sched <= 2 && st == LBM_OK; ++sched) {
+            for (int sched = 1; sched <= 3 && st == LBM_OK; ++sched) {
                 lbm_tuning t = best;
                 if (kernel == 0) {
                     t.phase_block = blocks[bi];
@@ -784,6 +824,7 @@ lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, in
                               voxel_affinity, init_phi, pre);
     if (!err.empty()) return fail(LBM_ERR_ARG, err);
     err = check_rank_lookup(*params, pre);
+    if (err.empty()) err = build_compact_lookup(pre);
     if (!err.empty()) return fail(LBM_ERR_STATE, "internal: " + err);
     *n_pore = pre.n_pore;
     *n_tail = pre.n_tail;

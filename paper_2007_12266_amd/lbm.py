@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_ERR_ARG, LBM_ERR_OOM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE, LBM_ERR_STATE = range(6)
 FP64, FP32_DEV, FP32_MIXED = 0, 1, 2
-NBR_AUTO, NBR_TABLE, NBR_RANK = 0, 1, 2
+NBR_AUTO, NBR_TABLE, NBR_RANK, NBR_COMPACT = 0, 1, 2, 3
 FIELDS = {"Na": 0, "Nb": 1, "phi": 2, "rho": 3, "p": 4, "ux": 5, "uy": 6, "uz": 7}
 
 # Every symbol include/lbm.h declares.
@@ -150,7 +150,7 @@ class Info(ctypes.Structure):
                 ("ld", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("step", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("neighbour_mode", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("compact_ex_waves", ctypes.c_int32)]
 
 
 class PoolInfo(ctypes.Structure):

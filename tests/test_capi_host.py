@@ -175,21 +175,54 @@ def test_prepass_pressure_faces_mirror_the_plane():
 
 def test_footprint_depends_on_the_neighbour_lookup():
     """The rank lookup stores 4 B per pore voxel plus 32 B per 64-voxel row segment instead of
-    the 72 B/voxel table; grids beyond its 10/11/11-bit coordinates fall back to the table."""
+    the 72 B/voxel table; AUTO takes the compact lookup, which has no grid limit, where the rank
+    lookup's 10/11/11-bit coordinates refuse a wide grid."""
     prob = inputs.sphere_problem(n=32)
     table = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_TABLE)
     rank = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_RANK)
+    compact = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_COMPACT)
     auto = lbm.footprint(prob, lbm.FP64)
-    assert auto == table > rank
+    assert auto == compact
+    assert table > compact > rank
     n = lbm.prepass_query(prob)["n_pore"]
     assert table - rank >= 60 * n
     wide = inputs.Problem(labels=np.ones((2, 1, 1030), np.int32),
                           label_kind=np.array([inputs.KIND_SOLID, inputs.KIND_FLUID_A], np.int8),
                           label_affinity=np.array([0.0, 0.0]), periodic=(True, True, True))
     assert lbm.footprint(wide, lbm.FP64) == lbm.footprint(wide, lbm.FP64,
-                                                          neighbour_mode=lbm.NBR_TABLE)
+                                                          neighbour_mode=lbm.NBR_COMPACT)
     with pytest.raises(lbm.LbmError):
         lbm.footprint(wide, lbm.FP64, neighbour_mode=lbm.NBR_RANK)
+
+
+def test_compact_lookup_footprint_and_exception_waves():
+    """The compact lookup holds 40 B per voxel slot and 160 B per 64-voxel wave instead of the
+    table's 72 B, plus 18 x 64 int32 entries per exception wave. On an open 300 x 300 x 4 box the
+    pore numbering runs in blocks of 16 rows, so the waves that straddle a block edge see their
+    +-y targets jump by a whole block: those, and only those few, are exception waves. The
+    query behind prepass_query decodes every compact entry and compares it with the table, so
+    its success checks the encoding, exception waves included."""
+    prob = inputs.sphere_problem(n=32)
+    ld = -(-lbm.prepass_query(prob)["n_pore"] // 64) * 64
+    table = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_TABLE)
+    compact = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_COMPACT)
+    saved = 72 * ld - 40 * ld - 160 * (ld // 64)
+    extra = saved - (table - compact)       # exception rows (256 B, the minimum, when none)
+    assert extra == 256 or (extra > 0 and extra % (18 * 64 * 4) == 0)
+    box = inputs.Problem(labels=np.ones((4, 300, 300), np.int32),
+                         label_kind=np.array([inputs.KIND_SOLID, inputs.KIND_FLUID_A], np.int8),
+                         label_affinity=np.array([0.0, 0.0]), periodic=(True, True, True))
+    n = lbm.prepass_query(box)["n_pore"]
+    assert n == 360000
+    ld = n
+    table = lbm.footprint(box, lbm.FP64, neighbour_mode=lbm.NBR_TABLE)
+    compact = lbm.footprint(box, lbm.FP64, neighbour_mode=lbm.NBR_COMPACT)
+    extra = 72 * ld - 40 * ld - 160 * (ld // 64) - (table - compact)
+    assert extra % (18 * 64 * 4) == 0
+    n_ex = extra // (18 * 64 * 4)
+    # 300 rows of y make 19 blocks, 18 block edges per z plane; a wave crossing one is an
+    # exception wave, the rest (>99%) are not.
+    assert 1 <= n_ex <= 4 * 18
 
 
 def test_steady_calls_reject_null_handles():

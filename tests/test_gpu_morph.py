@@ -133,14 +133,14 @@ def test_fp32_keeps_density_and_lookups_agree(lbm):
     assert d32.reduce()["unstable"] == 0
     d32.close()
     blobs = []
-    for nm in (lbm.NBR_TABLE, lbm.NBR_RANK):
+    for nm in (lbm.NBR_TABLE, lbm.NBR_RANK, lbm.NBR_COMPACT):
         d = lbm.Domain(prob, neighbour_mode=nm)
         d.step(20)
         d.morph(delta=-0.7)
         d.step(5)
         blobs.append(d.save())
         d.close()
-    assert blobs[0] == blobs[1]
+    assert blobs[0] == blobs[1] == blobs[2]
 
 
 def test_morph_argument_checks(lbm):

@@ -46,6 +46,10 @@ def _compare(gpu: dict, ref: dict, pore, tol=TOL, fields=FIELDS, u_abs=0.0):
     return errs
 
 
+def _nm(lbm, mode):
+    return {"table": lbm.NBR_TABLE, "rank": lbm.NBR_RANK, "compact": lbm.NBR_COMPACT}[mode]
+
+
 def _random_problem(shape, periodic, seed, force=(1e-5, -2e-5, 3e-5), tau=(0.8, 0.65),
                     solid_frac=0.25, alpha=0.01, wall=0.3):
     rng = np.random.default_rng(seed)
@@ -66,14 +70,14 @@ def spheres32():
     return inputs.sphere_problem(n=32)
 
 
-@pytest.mark.parametrize("mode", ["rank", "table"])
+@pytest.mark.parametrize("mode", ["rank", "table", "compact"])
 @pytest.mark.parametrize("steps", [200, 199])
 def test_sphere_pack_parity(lbm, spheres32, steps, mode):
     """32^3 random spheres, periodic x/y, walls in z, affinity +0.5, tau 0.7, alpha 0.005,
     beta 0.95, F_z = 1e-5, random phase at Sw = 0.5: 200 steps (and 199, the other AA parity),
-    with either neighbour lookup."""
+    with each neighbour lookup."""
     prob = spheres32
-    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    nm = _nm(lbm, mode)
     dom = lbm.Domain(prob, neighbour_mode=nm)
     assert dom.info()["neighbour_mode"] == nm
     dom.step(steps)
@@ -84,7 +88,7 @@ def test_sphere_pack_parity(lbm, spheres32, steps, mode):
     dom.close()
 
 
-@pytest.mark.parametrize("mode", ["rank", "table"])
+@pytest.mark.parametrize("mode", ["rank", "table", "compact"])
 @pytest.mark.parametrize("block", [64, 128, 256])
 @pytest.mark.parametrize("periodic", [(True, False, True), (False, True, False)])
 def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
@@ -92,7 +96,7 @@ def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
     per-voxel affinity, unequal viscosities (nu varies with phi), force in all components."""
     prob = _random_problem((13, 21, 19), periodic, seed=101 + periodic.index(False))
     steps = 37
-    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    nm = _nm(lbm, mode)
     dom = lbm.Domain(prob, block_size=block, neighbour_mode=nm)
     assert dom.n_pore % 64 != 0 and dom.n_pore > 4 * block
     dom.step(steps)
@@ -103,6 +107,8 @@ def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
 
 
 def test_block_size_and_launch_shape_do_not_change_results(lbm):
+    """Block sizes, and the three tile orders (launch order, XCD-aware runs, XCD-aware runs from
+    the end of the pore list) in every pairing of the two kernels, give the same state."""
     prob = _random_problem((17, 18, 19), (True, True, True), seed=5)
     outs = []
     for block in (64, 128, 256):
@@ -110,10 +116,16 @@ def test_block_size_and_launch_shape_do_not_change_results(lbm):
         dom.step(25)
         outs.append(dom.save())
         dom.close()
-    assert outs[0] == outs[1] == outs[2]
+    for ps, cs in ((1, 3), (3, 2), (3, 3), (2, 1)):
+        dom = lbm.Domain(prob)
+        dom.set_tuning(phase_block=128, phase_schedule=ps, collide_block=64, collide_schedule=cs)
+        dom.step(25)
+        outs.append(dom.save())
+        dom.close()
+    assert all(o == outs[0] for o in outs)
 
 
-@pytest.mark.parametrize("mode", ["rank", "table"])
+@pytest.mark.parametrize("mode", ["rank", "table", "compact"])
 def test_results_do_not_depend_on_the_pore_numbering(lbm, spheres32, mode):
     """The pore numbering (blocks of order_rows rows of y, each block plane by plane; ny rows
     is the dense z, y, x order) only decides where a voxel's values live in memory: dense
@@ -121,7 +133,7 @@ def test_results_do_not_depend_on_the_pore_numbering(lbm, spheres32, mode):
     order, on the sphere pack (walls in z) and on a displacement with pressure faces. The
     reductions sum in pore order, so they agree to rounding: 1e-14 relative, the flux
     relative to the sum of |u_z| over the box."""
-    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    nm = _nm(lbm, mode)
     disp = inputs.displacement_problem(shape=(40, 20, 18), seed_geom=8, porosity_target=0.3)
     for prob in (spheres32, disp):
         ny = prob.shape[1]
@@ -371,7 +383,7 @@ def test_autotune_restores_state_and_keeps_results(lbm, precision):
     dom.step(7)
     before = dom.save()
     t = dom.autotune(4)
-    assert t["phase_block"] in (64, 128, 256) and t["collide_schedule"] in (1, 2)
+    assert t["phase_block"] in (64, 128, 256) and t["collide_schedule"] in (1, 2, 3)
     assert t["phase_ms"] > 0 and t["collide_ms"] > 0
     assert dom.info()["step"] == 7 and dom.save() == before
     dom.step(13)
@@ -385,14 +397,14 @@ def test_autotune_restores_state_and_keeps_results(lbm, precision):
     dom.close()
 
 
-@pytest.mark.parametrize("mode", ["rank", "table"])
+@pytest.mark.parametrize("mode", ["rank", "table", "compact"])
 @pytest.mark.parametrize("steps", [60, 61])
 def test_pressure_faces_parity(lbm, steps, mode):
     """Displacement with pressure faces (rho 1.03 / 0.97), walls of affinity -0.7, GRF rock
     between 4-plane reservoirs, x/y periodic: GPU FP64 vs the oracle, both parities, with
-    either neighbour lookup (mirrored z neighbours through ghosts or computed)."""
+    each neighbour lookup (mirrored z neighbours through ghosts or computed)."""
     prob = inputs.displacement_problem(shape=(40, 20, 18), seed_geom=8, porosity_target=0.3)
-    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    nm = _nm(lbm, mode)
     dom = lbm.Domain(prob, neighbour_mode=nm)
     dom.step(steps)
     gpu = dom.fields()
@@ -421,16 +433,17 @@ def test_displacement_generator_at_128_over_500_steps(lbm):
     dom.close()
 
 
-@pytest.mark.parametrize("mode,steps", [("table", 40), ("table", 41), ("rank", 41)])
+@pytest.mark.parametrize("mode,steps", [("table", 40), ("table", 41), ("rank", 41),
+                                        ("compact", 41)])
 def test_flux_inlet_parity(lbm, mode, steps):
     """Flux inlet (the paper's flux boundary condition, reading R19): the inlet density is
     chosen every step so that u_z summed over the inlet plane equals the imposed flux. GPU FP64
-    against the oracle, both step parities, both neighbour lookups; the flux itself holds."""
+    against the oracle, both step parities, every neighbour lookup; the flux itself holds."""
     import dataclasses
     base = inputs.displacement_problem(shape=(30, 12, 14), seed_geom=21, porosity_target=0.3)
     n_in = int((base.solid_mask()[0] == 0).sum())
     prob = dataclasses.replace(base, inlet_mode=1, flux_in=0.01 * n_in, force=(0.0, 0.0, 3e-6))
-    nm = lbm.NBR_RANK if mode == "rank" else lbm.NBR_TABLE
+    nm = _nm(lbm, mode)
     dom = lbm.Domain(prob, neighbour_mode=nm)
     dom.step(steps)
     gpu = dom.fields()
@@ -477,29 +490,36 @@ def test_pressure_faces_fp32_dev_tracks_fp64(lbm):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
 def test_neighbour_lookups_are_bitwise_identical(lbm, precision):
-    """The table and the rank lookup name the same neighbours, so every stored value agrees
-    bitwise: walls in every direction, periodic wraps, and mirrored pressure faces."""
+    """The table, the rank lookup and the compact lookup name the same neighbours, so every
+    stored value agrees bitwise: walls in every direction, periodic wraps, mirrored pressure
+    faces, and compact exception waves (last problem, 89,920 pore voxels: a wave that holds the
+    edge between two blocks of 16 rows of y sees its +-y targets jump by a whole block, beyond
+    16 bits; 73 such waves)."""
     prec = lbm.FP64 if precision == "fp64" else lbm.FP32_DEV
     probs = [_random_problem((29, 14, 23), (False, False, False), seed=61),
              _random_problem((70, 9, 11), (True, False, True), seed=62),
-             inputs.displacement_problem(shape=(30, 18, 16), seed_geom=63, porosity_target=0.35)]
+             inputs.displacement_problem(shape=(30, 18, 16), seed_geom=63, porosity_target=0.35),
+             _random_problem((48, 40, 52), (True, True, True), seed=64, solid_frac=0.1)]
     for prob in probs:
-        blobs, reds = [], []
-        for nm in (lbm.NBR_TABLE, lbm.NBR_RANK):
+        blobs, reds, ex = [], [], 0
+        for nm in (lbm.NBR_TABLE, lbm.NBR_RANK, lbm.NBR_COMPACT):
             dom = lbm.Domain(prob, precision=prec, neighbour_mode=nm)
+            ex = max(ex, dom.info()["compact_ex_waves"])
             dom.step(23)
             blobs.append(dom.save())
             reds.append(dom.reduce())
             dom.close()
-        assert blobs[0] == blobs[1]
-        assert reds[0] == reds[1]
+        assert blobs[0] == blobs[1] == blobs[2]
+        assert reds[0] == reds[1] == reds[2]
+    assert ex == 73                                 # the last problem's exception waves
 
 
 def test_auto_mode_and_footprints(lbm):
     prob = _random_problem((17, 18, 19), (True, True, True), seed=5)
     dom = lbm.Domain(prob)
-    assert dom.info()["neighbour_mode"] == lbm.NBR_TABLE
+    assert dom.info()["neighbour_mode"] == lbm.NBR_COMPACT
     dom.close()
     table = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_TABLE)
     rank = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_RANK)
-    assert rank < table
+    compact = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_COMPACT)
+    assert rank < compact < table

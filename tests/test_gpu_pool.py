@@ -47,8 +47,9 @@ def test_members_match_solo_runs_bitwise(lbm, precision):
     probs = _mix()
     pool = lbm.Pool(1 << 34, precision=prec, max_slots=8, chunk_steps=20)
     pool.set_order(1 if precision == "fp64" else 0)     # both tile orders are covered
-    # Members alternate between the two neighbour lookups; each solo run uses the other one.
-    modes = [lbm.NBR_RANK if k % 2 == 0 else lbm.NBR_TABLE for k in range(len(probs))]
+    # Members cycle through the three neighbour lookups; each solo run uses the next one.
+    cycle = [lbm.NBR_RANK, lbm.NBR_TABLE, lbm.NBR_COMPACT]
+    modes = [cycle[k % 3] for k in range(len(probs))]
     doms = [lbm.Domain(p, precision=prec, neighbour_mode=m) for p, m in zip(probs, modes)]
     slots = [pool.admit(d) for d in doms]
     pool.step(53)                                  # 2 graph replays + 13 eager steps
@@ -57,7 +58,7 @@ def test_members_match_solo_runs_bitwise(lbm, precision):
     red = pool.reduce()
     for p, d, s, m in zip(probs, doms, slots, modes):
         assert d.info()["neighbour_mode"] == m
-        solo = lbm.Domain(p, precision=prec, neighbour_mode=lbm.NBR_RANK + lbm.NBR_TABLE - m)
+        solo = lbm.Domain(p, precision=prec, neighbour_mode=cycle[(cycle.index(m) + 1) % 3])
         solo.step(53)
         assert d.info()["step"] == 53
         assert d.save() == solo.save()
@@ -69,15 +70,18 @@ def test_members_match_solo_runs_bitwise(lbm, precision):
         d.close()
 
 
-@pytest.mark.parametrize("lookups", ["table", "rank-joins"])
+@pytest.mark.parametrize("lookups", ["table", "rank-joins", "compact-joins", "compact"])
 def test_membership_changes_keep_results(lbm, lookups):
-    """Members leave and join between graph chunks. With "rank-joins" the pool's kernels change
-    from the table specialisation to the mixed one when a rank-lookup member joins (the
-    captured graph is rebuilt)."""
+    """Members leave and join between graph chunks. With "rank-joins" ("compact-joins") the
+    pool's kernels change from the table specialisation to the mixed one when a rank-lookup
+    (compact-lookup) member joins (the captured graph is rebuilt); with "compact" every member
+    uses the compact lookup and the pool its compact specialisation."""
     probs = _mix()
     pool = lbm.Pool(1 << 34, precision=lbm.FP32_DEV, max_slots=3, chunk_steps=10)
-    mode_c = lbm.NBR_RANK if lookups == "rank-joins" else lbm.NBR_TABLE
-    a, b = (lbm.Domain(p, precision=lbm.FP32_DEV) for p in probs[:2])
+    mode_c = {"table": lbm.NBR_TABLE, "rank-joins": lbm.NBR_RANK,
+              "compact-joins": lbm.NBR_COMPACT, "compact": lbm.NBR_COMPACT}[lookups]
+    mode_ab = lbm.NBR_COMPACT if lookups == "compact" else lbm.NBR_TABLE
+    a, b = (lbm.Domain(p, precision=lbm.FP32_DEV, neighbour_mode=mode_ab) for p in probs[:2])
     c = lbm.Domain(probs[2], precision=lbm.FP32_DEV, neighbour_mode=mode_c)
     sa, sb = pool.admit(a), pool.admit(b)
     pool.step(30)
@@ -87,7 +91,7 @@ def test_membership_changes_keep_results(lbm, lookups):
     pool.step(24)
     assert a.info()["step"] == 30 and b.info()["step"] == 54 and c.info()["step"] == 24
     for dom, prob, n in ((a, probs[0], 30), (b, probs[1], 54), (c, probs[2], 24)):
-        solo = lbm.Domain(prob, precision=lbm.FP32_DEV)
+        solo = lbm.Domain(prob, precision=lbm.FP32_DEV, neighbour_mode=lbm.NBR_TABLE)
         solo.step(n)
         assert dom.save() == solo.save()
         solo.close()
@@ -154,7 +158,8 @@ def test_pressure_face_members_match_solo_runs_bitwise(lbm, precision):
     prec = {"fp32dev": lbm.FP32_DEV, "fp64": lbm.FP64, "mixed": lbm.FP32_MIXED}[precision]
     probs = [_displacement(7, (30, 14, 12)), _mix()[0], _displacement(8, (26, 10, 17), flux=0.02),
              _mix()[2]]
-    modes = [lbm.NBR_TABLE, lbm.NBR_RANK, lbm.NBR_RANK, lbm.NBR_TABLE]
+    cycle = [lbm.NBR_RANK, lbm.NBR_TABLE, lbm.NBR_COMPACT]
+    modes = [lbm.NBR_TABLE, lbm.NBR_RANK, lbm.NBR_COMPACT, lbm.NBR_TABLE]
     doms = [lbm.Domain(p, precision=prec, neighbour_mode=m) for p, m in zip(probs, modes)]
     pool = lbm.Pool(1 << 34, precision=prec, max_slots=4, chunk_steps=10)
     slots = [pool.admit(d) for d in doms[:3]]
@@ -165,7 +170,7 @@ def test_pressure_face_members_match_solo_runs_bitwise(lbm, precision):
     red = pool.reduce()
     for k, (p, d, s, m) in enumerate(zip(probs, doms, slots, modes)):
         n = 47 if k < 3 else 23
-        solo = lbm.Domain(p, precision=prec, neighbour_mode=lbm.NBR_RANK + lbm.NBR_TABLE - m)
+        solo = lbm.Domain(p, precision=prec, neighbour_mode=cycle[(cycle.index(m) + 1) % 3])
         solo.step(n)
         assert d.info()["step"] == n
         assert d.save() == solo.save(), k
