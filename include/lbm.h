@@ -164,10 +164,16 @@ typedef struct {
  * order: each of the 8 XCDs takes runs of 16 consecutive tiles, the runs interleaved, so that
  * neighbouring tiles share an L2; 3 = the XCD-aware order run from the end of the pore list, so
  * that a kernel following one in forward order starts where that one ended (on lines that may
- * still be cached). Results do not depend on the configuration (bitwise). */
+ * still be cached). stream: 1 = the data a launch touches once (even-step populations, the
+ * neighbour lookup, the moment slots, phi and N written for the next kernel) is read and
+ * written with non-temporal hints, so the L2 keeps the lines neighbouring voxels re-read; right
+ * for domains far larger than the 256 MB Infinity Cache, wrong for those it holds from one step
+ * to the next. lbm_domain_create sets stream = 1 when the domain's device memory exceeds
+ * 512 MiB. Results do not depend on the configuration (bitwise). */
 typedef struct {
     int32_t phase_block, phase_schedule;
     int32_t collide_block, collide_schedule;
+    int32_t phase_stream, collide_stream;
     double phase_ms, collide_ms;  /* average per launch measured by lbm_autotune, else 0        */
 } lbm_tuning;
 
@@ -333,15 +339,15 @@ lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes);
 
 lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out);
 
-/* Autotuner: times every (block, schedule) candidate of each step kernel over trial_steps >= 2
- * steps on this domain, applies the fastest, and writes it to *out (nullable). The state, step
+/* Autotuner: times every (block, schedule, stream) candidate of each step kernel over
+ * trial_steps >= 2 steps on this domain, applies the fastest, and writes it to *out (nullable). The state, step
  * counter and reduction history are restored afterwards, so the results of later steps are
  * unchanged. Synchronises; needs device memory for one copy of the populations (LBM_ERR_OOM
  * otherwise). */
 lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out);
 
 /* Apply a launch configuration (e.g. one cached from an earlier lbm_autotune on the same GPU,
- * precision and size class). LBM_ERR_ARG for an unsupported block or schedule. */
+ * precision and size class). LBM_ERR_ARG for an unsupported block, schedule or stream flag. */
 lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t);
 lbm_status lbm_get_tuning(lbm_domain* d, lbm_tuning* out);
 

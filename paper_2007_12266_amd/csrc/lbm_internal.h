@@ -64,6 +64,11 @@ constexpr int kXcdRun = 16;
 // ends on an even step).
 constexpr int64_t kStepGraphChunk = 64;
 
+// Device memory above which a new domain launches its step kernels with streaming
+// (non-temporal) accesses: twice the MI355X Infinity Cache (256 MB), so that a domain the cache
+// holds from one step to the next keeps that reuse.
+constexpr int64_t kStreamBytes = int64_t(512) << 20;
+
 struct BatchArgs {
     const StepArgs* doms;       // per-slot kernel arguments (N = 0 for an empty slot)
     const int32_t* tile_dom;    // slot of each tile
@@ -74,8 +79,8 @@ struct BatchArgs {
 
 // Kernel launchers (lbm_kernels.hip). `odd` is the parity of the step being taken.
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s);
-hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s);
-hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s);
+hipError_t launch_phase(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s);
+hipError_t launch_collide(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s);
 hipError_t launch_ghosts(const StepArgs& a, const int32_t* ghost_tail, const int32_t* ghost_src,
                          int32_t n, hipStream_t s);
 // faces: inlet pore indices (n_in) followed by outlet ones (n_out); next_odd: parity of the

@@ -123,21 +123,26 @@ template <typename S> struct PairOf;
 template <> struct PairOf<double> { using T = double2; };
 template <> struct PairOf<float> { using T = float2; };
 
-// Streaming accesses. Per launch the step touches most of its data once: the populations of the
-// even step (read and written in place), the neighbour table, the moment slots and phi written
-// for the next kernel. Marking those accesses non-temporal lets the L2 give their lines up
-// first, which keeps resident the lines that neighbouring voxels re-read within the launch
-// (phi in the collide kernel, the moment slots in the phase kernel). The odd step's populations
-// stay ordinary accesses: they land one neighbour away, so a cache line is shared between
-// adjacent waves and must be merged in the L2.
-template <typename T>
-__device__ __forceinline__ T load_stream(const T* p) {
-    return __builtin_nontemporal_load(p);
+// Streaming accesses (STREAM). Per launch the step touches most of its data once: the
+// populations of the even step (read and written in place), the neighbour table, the moment
+// slots and phi written for the next kernel. On a domain far larger than the caches, marking
+// those accesses non-temporal lets the L2 give their lines up first, which keeps resident the
+// lines that neighbouring voxels re-read within the launch (phi in the collide kernel, the
+// moment slots in the phase kernel). On a domain that fits the 256 MB Infinity Cache (and in
+// pools, whose members run in cache-sized groups) the same hint costs the reuse from one step
+// to the next, so it is a launch option (lbm_tuning). The odd step's populations stay ordinary
+// accesses either way: they land one neighbour away, so a cache line is shared between adjacent
+// waves and must be merged in the L2.
+template <bool STREAM, typename T>
+__device__ __forceinline__ T load_once(const T* p) {
+    if (STREAM) return __builtin_nontemporal_load(p);
+    return *p;
 }
 
-template <typename T>
-__device__ __forceinline__ void store_stream(T v, T* p) {
-    __builtin_nontemporal_store(v, p);
+template <bool STREAM, typename T>
+__device__ __forceinline__ void store_once(T v, T* p) {
+    if (STREAM) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 template <typename S>
@@ -146,14 +151,14 @@ __device__ __forceinline__ typename PairOf<S>::T load_pair(const S* __restrict__
     return reinterpret_cast<const typename PairOf<S>::T*>(M)[(size_t)k * ld + y];
 }
 
-// One 16-byte (FP64) or 8-byte (FP32) streaming store of a pair of slots.
-template <typename S>
+// One 16-byte (FP64) or 8-byte (FP32) store of a pair of slots.
+template <typename S, bool STREAM = false>
 __device__ __forceinline__ void store_pair(S* __restrict__ M, size_t ld, int k, int i, S x, S y) {
     typedef S Vec2 __attribute__((ext_vector_type(2)));
     Vec2 v;
     v.x = x;
     v.y = y;
-    store_stream(v, reinterpret_cast<Vec2*>(M) + ((size_t)k * ld + i));
+    store_once<STREAM>(v, reinterpret_cast<Vec2*>(M) + ((size_t)k * ld + i));
 }
 
 // Neighbour lookup, fixed at compile time for the single-domain step kernels and chosen per
@@ -196,7 +201,7 @@ struct Pos {
 // pore voxels (tiles of a multiple of 64 starting at a multiple of 64), so the record's address
 // is wave-uniform: it is read with scalar loads and the exception test is one scalar branch.
 // Directions a kernel never asks for are dead code (the phase kernel reads only the axis record).
-template <bool WAVE>
+template <bool WAVE, bool STREAM>
 __device__ __forceinline__ void compact_all(const StepArgs& a, int i, int (&cn)[18]) {
     const int w = WAVE ? __builtin_amdgcn_readfirstlane(i >> 6) : (i >> 6);
     const auto* rec = as_const(a.cwave) + (size_t)w * kCompactWaveInts;
@@ -204,14 +209,14 @@ __device__ __forceinline__ void compact_all(const StepArgs& a, int i, int (&cn)[
     if (row >= 0) {
         const int32_t* ex = a.cex + (size_t)row * 18 * 64 + (i & 63);
 #pragma unroll
-        for (int q = 1; q < 19; ++q) cn[q - 1] = load_stream(ex + (q - 1) * 64);
+        for (int q = 1; q < 19; ++q) cn[q - 1] = load_once<STREAM>(ex + (q - 1) * 64);
         return;
     }
     typedef uint32_t U4 __attribute__((ext_vector_type(4)));
     typedef uint32_t U2 __attribute__((ext_vector_type(2)));
-    const U4 ax = load_stream(reinterpret_cast<const U4*>(a.cax) + i);
-    const U4 d4 = load_stream(reinterpret_cast<const U4*>(a.cdg4) + i);
-    const U2 d2 = load_stream(reinterpret_cast<const U2*>(a.cdg2) + i);
+    const U4 ax = load_once<STREAM>(reinterpret_cast<const U4*>(a.cax) + i);
+    const U4 d4 = load_once<STREAM>(reinterpret_cast<const U4*>(a.cdg4) + i);
+    const U2 d2 = load_once<STREAM>(reinterpret_cast<const U2*>(a.cdg2) + i);
     const uint32_t words[9] = {ax.y, ax.z, ax.w, d4.x, d4.y, d4.z, d4.w, d2.x, d2.y};
 #pragma unroll
     for (int q = 1; q < 19; ++q) {
@@ -226,12 +231,12 @@ __device__ __forceinline__ void compact_all(const StepArgs& a, int i, int (&cn)[
 }
 
 // Per-voxel lookup state of pore voxel i (see Pos).
-template <int NB = NB_DYN, bool WAVE = false>
+template <int NB = NB_DYN, bool WAVE = false, bool STREAM = false>
 __device__ __forceinline__ Pos pos_of(const StepArgs& a, int i) {
     Pos p;
     p.x = p.y = p.z = 0;
     if (use_compact<NB>(a)) {
-        compact_all<WAVE>(a, i, p.cn);
+        compact_all<WAVE, STREAM>(a, i, p.cn);
         return p;
     }
     if (!use_rank<NB>(a)) return p;
@@ -257,13 +262,13 @@ __device__ __forceinline__ int rank_index(const StepArgs& a, int x, int y, int z
 // beyond a pressure face in the rank lookup: its phi is the in-plane voxel's, but streaming
 // bounces back there (stream index N). With the explicit table, such neighbours are tail
 // ghosts, already >= N.
-template <int NB = NB_DYN>
+template <int NB = NB_DYN, bool STREAM = false>
 __device__ __forceinline__ int nb(const StepArgs& a, int q, int i, Pos p, bool& mirror) {
     mirror = false;
     if (use_table<NB>(a)) {
         // Opposite directions (q, q + 1 for odd q) share one 8-byte entry.
         const int64_t e =
-            load_stream(reinterpret_cast<const int64_t*>(a.nbr) + ((size_t)((q - 1) >> 1) * a.ld + i));
+            load_once<STREAM>(reinterpret_cast<const int64_t*>(a.nbr) + ((size_t)((q - 1) >> 1) * a.ld + i));
         return (q & 1) ? (int)(uint32_t)e : (int)(e >> 32);
     }
     if (use_compact<NB>(a)) return p.cn[q - 1];
@@ -290,29 +295,29 @@ __device__ __forceinline__ int nb(const StepArgs& a, int q, int i, Pos p, bool& 
 }
 
 // Streaming neighbour of pore voxel i along q: a pore index, or >= N for a wall (bounce-back).
-template <int NB = NB_DYN>
+template <int NB = NB_DYN, bool STREAM = false>
 __device__ __forceinline__ int nb_stream(const StepArgs& a, int q, int i, Pos p) {
     bool mirror;
-    const int r = nb<NB>(a, q, i, p, mirror);
+    const int r = nb<NB, STREAM>(a, q, i, p, mirror);
     return mirror ? a.N : r;
 }
 
 // Incoming population q of voxel i (D3Q19 or D3Q7 array X).
-template <bool ODD, typename S>
+template <bool ODD, typename S, bool STREAM = false>
 __device__ __forceinline__ S load_in(const S* __restrict__ X, const StepArgs& a, int q, int i,
                                      int r_up) {
-    if (!ODD) return load_stream(&X[(size_t)q * a.ld + i]);
+    if (!ODD) return load_once<STREAM>(&X[(size_t)q * a.ld + i]);
     if (q == 0) return X[i];
     // r_up: neighbour along opp(q), i.e. the upstream voxel i - xi_q.
     return r_up < a.N ? X[(size_t)OPP[q] * a.ld + r_up] : X[(size_t)q * a.ld + i];
 }
 
 // Store the post-collision population q of voxel i.
-template <bool ODD, typename S>
+template <bool ODD, typename S, bool STREAM = false>
 __device__ __forceinline__ void store_out(S* __restrict__ X, const StepArgs& a, int q, int i,
                                           int r_down, S v) {
     if (!ODD) {
-        store_stream(v, &X[(size_t)OPP[q] * a.ld + i]);
+        store_once<STREAM>(v, &X[(size_t)OPP[q] * a.ld + i]);
     } else if (q == 0) {
         X[i] = v;
     } else {
@@ -380,7 +385,8 @@ __device__ __forceinline__ void out_ab(const S* __restrict__ M, int64_t ld, int 
 // All six neighbour indices are read first and every slot load is unconditional (a solid
 // upstream neighbour selects the voxel's own slots and flips the sign), so the loads of one
 // voxel are in flight together.
-template <int PREC, int NB = NB_DYN>
+// Callers keep each wave on 64 consecutive pore voxels (see compact_all).
+template <int PREC, int NB = NB_DYN, bool STREAM = false>
 __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, double& na,
                                           double& nbv) {
     using P = Prec<PREC>;
@@ -408,10 +414,10 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
         }
         return;
     }
-    const Pos pos = pos_of<NB, true>(a, i);
+    const Pos pos = pos_of<NB, true, STREAM>(a, i);
     int up[7];
 #pragma unroll
-    for (int q = 1; q < 7; ++q) up[q] = nb_stream<NB>(a, OPP[q], i, pos);  // voxel i - xi_q
+    for (int q = 1; q < 7; ++q) up[q] = nb_stream<NB, STREAM>(a, OPP[q], i, pos);  // i - xi_q
     if (a.face) {
         const int fc = a.face[i];
         if (fc) {
@@ -475,27 +481,27 @@ __device__ __forceinline__ void densities(const StepArgs& a, int i, bool fresh, 
 // Densities and phase indicator: N_a = sum_q A_q, N_b = sum_q B_q (q = 0..6) of the streamed-in
 // D3Q7 populations; phi = (N_a - N_b)/(N_a + N_b); N = N_a + N_b.
 // ------------------------------------------------------------------------------------------
-template <int PREC, int NB = NB_DYN>
+template <int PREC, int NB = NB_DYN, bool STREAM = false>
 __device__ __forceinline__ void phase_voxel(const StepArgs& a, int i, bool fresh) {
     using S = typename Prec<PREC>::S;
     double na, nbv;
-    densities<PREC, NB>(a, i, fresh, na, nbv);
+    densities<PREC, NB, STREAM>(a, i, fresh, na, nbv);
     const double nt = na + nbv;
-    store_stream((S)((na - nbv) / nt), (S*)a.phi + i);
-    store_stream((S)nt, (S*)a.ntot + i);
+    store_once<STREAM>((S)((na - nbv) / nt), (S*)a.phi + i);
+    store_once<STREAM>((S)nt, (S*)a.ntot + i);
 }
 
-template <int PREC, bool ODD, int NB>
+template <int PREC, bool ODD, int NB, bool STREAM>
 __global__ void __launch_bounds__(256) phase_kernel(StepArgs a) {
     const int i = logical_block(a) * blockDim.x + threadIdx.x;
-    if (i < a.N) phase_voxel<PREC, NB>(a, i, *a.fresh != 0);
+    if (i < a.N) phase_voxel<PREC, NB, STREAM>(a, i, *a.fresh != 0);
 }
 
 // ------------------------------------------------------------------------------------------
 // Fused colour gradient + MRT collision with interfacial terms and body force + recolouring +
 // AA streaming.
 // ------------------------------------------------------------------------------------------
-template <int PREC, bool ODD, int NB = NB_DYN>
+template <int PREC, bool ODD, int NB = NB_DYN, bool STREAM = false>
 __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     using P = Prec<PREC>;
     using F = typename P::F;
@@ -507,11 +513,11 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     uint32_t mirror = 0; // bit q: streaming along q bounces back although r[q] is a pore index
     r[0] = i;
     {
-        const Pos pos = pos_of<NB, true>(a, i);
+        const Pos pos = pos_of<NB, true, STREAM>(a, i);
 #pragma unroll
         for (int q = 1; q < 19; ++q) {
             bool m;
-            r[q] = nb<NB>(a, q, i, pos, m);
+            r[q] = nb<NB, STREAM>(a, q, i, pos, m);
             mirror |= (m ? 1u : 0u) << q;
         }
     }
@@ -545,7 +551,7 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     // Incoming populations (f, or f - t in deviation storage).
     R fl[19];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) fl[q] = (R)load_in<ODD>(f, a, q, i, RS(OPP[q]));
+    for (int q = 0; q < 19; ++q) fl[q] = (R)load_in<ODD, F, STREAM>(f, a, q, i, RS(OPP[q]));
 
     // rho (or rho - 1 in deviation storage) and j.
     R rho = 0, jx = 0, jy = 0, jz = 0;
@@ -570,10 +576,10 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     const R seg = (R)a.beta * na * nbv / nt;
     S* M = (S*)a.M;
     const size_t ld = (size_t)a.ld;
-    store_pair<S>(M, ld, 0, i, (S)na, (S)nbv);
-    store_pair<S>(M, ld, 1, i, (S)ux, (S)(seg * nx));
-    store_pair<S>(M, ld, 2, i, (S)uy, (S)(seg * ny));
-    store_pair<S>(M, ld, 3, i, (S)uz, (S)(seg * nz));
+    store_pair<S, STREAM>(M, ld, 0, i, (S)na, (S)nbv);
+    store_pair<S, STREAM>(M, ld, 1, i, (S)ux, (S)(seg * nx));
+    store_pair<S, STREAM>(M, ld, 2, i, (S)uy, (S)(seg * ny));
+    store_pair<S, STREAM>(M, ld, 3, i, (S)uz, (S)(seg * nz));
 
     const R nu = (R)0.5 * ((R)1 + phi_i) * (R)a.nu_a + (R)0.5 * ((R)1 - phi_i) * (R)a.nu_b;
     const R sp = (R)1 / ((R)3 * nu + (R)0.5);
@@ -626,15 +632,15 @@ __device__ __forceinline__ void collide_voxel(const StepArgs& a, int i) {
     }
 
 #pragma unroll
-    for (int q = 0; q < 19; ++q) store_out<ODD>(f, a, q, i, RS(q), (F)fs[q]);
+    for (int q = 0; q < 19; ++q) store_out<ODD, F, STREAM>(f, a, q, i, RS(q), (F)fs[q]);
 #undef RS
     if (i == 0) *a.fresh = 0;        // the state now holds outgoing moments
 }
 
-template <int PREC, bool ODD, int NB>
+template <int PREC, bool ODD, int NB, bool STREAM>
 __global__ void __launch_bounds__(256) collide_kernel(StepArgs a) {
     const int i = logical_block(a) * blockDim.x + threadIdx.x;
-    if (i < a.N) collide_voxel<PREC, ODD, NB>(a, i);
+    if (i < a.N) collide_voxel<PREC, ODD, NB, STREAM>(a, i);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -700,7 +706,7 @@ __device__ __forceinline__ void voxel_state(const StepArgs& a, int i, double& na
     const Pos pos = pos_of(a, i);
 #pragma unroll
     for (int q = 1; q < 19; ++q) r[q] = ODD ? nb_stream(a, q, i, pos) : 0;
-    densities<PREC>(a, i, *a.fresh != 0, na, nbv);
+    densities<PREC>(a, i, *a.fresh != 0, na, nbv);   // field and reduction kernels: waves aligned
     rho = 0.0;
     jx = jy = jz = 0.0;
 #pragma unroll
@@ -998,6 +1004,19 @@ dim3 step_grid(const StepArgs& a) {
             hipLaunchKernelGGL((KERNEL<P, false, NBV>), GRID, BLOCK, 0, s, __VA_ARGS__);       \
     } while (0)
 
+#define LBM_LAUNCH_ODD_NB_ST(KERNEL, P, NBV, GRID, BLOCK, ...)                                 \
+    do {                                                                                       \
+        if (odd && stream)                                                                     \
+            hipLaunchKernelGGL((KERNEL<P, true, NBV, true>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
+        else if (odd)                                                                          \
+            hipLaunchKernelGGL((KERNEL<P, true, NBV, false>), GRID, BLOCK, 0, s, __VA_ARGS__); \
+        else if (stream)                                                                       \
+            hipLaunchKernelGGL((KERNEL<P, false, NBV, true>), GRID, BLOCK, 0, s, __VA_ARGS__); \
+        else                                                                                   \
+            hipLaunchKernelGGL((KERNEL<P, false, NBV, false>), GRID, BLOCK, 0, s,              \
+                               __VA_ARGS__);                                                   \
+    } while (0)
+
 #define LBM_PREC_SWITCH(PREC, LAUNCH, KERNEL, ...)                                             \
     do {                                                                                       \
         if ((PREC) == LBM_FP32_DEV)                                                            \
@@ -1011,8 +1030,8 @@ dim3 step_grid(const StepArgs& a) {
 #define LBM_DISPATCH(KERNEL, GRID, BLOCK, ...)                                                 \
     LBM_PREC_SWITCH(a.prec, LBM_LAUNCH_ODD, KERNEL, GRID, BLOCK, __VA_ARGS__)
 
-#define LBM_DISPATCH_NB(KERNEL, GRID, BLOCK, ...)                                              \
-    LBM_PREC_SWITCH(a.prec, LBM_LAUNCH_ODD_NB, KERNEL, NB, GRID, BLOCK, __VA_ARGS__)
+#define LBM_DISPATCH_NB_ST(KERNEL, GRID, BLOCK, ...)                                           \
+    LBM_PREC_SWITCH(a.prec, LBM_LAUNCH_ODD_NB_ST, KERNEL, NB, GRID, BLOCK, __VA_ARGS__)
 
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s) {
     (void)block;
@@ -1028,29 +1047,30 @@ hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStre
     return hipGetLastError();
 }
 
-// Step kernels: also on the neighbour lookup, fixed per domain.
+// Step kernels: also on the neighbour lookup, fixed per domain, and on streaming accesses.
 template <int NB>
-hipError_t launch_phase_nb(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    LBM_DISPATCH_NB(phase_kernel, step_grid(a), dim3(block), a);
+hipError_t launch_phase_nb(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s) {
+    LBM_DISPATCH_NB_ST(phase_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
 }
 
 template <int NB>
-hipError_t launch_collide_nb(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    LBM_DISPATCH_NB(collide_kernel, step_grid(a), dim3(block), a);
+hipError_t launch_collide_nb(const StepArgs& a, bool odd, int block, bool stream,
+                             hipStream_t s) {
+    LBM_DISPATCH_NB_ST(collide_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
 }
 
-hipError_t launch_phase(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    return a.words ? launch_phase_nb<NB_RANK>(a, odd, block, s)
-           : a.cax ? launch_phase_nb<NB_COMPACT>(a, odd, block, s)
-                   : launch_phase_nb<NB_TABLE>(a, odd, block, s);
+hipError_t launch_phase(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s) {
+    return a.words ? launch_phase_nb<NB_RANK>(a, odd, block, stream, s)
+           : a.cax ? launch_phase_nb<NB_COMPACT>(a, odd, block, stream, s)
+                   : launch_phase_nb<NB_TABLE>(a, odd, block, stream, s);
 }
 
-hipError_t launch_collide(const StepArgs& a, bool odd, int block, hipStream_t s) {
-    return a.words ? launch_collide_nb<NB_RANK>(a, odd, block, s)
-           : a.cax ? launch_collide_nb<NB_COMPACT>(a, odd, block, s)
-                   : launch_collide_nb<NB_TABLE>(a, odd, block, s);
+hipError_t launch_collide(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s) {
+    return a.words ? launch_collide_nb<NB_RANK>(a, odd, block, stream, s)
+           : a.cax ? launch_collide_nb<NB_COMPACT>(a, odd, block, stream, s)
+                   : launch_collide_nb<NB_TABLE>(a, odd, block, stream, s);
 }
 
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,

@@ -96,13 +96,13 @@ lbm_status launch_step(lbm_domain* d, bool odd, Mark mark) {
     const StepArgs ap = d->args(tu.phase_block, tu.phase_schedule);
     const StepArgs ac = d->args(tu.collide_block, tu.collide_schedule);
     if (lbm_status s = mark(0, true)) return s;
-    HIP_TRY(launch_phase(ap, odd, tu.phase_block, d->stream));
+    HIP_TRY(launch_phase(ap, odd, tu.phase_block, tu.phase_stream != 0, d->stream));
     if (!d->rank && !d->pre.ghost_tail.empty())
         HIP_TRY(launch_ghosts(ap, d->ghost_tail, d->ghost_src, (int32_t)d->pre.ghost_tail.size(),
                               d->stream));
     if (lbm_status s = mark(0, false)) return s;
     if (lbm_status s = mark(1, true)) return s;
-    HIP_TRY(launch_collide(ac, odd, tu.collide_block, d->stream));
+    HIP_TRY(launch_collide(ac, odd, tu.collide_block, tu.collide_stream != 0, d->stream));
     if (lbm_status s = mark(1, false)) return s;
     if (d->p.bc_z == 1) {
         if (lbm_status s = mark(2, true)) return s;
@@ -478,6 +478,8 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         d->release();
         return fail(LBM_ERR_DEVICE, "internal: device footprint estimate out of date");
     }
+    // Streaming accesses only for domains well beyond the Infinity Cache.
+    d->tune.phase_stream = d->tune.collide_stream = d->device_bytes > kStreamBytes ? 1 : 0;
     *out = d.release();
     return LBM_OK;
 }
@@ -702,13 +704,15 @@ lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out) {
 static bool tuning_ok(const lbm_tuning& t) {
     auto blk = [](int b) { return b == 64 || b == 128 || b == 256; };
     auto sch = [](int v) { return v >= 1 && v <= 3; };
+    auto flag = [](int v) { return v == 0 || v == 1; };
     return blk(t.phase_block) && blk(t.collide_block) && sch(t.phase_schedule) &&
-           sch(t.collide_schedule);
+           sch(t.collide_schedule) && flag(t.phase_stream) && flag(t.collide_stream);
 }
 
 lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t) {
     if (lbm_status s = check_domain(d)) return s;
-    if (!t || !tuning_ok(*t)) return fail(LBM_ERR_ARG, "unsupported block or schedule");
+    if (!t || !tuning_ok(*t))
+        return fail(LBM_ERR_ARG, "unsupported block, schedule or stream flag");
     HIP_TRY(hipStreamSynchronize(d->stream));
     d->drop_step_graph();
     d->tune = *t;
@@ -756,15 +760,18 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     d->record_history = false;
     const int blocks[3] = {64, 128, 256};
     for (int kernel = 0; kernel < 2 && st == LBM_OK && he == hipSuccess; ++kernel) {
-        for (int bi = 0; bi < 3 && st == LBM_OK; ++bi) {
-            for (int sched = 1; sched <= 3 && st == LBM_OK; ++sched) {
+        for (int cand = 0; cand < 18 && st == LBM_OK; ++cand) {
+            const int bi = cand % 3, sched = 1 + (cand / 3) % 3, stream = cand / 9;
+            {
                 lbm_tuning t = best;
                 if (kernel == 0) {
                     t.phase_block = blocks[bi];
                     t.phase_schedule = sched;
+                    t.phase_stream = stream;
                 } else {
                     t.collide_block = blocks[bi];
                     t.collide_schedule = sched;
+                    t.collide_stream = stream;
                 }
                 d->tune = t;
                 lbm_timing tm;

@@ -106,21 +106,31 @@ def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
     dom.close()
 
 
-def test_block_size_and_launch_shape_do_not_change_results(lbm):
-    """Block sizes, and the three tile orders (launch order, XCD-aware runs, XCD-aware runs from
-    the end of the pore list) in every pairing of the two kernels, give the same state."""
+@pytest.mark.parametrize("mode", ["table", "rank", "compact"])
+def test_block_size_and_launch_shape_do_not_change_results(lbm, mode):
+    """Block sizes, the three tile orders (launch order, XCD-aware runs, XCD-aware runs from the
+    end of the pore list) in every pairing of the two kernels, and streaming (non-temporal)
+    accesses on or off in either kernel give the same state, with each neighbour lookup. A
+    small domain starts without streaming; its flags are valid only as 0 or 1."""
     prob = _random_problem((17, 18, 19), (True, True, True), seed=5)
+    nm = _nm(lbm, mode)
     outs = []
     for block in (64, 128, 256):
-        dom = lbm.Domain(prob, block_size=block)
+        dom = lbm.Domain(prob, block_size=block, neighbour_mode=nm)
+        t = dom.tuning()
+        assert t["phase_stream"] == 0 and t["collide_stream"] == 0
         dom.step(25)
         outs.append(dom.save())
         dom.close()
-    for ps, cs in ((1, 3), (3, 2), (3, 3), (2, 1)):
-        dom = lbm.Domain(prob)
-        dom.set_tuning(phase_block=128, phase_schedule=ps, collide_block=64, collide_schedule=cs)
-        dom.step(25)
+    for ps, cs, pst, cst in ((1, 3, 1, 1), (3, 2, 0, 1), (3, 3, 1, 0), (2, 1, 1, 1)):
+        dom = lbm.Domain(prob, neighbour_mode=nm)
+        dom.set_tuning(phase_block=128, phase_schedule=ps, collide_block=64, collide_schedule=cs,
+                       phase_stream=pst, collide_stream=cst)
+        dom.step(12)
+        dom.step(13)
         outs.append(dom.save())
+        with pytest.raises(lbm.LbmError):
+            dom.set_tuning(collide_stream=2)
         dom.close()
     assert all(o == outs[0] for o in outs)
 
@@ -384,6 +394,7 @@ def test_autotune_restores_state_and_keeps_results(lbm, precision):
     before = dom.save()
     t = dom.autotune(4)
     assert t["phase_block"] in (64, 128, 256) and t["collide_schedule"] in (1, 2, 3)
+    assert t["phase_stream"] in (0, 1) and t["collide_stream"] in (0, 1)
     assert t["phase_ms"] > 0 and t["collide_ms"] > 0
     assert dom.info()["step"] == 7 and dom.save() == before
     dom.step(13)
