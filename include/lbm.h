@@ -340,9 +340,9 @@ lbm_status lbm_state_load(lbm_domain* d, const void* host_buf, size_t nbytes);
 lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out);
 
 /* Autotuner: times every (block, schedule, stream) candidate of each step kernel over
- * trial_steps >= 2 steps on this domain, applies the fastest, and writes it to *out (nullable). The state, step
- * counter and reduction history are restored afterwards, so the results of later steps are
- * unchanged. Synchronises; needs device memory for one copy of the populations (LBM_ERR_OOM
+ * trial_steps >= 2 steps on this domain, applies the fastest, and writes it to *out (nullable).
+ * The state, step counter and reduction history are restored afterwards, so the results of later
+ * steps are unchanged. Synchronises; needs device memory for one copy of the populations (LBM_ERR_OOM
  * otherwise). */
 lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out);
 

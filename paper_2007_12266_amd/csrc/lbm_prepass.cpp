@@ -381,7 +381,8 @@ std::string build_compact_lookup(Prepass& pre) {
                     if (t < n) { plo = std::min(plo, t); phi = std::max(phi, t); }
                     else { tlo = std::min(tlo, t); thi = std::max(thi, t); }
                 }
-                if ((phi >= 0 && phi - plo > 0xffff) || (thi >= 0 && thi - tlo > 0xffff)) fits = false;
+                if ((phi >= 0 && phi - plo > 0xffff) || (thi >= 0 && thi - tlo > 0xffff))
+                    fits = false;
                 rec[q - 1] = phi >= 0 ? (int32_t)plo : 0;
                 rec[18 + q - 1] = thi >= 0 ? (int32_t)tlo : (int32_t)n;
             }
