@@ -578,8 +578,8 @@ def main():
                          "16-bit codes above per-wave bases")
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape PHASE_BLOCK,PHASE_SCHEDULE,COLLIDE_BLOCK,"
-                         "COLLIDE_SCHEDULE[,PHASE_STREAM,COLLIDE_STREAM] instead of the "
-                         "autotuner (profiled runs)")
+                         "COLLIDE_SCHEDULE[,PHASE_STREAM,COLLIDE_STREAM[,PHASE_WG,COLLIDE_WG]] "
+                         "instead of the autotuner (profiled runs)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of autotuning them")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -652,7 +652,7 @@ def main():
     if args.tuning:
         vals = [int(v) for v in args.tuning.split(",")]
         keys = ["phase_block", "phase_schedule", "collide_block", "collide_schedule",
-                "phase_stream", "collide_stream"][:len(vals)]
+                "phase_stream", "collide_stream", "phase_wg", "collide_wg"][:len(vals)]
         dom.set_tuning(**dict(zip(keys, vals)))
         tuning = {k: v for k, v in dom.tuning().items() if not k.endswith("_ms")}
         tuning["fixed"] = True

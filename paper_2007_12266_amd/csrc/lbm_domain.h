@@ -39,7 +39,8 @@ struct lbm_domain {
     lbm_params p{};
     lbm::Prepass pre;
     int block = 256;                 // read-back and init kernels
-    lbm_tuning tune{256, 2, 256, 2, 0, 0, 0.0, 0.0};
+    lbm_tuning tune{256, 2, 256, 2, 0, 0, 0, 0, 0.0, 0.0};
+    unsigned lds[2] = {0, 0};        // dynamic LDS of the phase / collide launches (tune.*_wg)
     lbm_allocator alloc{};
     bool has_alloc = false;
     hipStream_t stream = nullptr;

@@ -69,6 +69,9 @@ constexpr int64_t kStepGraphChunk = 64;
 // holds from one step to the next keeps that reuse.
 constexpr int64_t kStreamBytes = int64_t(512) << 20;
 
+// Largest per-CU workgroup limit a launch configuration may ask for (lbm_tuning.*_wg).
+constexpr int kMaxWgPerCu = 16;
+
 struct BatchArgs {
     const StepArgs* doms;       // per-slot kernel arguments (N = 0 for an empty slot)
     const int32_t* tile_dom;    // slot of each tile
@@ -79,8 +82,13 @@ struct BatchArgs {
 
 // Kernel launchers (lbm_kernels.hip). `odd` is the parity of the step being taken.
 hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStream_t s);
-hipError_t launch_phase(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s);
-hipError_t launch_collide(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s);
+hipError_t launch_phase(const StepArgs& a, bool odd, int block, bool stream, unsigned lds,
+                        hipStream_t s);
+hipError_t launch_collide(const StepArgs& a, bool odd, int block, bool stream, unsigned lds,
+                          hipStream_t s);
+// Dynamic LDS that bounds a step kernel (0: phase, 1: collide) to `wg` workgroups per CU.
+hipError_t step_kernel_lds(const StepArgs& a, int kernel, int block, bool stream, int wg,
+                           unsigned* lds);
 hipError_t launch_ghosts(const StepArgs& a, const int32_t* ghost_tail, const int32_t* ghost_src,
                          int32_t n, hipStream_t s);
 // faces: inlet pore indices (n_in) followed by outlet ones (n_out); next_odd: parity of the

@@ -56,6 +56,7 @@
 //    for q and opp(q)), so the same formulas serve all three.
 //  * No MFMA: nothing here is a dense contraction. The kernel is bound by HBM traffic.
 
+#include <algorithm>
 #include <cmath>
 
 #include "lbm_internal.h"
@@ -1004,16 +1005,21 @@ dim3 step_grid(const StepArgs& a) {
             hipLaunchKernelGGL((KERNEL<P, false, NBV>), GRID, BLOCK, 0, s, __VA_ARGS__);       \
     } while (0)
 
+// `lds`: dynamic LDS per workgroup, which the step kernels do not use; it only bounds how many
+// workgroups a CU holds at once (see step_kernel_lds).
 #define LBM_LAUNCH_ODD_NB_ST(KERNEL, P, NBV, GRID, BLOCK, ...)                                 \
     do {                                                                                       \
         if (odd && stream)                                                                     \
-            hipLaunchKernelGGL((KERNEL<P, true, NBV, true>), GRID, BLOCK, 0, s, __VA_ARGS__);  \
+            hipLaunchKernelGGL((KERNEL<P, true, NBV, true>), GRID, BLOCK, lds, s,              \
+                               __VA_ARGS__);                                                   \
         else if (odd)                                                                          \
-            hipLaunchKernelGGL((KERNEL<P, true, NBV, false>), GRID, BLOCK, 0, s, __VA_ARGS__); \
+            hipLaunchKernelGGL((KERNEL<P, true, NBV, false>), GRID, BLOCK, lds, s,             \
+                               __VA_ARGS__);                                                   \
         else if (stream)                                                                       \
-            hipLaunchKernelGGL((KERNEL<P, false, NBV, true>), GRID, BLOCK, 0, s, __VA_ARGS__); \
+            hipLaunchKernelGGL((KERNEL<P, false, NBV, true>), GRID, BLOCK, lds, s,             \
+                               __VA_ARGS__);                                                   \
         else                                                                                   \
-            hipLaunchKernelGGL((KERNEL<P, false, NBV, false>), GRID, BLOCK, 0, s,              \
+            hipLaunchKernelGGL((KERNEL<P, false, NBV, false>), GRID, BLOCK, lds, s,            \
                                __VA_ARGS__);                                                   \
     } while (0)
 
@@ -1049,28 +1055,99 @@ hipError_t launch_init(const StepArgs& a, const double* phi0, int block, hipStre
 
 // Step kernels: also on the neighbour lookup, fixed per domain, and on streaming accesses.
 template <int NB>
-hipError_t launch_phase_nb(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s) {
+hipError_t launch_phase_nb(const StepArgs& a, bool odd, int block, bool stream, unsigned lds,
+                           hipStream_t s) {
     LBM_DISPATCH_NB_ST(phase_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
 }
 
 template <int NB>
-hipError_t launch_collide_nb(const StepArgs& a, bool odd, int block, bool stream,
+hipError_t launch_collide_nb(const StepArgs& a, bool odd, int block, bool stream, unsigned lds,
                              hipStream_t s) {
     LBM_DISPATCH_NB_ST(collide_kernel, step_grid(a), dim3(block), a);
     return hipGetLastError();
 }
 
-hipError_t launch_phase(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s) {
-    return a.words ? launch_phase_nb<NB_RANK>(a, odd, block, stream, s)
-           : a.cax ? launch_phase_nb<NB_COMPACT>(a, odd, block, stream, s)
-                   : launch_phase_nb<NB_TABLE>(a, odd, block, stream, s);
+hipError_t launch_phase(const StepArgs& a, bool odd, int block, bool stream, unsigned lds,
+                        hipStream_t s) {
+    return a.words ? launch_phase_nb<NB_RANK>(a, odd, block, stream, lds, s)
+           : a.cax ? launch_phase_nb<NB_COMPACT>(a, odd, block, stream, lds, s)
+                   : launch_phase_nb<NB_TABLE>(a, odd, block, stream, lds, s);
 }
 
-hipError_t launch_collide(const StepArgs& a, bool odd, int block, bool stream, hipStream_t s) {
-    return a.words ? launch_collide_nb<NB_RANK>(a, odd, block, stream, s)
-           : a.cax ? launch_collide_nb<NB_COMPACT>(a, odd, block, stream, s)
-                   : launch_collide_nb<NB_TABLE>(a, odd, block, stream, s);
+hipError_t launch_collide(const StepArgs& a, bool odd, int block, bool stream, unsigned lds,
+                          hipStream_t s) {
+    return a.words ? launch_collide_nb<NB_RANK>(a, odd, block, stream, lds, s)
+           : a.cax ? launch_collide_nb<NB_COMPACT>(a, odd, block, stream, lds, s)
+                   : launch_collide_nb<NB_TABLE>(a, odd, block, stream, lds, s);
+}
+
+// The step kernel (0: phase, 1: collide) that launch_phase / launch_collide would run.
+template <int P, int NB, bool ST>
+static const void* step_kernel_fn(int kernel, bool odd) {
+    if (kernel == 0)
+        return odd ? (const void*)phase_kernel<P, true, NB, ST>
+                   : (const void*)phase_kernel<P, false, NB, ST>;
+    return odd ? (const void*)collide_kernel<P, true, NB, ST>
+               : (const void*)collide_kernel<P, false, NB, ST>;
+}
+
+template <int P, bool ST>
+static const void* step_kernel_fn_nb(const StepArgs& a, int kernel, bool odd) {
+    return a.words ? step_kernel_fn<P, NB_RANK, ST>(kernel, odd)
+           : a.cax ? step_kernel_fn<P, NB_COMPACT, ST>(kernel, odd)
+                   : step_kernel_fn<P, NB_TABLE, ST>(kernel, odd);
+}
+
+template <bool ST>
+static const void* step_kernel_fn_prec(const StepArgs& a, int kernel, bool odd) {
+    if (a.prec == LBM_FP32_DEV) return step_kernel_fn_nb<LBM_FP32_DEV, ST>(a, kernel, odd);
+    if (a.prec == LBM_FP32_MIXED) return step_kernel_fn_nb<LBM_FP32_MIXED, ST>(a, kernel, odd);
+    return step_kernel_fn_nb<LBM_FP64, ST>(a, kernel, odd);
+}
+
+// Occupancy limit. Fewer resident waves can be faster for these kernels: their in-flight
+// working set (a wave's gathers, the partially written lines of the odd step) competes for the
+// 4 MB L2 of an XCD, and past some occupancy the lines neighbouring voxels share are evicted
+// before they are reused. The hardware holds a workgroup only where its LDS fits, so reserving
+// LDS that the kernel never touches bounds the workgroups per CU. The smallest such reservation
+// (in 256-byte steps) that keeps both parities of the kernel at or below `wg` workgroups per CU
+// is found with the runtime's occupancy calculator; 0 where the registers already allow no
+// more, or for wg == 0 (no limit).
+hipError_t step_kernel_lds(const StepArgs& a, int kernel, int block, bool stream, int wg,
+                           unsigned* lds) {
+    *lds = 0;
+    if (wg <= 0) return hipSuccess;
+    int dev = 0, max_lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    unsigned need = 0;
+    for (int odd = 0; odd < 2; ++odd) {
+        const void* fn = stream ? step_kernel_fn_prec<true>(a, kernel, odd != 0)
+                                : step_kernel_fn_prec<false>(a, kernel, odd != 0);
+        auto blocks = [&](unsigned bytes, int* n) {
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, fn, block, bytes);
+        };
+        int n = 0;
+        if ((e = blocks(0, &n)) != hipSuccess) return e;
+        if (n <= wg) continue;
+        unsigned lo = 0, hi = (unsigned)max_lds & ~255u;   // blocks(lo) > wg
+        if ((e = blocks(hi, &n)) != hipSuccess) return e;
+        if (n > wg) {   // even the largest reservation cannot bound it this far
+            need = std::max(need, hi);
+            continue;
+        }
+        while (hi - lo > 256) {
+            const unsigned mid = ((lo + hi) / 2) & ~255u;
+            if ((e = blocks(mid, &n)) != hipSuccess) return e;
+            (n <= wg ? hi : lo) = mid;
+        }
+        need = std::max(need, hi);
+    }
+    *lds = need;
+    return hipSuccess;
 }
 
 hipError_t launch_reduce(const StepArgs& a, bool odd, double* partials, double* out,

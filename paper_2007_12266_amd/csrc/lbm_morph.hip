@@ -172,7 +172,8 @@ lbm_status ensure_buffers(lbm_domain* d) {
 lbm_status current_phase(lbm_domain* d) {
     const lbm_tuning& tu = d->tune;
     const StepArgs a = d->args(tu.phase_block, tu.phase_schedule);
-    HIP_TRY(launch_phase(a, (d->step & 1) != 0, tu.phase_block, tu.phase_stream != 0, d->stream));
+    HIP_TRY(launch_phase(a, (d->step & 1) != 0, tu.phase_block, tu.phase_stream != 0, d->lds[0],
+                         d->stream));
     return LBM_OK;
 }
 

@@ -96,13 +96,14 @@ lbm_status launch_step(lbm_domain* d, bool odd, Mark mark) {
     const StepArgs ap = d->args(tu.phase_block, tu.phase_schedule);
     const StepArgs ac = d->args(tu.collide_block, tu.collide_schedule);
     if (lbm_status s = mark(0, true)) return s;
-    HIP_TRY(launch_phase(ap, odd, tu.phase_block, tu.phase_stream != 0, d->stream));
+    HIP_TRY(launch_phase(ap, odd, tu.phase_block, tu.phase_stream != 0, d->lds[0], d->stream));
     if (!d->rank && !d->pre.ghost_tail.empty())
         HIP_TRY(launch_ghosts(ap, d->ghost_tail, d->ghost_src, (int32_t)d->pre.ghost_tail.size(),
                               d->stream));
     if (lbm_status s = mark(0, false)) return s;
     if (lbm_status s = mark(1, true)) return s;
-    HIP_TRY(launch_collide(ac, odd, tu.collide_block, tu.collide_stream != 0, d->stream));
+    HIP_TRY(launch_collide(ac, odd, tu.collide_block, tu.collide_stream != 0, d->lds[1],
+                           d->stream));
     if (lbm_status s = mark(1, false)) return s;
     if (d->p.bc_z == 1) {
         if (lbm_status s = mark(2, true)) return s;
@@ -306,6 +307,8 @@ lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
 
 const char* lbm_version(void) { return "colorlbm-gfx950 0.1"; }
 
+static lbm_status apply_tuning(lbm_domain* d, const lbm_tuning& t);
+
 lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, int32_t n_labels,
                              const int8_t* label_kind, const double* label_affinity,
                              const double* voxel_affinity, const double* init_phi,
@@ -478,8 +481,20 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         d->release();
         return fail(LBM_ERR_DEVICE, "internal: device footprint estimate out of date");
     }
-    // Streaming accesses only for domains well beyond the Infinity Cache.
-    d->tune.phase_stream = d->tune.collide_stream = d->device_bytes > kStreamBytes ? 1 : 0;
+    // Domains well beyond the Infinity Cache: streaming accesses and workgroup limits, the
+    // autotuner's choice at 512^3 for each precision (phase / collide: FP64 5 / 2, FP32-mixed
+    // 5 / 3, FP32-dev none / 3). Smaller domains keep neither.
+    const bool large = d->device_bytes > kStreamBytes;
+    lbm_tuning t0 = d->tune;
+    t0.phase_stream = t0.collide_stream = large ? 1 : 0;
+    if (large) {
+        t0.phase_wg = p.precision == LBM_FP32_DEV ? 0 : 5;
+        t0.collide_wg = p.precision == LBM_FP64 ? 2 : 3;
+    }
+    if (lbm_status s = apply_tuning(d.get(), t0)) {
+        d->release();
+        return s;
+    }
     *out = d.release();
     return LBM_OK;
 }
@@ -701,22 +716,37 @@ lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out) {
     return LBM_OK;
 }
 
+// Make t the domain's launch configuration, with the LDS reservations its workgroup limits
+// need (computed for the domain's own kernels by the runtime's occupancy calculator).
+static lbm_status apply_tuning(lbm_domain* d, const lbm_tuning& t) {
+    unsigned lds[2] = {0, 0};
+    HIP_TRY(step_kernel_lds(d->args(t.phase_block, t.phase_schedule), 0, t.phase_block,
+                            t.phase_stream != 0, t.phase_wg, &lds[0]));
+    HIP_TRY(step_kernel_lds(d->args(t.collide_block, t.collide_schedule), 1, t.collide_block,
+                            t.collide_stream != 0, t.collide_wg, &lds[1]));
+    d->tune = t;
+    d->lds[0] = lds[0];
+    d->lds[1] = lds[1];
+    return LBM_OK;
+}
+
 static bool tuning_ok(const lbm_tuning& t) {
     auto blk = [](int b) { return b == 64 || b == 128 || b == 256; };
     auto sch = [](int v) { return v >= 1 && v <= 3; };
     auto flag = [](int v) { return v == 0 || v == 1; };
+    auto wg = [](int v) { return v >= 0 && v <= kMaxWgPerCu; };
     return blk(t.phase_block) && blk(t.collide_block) && sch(t.phase_schedule) &&
-           sch(t.collide_schedule) && flag(t.phase_stream) && flag(t.collide_stream);
+           sch(t.collide_schedule) && flag(t.phase_stream) && flag(t.collide_stream) &&
+           wg(t.phase_wg) && wg(t.collide_wg);
 }
 
 lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t) {
     if (lbm_status s = check_domain(d)) return s;
     if (!t || !tuning_ok(*t))
-        return fail(LBM_ERR_ARG, "unsupported block, schedule or stream flag");
+        return fail(LBM_ERR_ARG, "unsupported block, schedule, stream flag or workgroup limit");
     HIP_TRY(hipStreamSynchronize(d->stream));
     d->drop_step_graph();
-    d->tune = *t;
-    return LBM_OK;
+    return apply_tuning(d, *t);
 }
 
 lbm_status lbm_get_tuning(lbm_domain* d, lbm_tuning* out) {
@@ -758,22 +788,31 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     lbm_tuning best = d->tune;
     double best_ms[2] = {1e30, 1e30};
     d->record_history = false;
+    // Per kernel: every (block, schedule, stream) with no workgroup limit, then limits of 1 to
+    // 8 workgroups per CU on the best of those.
     const int blocks[3] = {64, 128, 256};
+    const int limits[7] = {1, 2, 3, 4, 5, 6, 8};
     for (int kernel = 0; kernel < 2 && st == LBM_OK && he == hipSuccess; ++kernel) {
-        for (int cand = 0; cand < 18 && st == LBM_OK; ++cand) {
-            const int bi = cand % 3, sched = 1 + (cand / 3) % 3, stream = cand / 9;
+        for (int cand = 0; cand < 18 + 7 && st == LBM_OK; ++cand) {
+            const int bi = cand % 3, sched = 1 + (cand / 3) % 3, stream = (cand / 9) % 2;
             {
                 lbm_tuning t = best;
-                if (kernel == 0) {
+                int& wg = kernel == 0 ? t.phase_wg : t.collide_wg;
+                if (cand >= 18) {
+                    wg = limits[cand - 18];
+                } else if (kernel == 0) {
                     t.phase_block = blocks[bi];
                     t.phase_schedule = sched;
                     t.phase_stream = stream;
+                    wg = 0;
                 } else {
                     t.collide_block = blocks[bi];
                     t.collide_schedule = sched;
                     t.collide_stream = stream;
+                    wg = 0;
                 }
-                d->tune = t;
+                st = apply_tuning(d, t);
+                if (st != LBM_OK) break;
                 lbm_timing tm;
                 st = step_impl(d, 2, &tm);                 // warm-up of this shape
                 if (st == LBM_OK) st = step_impl(d, trial_steps, &tm);
@@ -798,17 +837,17 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
         d->device_bytes -= (int64_t)std::max<size_t>(bytes, 256);
     }
     if (he != hipSuccess) {
-        d->tune = keep;
+        (void)apply_tuning(d, keep);
         return fail(LBM_ERR_DEVICE, std::string("autotune copy: ") + hipGetErrorString(he));
     }
     if (st != LBM_OK) {
-        d->tune = keep;
+        (void)apply_tuning(d, keep);
         return st;
     }
     best.phase_ms = best_ms[0];
     best.collide_ms = best_ms[1];
     d->drop_step_graph();
-    d->tune = best;
+    if (lbm_status s = apply_tuning(d, best)) return s;
     if (out) *out = best;
     // Record the step chunk for the chosen launch shapes now (recording runs nothing), so its
     // one-time capture cost is not paid by the first lbm_step that replays it.

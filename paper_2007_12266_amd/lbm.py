@@ -140,6 +140,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("phase_block", ctypes.c_int32), ("phase_schedule", ctypes.c_int32),
                 ("collide_block", ctypes.c_int32), ("collide_schedule", ctypes.c_int32),
                 ("phase_stream", ctypes.c_int32), ("collide_stream", ctypes.c_int32),
+                ("phase_wg", ctypes.c_int32), ("collide_wg", ctypes.c_int32),
                 ("phase_ms", ctypes.c_double), ("collide_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:

@@ -109,9 +109,10 @@ def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
 @pytest.mark.parametrize("mode", ["table", "rank", "compact"])
 def test_block_size_and_launch_shape_do_not_change_results(lbm, mode):
     """Block sizes, the three tile orders (launch order, XCD-aware runs, XCD-aware runs from the
-    end of the pore list) in every pairing of the two kernels, and streaming (non-temporal)
-    accesses on or off in either kernel give the same state, with each neighbour lookup. A
-    small domain starts without streaming; its flags are valid only as 0 or 1."""
+    end of the pore list) in every pairing of the two kernels, streaming (non-temporal)
+    accesses on or off, and limits of 1 to 16 workgroups per CU in either kernel give the same
+    state, with each neighbour lookup. A small domain starts without streaming or limits; the
+    flags are valid only as 0 or 1, the limits from 0 to 16."""
     prob = _random_problem((17, 18, 19), (True, True, True), seed=5)
     nm = _nm(lbm, mode)
     outs = []
@@ -119,18 +120,23 @@ def test_block_size_and_launch_shape_do_not_change_results(lbm, mode):
         dom = lbm.Domain(prob, block_size=block, neighbour_mode=nm)
         t = dom.tuning()
         assert t["phase_stream"] == 0 and t["collide_stream"] == 0
+        assert t["phase_wg"] == 0 and t["collide_wg"] == 0
         dom.step(25)
         outs.append(dom.save())
         dom.close()
-    for ps, cs, pst, cst in ((1, 3, 1, 1), (3, 2, 0, 1), (3, 3, 1, 0), (2, 1, 1, 1)):
+    for ps, cs, pst, cst, pwg, cwg in ((1, 3, 1, 1, 0, 1), (3, 2, 0, 1, 5, 2),
+                                       (3, 3, 1, 0, 16, 3), (2, 1, 1, 1, 1, 8)):
         dom = lbm.Domain(prob, neighbour_mode=nm)
         dom.set_tuning(phase_block=128, phase_schedule=ps, collide_block=64, collide_schedule=cs,
-                       phase_stream=pst, collide_stream=cst)
+                       phase_stream=pst, collide_stream=cst, phase_wg=pwg, collide_wg=cwg)
+        assert dom.tuning()["collide_wg"] == cwg
         dom.step(12)
         dom.step(13)
         outs.append(dom.save())
         with pytest.raises(lbm.LbmError):
             dom.set_tuning(collide_stream=2)
+        with pytest.raises(lbm.LbmError):
+            dom.set_tuning(phase_wg=17)
         dom.close()
     assert all(o == outs[0] for o in outs)
 
@@ -395,6 +401,7 @@ def test_autotune_restores_state_and_keeps_results(lbm, precision):
     t = dom.autotune(4)
     assert t["phase_block"] in (64, 128, 256) and t["collide_schedule"] in (1, 2, 3)
     assert t["phase_stream"] in (0, 1) and t["collide_stream"] in (0, 1)
+    assert 0 <= t["phase_wg"] <= 8 and 0 <= t["collide_wg"] <= 8
     assert t["phase_ms"] > 0 and t["collide_ms"] > 0
     assert dom.info()["step"] == 7 and dom.save() == before
     dom.step(13)
