@@ -360,6 +360,14 @@ def final_errors(finals, refs) -> dict:
     for k, v in e.items():
         out[k + "_rel_max"] = float(max(v))
         out[k + "_rel_median"] = float(np.median(v))
+    # Where the flux error is largest: how many results miss 1e-4, and the size of that result's
+    # net flux against the typical one (a two-phase state with near-zero net flux amplifies a
+    # perturbation of the phase field).
+    worst = int(np.argmax(e["qz"]))
+    typical = float(np.median([abs(ref["qz"]) for ref in refs]))
+    out["qz_rel_over_1e-4"] = int(sum(x > 1e-4 for x in e["qz"]))
+    out["qz_worst_abs_vs_median"] = (float(abs(refs[worst]["qz"]) / typical) if typical > 0
+                                     else None)
     return out
 
 

@@ -270,3 +270,43 @@ def test_cache_groups_keep_results(lbm, precision):
     pool.close()
     for d in doms:
         d.close()
+
+
+def _open_box(seed, shape=(48, 40, 52)):
+    """An open box with 10% random solids: on this grid a 64-voxel wave that holds the edge
+    between two blocks of 16 rows of the pore numbering sees its +-y targets jump by a whole
+    block, beyond 16 bits, so the compact lookup keeps such waves as int32 exception rows."""
+    rng = np.random.default_rng(seed)
+    labels = np.where(rng.random(shape) < 0.1, 0, 1).astype(np.int32)
+    return inputs.Problem(labels=labels,
+                          label_kind=np.array([inputs.KIND_SOLID, inputs.KIND_PORE_INIT], np.int8),
+                          label_affinity=np.array([0.4, 0.0]),
+                          init_phi=inputs.bernoulli_phase(shape, 0.5, seed + 1),
+                          periodic=(True, True, True), tau_a=0.7, tau_b=0.8, alpha=0.005,
+                          force=(0, 0, 1e-5))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_compact_exception_waves_in_a_pool(lbm, precision):
+    """A member with compact exception waves steps bitwise as its solo run with the int32 table,
+    in a compact-only pool (the pool's compact specialisation) and beside a table member (the
+    per-domain lookup of a mixed pool), through graph replays and eager steps."""
+    prec = lbm.FP64 if precision == "fp64" else lbm.FP32_DEV
+    box = _open_box(70)
+    other = _mix()[0]
+    solo = lbm.Domain(box, precision=prec, neighbour_mode=lbm.NBR_TABLE)
+    solo.step(23)
+    want = solo.save()
+    solo.close()
+    for partner in (lbm.NBR_COMPACT, lbm.NBR_TABLE):
+        d = lbm.Domain(box, precision=prec, neighbour_mode=lbm.NBR_COMPACT)
+        assert d.info()["compact_ex_waves"] > 0
+        e = lbm.Domain(other, precision=prec, neighbour_mode=partner)
+        pool = lbm.Pool(1 << 34, precision=prec, max_slots=2, chunk_steps=10)
+        pool.admit(d)
+        pool.admit(e)
+        pool.step(23)                           # 2 graph replays + 3 eager steps
+        assert d.save() == want
+        pool.close()
+        d.close()
+        e.close()
