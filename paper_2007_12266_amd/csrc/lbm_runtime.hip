@@ -795,33 +795,31 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     for (int kernel = 0; kernel < 2 && st == LBM_OK && he == hipSuccess; ++kernel) {
         for (int cand = 0; cand < 18 + 7 && st == LBM_OK; ++cand) {
             const int bi = cand % 3, sched = 1 + (cand / 3) % 3, stream = (cand / 9) % 2;
-            {
-                lbm_tuning t = best;
-                int& wg = kernel == 0 ? t.phase_wg : t.collide_wg;
-                if (cand >= 18) {
-                    wg = limits[cand - 18];
-                } else if (kernel == 0) {
-                    t.phase_block = blocks[bi];
-                    t.phase_schedule = sched;
-                    t.phase_stream = stream;
-                    wg = 0;
-                } else {
-                    t.collide_block = blocks[bi];
-                    t.collide_schedule = sched;
-                    t.collide_stream = stream;
-                    wg = 0;
-                }
-                st = apply_tuning(d, t);
-                if (st != LBM_OK) break;
-                lbm_timing tm;
-                st = step_impl(d, 2, &tm);                 // warm-up of this shape
-                if (st == LBM_OK) st = step_impl(d, trial_steps, &tm);
-                if (st != LBM_OK) break;
-                const double ms = kernel == 0 ? tm.phase_ms : tm.collide_ms;
-                if (ms < best_ms[kernel]) {
-                    best_ms[kernel] = ms;
-                    best = t;
-                }
+            lbm_tuning t = best;
+            int& wg = kernel == 0 ? t.phase_wg : t.collide_wg;
+            if (cand >= 18) {
+                wg = limits[cand - 18];
+            } else if (kernel == 0) {
+                t.phase_block = blocks[bi];
+                t.phase_schedule = sched;
+                t.phase_stream = stream;
+                wg = 0;
+            } else {
+                t.collide_block = blocks[bi];
+                t.collide_schedule = sched;
+                t.collide_stream = stream;
+                wg = 0;
+            }
+            st = apply_tuning(d, t);
+            if (st != LBM_OK) break;
+            lbm_timing tm;
+            st = step_impl(d, 2, &tm);                 // warm-up of this shape
+            if (st == LBM_OK) st = step_impl(d, trial_steps, &tm);
+            if (st != LBM_OK) break;
+            const double ms = kernel == 0 ? tm.phase_ms : tm.collide_ms;
+            if (ms < best_ms[kernel]) {
+                best_ms[kernel] = ms;
+                best = t;
             }
         }
     }
