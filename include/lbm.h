@@ -372,9 +372,10 @@ lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
  * voxel, pore order), nbr[18 * n_pore] (row q-1 holds the neighbour of every pore voxel along
  * D3Q19 velocity q = 1..18: a pore index < n_pore, or n_pore + t for tail entry t, a solid or
  * wall neighbour), tail_phi[n_tail] (phi_s of each tail entry; entry 0 is the wall outside
- * non-periodic faces). Call once with NULL arrays to learn the sizes. Where the rank lookup
- * applies, the query also replays it for every pore voxel and direction against this table and
- * returns LBM_ERR_STATE if the two disagree (an internal error, never expected). */
+ * non-periodic faces). Call once with NULL arrays to learn the sizes. The query also replays
+ * the rank lookup (where it applies) and decodes the compact lookup for every pore voxel and
+ * direction against this table, and returns LBM_ERR_STATE if they disagree (an internal error,
+ * never expected). Only the image and its labels are checked here, not the fluid parameters. */
 lbm_status lbm_prepass_query(const lbm_params* params, const int32_t* labels, int32_t n_labels,
                              const int8_t* label_kind, const double* label_affinity,
                              const double* voxel_affinity, const double* init_phi,

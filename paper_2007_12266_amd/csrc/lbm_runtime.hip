@@ -285,12 +285,37 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 static const char* const kRankLimits =
     "rank neighbour lookup needs nx <= 1024 and ny, nz <= 2048";
 
+// Checks of the fluid and run parameters shared by lbm_domain_create and lbm_domain_footprint
+// (the image itself is checked by the pre-pass). "" when they are valid.
+static std::string param_error(const lbm_params& p) {
+    if (!(p.tau_a > 0.5) || !(p.tau_b > 0.5)) return "tau must exceed 1/2";
+    if (!(p.beta > 0.0 && p.beta < 1.0)) return "beta must lie in (0, 1)";
+    if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return "alpha must be >= 0";
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(p.force[c])) return "force must be finite";
+    if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV && p.precision != LBM_FP32_MIXED)
+        return "precision must be a lbm_precision";
+    if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
+        return "rho_in and rho_out must be positive";
+    if (p.inlet_mode != 0 && p.inlet_mode != 1) return "inlet_mode must be 0 or 1";
+    if (p.inlet_mode == 1 && (p.bc_z != 1 || !std::isfinite(p.flux_in)))
+        return "a flux inlet needs bc_z == 1 and a finite flux_in";
+    if (p.reduce_every < 0) return "reduce_every must be >= 0";
+    if (p.neighbour_mode < LBM_NBR_AUTO || p.neighbour_mode > LBM_NBR_COMPACT)
+        return "neighbour_mode must be a lbm_neighbour_mode";
+    if (p.block_size != 0 && p.block_size != 64 && p.block_size != 128 && p.block_size != 256)
+        return "block_size must be 0, 64, 128 or 256";
+    return "";
+}
+
 lbm_status lbm_domain_footprint(const lbm_params* params, const int32_t* labels,
                                 int32_t n_labels, const int8_t* label_kind,
                                 const double* label_affinity, const double* voxel_affinity,
                                 const double* init_phi, int64_t* bytes) {
     g_err.clear();
     if (!params || !bytes) return fail(LBM_ERR_ARG, "null argument");
+    const std::string perr = param_error(*params);
+    if (!perr.empty()) return fail(LBM_ERR_ARG, perr);
     Prepass pre;
     std::string err = prepass(*params, labels, n_labels, label_kind, label_affinity,
                               voxel_affinity, init_phi, pre);
@@ -317,25 +342,9 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
     if (!params || !out) return fail(LBM_ERR_ARG, "params and out must be non-null");
     *out = nullptr;
     const lbm_params& p = *params;
-    if (!(p.tau_a > 0.5) || !(p.tau_b > 0.5)) return fail(LBM_ERR_ARG, "tau must exceed 1/2");
-    if (!(p.beta > 0.0 && p.beta < 1.0)) return fail(LBM_ERR_ARG, "beta must lie in (0, 1)");
-    if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return fail(LBM_ERR_ARG, "alpha must be >= 0");
-    for (int c = 0; c < 3; ++c)
-        if (!std::isfinite(p.force[c])) return fail(LBM_ERR_ARG, "force must be finite");
-    if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV && p.precision != LBM_FP32_MIXED)
-        return fail(LBM_ERR_ARG, "precision must be a lbm_precision");
-    if (p.bc_z == 1 && !(p.rho_in > 0.0 && p.rho_out > 0.0))
-        return fail(LBM_ERR_ARG, "rho_in and rho_out must be positive");
-    if (p.inlet_mode != 0 && p.inlet_mode != 1)
-        return fail(LBM_ERR_ARG, "inlet_mode must be 0 or 1");
-    if (p.inlet_mode == 1 && (p.bc_z != 1 || !std::isfinite(p.flux_in)))
-        return fail(LBM_ERR_ARG, "a flux inlet needs bc_z == 1 and a finite flux_in");
-    if (p.reduce_every < 0) return fail(LBM_ERR_ARG, "reduce_every must be >= 0");
-    if (p.neighbour_mode < LBM_NBR_AUTO || p.neighbour_mode > LBM_NBR_COMPACT)
-        return fail(LBM_ERR_ARG, "neighbour_mode must be a lbm_neighbour_mode");
-    int block = p.block_size == 0 ? 256 : p.block_size;
-    if (block != 64 && block != 128 && block != 256)
-        return fail(LBM_ERR_ARG, "block_size must be 0, 64, 128 or 256");
+    const std::string perr = param_error(p);
+    if (!perr.empty()) return fail(LBM_ERR_ARG, perr);
+    const int block = p.block_size == 0 ? 256 : p.block_size;
     if (alloc && (!alloc->alloc || !alloc->free))
         return fail(LBM_ERR_ARG, "allocator needs both alloc and free");
 
