@@ -315,6 +315,26 @@ def _cpu_model() -> str:
 PRECISIONS = ("fp64", "fp32dev", "mixed")
 
 
+def copy_ceiling_gbs(torch, nbytes=2 << 30, reps=5):
+    """The practical bandwidth ceiling: a plain 2 GiB device-to-device copy (read + write bytes
+    per second), best of a few repetitions timed with events on the current stream."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del a, b
+    torch.cuda.synchronize()
+    return 2 * nbytes / best / 1e9
+
+
 def prec_of(lbm, name):
     return {"fp64": lbm.FP64, "fp32dev": lbm.FP32_DEV, "mixed": lbm.FP32_MIXED}[name]
 
@@ -720,6 +740,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    copy_gbs = copy_ceiling_gbs(torch)
 
     red = dom.reduce()
     block = dom.info()["block_size"]
@@ -746,7 +767,9 @@ def main():
                   "row_bytes_per_launch": nbytes["row_bytes"],
                   "neighbours": nb_name,
                   "compact_ex_waves": dinfo["compact_ex_waves"],
-                  "kernel_ms": round(timing["collide_ms"], 5)},
+                  "kernel_ms": round(timing["collide_ms"], 5),
+                  "copy_ceiling_gbs": round(copy_gbs, 1),
+                  "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)},
         step_hbm={"bytes_per_voxel": nbytes["per_voxel"]["step"],
                   "achieved_gbs": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                   "survey_bytes_per_voxel": sbytes["step"],
