@@ -1,0 +1,116 @@
+"""Full-size parity at 512^3, in the launch configuration bench.py times.
+
+The dense FP64 oracle cannot hold a 512^3 domain (about 70 GB), but after two steps a voxel's
+state depends only on the initial state within a few voxels: the phase kernel reads the upstream
+neighbours' moment slots, the collide kernel the neighbours' phi and (odd step) populations, and
+the read-out one more neighbour, so the cone has a radius of at most 2 per step plus 1. The
+oracle run for two steps on a 15^3 crop centred on a voxel therefore gives that voxel's exact
+two-step state, and the GPU's value there is compared with it. The domain runs as bench.py runs
+it: FP64, the compact neighbour lookup with its exception waves, streaming accesses and the
+per-CU workgroup limits that lbm_domain_create gives a domain of this size.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2007_12266_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+R = 7                     # crop half-width: more than the two-step cone (5)
+STEPS = 2                 # both AA parities
+SAMPLES = 12
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_12266_amd import lbm as mod
+    mod.load_library()
+    return mod
+
+
+def _crop(prob, c, z_lo=None):
+    """Problem on the (2R+1)^3 box around voxel c = (z, y, x), wrapping the periodic axes. With
+    z_lo the box starts at that plane instead (kept as a pressure face of the crop)."""
+    nz, ny, nx = prob.shape
+    z0 = c[0] - R if z_lo is None else z_lo
+    idx = [np.arange(z0, z0 + 2 * R + 1) % nz, np.arange(c[1] - R, c[1] + R + 1) % ny,
+           np.arange(c[2] - R, c[2] + R + 1) % nx]
+    take = np.ix_(*idx)
+    crop = dataclasses.replace(
+        prob, labels=np.ascontiguousarray(prob.labels[take]),
+        voxel_affinity=None if prob.voxel_affinity is None
+        else np.ascontiguousarray(prob.voxel_affinity[take]),
+        init_phi=None if prob.init_phi is None else np.ascontiguousarray(prob.init_phi[take]),
+        periodic=(False, False, False), bc_z=1 if z_lo is not None else 0)
+    centre = (c[0] - z0, R, R)
+    return crop, centre
+
+
+def _check(lbm, prob, centres, face_planes=None):
+    dom = lbm.Domain(prob)
+    info, tune = dom.info(), dom.tuning()
+    # The launch configuration of the bench line at this size.
+    assert info["neighbour_mode"] == lbm.NBR_COMPACT and info["compact_ex_waves"] > 0
+    assert tune["phase_stream"] == 1 and tune["collide_stream"] == 1
+    assert tune["phase_wg"] == 5 and tune["collide_wg"] == 2
+    dom.step(STEPS)
+    names = ("Na", "Nb", "phi", "rho", "ux", "uy", "uz")
+    gpu = {}
+    for k in names:
+        dense = dom.field(k)
+        gpu[k] = np.array([dense[c] for c in centres])
+        del dense
+    dom.close()
+    ref = {k: [] for k in names}
+    for j, c in enumerate(centres):
+        z_lo = 0 if face_planes is not None and c[0] < face_planes else None
+        crop, mid = _crop(prob, c, z_lo)
+        f = O.state_for(crop).run(STEPS).fields()
+        for k in names:
+            ref[k].append(f[k][mid])
+    u_scale = max(np.abs(np.array(ref[k])).max() for k in ("ux", "uy", "uz"))
+    for k in names:
+        r = np.array(ref[k])
+        tol = 1e-12 * (u_scale if k.startswith("u") else max(1.0, np.abs(r).max()))
+        tol = max(tol, 1e-15) if k.startswith("u") else tol
+        err = np.abs(gpu[k] - r).max()
+        assert err <= tol, (k, err, tol)
+    return u_scale
+
+
+def _pore_samples(prob, rng, count, z_range):
+    solid = prob.solid_mask()
+    nz, ny, nx = prob.shape
+    out = []
+    while len(out) < count:
+        c = (int(rng.integers(*z_range)), int(rng.integers(ny)), int(rng.integers(nx)))
+        if solid[c] == 0:
+            out.append(c)
+    return out
+
+
+def test_steady_flow_512_sampled_voxels_match_oracle_crops(lbm):
+    """512^3 GRF rock of the steady-flow generator (periodic, per-voxel affinity, random phase
+    at Sw = 0.5, F_z = 1e-5): 12 pore voxels spread over the domain, every field to 1e-12 after
+    two steps (velocities against the largest sampled |u|)."""
+    prob = inputs.grf_problem(n=512, seed_geom=5, seed_aff=6, seed_phase=7)
+    rng = np.random.default_rng(512)
+    u_scale = _check(lbm, prob, _pore_samples(prob, rng, SAMPLES, (0, 512)))
+    assert u_scale > 0
+
+
+def test_displacement_512_sampled_voxels_match_oracle_crops(lbm):
+    """The 512^3 displacement workload (the bench line's): 6 pore voxels on the first 3 planes,
+    whose crops keep the inlet pressure face at z = 0, and 6 in the rock, to 1e-12 after two
+    steps."""
+    prob = inputs.displacement_problem(n=512, seed_geom=5)
+    rng = np.random.default_rng(513)
+    centres = (_pore_samples(prob, rng, SAMPLES // 2, (0, 3))
+               + _pore_samples(prob, rng, SAMPLES // 2, (20, 492)))
+    _check(lbm, prob, centres, face_planes=3)
