@@ -106,18 +106,21 @@ def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
     dom.close()
 
 
-@pytest.mark.parametrize("mode", ["table", "rank", "compact"])
-def test_block_size_and_launch_shape_do_not_change_results(lbm, mode):
+@pytest.mark.parametrize("mode,precision", [("table", "fp64"), ("rank", "fp64"),
+                                            ("compact", "fp64"), ("compact", "mixed"),
+                                            ("compact", "fp32dev")])
+def test_block_size_and_launch_shape_do_not_change_results(lbm, mode, precision):
     """Block sizes, the three tile orders (launch order, XCD-aware runs, XCD-aware runs from the
     end of the pore list) in every pairing of the two kernels, streaming (non-temporal)
     accesses on or off, and limits of 1 to 16 workgroups per CU in either kernel give the same
     state, with each neighbour lookup. A small domain starts without streaming or limits; the
-    flags are valid only as 0 or 1, the limits from 0 to 16."""
+    flags are valid only as 0 or 1, the limits from 0 to 16. In every storage precision."""
     prob = _random_problem((17, 18, 19), (True, True, True), seed=5)
     nm = _nm(lbm, mode)
+    prec = {"fp64": lbm.FP64, "mixed": lbm.FP32_MIXED, "fp32dev": lbm.FP32_DEV}[precision]
     outs = []
     for block in (64, 128, 256):
-        dom = lbm.Domain(prob, block_size=block, neighbour_mode=nm)
+        dom = lbm.Domain(prob, block_size=block, neighbour_mode=nm, precision=prec)
         t = dom.tuning()
         assert t["phase_stream"] == 0 and t["collide_stream"] == 0
         assert t["phase_wg"] == 0 and t["collide_wg"] == 0
@@ -126,7 +129,7 @@ def test_block_size_and_launch_shape_do_not_change_results(lbm, mode):
         dom.close()
     for ps, cs, pst, cst, pwg, cwg in ((1, 3, 1, 1, 0, 1), (3, 2, 0, 1, 5, 2),
                                        (3, 3, 1, 0, 16, 3), (2, 1, 1, 1, 1, 8)):
-        dom = lbm.Domain(prob, neighbour_mode=nm)
+        dom = lbm.Domain(prob, neighbour_mode=nm, precision=prec)
         dom.set_tuning(phase_block=128, phase_schedule=ps, collide_block=64, collide_schedule=cs,
                        phase_stream=pst, collide_stream=cst, phase_wg=pwg, collide_wg=cwg)
         assert dom.tuning()["collide_wg"] == cwg
