@@ -5,6 +5,8 @@ Tolerance: the FP64 step must match the oracle to 1e-12 relative per field, meas
 Both sides evaluate the same readings in FP64; they differ only in rounding order (explicit
 19x19 moment matrix in the oracle, two-relaxation-time pair form in the kernel).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -544,3 +546,38 @@ def test_auto_mode_and_footprints(lbm):
     rank = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_RANK)
     compact = lbm.footprint(prob, lbm.FP64, neighbour_mode=lbm.NBR_COMPACT)
     assert rank < compact < table
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_randomized_configurations_match_the_oracle(lbm, case):
+    """Seeded random draws over what a caller can choose: grid shape (9 to 26 per axis, so pore
+    counts are ragged), periodicity per axis, solid fraction, viscosities, alpha, beta, force,
+    wall affinity, step count of either parity, neighbour lookup, block sizes, tile orders,
+    streaming and workgroup limits. FP64 against the oracle, every field to 1e-12 (velocities
+    with the stated absolute bound of 1e-15 where they are tiny)."""
+    rng = np.random.default_rng(9000 + case)
+    shape = tuple(int(v) for v in rng.integers(9, 27, 3))
+    periodic = tuple(bool(v) for v in rng.random(3) < 0.5)
+    tau = (float(rng.uniform(0.55, 1.2)), float(rng.uniform(0.55, 1.2)))
+    force = tuple(float(v) for v in rng.uniform(-3e-5, 3e-5, 3))
+    prob = _random_problem(shape, periodic, seed=int(rng.integers(1 << 30)), force=force,
+                           tau=tau, solid_frac=float(rng.uniform(0.05, 0.4)),
+                           alpha=float(rng.uniform(0.0, 0.02)),
+                           wall=float(rng.uniform(-0.9, 0.9)))
+    prob = dataclasses.replace(prob, beta=float(rng.uniform(0.5, 0.99)))
+    mode = ("table", "rank", "compact")[case % 3]
+    blocks = (64, 128, 256)
+    dom = lbm.Domain(prob, neighbour_mode=_nm(lbm, mode))
+    dom.set_tuning(phase_block=int(rng.choice(blocks)), collide_block=int(rng.choice(blocks)),
+                   phase_schedule=int(rng.integers(1, 4)), collide_schedule=int(rng.integers(1, 4)),
+                   phase_stream=int(rng.integers(0, 2)), collide_stream=int(rng.integers(0, 2)),
+                   phase_wg=int(rng.integers(0, 9)), collide_wg=int(rng.integers(0, 9)))
+    steps = int(rng.integers(5, 40))
+    dom.step(steps)
+    gpu = dom.fields()
+    ref = O.state_for(prob).run(steps).fields()
+    errs = _compare(gpu, ref, prob.solid_mask() == 0, u_abs=1e-15)
+    print("case %d: shape %s periodic %s mode %s steps %d tuning %s errors %s"
+          % (case, shape, periodic, mode, steps, dom.tuning(), errs))
+    dom.close()
+
