@@ -24,6 +24,9 @@ namespace lbm {
 void finish_reduction(const lbm_domain* d, const double* acc, int64_t step, lbm_reduction* r);
 // A member's launch arguments changed: the pool re-uploads them before its next step.
 lbm_status pool_member_changed(lbm_pool* p, const lbm_domain* d);
+// The launches of one time step of d alone at parity `odd` on d->stream, with d's own launch
+// configuration (lbm_runtime.hip).
+lbm_status launch_domain_step(lbm_domain* d, bool odd);
 }  // namespace lbm
 
 #define HIP_TRY(expr)                                                                        \

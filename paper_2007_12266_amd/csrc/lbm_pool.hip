@@ -302,8 +302,20 @@ lbm_status capture(lbm_pool* p) {
     if (p->groups.empty()) {
         st = launch_steps(p, 0, p->chunk);
     } else {
-        for (size_t g = 0; g < p->groups.size() && st == LBM_OK; ++g)
-            st = launch_steps_of(p, p->group_batch(g), p->groups[g].members, 0, p->chunk);
+        for (size_t g = 0; g < p->groups.size() && st == LBM_OK; ++g) {
+            const std::vector<int32_t>& members = p->groups[g].members;
+            if (members.size() == 1) {
+                // A member alone in its group gains nothing from the batched launch: its chunk
+                // runs the single-domain launches with the member's own configuration (for a
+                // large member, streaming accesses and workgroup limits). Same arithmetic per
+                // voxel, so the result is the same bitwise.
+                lbm_domain* d = p->slots[members[0]];
+                for (int64_t k = 0; k < p->chunk && st == LBM_OK; ++k)
+                    st = launch_domain_step(d, (k & 1) != 0);
+            } else {
+                st = launch_steps_of(p, p->group_batch(g), members, 0, p->chunk);
+            }
+        }
     }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(p->stream, &g);

@@ -237,6 +237,10 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
 
 }  // namespace
 
+namespace lbm {
+lbm_status launch_domain_step(lbm_domain* d, bool odd) { return launch_step(d, odd, no_mark); }
+}  // namespace lbm
+
 // Device bytes lbm_domain_create allocates for a pre-passed input (every buffer is rounded up to
 // 256 bytes by lbm_domain::dalloc).
 static bool uses_rank(const lbm_params& p, const Prepass& pre) {
