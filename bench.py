@@ -606,7 +606,8 @@ def main():
                          "16-bit codes above per-wave bases")
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape PHASE_BLOCK,PHASE_SCHEDULE,COLLIDE_BLOCK,"
-                         "COLLIDE_SCHEDULE[,PHASE_STREAM,COLLIDE_STREAM[,PHASE_WG,COLLIDE_WG]] "
+                         "COLLIDE_SCHEDULE[,PHASE_STREAM,COLLIDE_STREAM[,PHASE_WG,COLLIDE_WG"
+                         "[,PHASE_RUN_EVEN,PHASE_RUN_ODD,COLLIDE_RUN_EVEN,COLLIDE_RUN_ODD]]] "
                          "instead of the autotuner (profiled runs)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of autotuning them")
@@ -679,9 +680,14 @@ def main():
     tuning = None
     if args.tuning:
         vals = [int(v) for v in args.tuning.split(",")]
+        if len(vals) not in (4, 6, 8, 12):
+            raise SystemExit("--tuning takes 4, 6, 8 or 12 integers")
         keys = ["phase_block", "phase_schedule", "collide_block", "collide_schedule",
                 "phase_stream", "collide_stream", "phase_wg", "collide_wg"][:len(vals)]
-        dom.set_tuning(**dict(zip(keys, vals)))
+        kw = dict(zip(keys, vals))
+        if len(vals) == 12:
+            kw["phase_run"], kw["collide_run"] = vals[8:10], vals[10:12]
+        dom.set_tuning(**kw)
         tuning = {k: v for k, v in dom.tuning().items() if not k.endswith("_ms")}
         tuning["fixed"] = True
         log("tuning: %s" % tuning)

@@ -161,24 +161,29 @@ typedef struct {
 
 /* Launch configuration of the two step kernels. block: threads per workgroup (64, 128 or 256);
  * schedule: 1 = workgroups take consecutive tiles of the pore list in launch order, 2 = XCD-aware
- * order: each of the 8 XCDs takes runs of 16 consecutive tiles, the runs interleaved, so that
+ * order: each of the 8 XCDs takes runs of consecutive tiles, the runs interleaved, so that
  * neighbouring tiles share an L2; 3 = the XCD-aware order run from the end of the pore list, so
  * that a kernel following one in forward order starts where that one ended (on lines that may
- * still be cached). stream: 1 = the data a launch touches once (even-step populations, the
+ * still be cached). run: the run length in tiles of schedules 2 and 3 (1 to 64; default 16), on
+ * even [0] and odd [1] steps: the odd AA step's reads and writes land a neighbour away, so it
+ * gains from longer runs (more of the lines it shares with nearby tiles stay on one XCD), the
+ * even step from shorter ones. stream: 1 = the data a launch touches once (even-step populations, the
  * neighbour lookup, the moment slots, phi and N written for the next kernel) is read and
  * written with non-temporal hints, so the L2 keeps the lines neighbouring voxels re-read; right
  * for domains far larger than the 256 MB Infinity Cache, wrong for those it holds from one step
  * to the next. wg: at most this many workgroups of the kernel resident per CU (0: as many as its
  * registers allow; up to 16), enforced by reserving LDS the kernel does not use; fewer resident
  * waves keep more of the lines that neighbouring voxels share in the L2. When the domain's device
- * memory exceeds 512 MiB, lbm_domain_create sets stream = 1 and the limits the autotuner picks
- * at 512^3 (phase / collide wg: FP64 5 / 2, FP32-mixed 5 / 3, FP32-dev 0 / 3); else 0.
+ * memory exceeds 512 MiB, lbm_domain_create sets stream = 1, the limits the autotuner picks
+ * at 512^3 (phase / collide wg: FP64 5 / 2, FP32-mixed 5 / 3, FP32-dev 0 / 3) and collide runs
+ * of 4 (even) / 32 (odd) tiles; else stream 0, no limits and runs of 16.
  * Results do not depend on the configuration (bitwise). */
 typedef struct {
     int32_t phase_block, phase_schedule;
     int32_t collide_block, collide_schedule;
     int32_t phase_stream, collide_stream;
     int32_t phase_wg, collide_wg;
+    int32_t phase_run[2], collide_run[2];  /* [0]: even steps, [1]: odd steps                  */
     double phase_ms, collide_ms;  /* average per launch measured by lbm_autotune, else 0        */
 } lbm_tuning;
 
@@ -346,15 +351,16 @@ lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out);
 
 /* Autotuner: times every (block, schedule, stream) candidate of each step kernel over
  * trial_steps >= 2 steps on this domain, then workgroup limits of 1 to 8 per CU on the best of
- * them, applies the fastest, and writes it to *out (nullable).
+ * them, then (XCD-aware schedules) run lengths of 4 to 64 tiles for each step parity in turn,
+ * applies the fastest, and writes it to *out (nullable).
  * The state, step counter and reduction history are restored afterwards, so the results of later
  * steps are unchanged. Synchronises; needs device memory for one copy of the populations (LBM_ERR_OOM
  * otherwise). */
 lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out);
 
 /* Apply a launch configuration (e.g. one cached from an earlier lbm_autotune on the same GPU,
- * precision and size class). LBM_ERR_ARG for an unsupported block, schedule, stream flag or
- * workgroup limit. */
+ * precision and size class). LBM_ERR_ARG for an unsupported block, schedule, stream flag,
+ * workgroup limit or run length. */
 lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t);
 lbm_status lbm_get_tuning(lbm_domain* d, lbm_tuning* out);
 

@@ -42,7 +42,7 @@ struct lbm_domain {
     lbm_params p{};
     lbm::Prepass pre;
     int block = 256;                 // read-back and init kernels
-    lbm_tuning tune{256, 2, 256, 2, 0, 0, 0, 0, 0.0, 0.0};
+    lbm_tuning tune{256, 2, 256, 2, 0, 0, 0, 0, {16, 16}, {16, 16}, 0.0, 0.0};
     unsigned lds[2] = {0, 0};        // dynamic LDS of the phase / collide launches (tune.*_wg)
     lbm_allocator alloc{};
     bool has_alloc = false;
@@ -110,8 +110,9 @@ struct lbm_domain {
         step_graph = nullptr;
     }
 
-    // Kernel arguments for a launch with `blk` threads per workgroup and schedule `sched`.
-    lbm::StepArgs args(int blk = 256, int sched = 1) const {
+    // Kernel arguments for a launch with `blk` threads per workgroup and schedule `sched`
+    // (XCD runs of `run` tiles for schedules 2 and 3).
+    lbm::StepArgs args(int blk = 256, int sched = 1, int run = lbm::kXcdRun) const {
         lbm::StepArgs a{};
         a.N = (int32_t)pre.n_pore;
         a.nblocks = (int32_t)((pre.n_pore + blk - 1) / blk);
@@ -128,7 +129,7 @@ struct lbm_domain {
         a.alpha = p.alpha;
         a.beta = p.beta;
         for (int c = 0; c < 3; ++c) a.F[c] = p.force[c];
-        a.xcd_remap = sched >= 2 ? 1 : 0;
+        a.xcd_run = sched >= 2 ? run : 0;
         a.reverse = sched == 3 ? 1 : 0;
         a.coord = rank ? coord : nullptr;
         a.words = rank ? words : nullptr;

@@ -38,7 +38,7 @@ struct StepArgs {
     double nu_a, nu_b;  // kinematic viscosities
     double alpha, beta;
     double F[3];
-    int32_t xcd_remap;  // 1: XCD-aware order (runs of consecutive tiles per XCD)
+    int32_t xcd_run;    // 0: linear tile order; > 0: XCD-aware order, runs of this many tiles
     int32_t reverse;    // 1: the tile order runs from the end of the pore list
     int32_t prec;       // lbm_precision
     // Rank lookup of neighbours (used instead of nbr when words != null):
@@ -57,8 +57,11 @@ struct StepArgs {
 
 // Arguments of the batched (pool) kernels. All arrays live in device memory.
 // XCD-aware tile order: the hardware deals workgroups round-robin to the 8 XCDs; each XCD is
-// given runs of kXcdRun consecutive tiles, the runs interleaved (grid a multiple of 8 kXcdRun).
+// given runs of consecutive tiles, the runs interleaved (grid a multiple of 8 runs). kXcdRun is
+// the run length of the batched launches and the default of a domain's own launches, which may
+// choose any length up to kMaxXcdRun for each kernel and step parity (lbm_tuning).
 constexpr int kXcdRun = 16;
+constexpr int kMaxXcdRun = 64;
 
 // Steps in the captured chunk of the single-domain step loop (even, so every chunk starts and
 // ends on an even step).

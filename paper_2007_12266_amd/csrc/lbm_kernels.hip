@@ -42,7 +42,7 @@
 //    opposite pairs. The equilibrium in population space is the second-order polynomial plus the
 //    image of the alpha|C| moment terms under M^-1 (closed form below).
 //  * Workgroup -> tile mapping can be XCD-aware: the hardware deals workgroups round-robin to
-//    the 8 XCDs, so each XCD is given runs of kXcdRun consecutive tiles, the XCDs' runs
+//    the 8 XCDs, so each XCD is given runs of consecutive tiles, the XCDs' runs
 //    interleaved. Neighbouring tiles then share an L2 (the cache lines a wave's scattered
 //    accesses leave half used are completed by the next tile on the same XCD) while all XCDs
 //    still stream through the pore list together.
@@ -102,18 +102,19 @@ template <> struct Prec<LBM_FP32_MIXED> {
 };
 
 // Hardware block b runs on XCD b % 8 as that XCD's (b / 8)-th block; it takes logical tile
-// ((j / C) * 8 + x) * C + j % C (x = b % 8, j = b / 8, C = kXcdRun). With gridDim.x a
-// multiple of 8 C this is a bijection of [0, gridDim.x).
-__device__ __forceinline__ int xcd_run_tile(int b) {
+// ((j / C) * 8 + x) * C + j % C (x = b % 8, j = b / 8, C = run length). With gridDim.x a
+// multiple of 8 C this is a bijection of [0, gridDim.x). b and C are uniform over the
+// workgroup, so the division is scalar work, once per workgroup.
+__device__ __forceinline__ int xcd_run_tile(int b, int C) {
     const int x = b & 7, j = b >> 3;
-    return ((j / kXcdRun) * 8 + x) * kXcdRun + (j % kXcdRun);
+    return ((j / C) * 8 + x) * C + (j % C);
 }
 
 // Tile of this workgroup. With `reverse` the order runs from the end of the (padded) grid, so a
 // kernel launched after one in forward order starts on the tiles the other finished last, whose
 // lines may still be in the caches; on a padded grid the tiles beyond the pore list still exit.
 __device__ __forceinline__ int logical_block(const StepArgs& a) {
-    const int t = a.xcd_remap ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
+    const int t = a.xcd_run ? xcd_run_tile((int)blockIdx.x, a.xcd_run) : (int)blockIdx.x;
     return a.reverse ? (int)gridDim.x - 1 - t : t;
 }
 
@@ -672,7 +673,7 @@ __device__ __forceinline__ T load_const(const T* p) {
 template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) phase_batched(BatchArgs b) {
     const int nt = *as_const(b.ntiles);
-    const int first = b.xcd ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
+    const int first = b.xcd ? xcd_run_tile((int)blockIdx.x, kXcdRun) : (int)blockIdx.x;
     for (int t = first; t < nt; t += gridDim.x) {
         const int d = as_const(b.tile_dom)[t];
         const StepArgs a = load_const(b.doms + d);
@@ -684,7 +685,7 @@ __global__ void __launch_bounds__(256) phase_batched(BatchArgs b) {
 template <int PREC, bool ODD, int NB>
 __global__ void __launch_bounds__(256) collide_batched(BatchArgs b) {
     const int nt = *as_const(b.ntiles);
-    const int first = b.xcd ? xcd_run_tile((int)blockIdx.x) : (int)blockIdx.x;
+    const int first = b.xcd ? xcd_run_tile((int)blockIdx.x, kXcdRun) : (int)blockIdx.x;
     for (int t = first; t < nt; t += gridDim.x) {
         const int d = as_const(b.tile_dom)[t];
         const StepArgs a = load_const(b.doms + d);
@@ -979,8 +980,8 @@ __global__ void __launch_bounds__(kInletBlocks) inlet_finish_kernel(
 int grid_for(const StepArgs& a, int block) { return (a.N + block - 1) / block; }
 
 dim3 step_grid(const StepArgs& a) {
-    const int g = 8 * kXcdRun;    // XCD-aware order: whole runs on every XCD
-    return dim3(a.xcd_remap ? ((a.nblocks + g - 1) / g) * g : a.nblocks);
+    const int g = 8 * a.xcd_run;  // XCD-aware order: whole runs on every XCD
+    return dim3(a.xcd_run ? ((a.nblocks + g - 1) / g) * g : a.nblocks);
 }
 
 }  // namespace

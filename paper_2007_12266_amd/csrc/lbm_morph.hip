@@ -171,8 +171,9 @@ lbm_status ensure_buffers(lbm_domain* d) {
 // first kernel, run on the current state; it changes no state).
 lbm_status current_phase(lbm_domain* d) {
     const lbm_tuning& tu = d->tune;
-    const StepArgs a = d->args(tu.phase_block, tu.phase_schedule);
-    HIP_TRY(launch_phase(a, (d->step & 1) != 0, tu.phase_block, tu.phase_stream != 0, d->lds[0],
+    const bool odd = (d->step & 1) != 0;
+    const StepArgs a = d->args(tu.phase_block, tu.phase_schedule, tu.phase_run[odd ? 1 : 0]);
+    HIP_TRY(launch_phase(a, odd, tu.phase_block, tu.phase_stream != 0, d->lds[0],
                          d->stream));
     return LBM_OK;
 }

@@ -93,8 +93,9 @@ lbm_status check_domain(lbm_domain* d) {
 template <typename Mark>
 lbm_status launch_step(lbm_domain* d, bool odd, Mark mark) {
     const lbm_tuning& tu = d->tune;
-    const StepArgs ap = d->args(tu.phase_block, tu.phase_schedule);
-    const StepArgs ac = d->args(tu.collide_block, tu.collide_schedule);
+    const int par = odd ? 1 : 0;
+    const StepArgs ap = d->args(tu.phase_block, tu.phase_schedule, tu.phase_run[par]);
+    const StepArgs ac = d->args(tu.collide_block, tu.collide_schedule, tu.collide_run[par]);
     if (lbm_status s = mark(0, true)) return s;
     HIP_TRY(launch_phase(ap, odd, tu.phase_block, tu.phase_stream != 0, d->lds[0], d->stream));
     if (!d->rank && !d->pre.ghost_tail.empty())
@@ -494,15 +495,18 @@ lbm_status lbm_domain_create(const lbm_params* params, const int32_t* labels, in
         d->release();
         return fail(LBM_ERR_DEVICE, "internal: device footprint estimate out of date");
     }
-    // Domains well beyond the Infinity Cache: streaming accesses and workgroup limits, the
-    // autotuner's choice at 512^3 for each precision (phase / collide: FP64 5 / 2, FP32-mixed
-    // 5 / 3, FP32-dev none / 3). Smaller domains keep neither.
+    // Domains well beyond the Infinity Cache: streaming accesses, workgroup limits and collide
+    // run lengths, the autotuner's choice at 512^3 for each precision (phase / collide wg: FP64
+    // 5 / 2, FP32-mixed 5 / 3, FP32-dev none / 3; collide runs of 4 tiles on even steps, 32 on
+    // odd ones in all three). Smaller domains keep the plain defaults.
     const bool large = d->device_bytes > kStreamBytes;
     lbm_tuning t0 = d->tune;
     t0.phase_stream = t0.collide_stream = large ? 1 : 0;
     if (large) {
         t0.phase_wg = p.precision == LBM_FP32_DEV ? 0 : 5;
         t0.collide_wg = p.precision == LBM_FP64 ? 2 : 3;
+        t0.collide_run[0] = 4;
+        t0.collide_run[1] = 32;
     }
     if (lbm_status s = apply_tuning(d.get(), t0)) {
         d->release();
@@ -748,15 +752,19 @@ static bool tuning_ok(const lbm_tuning& t) {
     auto sch = [](int v) { return v >= 1 && v <= 3; };
     auto flag = [](int v) { return v == 0 || v == 1; };
     auto wg = [](int v) { return v >= 0 && v <= kMaxWgPerCu; };
+    auto run = [](const int32_t* r) {
+        return r[0] >= 1 && r[0] <= kMaxXcdRun && r[1] >= 1 && r[1] <= kMaxXcdRun;
+    };
     return blk(t.phase_block) && blk(t.collide_block) && sch(t.phase_schedule) &&
            sch(t.collide_schedule) && flag(t.phase_stream) && flag(t.collide_stream) &&
-           wg(t.phase_wg) && wg(t.collide_wg);
+           wg(t.phase_wg) && wg(t.collide_wg) && run(t.phase_run) && run(t.collide_run);
 }
 
 lbm_status lbm_set_tuning(lbm_domain* d, const lbm_tuning* t) {
     if (lbm_status s = check_domain(d)) return s;
     if (!t || !tuning_ok(*t))
-        return fail(LBM_ERR_ARG, "unsupported block, schedule, stream flag or workgroup limit");
+        return fail(LBM_ERR_ARG,
+                    "unsupported block, schedule, stream flag, workgroup limit or run length");
     HIP_TRY(hipStreamSynchronize(d->stream));
     d->drop_step_graph();
     return apply_tuning(d, *t);
@@ -801,27 +809,39 @@ lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out) {
     lbm_tuning best = d->tune;
     double best_ms[2] = {1e30, 1e30};
     d->record_history = false;
-    // Per kernel: every (block, schedule, stream) with no workgroup limit, then limits of 1 to
-    // 8 workgroups per CU on the best of those.
+    // Per kernel: every (block, schedule, stream) with no workgroup limit and runs of 16, then
+    // limits of 1 to 8 workgroups per CU on the best of those, then (XCD-aware schedules only)
+    // run lengths for the even and then the odd steps. A trial times both parities; while one
+    // parity's run varies the other's launches stay the same, so the mean ranks that parity.
     const int blocks[3] = {64, 128, 256};
     const int limits[7] = {1, 2, 3, 4, 5, 6, 8};
+    const int runs[5] = {4, 8, 16, 32, 64};
     for (int kernel = 0; kernel < 2 && st == LBM_OK && he == hipSuccess; ++kernel) {
-        for (int cand = 0; cand < 18 + 7 && st == LBM_OK; ++cand) {
+        for (int cand = 0; cand < 18 + 7 + 10 && st == LBM_OK; ++cand) {
             const int bi = cand % 3, sched = 1 + (cand / 3) % 3, stream = (cand / 9) % 2;
             lbm_tuning t = best;
             int& wg = kernel == 0 ? t.phase_wg : t.collide_wg;
-            if (cand >= 18) {
+            int32_t* run = kernel == 0 ? t.phase_run : t.collide_run;
+            const int sched_now = kernel == 0 ? t.phase_schedule : t.collide_schedule;
+            if (cand >= 25) {
+                if (sched_now == 1) break;               // no runs in linear order
+                const int par = (cand - 25) / 5, r = runs[(cand - 25) % 5];
+                if (run[par] == r) continue;             // the incumbent, already timed
+                run[par] = r;
+            } else if (cand >= 18) {
                 wg = limits[cand - 18];
             } else if (kernel == 0) {
                 t.phase_block = blocks[bi];
                 t.phase_schedule = sched;
                 t.phase_stream = stream;
                 wg = 0;
+                run[0] = run[1] = kXcdRun;
             } else {
                 t.collide_block = blocks[bi];
                 t.collide_schedule = sched;
                 t.collide_stream = stream;
                 wg = 0;
+                run[0] = run[1] = kXcdRun;
             }
             st = apply_tuning(d, t);
             if (st != LBM_OK) break;

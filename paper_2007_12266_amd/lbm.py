@@ -141,10 +141,16 @@ class Tuning(ctypes.Structure):
                 ("collide_block", ctypes.c_int32), ("collide_schedule", ctypes.c_int32),
                 ("phase_stream", ctypes.c_int32), ("collide_stream", ctypes.c_int32),
                 ("phase_wg", ctypes.c_int32), ("collide_wg", ctypes.c_int32),
+                ("phase_run", ctypes.c_int32 * 2), ("collide_run", ctypes.c_int32 * 2),
                 ("phase_ms", ctypes.c_double), ("collide_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        """Field values; the run lengths as [even, odd] lists."""
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 class Info(ctypes.Structure):
@@ -492,9 +498,13 @@ class Domain:
         return t.as_dict()
 
     def set_tuning(self, **kw):
+        """Change fields of the current launch configuration (phase_run and collide_run take an
+        [even, odd] pair)."""
         t = Tuning()
         _check(load_library().lbm_get_tuning(self.handle, ctypes.byref(t)))
         for k, v in kw.items():
+            if k in ("phase_run", "collide_run"):
+                v = (ctypes.c_int32 * 2)(*(int(x) for x in v))
             setattr(t, k, v)
         _check(load_library().lbm_set_tuning(self.handle, ctypes.byref(t)))
         return self

@@ -41,6 +41,7 @@ int main(void) {
     FIELD(lbm_params, rho_a);
     FIELD(lbm_tuning, phase_stream);
     FIELD(lbm_tuning, collide_wg);
+    FIELD(lbm_tuning, collide_run);
     FIELD(lbm_tuning, phase_ms);
     FIELD(lbm_domain_info, neighbour_mode);
     FIELD(lbm_domain_info, compact_ex_waves);

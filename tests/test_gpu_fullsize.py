@@ -6,8 +6,9 @@ neighbours' moment slots, the collide kernel the neighbours' phi and (odd step) 
 the read-out one more neighbour, so the cone has a radius of at most 2 per step plus 1. The
 oracle run for two steps on a 15^3 crop centred on a voxel therefore gives that voxel's exact
 two-step state, and the GPU's value there is compared with it. The domain runs as bench.py runs
-it: FP64, the compact neighbour lookup with its exception waves, streaming accesses and the
-per-CU workgroup limits that lbm_domain_create gives a domain of this size.
+it: FP64, the compact neighbour lookup with its exception waves, streaming accesses, the
+per-CU workgroup limits and the per-parity XCD run lengths that lbm_domain_create gives a
+domain of this size.
 """
 import dataclasses
 
@@ -59,6 +60,7 @@ def _check(lbm, prob, centres, face_planes=None):
     assert info["neighbour_mode"] == lbm.NBR_COMPACT and info["compact_ex_waves"] > 0
     assert tune["phase_stream"] == 1 and tune["collide_stream"] == 1
     assert tune["phase_wg"] == 5 and tune["collide_wg"] == 2
+    assert tune["collide_run"] == [4, 32]
     dom.step(STEPS)
     names = ("Na", "Nb", "phi", "rho", "ux", "uy", "uz")
     gpu = {}

@@ -113,10 +113,12 @@ def test_ragged_domains_all_block_sizes(lbm, block, periodic, mode):
                                             ("compact", "fp32dev")])
 def test_block_size_and_launch_shape_do_not_change_results(lbm, mode, precision):
     """Block sizes, the three tile orders (launch order, XCD-aware runs, XCD-aware runs from the
-    end of the pore list) in every pairing of the two kernels, streaming (non-temporal)
-    accesses on or off, and limits of 1 to 16 workgroups per CU in either kernel give the same
-    state, with each neighbour lookup. A small domain starts without streaming or limits; the
-    flags are valid only as 0 or 1, the limits from 0 to 16. In every storage precision."""
+    end of the pore list) in every pairing of the two kernels, XCD run lengths of 1 to 64 tiles
+    chosen apart for the two step parities, streaming (non-temporal) accesses on or off, and
+    limits of 1 to 16 workgroups per CU in either kernel give the same state, with each
+    neighbour lookup. A small domain starts without streaming or limits and with runs of 16; the
+    flags are valid only as 0 or 1, the limits from 0 to 16, the runs from 1 to 64. In every
+    storage precision."""
     prob = _random_problem((17, 18, 19), (True, True, True), seed=5)
     nm = _nm(lbm, mode)
     prec = {"fp64": lbm.FP64, "mixed": lbm.FP32_MIXED, "fp32dev": lbm.FP32_DEV}[precision]
@@ -126,15 +128,19 @@ def test_block_size_and_launch_shape_do_not_change_results(lbm, mode, precision)
         t = dom.tuning()
         assert t["phase_stream"] == 0 and t["collide_stream"] == 0
         assert t["phase_wg"] == 0 and t["collide_wg"] == 0
+        assert t["phase_run"] == [16, 16] and t["collide_run"] == [16, 16]
         dom.step(25)
         outs.append(dom.save())
         dom.close()
-    for ps, cs, pst, cst, pwg, cwg in ((1, 3, 1, 1, 0, 1), (3, 2, 0, 1, 5, 2),
-                                       (3, 3, 1, 0, 16, 3), (2, 1, 1, 1, 1, 8)):
+    for ps, cs, pst, cst, pwg, cwg, pr, cr in ((1, 3, 1, 1, 0, 1, (16, 16), (1, 64)),
+                                               (3, 2, 0, 1, 5, 2, (3, 7), (8, 32)),
+                                               (3, 3, 1, 0, 16, 3, (64, 1), (5, 13)),
+                                               (2, 1, 1, 1, 1, 8, (2, 9), (64, 64))):
         dom = lbm.Domain(prob, neighbour_mode=nm, precision=prec)
         dom.set_tuning(phase_block=128, phase_schedule=ps, collide_block=64, collide_schedule=cs,
-                       phase_stream=pst, collide_stream=cst, phase_wg=pwg, collide_wg=cwg)
-        assert dom.tuning()["collide_wg"] == cwg
+                       phase_stream=pst, collide_stream=cst, phase_wg=pwg, collide_wg=cwg,
+                       phase_run=pr, collide_run=cr)
+        assert dom.tuning()["collide_wg"] == cwg and dom.tuning()["collide_run"] == list(cr)
         dom.step(12)
         dom.step(13)
         outs.append(dom.save())
@@ -142,6 +148,10 @@ def test_block_size_and_launch_shape_do_not_change_results(lbm, mode, precision)
             dom.set_tuning(collide_stream=2)
         with pytest.raises(lbm.LbmError):
             dom.set_tuning(phase_wg=17)
+        with pytest.raises(lbm.LbmError):
+            dom.set_tuning(collide_run=(0, 16))
+        with pytest.raises(lbm.LbmError):
+            dom.set_tuning(phase_run=(16, 65))
         dom.close()
     assert all(o == outs[0] for o in outs)
 
@@ -407,6 +417,7 @@ def test_autotune_restores_state_and_keeps_results(lbm, precision):
     assert t["phase_block"] in (64, 128, 256) and t["collide_schedule"] in (1, 2, 3)
     assert t["phase_stream"] in (0, 1) and t["collide_stream"] in (0, 1)
     assert 0 <= t["phase_wg"] <= 8 and 0 <= t["collide_wg"] <= 8
+    assert all(r in (4, 8, 16, 32, 64) for r in t["phase_run"] + t["collide_run"])
     assert t["phase_ms"] > 0 and t["collide_ms"] > 0
     assert dom.info()["step"] == 7 and dom.save() == before
     dom.step(13)
@@ -573,6 +584,8 @@ def test_randomized_configurations_match_the_oracle(lbm, case):
                    phase_stream=int(rng.integers(0, 2)), collide_stream=int(rng.integers(0, 2)),
                    phase_wg=int(rng.integers(0, 9)), collide_wg=int(rng.integers(0, 9)))
     steps = int(rng.integers(5, 40))
+    dom.set_tuning(phase_run=[int(v) for v in rng.integers(1, 65, 2)],
+                   collide_run=[int(v) for v in rng.integers(1, 65, 2)])
     dom.step(steps)
     gpu = dom.fields()
     ref = O.state_for(prob).run(steps).fields()

@@ -242,13 +242,13 @@ def test_cache_groups_keep_results(lbm, precision):
     group after the other) leave every member bitwise equal to its solo run, through eager
     steps, a change of grouping and membership changes; a member larger than the group size
     forms a group of its own, and a member alone in its group runs the single-domain launches
-    with its own configuration (one member here with streaming accesses and workgroup limits,
-    as a large domain gets them)."""
+    with its own configuration (one member here with streaming accesses, workgroup limits and
+    per-parity run lengths, as a large domain gets them)."""
     prec = {"fp32dev": lbm.FP32_DEV, "fp64": lbm.FP64, "mixed": lbm.FP32_MIXED}[precision]
     probs = _mix() + [_displacement(10, (24, 12, 16), flux=0.015)]
     doms = [lbm.Domain(p, precision=prec) for p in probs]
     doms[2].set_tuning(phase_stream=1, collide_stream=1, phase_wg=5, collide_wg=2,
-                       collide_schedule=3)
+                       collide_schedule=3, collide_run=(8, 32))
     sizes = [d.info()["device_bytes"] for d in doms]
     pool = lbm.Pool(1 << 34, precision=prec, max_slots=8, chunk_steps=10)
     pool.set_group_bytes(sorted(sizes)[-2] + sorted(sizes)[0])
