@@ -631,8 +631,8 @@ def main():
                          "every 100 steps")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: a domain runs on one GPU (no slab halo exchange "
+              "or collectives are built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
         precs = tuple(p for p in args.batch_precisions.split(",") if p)

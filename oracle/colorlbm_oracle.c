@@ -10,7 +10,7 @@
  * a dense grid, pull-free "push" streaming into a second buffer, explicit 19x19 moment matrix M
  * built from the d'Humieres D3Q19 basis polynomials, and an explicit inverse.
  *
- * Readings where the paper is silent or garbled (each is listed in the design notes):
+ * Readings where the paper is silent or garbled, each taken as stated here:
  *   - m1 equilibrium: e_eq = -11 rho + 19 |j|^2 - 19 alpha |C|  (the printed "(j.j) - alpha|C|"
  *     is the d'Humieres energy row scaled by 1/19, applied to both terms);
  *   - colour gradient stencil: C = sum_q c_q xi_q phi(x + xi_q) with c_q = 1 on the six axis
