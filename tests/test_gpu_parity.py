@@ -362,6 +362,20 @@ def test_degenerate_domains(lbm):
         dom.close()
 
 
+def test_zero_steps_change_nothing_and_negative_counts_are_refused(lbm, spheres32):
+    dom = lbm.Domain(spheres32)
+    dom.step(3)
+    before = dom.save()
+    dom.step(0)
+    assert dom.save() == before and dom.info()["step"] == 3
+    with pytest.raises(lbm.LbmError, match="nsteps"):
+        dom.step(-1)
+    assert dom.save() == before and dom.info()["step"] == 3
+    dom.step(1)
+    assert dom.info()["step"] == 4
+    dom.close()
+
+
 def test_gpu_slit_poiseuille_exact(lbm):
     H, Fz, tau = 16, 1e-6, 0.7
     labels = np.ones((1, H + 2, 1), np.int32)

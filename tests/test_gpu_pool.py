@@ -276,6 +276,30 @@ def test_cache_groups_keep_results(lbm, precision):
         d.close()
 
 
+def test_pool_zero_steps_change_nothing_and_negative_counts_are_refused(lbm):
+    probs = _mix()[:2]
+    doms = [lbm.Domain(p, precision=lbm.FP64) for p in probs]
+    pool = lbm.Pool(1 << 32, precision=lbm.FP64, max_slots=4, chunk_steps=10)
+    slots = [pool.admit(d) for d in doms]
+    pool.step(4)
+    before = [pool.reduce_slot(s) for s in slots]
+    pool.step(0)
+    with pytest.raises(lbm.LbmError, match="nsteps"):
+        pool.step(-2)
+    after = [pool.reduce_slot(s) for s in slots]
+    assert after == before and all(r["step"] == 4 for r in after)
+    out = [pool.retire(s) for s in slots]
+    saved = [d.save() for d in out]
+    for p, blob in zip(probs, saved):
+        ref = lbm.Domain(p, precision=lbm.FP64)
+        ref.step(4)
+        assert ref.save() == blob
+        ref.close()
+    pool.close()
+    for d in doms:
+        d.close()
+
+
 def _open_box(seed, shape=(48, 40, 52)):
     """An open box with 10% random solids: on this grid a 64-voxel wave that holds the edge
     between two blocks of 16 rows of the pore numbering sees its +-y targets jump by a whole
