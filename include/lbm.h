@@ -167,11 +167,11 @@ typedef struct {
  * still be cached). run: the run length in tiles of schedules 2 and 3 (1 to 64; default 16), on
  * even [0] and odd [1] steps: the odd AA step's reads and writes land a neighbour away, so it
  * gains from longer runs (more of the lines it shares with nearby tiles stay on one XCD), the
- * even step from shorter ones. stream: 1 = the data a launch touches once (even-step populations, the
- * neighbour lookup, the moment slots, phi and N written for the next kernel) is read and
- * written with non-temporal hints, so the L2 keeps the lines neighbouring voxels re-read; right
- * for domains far larger than the 256 MB Infinity Cache, wrong for those it holds from one step
- * to the next. wg: at most this many workgroups of the kernel resident per CU (0: as many as its
+ * even step from shorter ones. stream: 1 = the data a launch touches once (even-step
+ * populations, the neighbour lookup, the moment slots, phi and N written for the next kernel)
+ * is read and written with non-temporal hints, so the L2 keeps the lines neighbouring voxels
+ * re-read; right for domains far larger than the 256 MB Infinity Cache, wrong for those it
+ * holds from one step to the next. wg: at most this many workgroups of the kernel resident per CU (0: as many as its
  * registers allow; up to 16), enforced by reserving LDS the kernel does not use; fewer resident
  * waves keep more of the lines that neighbouring voxels share in the L2. When the domain's device
  * memory exceeds 512 MiB, lbm_domain_create sets stream = 1, the limits the autotuner picks
@@ -354,8 +354,8 @@ lbm_status lbm_domain_get_info(lbm_domain* d, lbm_domain_info* out);
  * them, then (XCD-aware schedules) run lengths of 4 to 64 tiles for each step parity in turn,
  * applies the fastest, and writes it to *out (nullable).
  * The state, step counter and reduction history are restored afterwards, so the results of later
- * steps are unchanged. Synchronises; needs device memory for one copy of the populations (LBM_ERR_OOM
- * otherwise). */
+ * steps are unchanged. Synchronises; needs device memory for one copy of the populations
+ * (LBM_ERR_OOM otherwise). */
 lbm_status lbm_autotune(lbm_domain* d, int32_t trial_steps, lbm_tuning* out);
 
 /* Apply a launch configuration (e.g. one cached from an earlier lbm_autotune on the same GPU,
