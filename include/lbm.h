@@ -171,10 +171,10 @@ typedef struct {
  * populations, the neighbour lookup, the moment slots, phi and N written for the next kernel)
  * is read and written with non-temporal hints, so the L2 keeps the lines neighbouring voxels
  * re-read; right for domains far larger than the 256 MB Infinity Cache, wrong for those it
- * holds from one step to the next. wg: at most this many workgroups of the kernel resident per CU (0: as many as its
- * registers allow; up to 16), enforced by reserving LDS the kernel does not use; fewer resident
- * waves keep more of the lines that neighbouring voxels share in the L2. When the domain's device
- * memory exceeds 512 MiB, lbm_domain_create sets stream = 1, the limits the autotuner picks
+ * holds from one step to the next. wg: at most this many workgroups of the kernel resident per
+ * CU (0: as many as its registers allow; up to 16), enforced by reserving LDS the kernel does
+ * not use; fewer resident waves keep more of the lines that neighbouring voxels share in the
+ * L2. When the domain's device memory exceeds 512 MiB, lbm_domain_create sets stream = 1, the limits the autotuner picks
  * at 512^3 (phase / collide wg: FP64 5 / 2, FP32-mixed 5 / 3, FP32-dev 0 / 3) and collide runs
  * of 4 (even) / 32 (odd) tiles; else stream 0, no limits and runs of 16.
  * Results do not depend on the configuration (bitwise). */
