@@ -166,18 +166,18 @@ typedef struct {
  * that a kernel following one in forward order starts where that one ended (on lines that may
  * still be cached). run: the run length in tiles of schedules 2 and 3 (1 to 64; default 16), on
  * even [0] and odd [1] steps: the odd AA step's reads and writes land a neighbour away, so it
- * gains from longer runs (more of the lines it shares with nearby tiles stay on one XCD), the
- * even step from shorter ones. stream: 1 = the data a launch touches once (even-step
- * populations, the neighbour lookup, the moment slots, phi and N written for the next kernel)
- * is read and written with non-temporal hints, so the L2 keeps the lines neighbouring voxels
- * re-read; right for domains far larger than the 256 MB Infinity Cache, wrong for those it
- * holds from one step to the next. wg: at most this many workgroups of the kernel resident per
- * CU (0: as many as its registers allow; up to 16), enforced by reserving LDS the kernel does
- * not use; fewer resident waves keep more of the lines that neighbouring voxels share in the
- * L2. When the domain's device memory exceeds 512 MiB, lbm_domain_create sets stream = 1, the limits the autotuner picks
- * at 512^3 (phase / collide wg: FP64 5 / 2, FP32-mixed 5 / 3, FP32-dev 0 / 3) and collide runs
- * of 4 (even) / 32 (odd) tiles; else stream 0, no limits and runs of 16.
- * Results do not depend on the configuration (bitwise). */
+ * gains from longer runs (more of the lines it shares with nearby tiles stay on one XCD), the even
+ * step from shorter ones. stream: 1 = the data a launch touches once (even-step populations, the
+ * neighbour lookup, the moment slots, phi and N written for the next kernel) is read and written
+ * with non-temporal hints, so the L2 keeps the lines neighbouring voxels re-read; right for
+ * domains far larger than the 256 MB Infinity Cache, wrong for those it holds from one step to the
+ * next. wg: at most this many workgroups of the kernel resident per CU (0: as many as its
+ * registers allow; up to 16), enforced by reserving LDS the kernel does not use; fewer resident
+ * waves keep more of the lines that neighbouring voxels share in the L2. When the domain's device
+ * memory exceeds 512 MiB, lbm_domain_create sets stream = 1, the limits the autotuner picks at
+ * 512^3 (phase / collide wg: FP64 5 / 2, FP32-mixed 5 / 3, FP32-dev 0 / 3) and collide runs of 4
+ * (even) / 32 (odd) tiles; else stream 0, no limits and runs of 16. Results do not depend on the
+ * configuration (bitwise). */
 typedef struct {
     int32_t phase_block, phase_schedule;
     int32_t collide_block, collide_schedule;
