@@ -774,6 +774,7 @@ def main():
                   "neighbours": nb_name,
                   "compact_ex_waves": dinfo["compact_ex_waves"],
                   "kernel_ms": round(timing["collide_ms"], 5),
+                  "kernel_ms_even_odd": [round(v, 5) for v in timing["collide_parity_ms"]],
                   "copy_ceiling_gbs": round(copy_gbs, 1),
                   "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)},
         step_hbm={"bytes_per_voxel": nbytes["per_voxel"]["step"],

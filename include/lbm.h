@@ -157,6 +157,7 @@ typedef struct {
     double bc_ms;             /* pressure-face kernel (0 if unused)                          */
     double step_ms;           /* wall time per step between the first and last event         */
     int64_t phase_launches, collide_launches, bc_launches;
+    double collide_parity_ms[2]; /* collide_ms over the even [0] and odd [1] AA steps alone    */
 } lbm_timing;
 
 /* Launch configuration of the two step kernels. block: threads per workgroup (64, 128 or 256);

@@ -171,7 +171,7 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
         ev.push_back(*out);
         return hipEventRecord(*out, d->stream);
     };
-    struct Span { hipEvent_t a, b; int kind; };
+    struct Span { hipEvent_t a, b; int kind, odd; };
     std::vector<Span> spans;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (timing) {
@@ -180,7 +180,7 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
     }
     auto mark = [&](int kind, bool begin) -> lbm_status {
         if (begin) {
-            spans.push_back(Span{nullptr, nullptr, kind});
+            spans.push_back(Span{nullptr, nullptr, kind, (int)(d->step & 1)});
             HIP_TRY(event(&spans.back().a));
         } else {
             HIP_TRY(event(&spans.back().b));
@@ -214,13 +214,17 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
     if (timing && st == LBM_OK) {
         HIP_TRY(event(&t1));
         HIP_TRY(hipEventSynchronize(t1));
-        double sum[3] = {0, 0, 0};
-        int64_t cnt[3] = {0, 0, 0};
+        double sum[3] = {0, 0, 0}, par_sum[2] = {0, 0};
+        int64_t cnt[3] = {0, 0, 0}, par_cnt[2] = {0, 0};
         for (const Span& sp : spans) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, sp.a, sp.b));
             sum[sp.kind] += ms;
             cnt[sp.kind] += 1;
+            if (sp.kind == 1) {
+                par_sum[sp.odd] += ms;
+                par_cnt[sp.odd] += 1;
+            }
         }
         float tot = 0.f;
         HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
@@ -231,6 +235,8 @@ lbm_status step_impl(lbm_domain* d, int64_t nsteps, lbm_timing* timing) {
         timing->phase_launches = cnt[0];
         timing->collide_launches = cnt[1];
         timing->bc_launches = cnt[2];
+        for (int k = 0; k < 2; ++k)
+            timing->collide_parity_ms[k] = par_cnt[k] ? par_sum[k] / par_cnt[k] : 0.0;
     }
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     return st;

@@ -133,7 +133,7 @@ class Timing(ctypes.Structure):
     _fields_ = [("phase_ms", ctypes.c_double), ("collide_ms", ctypes.c_double),
                 ("bc_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
                 ("phase_launches", ctypes.c_int64), ("collide_launches", ctypes.c_int64),
-                ("bc_launches", ctypes.c_int64)]
+                ("bc_launches", ctypes.c_int64), ("collide_parity_ms", ctypes.c_double * 2)]
 
 
 class Tuning(ctypes.Structure):
@@ -394,7 +394,9 @@ class Domain:
     def step_timed(self, n: int) -> dict:
         t = Timing()
         _check(load_library().lbm_step_timed(self.handle, int(n), ctypes.byref(t)))
-        return {k: getattr(t, k) for k, _ in Timing._fields_}
+        out = {k: getattr(t, k) for k, _ in Timing._fields_}
+        out["collide_parity_ms"] = list(out["collide_parity_ms"])   # [even, odd]
+        return out
 
     def field(self, name: str) -> np.ndarray:
         out = np.empty(self.shape, dtype=np.float64)

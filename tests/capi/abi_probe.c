@@ -47,6 +47,7 @@ int main(void) {
     FIELD(lbm_domain_info, compact_ex_waves);
     FIELD(lbm_reduction, ca);
     FIELD(lbm_reduction, unstable);
+    FIELD(lbm_timing, collide_parity_ms);
 
     s = lbm_prepass_query(&p, labels, 2, kind, aff, NULL, NULL, &n_pore, &n_tail, NULL, NULL,
                           NULL);

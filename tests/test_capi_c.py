@@ -41,7 +41,7 @@ def test_struct_layouts_match_the_binding(probe_output):
     for cname, py in sizes.items():
         assert int(probe_output["sizeof." + cname][0]) == ctypes.sizeof(py), cname
     fields = {"lbm_params": lbm.Params, "lbm_tuning": lbm.Tuning, "lbm_domain_info": lbm.Info,
-              "lbm_reduction": lbm.Reduction}
+              "lbm_reduction": lbm.Reduction, "lbm_timing": lbm.Timing}
     for key, val in probe_output.items():
         struct, _, field = key.partition(".")
         if struct in fields:

@@ -196,8 +196,12 @@ def test_captured_step_chunks_equal_step_by_step_launches(lbm, spheres32):
         a.step(1)
         b.step_timed(1)
         a.step(250)
-        b.step_timed(250)
+        t = b.step_timed(250)
         assert a.save() == b.save(), every
+        # From step 1: 125 even and 125 odd collide launches, timed apart and together.
+        even, odd = t["collide_parity_ms"]
+        assert t["collide_launches"] == 250 and even > 0 and odd > 0
+        assert abs((even + odd) / 2 - t["collide_ms"]) <= 1e-9 * t["collide_ms"] + 1e-12
         assert a.history() == b.history(), every
         force = (0.0, 2e-6, 2e-5)
         a.set_force(force)
